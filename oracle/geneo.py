@@ -1,0 +1,102 @@
+"""GenEO coarse space (oracle; test infrastructure).
+
+Section 2.3: in every subdomain a few of the lowest-energy modes of a local generalised
+eigenproblem are computed (rigid-body modes and composite low-energy modes, Fig. fig-eig),
+multiplied by the partition of unity and combined into a coarse space; the coarse problem
+is solved directly.  The paper defers the exact eigenproblem to Spillane et al. (its
+reference for GenEO); the reading used here is that form:
+
+    A_j^N p = lambda B_j p,   B_j = Xt_j A_j^o Xt_j,
+
+with A_j^N the stiffness assembled over the elements of Omega_j on the free DOFs of its
+nodes (Neumann matrix), A_j^o the same over the elements of Omega_j that also lie in another
+subdomain, and Xt_j the partition of unity extended by zero off I_j.  Selected are the
+pairs with lambda < tau (at most nev_max), or the nev smallest when nev > 0.  The coarse
+basis vectors are z = R_j^T (Xt_j p)|_{I_j}, and K_0 = Z^T K Z is Cholesky-factored.
+
+Solver: ARPACK in shift-invert mode about -sigma (sigma = 1e-3 tau, or 1e-4 when nev is
+given), i.e. the largest mu of B p = mu (A^N + sigma B) p; A^N + sigma B is SPD because no
+rigid-body mode lies in the null space of B.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .fem import assemble
+
+
+def local_matrices(dec, j):
+    prob = dec.prob
+    mesh = prob.mesh
+    free = prob.free_idx
+    AN = assemble(mesh, prob.Ke, dec.elems[j])[free][:, free]
+    Ao = assemble(mesh, prob.Ke, dec.overlap_elems[j])[free][:, free]
+    Dj = dec.D[j]
+    AN = AN[Dj][:, Dj].tocsc()
+    Ao = Ao[Dj][:, Dj].tocsc()
+    xt = np.zeros(len(Dj))
+    pos = np.searchsorted(Dj, dec.I[j])
+    xt[pos] = dec.X[j]
+    B = (sp.diags(xt) @ Ao @ sp.diags(xt)).tocsc()
+    return AN, B, xt, pos
+
+
+def solve_local_eigen(AN, B, nev=0, tau=0.1, nev_max=32, tol=1e-13, dense=None):
+    """Smallest eigenpairs of A^N p = lambda B p by shift-invert (or dense for tiny sizes).
+
+    dense=None picks the dense solver below 600 DOFs, True/False force one or the other.
+    """
+    n = AN.shape[0]
+    shift = 1e-4 * (tau if tau else 1.0) if nev > 0 else 1e-3 * tau
+    if dense or (dense is None and n <= 600):
+        M = (AN + shift * B).toarray()
+        mu, V = sla.eigh(B.toarray(), M)
+        with np.errstate(divide="ignore"):
+            lam = 1.0 / mu[::-1] - shift
+        V = V[:, ::-1]
+        ok = mu[::-1] > 0
+        lam, V = lam[ok], V[:, ok]
+        k = nev if nev > 0 else min(nev_max, int(np.sum(lam < tau)))
+        return lam[:k], V[:, :k]
+    k = nev if nev > 0 else min(8, nev_max)
+    while True:
+        kk = min(k, n - 2)
+        lam, V = spla.eigsh(AN, k=kk, M=B, sigma=-shift, which="LM", tol=tol)
+        order = np.argsort(lam)
+        lam, V = lam[order], V[:, order]
+        if nev > 0:
+            return lam[:nev], V[:, :nev]
+        if lam[-1] >= tau or k >= nev_max:
+            sel = lam < tau
+            return lam[sel][:nev_max], V[:, sel][:, :nev_max]
+        k = min(2 * k, nev_max)
+
+
+class Coarse:
+    def __init__(self, dec, nev=0, tau=0.1, nev_max=32, dense=None):
+        self.dec = dec
+        n = dec.prob.n
+        cols, self.lams, self.nev = [], [], []
+        for j in range(dec.n_sub):
+            AN, B, xt, pos = local_matrices(dec, j)
+            lam, V = solve_local_eigen(AN, B, nev=nev, tau=tau, nev_max=nev_max, dense=dense)
+            self.lams.append(lam)
+            self.nev.append(len(lam))
+            for c in range(V.shape[1]):
+                z = np.zeros(n)
+                z[dec.I[j]] = (xt * V[:, c])[pos]
+                cols.append(z)
+        self.n0 = len(cols)
+        self.Z = np.array(cols).T if cols else np.zeros((n, 0))
+        K = dec.prob.K
+        self.K0 = self.Z.T @ (K @ self.Z)
+        self.K0 = 0.5 * (self.K0 + self.K0.T)
+        self.chol = sla.cho_factor(self.K0, lower=True) if self.n0 else None
+
+    def apply(self, r):
+        if not self.n0:
+            return np.zeros_like(r)
+        return self.Z @ sla.cho_solve(self.chol, self.Z.T @ r)
