@@ -1,0 +1,237 @@
+/*
+ * gx — AS-GenEO preconditioned conjugate gradients for laminated composites on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the linear elasticity system K u = f of the paper's Eq. (eq-1)
+ * (Reinarz et al., "dune-composites", section 2.3) for layered composites meshed with
+ * 20-node serendipity hexahedra (section 2.1), by CG on P K u = P f (Eq. eq-pre) with P
+ * the two-level overlapping additive Schwarz preconditioner whose coarse space is built
+ * from local generalised eigenproblems (GenEO, section 2.3).
+ *
+ * Conventions (all entry points)
+ *   - Units: mm, N, MPa.  Indices are 0-based.
+ *   - A displacement-sized vector has 3 * n_nodes FP64 entries, DOF = 3 * node + component
+ *     (x, y, z).  Clamped DOFs carry 0 on output; their input values are ignored.
+ *   - Arrays whose length grows with the mesh are DEVICE pointers (e.g. a torch tensor's
+ *     data_ptr() on the context's device); descriptor structs and per-layer / per-subdomain
+ *     tables are HOST pointers.  Every input is borrowed for the duration of the call only:
+ *     the library copies what it keeps.
+ *   - All work is queued on the context's HIP stream; calls return after that work has
+ *     completed (results are ready for any stream).
+ *   - No exception crosses this interface.  Every call returns a gx_status; on failure a
+ *     message is available from gx_last_error().  One context per host thread.
+ *   - Library-owned state (mesh copy, element matrices, K, decomposition, factors, coarse
+ *     space) lives in the context and is released by gx_destroy().
+ */
+#ifndef GX_H
+#define GX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gx_ctx gx_ctx;
+typedef int32_t gx_status;
+
+enum {
+  GX_OK = 0,
+  GX_EINVAL = 1,      /* bad argument (null pointer, size, unsupported option) */
+  GX_ENOMEM = 2,      /* device allocation failed */
+  GX_EHIP = 3,        /* a HIP runtime call failed */
+  GX_ENOTSPD = 4,     /* non-positive pivot in a Cholesky factorisation */
+  GX_ENOCONV = 5,     /* iteration limit reached; outputs hold the last iterate */
+  GX_EBREAKDOWN = 6,  /* CG breakdown: p^T K p <= 0 or not finite */
+  GX_ESTATE = 7       /* call made out of order (e.g. solve before setup) */
+};
+
+enum { GX_GEOM_FLAT = 0, GX_GEOM_LSECTION = 1 };
+enum { GX_FP64 = 0, GX_MIXED = 1 };
+
+/* ------------------------------------------------------------------------------------
+ * Context
+ * ------------------------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to queue work on,
+ * or NULL to let the library create (and own) one. */
+gx_status gx_create(gx_ctx** ctx, int32_t device, void* hip_stream);
+void gx_destroy(gx_ctx* ctx);
+/* Message of the last failed call on this context ("" if none).  Never NULL. */
+const char* gx_last_error(const gx_ctx* ctx);
+/* Library version string. */
+const char* gx_version(void);
+
+/* ------------------------------------------------------------------------------------
+ * Laminate mesh (sections 2.2 and 3: tensor-product laminate grids; the flat ->
+ * wrinkled -> curved mapping of Eq. eq-wrinkle and the curved map that follows it).
+ *
+ * Layers are listed from zeta = 0 (inner radius / bottom) outwards, each split into
+ * layer_nel equal element layers.  Along s the flat part has nx equal elements over
+ * `length`; the L-section has nx_limb equal elements on each straight limb of length
+ * `limb` and nx - 2 nx_limb equal elements on a 90 degree arc of mid-surface radius
+ * radius + T/2 centred at (limb, 0) (T = total thickness), s = 0 at mid-arc.  Along l
+ * there are ny equal elements over `width`.  The wrinkle displaces every layer by
+ * w(s - s_c) = A exp(-((s - s_c)/L)^2) cos(2 pi (s - s_c)/L) along the laminate normal
+ * (s_c = length/2 for a flat part, 0 for the L-section); A = 0 disables it.
+ *
+ * Node numbering: nodes sit on a doubled lattice (i2, j2, k2) with at most one odd index
+ * (8 vertices and 12 edge midpoints per element, section 2.1); the node number is the rank
+ * of (k2, j2, i2) in lexicographic order, i2 fastest.  Element e = (ez * ny + ey) * nx + ex.
+ * Element-local node order: 8 vertices (di, dj, dk) lexicographic with di fastest; then
+ * x-directed edges at (dj, dk) = (0,0),(1,0),(0,1),(1,1); y-directed at (di, dk); z-directed
+ * at (di, dj).
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+  int32_t geometry;          /* GX_GEOM_FLAT or GX_GEOM_LSECTION */
+  int32_t nx, ny;            /* elements along s and along l */
+  int32_t nx_limb;           /* L-section only: elements on each limb */
+  int32_t n_layers;          /* material layers (<= 96) */
+  const double* layer_t;     /* host [n_layers] thickness (mm) */
+  const int32_t* layer_nel;  /* host [n_layers] element layers (>= 1) */
+  double length;             /* flat only: extent along s (mm) */
+  double width;              /* extent along l (mm) */
+  double radius, limb;       /* L-section only: inner radius and limb length (mm) */
+  double wrinkle_amp, wrinkle_len;  /* A and L of w(s) (mm) */
+} gx_laminate;
+
+/* Node, element, clamped-node and loaded-face counts of a laminate (host only). */
+gx_status gx_laminate_counts(const gx_laminate* lam, int64_t* n_nodes, int64_t* n_elems,
+                             int64_t* n_clamped, int64_t* n_faces);
+
+/* Build the mesh on the device: xyz [3 n_nodes], conn [20 n_elems], elem_layer [n_elems]
+ * (material layer index of each element), all device buffers sized by gx_laminate_counts.
+ * Also fills the boundary lists: clamped [n_clamped] (every node on the s = s_min end,
+ * all three components fixed, section 2.2) and the loaded faces face_elem/face_id
+ * [n_faces] (local face 1 = xi = +1 of the elements on the s = s_max end).
+ * Any of the boundary pointers may be NULL. */
+gx_status gx_laminate_mesh(gx_ctx* ctx, const gx_laminate* lam, double* xyz, int32_t* conn,
+                           int32_t* elem_layer, int32_t* clamped, int32_t* face_elem,
+                           int32_t* face_id);
+
+/* Box partition of a laminate into px * py in-plane subdomains of element index ranges
+ * (full thickness), box p along an axis of n elements covering [p n / P, (p + 1) n / P)
+ * (section 2.3: subdomains of roughly equal size).  elem_part: device [n_elems], value
+ * iy * px + ix. */
+gx_status gx_laminate_partition(gx_ctx* ctx, const gx_laminate* lam, int32_t px, int32_t py,
+                                int32_t* elem_part);
+
+/* Parameters of the end load of a laminate (host only):
+ * kind 0: uniform traction `value[0..2]` (MPa);
+ * kind 1: end moment value[0] per unit width (N mm / mm), applied as the linear normal
+ *         traction -12 M (zeta - T/2) / T^3 on the s = s_max face, which has zero force
+ *         resultant and puts the inner face in tension along the limb (opens a corner,
+ *         section 2.2). */
+typedef struct {
+  double t0[3];     /* uniform traction vector (MPa) */
+  double k;         /* linear normal part: t += k * ((x - c) . d) * n_out */
+  double c[3], d[3];
+} gx_traction;
+gx_status gx_laminate_traction(const gx_laminate* lam, int32_t kind, const double* value,
+                               gx_traction* out);
+
+/* ------------------------------------------------------------------------------------
+ * Assembly of K and f (Eq. eq-1; section 2.1: full 3x3x3 Gauss integration).
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n_layers;
+  const double* eng;        /* host [9 n_layers]: E1 E2 E3 G12 G13 G23 nu12 nu13 nu23 (MPa)
+                               of each material layer in its material axes (Table 1);
+                               G12 <= 0 marks an isotropic layer given by E = E1 and
+                               nu = nu12 alone (shear modulus E / (2 (1 + nu))) */
+  const double* angle_deg;  /* host [n_layers]: ply angle, fibre = cos(a) e1 + sin(a) e2
+                               about the local normal e3 (e1 along s, e2 along l) */
+} gx_plystack;
+
+typedef struct {
+  int64_t n_nodes, n_elems;
+  const double* xyz;        /* device [3 n_nodes] */
+  const int32_t* conn;      /* device [20 n_elems], element-local order above */
+  const int32_t* elem_layer;/* device [n_elems], index into the ply stack */
+} gx_mesh;
+
+typedef struct {
+  int64_t n_clamped;
+  const int32_t* clamped;   /* device [n_clamped] nodes with all three components fixed */
+  int64_t n_faces;
+  const int32_t* face_elem; /* device [n_faces] */
+  const int32_t* face_id;   /* device [n_faces] local face: 0/1 = xi -/+, 2/3 eta, 4/5 zeta */
+  gx_traction traction;
+} gx_loads;
+
+/* Assemble the stiffness K (kept in the context as 3x3-block CSR over all nodes, clamped
+ * DOFs replaced by identity rows and columns) and the load vector f_out (device
+ * [3 n_nodes], zero on clamped DOFs).  The material stiffness is rotated at every Gauss
+ * point into the frame e1 = unit dx/dxi, e2 = unit part of dx/deta orthogonal to e1,
+ * e3 = e1 x e2, then by the ply angle about e3.  Any previous setup is discarded. */
+gx_status gx_assemble(gx_ctx* ctx, const gx_mesh* mesh, const gx_plystack* plies,
+                      const gx_loads* loads, double* f_out);
+
+/* Number of block rows (= nodes) and 3x3 blocks of K. */
+gx_status gx_matrix_info(gx_ctx* ctx, int64_t* n_block_rows, int64_t* n_blocks);
+/* Copy K out: row_ptr device [n_block_rows + 1], col device [n_blocks], val device
+ * [9 n_blocks] (each block row-major).  Columns are sorted within each row. */
+gx_status gx_matrix_copy(gx_ctx* ctx, int32_t* row_ptr, int32_t* col, double* val);
+/* y = K x (device vectors of 3 n_nodes). */
+gx_status gx_spmv(gx_ctx* ctx, const double* x, double* y);
+
+/* ------------------------------------------------------------------------------------
+ * Two-level overlapping Schwarz preconditioner with GenEO coarse space (section 2.3).
+ * Subdomain j grows its core elements `overlap` times by every element sharing a node;
+ * its local problem is K restricted to the DOFs of nodes all of whose elements lie in the
+ * subdomain (zero displacement on the artificial boundary), solved exactly by a banded
+ * Cholesky factorisation.  The partition of unity is 1 / (number of subdomains holding a
+ * DOF as interior).  GenEO: A_j^N p = lambda X_j A_j^o X_j p on the DOFs of the
+ * subdomain's nodes (A^N over the subdomain's elements, A^o over those also in another
+ * subdomain); the coarse vectors are the partition of unity times the eigenvectors with
+ * lambda < tau (at most nev_max), or the nev smallest when nev > 0.
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n_sub;
+  const int32_t* elem_part;  /* device [n_elems]: core subdomain of each element */
+  int32_t overlap;           /* element layers of overlap (>= 1) */
+  double tau;                /* eigenvalue threshold (used when nev <= 0) */
+  int32_t nev;               /* > 0: fixed number of modes per subdomain */
+  int32_t nev_max;           /* cap per subdomain (<= 48) */
+  int32_t precision;         /* GX_FP64, or GX_MIXED: FP32 subdomain factors and solves */
+  int32_t coarse;            /* 1: two-level (GenEO); 0: one-level Schwarz */
+  const int32_t* nev_per_sub;/* optional host [n_sub]: modes per subdomain (overrides) */
+  double eig_tol;            /* relative eigen-residual target (0: default 1e-10) */
+  int32_t eig_maxit;         /* eigensolver iteration cap (0: default 200) */
+} gx_geneo_opts;
+
+/* Build the decomposition, factor the subdomain matrices, solve the local eigenproblems
+ * and factor the coarse matrix K_0 = Z^T K Z.  nev_out: host [n_sub] modes kept per
+ * subdomain (may be NULL); n0_out: coarse dimension (may be NULL). */
+gx_status gx_geneo_setup(gx_ctx* ctx, const gx_geneo_opts* opts, int32_t* nev_out,
+                         int64_t* n0_out);
+
+/* Per-subdomain sizes: interior DOFs, Neumann DOFs, half bandwidth of the interior factor
+ * (host arrays [n_sub], any may be NULL). */
+gx_status gx_subdomain_info(gx_ctx* ctx, int64_t* n_interior, int64_t* n_neumann,
+                            int64_t* half_band);
+/* GenEO eigenvalues of subdomain j: lam host [nev_out[j]]. */
+gx_status gx_geneo_eigenvalues(gx_ctx* ctx, int32_t j, double* lam);
+
+/* z = P r (device vectors of 3 n_nodes). */
+gx_status gx_precond_apply(gx_ctx* ctx, const double* r, double* z);
+
+/* ------------------------------------------------------------------------------------
+ * Preconditioned CG (section 2.3): x (device, in: initial guess, out: solution) for
+ * K x = b; stops when ||b - K x||_2 <= rtol ||b||_2 (recurrence residual), or after maxit
+ * iterations (GX_ENOCONV, x holds the last iterate).  iters_out: CG iterations (products
+ * with K inside the loop); relres_out: final ||r|| / ||b||; hist: host [maxit + 1] or
+ * NULL, relative residual before each iteration and after the last.
+ * ------------------------------------------------------------------------------------ */
+gx_status gx_pcg_solve(gx_ctx* ctx, const double* b, double* x, double rtol, int32_t maxit,
+                       int32_t* iters_out, double* relres_out, double* hist);
+
+/* Time spent in the last call of each phase, milliseconds (host [8], may be NULL):
+ * assemble, decomposition, local factors, eigensolves, coarse, pcg, precond total in pcg,
+ * spmv total in pcg. */
+gx_status gx_phase_times(gx_ctx* ctx, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GX_H */

@@ -1,0 +1,316 @@
+"""Python binding of libgx (ctypes): AS-GenEO preconditioned CG for laminates on MI355X.
+
+Argument marshalling only: every step of the solve runs in the library's HIP kernels.
+Device arrays are torch tensors on the context's device; descriptors are plain dicts (the
+laminate descriptors of the ``workloads`` module) turned into the C structs of gx.h.
+
+The library must be built (``python -m paper_1707_04228_amd.build``); importing this module
+on a machine without the built library raises immediately — there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+# torch is imported before libgx is loaded so that the process holds a single HIP runtime:
+# libgx's libamdhip64.so.7 dependency then resolves to the one torch already mapped.
+import torch  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgx.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libgx.so is not built ({LIB_PATH}); run python -m "
+                      "paper_1707_04228_amd.build")
+lib = C.CDLL(LIB_PATH)
+
+GX_OK, GX_EINVAL, GX_ENOMEM, GX_EHIP, GX_ENOTSPD, GX_ENOCONV, GX_EBREAKDOWN, GX_ESTATE = range(8)
+STATUS = {0: "GX_OK", 1: "GX_EINVAL", 2: "GX_ENOMEM", 3: "GX_EHIP", 4: "GX_ENOTSPD",
+          5: "GX_ENOCONV", 6: "GX_EBREAKDOWN", 7: "GX_ESTATE"}
+GX_GEOM_FLAT, GX_GEOM_LSECTION = 0, 1
+GX_FP64, GX_MIXED = 0, 1
+
+i32p, i64p, f64p, vp = (C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                        C.c_void_p)
+
+
+class Laminate(C.Structure):
+    _fields_ = [("geometry", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("nx_limb", C.c_int32), ("n_layers", C.c_int32),
+                ("layer_t", f64p), ("layer_nel", i32p),
+                ("length", C.c_double), ("width", C.c_double), ("radius", C.c_double),
+                ("limb", C.c_double), ("wrinkle_amp", C.c_double),
+                ("wrinkle_len", C.c_double)]
+
+
+class PlyStack(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("eng", f64p), ("angle_deg", f64p)]
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_elems", C.c_int64), ("xyz", vp), ("conn", vp),
+                ("elem_layer", vp)]
+
+
+class Traction(C.Structure):
+    _fields_ = [("t0", C.c_double * 3), ("k", C.c_double), ("c", C.c_double * 3),
+                ("d", C.c_double * 3)]
+
+
+class Loads(C.Structure):
+    _fields_ = [("n_clamped", C.c_int64), ("clamped", vp), ("n_faces", C.c_int64),
+                ("face_elem", vp), ("face_id", vp), ("traction", Traction)]
+
+
+class GeneoOpts(C.Structure):
+    _fields_ = [("n_sub", C.c_int32), ("elem_part", vp), ("overlap", C.c_int32),
+                ("tau", C.c_double), ("nev", C.c_int32), ("nev_max", C.c_int32),
+                ("precision", C.c_int32), ("coarse", C.c_int32), ("nev_per_sub", i32p),
+                ("eig_tol", C.c_double), ("eig_maxit", C.c_int32)]
+
+
+def _sig(name, args, res=C.c_int32):
+    f = getattr(lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_sig("gx_create", [C.POINTER(vp), C.c_int32, vp])
+_sig("gx_destroy", [vp], None)
+_sig("gx_last_error", [vp], C.c_char_p)
+_sig("gx_version", [], C.c_char_p)
+_sig("gx_laminate_counts", [C.POINTER(Laminate), i64p, i64p, i64p, i64p])
+_sig("gx_laminate_mesh", [vp, C.POINTER(Laminate), vp, vp, vp, vp, vp, vp])
+_sig("gx_laminate_partition", [vp, C.POINTER(Laminate), C.c_int32, C.c_int32, vp])
+_sig("gx_laminate_traction", [C.POINTER(Laminate), C.c_int32, f64p, C.POINTER(Traction)])
+_sig("gx_assemble", [vp, C.POINTER(Mesh), C.POINTER(PlyStack), C.POINTER(Loads), vp])
+_sig("gx_matrix_info", [vp, i64p, i64p])
+_sig("gx_matrix_copy", [vp, vp, vp, vp])
+_sig("gx_spmv", [vp, vp, vp])
+_sig("gx_phase_times", [vp, f64p])
+for _name, _args in [("gx_geneo_setup", [vp, C.POINTER(GeneoOpts), i32p, i64p]),
+                     ("gx_subdomain_info", [vp, i64p, i64p, i64p]),
+                     ("gx_geneo_eigenvalues", [vp, C.c_int32, f64p]),
+                     ("gx_precond_apply", [vp, vp, vp]),
+                     ("gx_pcg_solve", [vp, vp, vp, C.c_double, C.c_int32, i32p, f64p, f64p])]:
+    if hasattr(lib, _name):
+        _sig(_name, _args)
+
+EXPORTS = ["gx_create", "gx_destroy", "gx_last_error", "gx_version", "gx_laminate_counts",
+           "gx_laminate_mesh", "gx_laminate_partition", "gx_laminate_traction",
+           "gx_assemble", "gx_matrix_info", "gx_matrix_copy", "gx_spmv", "gx_geneo_setup",
+           "gx_subdomain_info", "gx_geneo_eigenvalues", "gx_precond_apply", "gx_pcg_solve",
+           "gx_phase_times"]
+
+
+class GxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def laminate_struct(cfg):
+    """gx_laminate for a workload descriptor; returns (struct, keep-alive arrays)."""
+    t = np.array([L["t"] for L in cfg["layers"]], dtype=np.float64)
+    nel = np.array([L["nel"] for L in cfg["layers"]], dtype=np.int32)
+    s = Laminate()
+    s.geometry = GX_GEOM_FLAT if cfg["geometry"] == "flat" else GX_GEOM_LSECTION
+    s.nx, s.ny = cfg["nx"], cfg["ny"]
+    s.nx_limb = cfg.get("nx_limb", 0)
+    s.n_layers = len(t)
+    s.layer_t = t.ctypes.data_as(f64p)
+    s.layer_nel = nel.ctypes.data_as(i32p)
+    s.length = cfg.get("length", 0.0)
+    s.width = cfg["width"]
+    s.radius = cfg.get("radius", 0.0)
+    s.limb = cfg.get("limb", 0.0)
+    A, Lw = cfg.get("wrinkle", (0.0, 0.0))
+    s.wrinkle_amp, s.wrinkle_len = A, Lw
+    return s, (t, nel)
+
+
+def plystack_arrays(cfg):
+    """Engineering constants and angles per layer (isotropic layers as E, nu with G12 = 0)."""
+    from workloads import PLY, RESIN
+    eng, ang = [], []
+    for L in cfg["layers"]:
+        if L["mat"] == "ply":
+            p = dict(PLY)
+            if "E1" in L:
+                p["E1"] = L["E1"]
+            eng.append([p["E1"], p["E2"], p["E3"], p["G12"], p["G13"], p["G23"],
+                        p["nu12"], p["nu13"], p["nu23"]])
+        else:
+            eng.append([RESIN["E"], 0, 0, 0, 0, 0, RESIN["nu"], 0, 0])
+        ang.append(L["angle"])
+    return np.array(eng, dtype=np.float64), np.array(ang, dtype=np.float64)
+
+
+class Solver:
+    """One gx context on a torch CUDA (HIP) device, holding mesh, K, P and work vectors."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        torch.cuda.init()
+        h = vp()
+        st = C.c_void_p(stream.cuda_stream) if stream is not None else None
+        self._check_plain(lib.gx_create(C.byref(h), device, st), "gx_create")
+        self.h = h
+        self.nev = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.gx_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def _check_plain(self, code, what):
+        if code != GX_OK:
+            raise GxError(code, what)
+
+    def _check(self, code):
+        if code != GX_OK:
+            raise GxError(code, lib.gx_last_error(self.h).decode())
+        return code
+
+    # ---- mesh --------------------------------------------------------------------
+    def laminate(self, cfg):
+        """Build the laminate mesh and boundary lists of a workload descriptor."""
+        torch = self.torch
+        lam, keep = laminate_struct(cfg)
+        nn, ne, nc, nf = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        self._check_plain(lib.gx_laminate_counts(C.byref(lam), C.byref(nn), C.byref(ne),
+                                                 C.byref(nc), C.byref(nf)),
+                          "gx_laminate_counts")
+        d = self.device
+        m = dict(n_nodes=nn.value, n_elems=ne.value,
+                 xyz=torch.empty(3 * nn.value, dtype=torch.float64, device=d),
+                 conn=torch.empty(20 * ne.value, dtype=torch.int32, device=d),
+                 elem_layer=torch.empty(ne.value, dtype=torch.int32, device=d),
+                 clamped=torch.empty(nc.value, dtype=torch.int32, device=d),
+                 face_elem=torch.empty(nf.value, dtype=torch.int32, device=d),
+                 face_id=torch.empty(nf.value, dtype=torch.int32, device=d))
+        self._check(lib.gx_laminate_mesh(self.h, C.byref(lam), _ptr(m["xyz"]),
+                                         _ptr(m["conn"]), _ptr(m["elem_layer"]),
+                                         _ptr(m["clamped"]), _ptr(m["face_elem"]),
+                                         _ptr(m["face_id"])))
+        load = cfg["load"]
+        tr = Traction()
+        if load["kind"] == "traction":
+            v = np.array(load["t0"], dtype=np.float64)
+            kind = 0
+        else:
+            v = np.array([load["M"], 0, 0], dtype=np.float64)
+            kind = 1
+        self._check_plain(lib.gx_laminate_traction(C.byref(lam), kind,
+                                                   v.ctypes.data_as(f64p), C.byref(tr)),
+                          "gx_laminate_traction")
+        m["traction"] = tr
+        m["cfg"] = cfg
+        self.mesh = m
+        return m
+
+    def partition(self, cfg, px, py):
+        lam, keep = laminate_struct(cfg)
+        part = self.torch.empty(self.mesh["n_elems"], dtype=self.torch.int32,
+                                device=self.device)
+        self._check(lib.gx_laminate_partition(self.h, C.byref(lam), px, py, _ptr(part)))
+        return part
+
+    # ---- assembly ------------------------------------------------------------------
+    def assemble(self, cfg=None, mesh=None):
+        m = mesh or self.mesh
+        cfg = cfg or m["cfg"]
+        eng, ang = plystack_arrays(cfg)
+        ps = PlyStack(len(ang), eng.ctypes.data_as(f64p), ang.ctypes.data_as(f64p))
+        ms = Mesh(m["n_nodes"], m["n_elems"], _ptr(m["xyz"]), _ptr(m["conn"]),
+                  _ptr(m["elem_layer"]))
+        ld = Loads(m["clamped"].numel(), _ptr(m["clamped"]), m["face_elem"].numel(),
+                   _ptr(m["face_elem"]), _ptr(m["face_id"]), m["traction"])
+        f = self.torch.empty(3 * m["n_nodes"], dtype=self.torch.float64, device=self.device)
+        self._check(lib.gx_assemble(self.h, C.byref(ms), C.byref(ps), C.byref(ld), _ptr(f)))
+        self.f = f
+        self.n_dofs = 3 * m["n_nodes"]
+        return f
+
+    def matrix(self):
+        """K as (row_ptr, col, val) torch tensors on the device."""
+        torch = self.torch
+        nr, nb = C.c_int64(), C.c_int64()
+        self._check(lib.gx_matrix_info(self.h, C.byref(nr), C.byref(nb)))
+        rp = torch.empty(nr.value + 1, dtype=torch.int32, device=self.device)
+        col = torch.empty(nb.value, dtype=torch.int32, device=self.device)
+        val = torch.empty(9 * nb.value, dtype=torch.float64, device=self.device)
+        self._check(lib.gx_matrix_copy(self.h, _ptr(rp), _ptr(col), _ptr(val)))
+        return rp, col, val
+
+    def spmv(self, x, y=None):
+        y = self.torch.empty_like(x) if y is None else y
+        self._check(lib.gx_spmv(self.h, _ptr(x), _ptr(y)))
+        return y
+
+    # ---- preconditioner and solve ----------------------------------------------------
+    def geneo_setup(self, part, n_sub, overlap=1, tau=0.1, nev=0, nev_max=32,
+                    precision=GX_FP64, coarse=True, nev_per_sub=None, eig_tol=0.0,
+                    eig_maxit=0):
+        nps = None
+        keep = None
+        if nev_per_sub is not None:
+            keep = np.ascontiguousarray(nev_per_sub, dtype=np.int32)
+            nps = keep.ctypes.data_as(i32p)
+        o = GeneoOpts(n_sub, _ptr(part), overlap, tau, nev, nev_max, precision,
+                      1 if coarse else 0, nps, eig_tol, eig_maxit)
+        nev_out = np.zeros(n_sub, dtype=np.int32)
+        n0 = C.c_int64()
+        self._check(lib.gx_geneo_setup(self.h, C.byref(o), nev_out.ctypes.data_as(i32p),
+                                       C.byref(n0)))
+        self.nev = nev_out
+        self.n0 = n0.value
+        self.n_sub = n_sub
+        return nev_out, n0.value
+
+    def subdomain_info(self):
+        n = self.n_sub
+        a, b, c = (np.zeros(n, dtype=np.int64) for _ in range(3))
+        self._check(lib.gx_subdomain_info(self.h, a.ctypes.data_as(i64p),
+                                          b.ctypes.data_as(i64p), c.ctypes.data_as(i64p)))
+        return a, b, c
+
+    def eigenvalues(self, j):
+        lam = np.zeros(max(1, int(self.nev[j])), dtype=np.float64)
+        self._check(lib.gx_geneo_eigenvalues(self.h, j, lam.ctypes.data_as(f64p)))
+        return lam[: int(self.nev[j])]
+
+    def precond(self, r, z=None):
+        z = self.torch.empty_like(r) if z is None else z
+        self._check(lib.gx_precond_apply(self.h, _ptr(r), _ptr(z)))
+        return z
+
+    def pcg(self, b, x=None, rtol=1e-8, maxit=1000, history=False, allow_noconv=False):
+        x = self.torch.zeros_like(b) if x is None else x
+        it = C.c_int32()
+        rr = C.c_double()
+        hist = np.zeros(maxit + 1) if history else None
+        code = lib.gx_pcg_solve(self.h, _ptr(b), _ptr(x), rtol, maxit, C.byref(it),
+                                C.byref(rr), hist.ctypes.data_as(f64p) if history else None)
+        if not (code == GX_OK or (allow_noconv and code == GX_ENOCONV)):
+            self._check(code)
+        out = dict(x=x, iters=it.value, relres=rr.value, status=code)
+        if history:
+            out["hist"] = hist[: it.value + 1]
+        return out
+
+    def phase_times(self):
+        t = np.zeros(8)
+        lib.gx_phase_times(self.h, t.ctypes.data_as(f64p))
+        return dict(zip(["assemble", "decomposition", "local_factors", "eigensolves",
+                         "coarse", "pcg", "pcg_precond", "pcg_spmv"], t.tolist()))

@@ -1,0 +1,684 @@
+// Assembly of K and f (Eq. eq-1) for 20-node serendipity hexahedra with full 3x3x3 Gauss
+// integration (section 2.1), and the 3x3-block CSR product y = K x.
+//
+// Pipeline (all on the device):
+//   1. node -> element incidence (counting sort, each list sorted by element number);
+//   2. block-CSR pattern: per node, the sorted union of the nodes of its elements;
+//   3. material stiffness of each layer from engineering constants (C = S^-1, Table 1);
+//   4. element matrices K_e = sum_q B^T C_q B det J w, one work-group per element, with the
+//      reference shape-function gradients staged in LDS and C rotated at every Gauss
+//      point into the geometric frame and the ply angle by the Bond strain transformation;
+//   5. deterministic gather: every block row sums its elements' blocks in element order
+//      (no floating-point atomics), then clamped DOFs become identity rows / columns;
+//   6. consistent face loads from a 3x3 Gauss rule on each loaded face.
+#include <cmath>
+
+#include "gx_internal.h"
+
+namespace gx {
+
+constexpr int MAX_ADJ = 32;        // elements sharing one node
+constexpr int MAX_ROW = 128;       // blocks in one block row of K
+
+// ---------------------------------------------------------------------------------------
+// Serendipity shape functions on the reference cube [-1, 1]^3.
+__device__ __constant__ int8_t c_ref[20][3] = {
+    {-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {1, 1, -1},
+    {-1, -1, 1},  {1, -1, 1},  {-1, 1, 1},  {1, 1, 1},
+    {0, -1, -1},  {0, 1, -1},  {0, -1, 1},  {0, 1, 1},
+    {-1, 0, -1},  {1, 0, -1},  {-1, 0, 1},  {1, 0, 1},
+    {-1, -1, 0},  {1, -1, 0},  {-1, 1, 0},  {1, 1, 0}};
+
+// value and reference gradient of shape function a at (p0, p1, p2)
+__device__ inline void shape_one(int a, double p0, double p1, double p2, double* N,
+                                 double* d) {
+  const double r0 = c_ref[a][0], r1 = c_ref[a][1], r2 = c_ref[a][2];
+  const double f0 = 1 + p0 * r0, f1 = 1 + p1 * r1, f2 = 1 + p2 * r2;
+  if (r0 != 0 && r1 != 0 && r2 != 0) {
+    const double g = p0 * r0 + p1 * r1 + p2 * r2 - 2;
+    *N = 0.125 * f0 * f1 * f2 * g;
+    d[0] = 0.125 * r0 * f1 * f2 * (g + f0);
+    d[1] = 0.125 * r1 * f0 * f2 * (g + f1);
+    d[2] = 0.125 * r2 * f0 * f1 * (g + f2);
+  } else if (r0 == 0) {                          // edge along xi: bubble (1 - xi^2)
+    const double b = 1 - p0 * p0;
+    *N = 0.25 * b * f1 * f2;
+    d[0] = -0.5 * p0 * f1 * f2;
+    d[1] = 0.25 * b * r1 * f2;
+    d[2] = 0.25 * b * f1 * r2;
+  } else if (r1 == 0) {                          // edge along eta
+    const double b = 1 - p1 * p1;
+    *N = 0.25 * b * f0 * f2;
+    d[0] = 0.25 * b * r0 * f2;
+    d[1] = -0.5 * p1 * f0 * f2;
+    d[2] = 0.25 * b * f0 * r2;
+  } else {                                       // edge along zeta
+    const double b = 1 - p2 * p2;
+    *N = 0.25 * b * f0 * f1;
+    d[0] = 0.25 * b * r0 * f1;
+    d[1] = 0.25 * b * f0 * r1;
+    d[2] = -0.5 * p2 * f0 * f1;
+  }
+}
+
+__device__ inline void gauss3(int i, double* x, double* w) {
+  const double s = 0.7745966692414833770358531;  // sqrt(3/5)
+  *x = (i == 0) ? -s : ((i == 1) ? 0.0 : s);
+  *w = (i == 1) ? 8.0 / 9.0 : 5.0 / 9.0;
+}
+
+// ---------------------------------------------------------------------------------------
+// 1. node -> element incidence
+__global__ void k_ne_count(const int32_t* conn, int64_t n_elems, int32_t* cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_elems * 20) return;
+  atomicAdd(&cnt[conn[i]], 1);
+}
+__global__ void k_ne_fill(const int32_t* conn, int64_t n_elems, const int32_t* ptr,
+                          int32_t* cursor, int32_t* idx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_elems * 20) return;
+  const int n = conn[i];
+  const int pos = atomicAdd(&cursor[n], 1);
+  idx[ptr[n] + pos] = (int32_t)(i / 20);
+}
+__global__ void k_ne_sort(int64_t n_nodes, const int32_t* ptr, int32_t* idx, int* err) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= n_nodes) return;
+  const int b = ptr[n], e = ptr[n + 1];
+  if (e - b > MAX_ADJ) { atomicOr(err, 1); return; }
+  if (e == b) atomicOr(err, 2);
+  for (int i = b + 1; i < e; ++i) {              // insertion sort (short lists)
+    const int v = idx[i];
+    int j = i - 1;
+    while (j >= b && idx[j] > v) { idx[j + 1] = idx[j]; --j; }
+    idx[j + 1] = v;
+  }
+}
+
+void build_node_elem(gx_ctx* c) {
+  const int64_t N = c->n_nodes, E = c->n_elems;
+  c->ne_ptr.alloc(N + 1);
+  DevBuf<int32_t> cur(N);
+  DevBuf<int> err(1);
+  DevBuf<int64_t> tmp(scan_tmp_size(N + 1));
+  zero(c->ne_ptr, c->stream);
+  zero(cur, c->stream);
+  zero(err, c->stream);
+  hipLaunchKernelGGL(k_ne_count, dim3(nblocks(E * 20, 256)), dim3(256), 0, c->stream,
+                     c->conn.p, E, c->ne_ptr.p);
+  const int64_t tot = exclusive_scan32(c->ne_ptr.p, N + 1, tmp.p, c->stream);
+  GX_REQUIRE(tot == E * 20, "incidence count mismatch");
+  c->ne_idx.alloc(E * 20);
+  hipLaunchKernelGGL(k_ne_fill, dim3(nblocks(E * 20, 256)), dim3(256), 0, c->stream,
+                     c->conn.p, E, c->ne_ptr.p, cur.p, c->ne_idx.p);
+  hipLaunchKernelGGL(k_ne_sort, dim3(nblocks(N, 256)), dim3(256), 0, c->stream, N,
+                     c->ne_ptr.p, c->ne_idx.p, err.p);
+  GX_HIP(hipGetLastError());
+  int h = 0;
+  to_host(&h, err.p, 1, c->stream);
+  GX_REQUIRE(!(h & 1), "a node is shared by more than 32 elements");
+  GX_REQUIRE(!(h & 2), "a node belongs to no element");
+}
+
+// ---------------------------------------------------------------------------------------
+// 2. block-CSR pattern, one 64-lane work-group per node
+__device__ inline void bitonic_sort(int32_t* s, int n) {
+  for (int k = 2; k <= n; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool up = (i & k) == 0;
+          const int32_t a = s[i], b = s[l];
+          if ((a > b) == up) { s[i] = b; s[l] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// fill == nullptr: count unique neighbours into row_len; else write them at fill + ptr[n]
+__global__ void __launch_bounds__(64) k_pattern(const int32_t* conn, const int32_t* ne_ptr,
+                                                const int32_t* ne_idx, int32_t* row_len,
+                                                const int32_t* ptr, int32_t* fill,
+                                                int* err) {
+  __shared__ int32_t s[MAX_ADJ * 32];
+  __shared__ int32_t wsum[64];
+  const int64_t n = blockIdx.x;
+  const int b = ne_ptr[n], e = ne_ptr[n + 1];
+  const int cnt = (e - b) * 20;
+  int sz = 1;
+  while (sz < cnt) sz <<= 1;
+  for (int i = threadIdx.x; i < sz; i += 64)
+    s[i] = i < cnt ? conn[(int64_t)ne_idx[b + i / 20] * 20 + i % 20] : 0x7fffffff;
+  __syncthreads();
+  bitonic_sort(s, sz);
+  // each lane owns a contiguous chunk; count first occurrences
+  const int chunk = (sz + 63) / 64;
+  const int lo = threadIdx.x * chunk, hi = min(sz, lo + chunk);
+  int mine = 0;
+  for (int i = lo; i < hi; ++i)
+    mine += (s[i] != 0x7fffffff) && (i == 0 || s[i] != s[i - 1]);
+  wsum[threadIdx.x] = mine;
+  __syncthreads();
+  if (fill == nullptr) {
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int i = 0; i < 64; ++i) t += wsum[i];
+      if (t > MAX_ROW) atomicOr(err, 1);
+      row_len[n] = t;
+    }
+    return;
+  }
+  int before = 0;
+  for (int i = 0; i < (int)threadIdx.x; ++i) before += wsum[i];
+  int32_t* out = fill + ptr[n] + before;
+  for (int i = lo; i < hi; ++i)
+    if ((s[i] != 0x7fffffff) && (i == 0 || s[i] != s[i - 1])) *out++ = s[i];
+}
+
+// ---------------------------------------------------------------------------------------
+// 3. layer stiffness C = S^-1 from engineering constants (Voigt 11,22,33,23,13,12 with
+//    engineering shear strains).  The orthotropic compliance is block diagonal: the normal
+//    3x3 block is inverted by cofactors, the shear block is diag(1/G23, 1/G13, 1/G12).
+__global__ void k_layer_stiffness(int n_layers, const double* eng, double* C, int* err) {
+  const int L = blockIdx.x * blockDim.x + threadIdx.x;
+  if (L >= n_layers) return;
+  const double* p = eng + 9 * L;
+  double E1 = p[0], E2 = p[1], E3 = p[2], G12 = p[3], G13 = p[4], G23 = p[5];
+  double n12 = p[6], n13 = p[7], n23 = p[8];
+  if (!(G12 > 0)) {                              // isotropic layer given as (E, nu)
+    E2 = E3 = E1;
+    n13 = n23 = n12;
+    G12 = G13 = G23 = E1 / (2.0 * (1.0 + n12));
+  }
+  const double s11 = 1 / E1, s22 = 1 / E2, s33 = 1 / E3;
+  const double s12 = -n12 / E1, s13 = -n13 / E1, s23 = -n23 / E2;
+  const double c11 = s22 * s33 - s23 * s23, c22 = s11 * s33 - s13 * s13,
+               c33 = s11 * s22 - s12 * s12;
+  const double c12 = s13 * s23 - s12 * s33, c13 = s12 * s23 - s13 * s22,
+               c23 = s12 * s13 - s11 * s23;
+  const double det = s11 * c11 + s12 * c12 + s13 * c13;
+  if (!(det > 0) || !(G12 > 0) || !(G13 > 0) || !(G23 > 0) || !(E1 > 0) || !(E2 > 0) ||
+      !(E3 > 0)) {
+    atomicOr(err, 1);
+    return;
+  }
+  double* o = C + 36 * L;
+  for (int i = 0; i < 36; ++i) o[i] = 0.0;
+  o[0] = c11 / det; o[7] = c22 / det; o[14] = c33 / det;
+  o[1] = o[6] = c12 / det;
+  o[2] = o[12] = c13 / det;
+  o[8] = o[13] = c23 / det;
+  o[21] = G23; o[28] = G13; o[35] = G12;
+}
+
+// ---------------------------------------------------------------------------------------
+// 4. element stiffness, one 256-thread work-group per element (grid-stride)
+struct ElemSmem {
+  double dNr[27][20][3];     // reference gradients at the Gauss points
+  double X[20][3];
+  double G[27][20][3];       // physical gradients
+  double Cg[27][36];         // rotated stiffness
+  double dv[27];             // det J * weight
+  double CB[20][6][3];       // C_q B_b for the current Gauss point
+};
+
+// strain-displacement entry B_a[I][i] (Voigt row I, displacement component i) from g = grad N_a
+__device__ inline double bent(int I, int i, const double* g) {
+  // rows: 0 e11, 1 e22, 2 e33, 3 g23, 4 g13, 5 g12
+  switch (I) {
+    case 0: return i == 0 ? g[0] : 0.0;
+    case 1: return i == 1 ? g[1] : 0.0;
+    case 2: return i == 2 ? g[2] : 0.0;
+    case 3: return i == 1 ? g[2] : (i == 2 ? g[1] : 0.0);
+    case 4: return i == 0 ? g[2] : (i == 2 ? g[0] : 0.0);
+    default: return i == 0 ? g[1] : (i == 1 ? g[0] : 0.0);
+  }
+}
+
+__device__ inline void gauss_point_setup(int q, const ElemSmem& sm, const double* Cl,
+                                         double angle, double* Gout, double* Cgout,
+                                         double* dvout, int* bad) {
+  // Jacobian J[i][j] = dx_i / dxi_j
+  double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int a = 0; a < 20; ++a)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) J[i][j] += sm.X[a][i] * sm.dNr[q][a][j];
+  const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                     J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                     J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  if (!(det > 0)) *bad = 1;
+  const double id = 1.0 / det;
+  double Ji[3][3];                               // Ji[j][i] = dxi_j / dx_i
+  Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
+  Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+  Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+  Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+  Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+  Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+  Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+  Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+  Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+  for (int a = 0; a < 20; ++a)
+    for (int i = 0; i < 3; ++i)
+      Gout[3 * a + i] = sm.dNr[q][a][0] * Ji[0][i] + sm.dNr[q][a][1] * Ji[1][i] +
+                        sm.dNr[q][a][2] * Ji[2][i];
+  // geometric frame: e1 along dx/dxi, e2 from dx/deta (Gram-Schmidt), e3 = e1 x e2
+  double e1[3] = {J[0][0], J[1][0], J[2][0]}, t2[3] = {J[0][1], J[1][1], J[2][1]};
+  const double n1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+  for (int i = 0; i < 3; ++i) e1[i] /= n1;
+  const double pr = t2[0] * e1[0] + t2[1] * e1[1] + t2[2] * e1[2];
+  double e2[3] = {t2[0] - pr * e1[0], t2[1] - pr * e1[1], t2[2] - pr * e1[2]};
+  const double n2 = sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+  for (int i = 0; i < 3; ++i) e2[i] /= n2;
+  const double e3[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                        e1[0] * e2[1] - e1[1] * e2[0]};
+  // material axes (rows of Q, global components): fibre rotated by the ply angle about e3
+  const double ca = cos(angle), sa = sin(angle);
+  double Q[3][3];
+  for (int i = 0; i < 3; ++i) {
+    Q[0][i] = ca * e1[i] + sa * e2[i];
+    Q[1][i] = -sa * e1[i] + ca * e2[i];
+    Q[2][i] = e3[i];
+  }
+  // Bond matrix: local engineering strain = T * global engineering strain
+  const int vi[6] = {0, 1, 2, 1, 0, 0}, vj[6] = {0, 1, 2, 2, 2, 1};
+  double T[6][6];
+  for (int I = 0; I < 6; ++I) {
+    const int i = vi[I], j = vj[I];
+    for (int K = 0; K < 6; ++K) {
+      const int k = vi[K], l = vj[K];
+      if (I < 3)
+        T[I][K] = (K < 3) ? Q[i][k] * Q[i][k] : Q[i][k] * Q[i][l];
+      else
+        T[I][K] = (K < 3) ? 2.0 * Q[i][k] * Q[j][k] : Q[i][k] * Q[j][l] + Q[i][l] * Q[j][k];
+    }
+  }
+  // C_g = T^T C T
+  double CT[6][6];
+  for (int I = 0; I < 6; ++I)
+    for (int K = 0; K < 6; ++K) {
+      double s = 0;
+      for (int L = 0; L < 6; ++L) s += Cl[6 * I + L] * T[L][K];
+      CT[I][K] = s;
+    }
+  for (int I = 0; I < 6; ++I)
+    for (int K = I; K < 6; ++K) {
+      double s = 0;
+      for (int L = 0; L < 6; ++L) s += T[L][I] * CT[L][K];
+      Cgout[6 * I + K] = s;
+      Cgout[6 * K + I] = s;
+    }
+  double xq, wq, yq, wy, zq, wz;
+  gauss3(q % 3, &xq, &wq);
+  gauss3((q / 3) % 3, &yq, &wy);
+  gauss3(q / 9, &zq, &wz);
+  *dvout = det * wq * wy * wz;
+}
+
+__global__ void __launch_bounds__(256) k_element(int64_t n_elems, const double* xyz,
+                                                 const int32_t* conn, const int32_t* elayer,
+                                                 const double* Clayer, const double* angle,
+                                                 double* Ke, int* err) {
+  extern __shared__ double smem_raw[];
+  ElemSmem& sm = *reinterpret_cast<ElemSmem*>(smem_raw);
+  const int t = threadIdx.x;
+  // reference gradients at the 27 Gauss points (q = i + 3 j + 9 k)
+  for (int idx = t; idx < 27 * 20; idx += blockDim.x) {
+    const int q = idx / 20, a = idx % 20;
+    double x0, x1, x2, w;
+    gauss3(q % 3, &x0, &w);
+    gauss3((q / 3) % 3, &x1, &w);
+    gauss3(q / 9, &x2, &w);
+    double N, d[3];
+    shape_one(a, x0, x1, x2, &N, d);
+    sm.dNr[q][a][0] = d[0];
+    sm.dNr[q][a][1] = d[1];
+    sm.dNr[q][a][2] = d[2];
+  }
+  // node pair (pa <= pb) owned by this thread
+  int pa = -1, pb = -1;
+  if (t < 210) {
+    int r = t, a = 0;
+    while (r >= 20 - a) { r -= 20 - a; ++a; }
+    pa = a;
+    pb = a + r;
+  }
+  __syncthreads();
+  for (int64_t e = blockIdx.x; e < n_elems; e += gridDim.x) {
+    if (t < 60) sm.X[t / 3][t % 3] = xyz[3 * (int64_t)conn[20 * e + t / 3] + t % 3];
+    __syncthreads();
+    const int L = elayer[e];
+    if (t < 27) {
+      int bad = 0;
+      gauss_point_setup(t, sm, Clayer + 36 * L, angle[L] * (M_PI / 180.0), &sm.G[t][0][0],
+                        &sm.Cg[t][0], &sm.dv[t], &bad);
+      if (bad) atomicOr(err, 1);
+    }
+    __syncthreads();
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int q = 0; q < 27; ++q) {
+      if (t < 60) {                                // C_q B_b, node b, component k
+        const int b = t / 3, k = t % 3;
+        const double* g = sm.G[q][b];
+        for (int I = 0; I < 6; ++I) {
+          double s = 0;
+          for (int J = 0; J < 6; ++J) s += sm.Cg[q][6 * I + J] * bent(J, k, g);
+          sm.CB[b][I][k] = s;
+        }
+      }
+      __syncthreads();
+      if (pa >= 0) {
+        const double* g = sm.G[q][pa];
+        const double dv = sm.dv[q];
+        for (int i = 0; i < 3; ++i)
+          for (int k = 0; k < 3; ++k) {
+            double s = 0;
+            for (int I = 0; I < 6; ++I) s += bent(I, i, g) * sm.CB[pb][I][k];
+            acc[3 * i + k] += dv * s;
+          }
+      }
+      __syncthreads();
+    }
+    if (pa >= 0) {
+      double* out = Ke + (((int64_t)e * 20 + pa) * 20 + pb) * 9;
+      for (int i = 0; i < 9; ++i) out[i] = acc[i];
+      if (pa != pb) {
+        double* o2 = Ke + (((int64_t)e * 20 + pb) * 20 + pa) * 9;
+        for (int i = 0; i < 3; ++i)
+          for (int k = 0; k < 3; ++k) o2[3 * k + i] = acc[3 * i + k];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// 5. deterministic gather of element blocks into block rows; clamped DOFs -> identity
+__global__ void __launch_bounds__(64) k_gather(const int32_t* conn, const int32_t* ne_ptr,
+                                               const int32_t* ne_idx, const int32_t* row_ptr,
+                                               const int32_t* col, const double* Ke,
+                                               const uint8_t* fixed, double* val) {
+  __shared__ double rv[MAX_ROW * 9];
+  __shared__ int32_t rc[MAX_ROW];
+  const int64_t n = blockIdx.x;
+  const int rb = row_ptr[n], len = row_ptr[n + 1] - rb;
+  for (int i = threadIdx.x; i < len; i += 64) rc[i] = col[rb + i];
+  for (int i = threadIdx.x; i < len * 9; i += 64) rv[i] = 0.0;
+  __syncthreads();
+  for (int k = ne_ptr[n]; k < ne_ptr[n + 1]; ++k) {
+    const int64_t e = ne_idx[k];
+    int a = 0;
+    while (conn[20 * e + a] != n) ++a;
+    for (int v = threadIdx.x; v < 180; v += 64) {
+      const int b = v / 9, comp = v - 9 * (v / 9);
+      const int m = conn[20 * e + b];
+      int lo = 0, hi = len - 1;                  // binary search of m in the row
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (rc[mid] < m) lo = mid + 1; else hi = mid;
+      }
+      rv[9 * lo + comp] += Ke[((e * 20 + a) * 20 + b) * 9 + comp];
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < len * 9; i += 64) {
+    const int blk = i / 9, comp = i - 9 * (i / 9);
+    const int ri = comp / 3, ci = comp - 3 * (comp / 3);
+    const int64_t rd = 3 * n + ri, cd = 3 * (int64_t)rc[blk] + ci;
+    double v = rv[i];
+    if (fixed[rd] || fixed[cd]) v = (rd == cd) ? 1.0 : 0.0;
+    val[(int64_t)rb * 9 + i] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// 6. consistent face loads; t = t0 + k ((x - c) . d) n_out, 3x3 Gauss rule on the face;
+//    one thread per (face, element node), summed into f with FP64 atomics
+__global__ void k_face_loads(int64_t n_faces, const int32_t* fe, const int32_t* fid,
+                             const double* xyz, const int32_t* conn, gx_traction tr,
+                             const uint8_t* fixed, double* f) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_faces * 20) return;
+  const int64_t e = fe[idx / 20];
+  const int na = (int)(idx % 20);
+  const int face = fid[idx / 20];
+  const int ax = face / 2;
+  const double sgn = (face & 1) ? 1.0 : -1.0;
+  double fl0 = 0, fl1 = 0, fl2 = 0;
+  for (int qb = 0; qb < 3; ++qb)
+    for (int qc = 0; qc < 3; ++qc) {
+      double pb, wb, pc, wc;
+      gauss3(qb, &pb, &wb);
+      gauss3(qc, &pc, &wc);
+      // reference point on the face: fixed axis ax, in-face axes (ax+1)%3, (ax+2)%3
+      const double p0 = ax == 0 ? sgn : (ax == 1 ? pc : pb);
+      const double p1 = ax == 1 ? sgn : (ax == 2 ? pc : pb);
+      const double p2 = ax == 2 ? sgn : (ax == 0 ? pc : pb);
+      double x0 = 0, x1 = 0, x2 = 0, tb0 = 0, tb1 = 0, tb2 = 0, tc0 = 0, tc1 = 0, tc2 = 0,
+             Na = 0;
+      for (int a = 0; a < 20; ++a) {
+        double N, d[3];
+        shape_one(a, p0, p1, p2, &N, d);
+        const double db = ax == 0 ? d[1] : (ax == 1 ? d[2] : d[0]);
+        const double dc = ax == 0 ? d[2] : (ax == 1 ? d[0] : d[1]);
+        const int64_t nd = conn[20 * e + a];
+        const double X0 = xyz[3 * nd], X1 = xyz[3 * nd + 1], X2 = xyz[3 * nd + 2];
+        x0 += N * X0; x1 += N * X1; x2 += N * X2;
+        tb0 += db * X0; tb1 += db * X1; tb2 += db * X2;
+        tc0 += dc * X0; tc1 += dc * X1; tc2 += dc * X2;
+        if (a == na) Na = N;
+      }
+      const double nv0 = tb1 * tc2 - tb2 * tc1, nv1 = tb2 * tc0 - tb0 * tc2,
+                   nv2 = tb0 * tc1 - tb1 * tc0;
+      const double dA = sqrt(nv0 * nv0 + nv1 * nv1 + nv2 * nv2);
+      const double lin = tr.k * ((x0 - tr.c[0]) * tr.d[0] + (x1 - tr.c[1]) * tr.d[1] +
+                                 (x2 - tr.c[2]) * tr.d[2]);
+      const double w = wb * wc * dA * Na;
+      fl0 += (tr.t0[0] + lin * sgn * nv0 / dA) * w;
+      fl1 += (tr.t0[1] + lin * sgn * nv1 / dA) * w;
+      fl2 += (tr.t0[2] + lin * sgn * nv2 / dA) * w;
+    }
+  const int64_t d = 3 * (int64_t)conn[20 * e + na];
+  if (!fixed[d] && fl0 != 0.0) atomicAdd(&f[d], fl0);
+  if (!fixed[d + 1] && fl1 != 0.0) atomicAdd(&f[d + 1], fl1);
+  if (!fixed[d + 2] && fl2 != 0.0) atomicAdd(&f[d + 2], fl2);
+}
+
+__global__ void k_fixed(int64_t n, const int32_t* nodes, uint8_t* fixed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t d = 3 * (int64_t)nodes[i];
+  fixed[d] = fixed[d + 1] = fixed[d + 2] = 1;
+}
+
+// ---------------------------------------------------------------------------------------
+// y = K x, one 64-lane wavefront per block row; lane v of the row reads value v (values of
+// a row are contiguous, so every load instruction is a coalesced 512-byte segment)
+__global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, const int32_t* __restrict__ rp,
+                                              const int32_t* __restrict__ col,
+                                              const double* __restrict__ val,
+                                              const double* __restrict__ x,
+                                              double* __restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n_rows) return;
+  const int b0 = rp[row], b1 = rp[row + 1];
+  const int64_t v0 = (int64_t)b0 * 9, nv = (int64_t)(b1 - b0) * 9;
+  double a0 = 0, a1 = 0, a2 = 0;
+  for (int v = lane; v < nv; v += 64) {
+    const int blk = v / 9, c9 = v - 9 * blk;
+    const int r = c9 / 3, cc = c9 - 3 * r;
+    const double p = val[v0 + v] * x[3 * (int64_t)col[b0 + blk] + cc];
+    a0 += r == 0 ? p : 0.0;
+    a1 += r == 1 ? p : 0.0;
+    a2 += r == 2 ? p : 0.0;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    a0 += __shfl_xor(a0, off);
+    a1 += __shfl_xor(a1, off);
+    a2 += __shfl_xor(a2, off);
+  }
+  if (lane == 0) {
+    y[3 * row + 0] = a0;
+    y[3 * row + 1] = a1;
+    y[3 * row + 2] = a2;
+  }
+}
+
+void spmv(gx_ctx* c, const double* x, double* y) {
+  hipLaunchKernelGGL(k_spmv, dim3(nblocks(c->n_nodes, 4)), dim3(256), 0, c->stream,
+                     c->n_nodes, c->row_ptr.p, c->col.p, c->val.p, x, y);
+}
+
+}  // namespace gx
+
+using namespace gx;
+
+extern "C" {
+
+gx_status gx_assemble(gx_ctx* c, const gx_mesh* m, const gx_plystack* ps, const gx_loads* ld,
+                      double* f_out) {
+  GX_API_BEGIN(c)
+  GX_REQUIRE(m && ps && ld && f_out, "null argument");
+  GX_REQUIRE(m->n_nodes > 0 && m->n_elems > 0 && m->xyz && m->conn && m->elem_layer,
+             "bad mesh");
+  GX_REQUIRE(m->n_nodes < ((int64_t)1 << 31) / 3, "too many nodes");
+  GX_REQUIRE(ps->n_layers >= 1 && ps->eng && ps->angle_deg, "bad ply stack");
+  Timer tm(c->stream);
+  hipStream_t s = c->stream;
+  c->assembled = false;
+  c->setup_done = false;
+  c->sw = Schwarz();
+  c->n_nodes = m->n_nodes;
+  c->n_elems = m->n_elems;
+  const int64_t N = c->n_nodes, E = c->n_elems;
+  c->xyz.alloc(3 * N);
+  c->conn.alloc(20 * E);
+  c->elayer.alloc(E);
+  GX_HIP(hipMemcpyAsync(c->xyz.p, m->xyz, 3 * N * sizeof(double), hipMemcpyDefault, s));
+  GX_HIP(hipMemcpyAsync(c->conn.p, m->conn, 20 * E * sizeof(int32_t), hipMemcpyDefault, s));
+  GX_HIP(hipMemcpyAsync(c->elayer.p, m->elem_layer, E * sizeof(int32_t), hipMemcpyDefault, s));
+  {  // validate indices on the host side of a copy (cheap relative to assembly)
+    std::vector<int32_t> hc(20 * E), hl(E);
+    to_host(hc.data(), c->conn.p, 20 * E, s);
+    to_host(hl.data(), c->elayer.p, E, s);
+    for (int32_t v : hc) GX_REQUIRE(v >= 0 && v < N, "connectivity index out of range");
+    for (int32_t v : hl) GX_REQUIRE(v >= 0 && v < ps->n_layers, "layer index out of range");
+  }
+  // clamped DOFs
+  c->fixed.alloc(3 * N);
+  zero(c->fixed, s);
+  if (ld->n_clamped > 0) {
+    GX_REQUIRE(ld->clamped, "null clamped list");
+    std::vector<int32_t> h(ld->n_clamped);
+    GX_HIP(hipMemcpyAsync(h.data(), ld->clamped, h.size() * sizeof(int32_t), hipMemcpyDefault,
+                          s));
+    GX_HIP(hipStreamSynchronize(s));
+    for (int32_t v : h) GX_REQUIRE(v >= 0 && v < N, "clamped node out of range");
+    DevBuf<int32_t> dn(ld->n_clamped);
+    to_dev(dn.p, h.data(), h.size(), s);
+    hipLaunchKernelGGL(k_fixed, dim3(nblocks(ld->n_clamped, 256)), dim3(256), 0, s,
+                       (int64_t)ld->n_clamped, dn.p, c->fixed.p);
+    GX_HIP(hipStreamSynchronize(s));
+  }
+  build_node_elem(c);
+  // pattern
+  DevBuf<int> err(1);
+  zero(err, s);
+  c->row_ptr.alloc(N + 1);
+  zero(c->row_ptr, s);
+  hipLaunchKernelGGL(k_pattern, dim3((unsigned)N), dim3(64), 0, s, c->conn.p, c->ne_ptr.p,
+                     c->ne_idx.p, c->row_ptr.p, (const int32_t*)nullptr, (int32_t*)nullptr,
+                     err.p);
+  GX_HIP(hipGetLastError());
+  DevBuf<int64_t> tmp(scan_tmp_size(N + 1));
+  const int64_t nnzb = exclusive_scan32(c->row_ptr.p, N + 1, tmp.p, s);
+  GX_REQUIRE(nnzb * 9 < ((int64_t)1 << 40), "matrix too large");
+  c->nnzb = nnzb;
+  c->col.alloc(nnzb);
+  hipLaunchKernelGGL(k_pattern, dim3((unsigned)N), dim3(64), 0, s, c->conn.p, c->ne_ptr.p,
+                     c->ne_idx.p, (int32_t*)nullptr, c->row_ptr.p, c->col.p, err.p);
+  GX_HIP(hipGetLastError());
+  int herr = 0;
+  to_host(&herr, err.p, 1, s);
+  GX_REQUIRE(!herr, "a block row has more than 128 blocks");
+  // materials
+  DevBuf<double> eng(9 * ps->n_layers), ang(ps->n_layers), Cl(36 * ps->n_layers);
+  to_dev(eng.p, ps->eng, 9 * ps->n_layers, s);
+  to_dev(ang.p, ps->angle_deg, ps->n_layers, s);
+  hipLaunchKernelGGL(k_layer_stiffness, dim3(nblocks(ps->n_layers, 64)), dim3(64), 0, s,
+                     ps->n_layers, eng.p, Cl.p, err.p);
+  to_host(&herr, err.p, 1, s);
+  GX_REQUIRE(!herr, "singular material compliance");
+  // element matrices
+  c->Ke.alloc((size_t)E * 3600);
+  const unsigned eg = (unsigned)std::min<int64_t>(E, 256 * 32);
+  hipLaunchKernelGGL(k_element, dim3(eg), dim3(256), sizeof(ElemSmem), s, E, c->xyz.p,
+                     c->conn.p, c->elayer.p, Cl.p, ang.p, c->Ke.p, err.p);
+  GX_HIP(hipGetLastError());
+  to_host(&herr, err.p, 1, s);
+  GX_REQUIRE(!herr, "non-positive Jacobian determinant in an element");
+  // global matrix
+  c->val.alloc((size_t)nnzb * 9);
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)N), dim3(64), 0, s, c->conn.p, c->ne_ptr.p,
+                     c->ne_idx.p, c->row_ptr.p, c->col.p, c->Ke.p, c->fixed.p, c->val.p);
+  GX_HIP(hipGetLastError());
+  // loads
+  GX_HIP(hipMemsetAsync(f_out, 0, 3 * N * sizeof(double), s));
+  if (ld->n_faces > 0) {
+    GX_REQUIRE(ld->face_elem && ld->face_id, "null face list");
+    std::vector<int32_t> he(ld->n_faces), hf(ld->n_faces);
+    GX_HIP(hipMemcpyAsync(he.data(), ld->face_elem, he.size() * 4, hipMemcpyDefault, s));
+    GX_HIP(hipMemcpyAsync(hf.data(), ld->face_id, hf.size() * 4, hipMemcpyDefault, s));
+    GX_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < ld->n_faces; ++i)
+      GX_REQUIRE(he[i] >= 0 && he[i] < E && hf[i] >= 0 && hf[i] < 6, "bad load face");
+    DevBuf<int32_t> de(ld->n_faces), df(ld->n_faces);
+    to_dev(de.p, he.data(), he.size(), s);
+    to_dev(df.p, hf.data(), hf.size(), s);
+    hipLaunchKernelGGL(k_face_loads, dim3(nblocks(ld->n_faces * 20, 64)), dim3(64), 0, s,
+                       (int64_t)ld->n_faces, de.p, df.p, c->xyz.p, c->conn.p, ld->traction,
+                       c->fixed.p, f_out);
+    GX_HIP(hipGetLastError());
+    GX_HIP(hipStreamSynchronize(s));
+  }
+  GX_HIP(hipStreamSynchronize(s));
+  c->assembled = true;
+  c->phase_ms[0] = tm.ms();
+  GX_API_END(c)
+}
+
+gx_status gx_matrix_info(gx_ctx* c, int64_t* nr, int64_t* nb) {
+  GX_API_BEGIN(c)
+  if (!c->assembled) throw Error(GX_ESTATE, "matrix not assembled");
+  if (nr) *nr = c->n_nodes;
+  if (nb) *nb = c->nnzb;
+  GX_API_END(c)
+}
+
+gx_status gx_matrix_copy(gx_ctx* c, int32_t* rp, int32_t* col, double* val) {
+  GX_API_BEGIN(c)
+  if (!c->assembled) throw Error(GX_ESTATE, "matrix not assembled");
+  hipStream_t s = c->stream;
+  if (rp)
+    GX_HIP(hipMemcpyAsync(rp, c->row_ptr.p, (c->n_nodes + 1) * 4, hipMemcpyDefault, s));
+  if (col) GX_HIP(hipMemcpyAsync(col, c->col.p, c->nnzb * 4, hipMemcpyDefault, s));
+  if (val) GX_HIP(hipMemcpyAsync(val, c->val.p, c->nnzb * 72, hipMemcpyDefault, s));
+  GX_HIP(hipStreamSynchronize(s));
+  GX_API_END(c)
+}
+
+gx_status gx_spmv(gx_ctx* c, const double* x, double* y) {
+  GX_API_BEGIN(c)
+  if (!c->assembled) throw Error(GX_ESTATE, "matrix not assembled");
+  GX_REQUIRE(x && y, "null vector");
+  spmv(c, x, y);
+  GX_HIP(hipGetLastError());
+  GX_HIP(hipStreamSynchronize(c->stream));
+  GX_API_END(c)
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Context management, error reporting and a device exclusive prefix sum.
+#include "gx_internal.h"
+
+namespace gx {
+
+constexpr int SCAN_BS = 256;
+constexpr int SCAN_PT = 8;                       // items per thread
+constexpr int SCAN_TILE = SCAN_BS * SCAN_PT;
+
+// Block-level exclusive scan; writes the tile total to sums[blockIdx.x].
+template <class T>
+__global__ void scan_tiles(T* data, int64_t n, int64_t* sums) {
+  __shared__ int64_t part[SCAN_BS];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PT;
+  int64_t v[SCAN_PT];
+  int64_t acc = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_PT; ++i) {
+    const int64_t idx = base + i;
+    v[i] = idx < n ? (int64_t)data[idx] : 0;
+    acc += v[i];
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the per-thread sums
+  for (int off = 1; off < SCAN_BS; off <<= 1) {
+    int64_t add = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int64_t run = part[threadIdx.x] - acc;         // exclusive prefix of this thread
+#pragma unroll
+  for (int i = 0; i < SCAN_PT; ++i) {
+    const int64_t idx = base + i;
+    if (idx < n) data[idx] = (T)run;
+    run += v[i];
+  }
+  if (threadIdx.x == SCAN_BS - 1) sums[blockIdx.x] = part[SCAN_BS - 1];
+}
+
+template <class T>
+__global__ void scan_add(T* data, int64_t n, const int64_t* sums) {
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  const int64_t add = sums[blockIdx.x];
+  for (int i = threadIdx.x; i < SCAN_TILE; i += SCAN_BS) {
+    const int64_t idx = base + i;
+    if (idx < n) data[idx] = (T)((int64_t)data[idx] + add);
+  }
+}
+
+size_t scan_tmp_size(int64_t n) {
+  size_t tot = 1;
+  while (n > 1) {
+    n = (n + SCAN_TILE - 1) / SCAN_TILE;
+    tot += (size_t)n + 1;
+  }
+  return tot + 2;
+}
+
+template <class T>
+static void scan_rec(T* data, int64_t n, int64_t* tmp, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  hipLaunchKernelGGL(scan_tiles<T>, dim3((unsigned)nb), dim3(SCAN_BS), 0, s, data, n, tmp);
+  GX_HIP(hipGetLastError());
+  if (nb > 1) {
+    scan_rec<int64_t>(tmp, nb, tmp + nb + 1, s);
+    hipLaunchKernelGGL(scan_add<T>, dim3((unsigned)nb), dim3(SCAN_BS), 0, s, data, n, tmp);
+    GX_HIP(hipGetLastError());
+  }
+}
+
+template <class T>
+static int64_t scan_impl(T* data, int64_t n, int64_t* tmp, hipStream_t s) {
+  if (n <= 0) return 0;
+  T last;
+  GX_HIP(hipMemcpyAsync(&last, data + n - 1, sizeof(T), hipMemcpyDeviceToHost, s));
+  GX_HIP(hipStreamSynchronize(s));
+  scan_rec<T>(data, n, tmp, s);
+  T lastx;
+  GX_HIP(hipMemcpyAsync(&lastx, data + n - 1, sizeof(T), hipMemcpyDeviceToHost, s));
+  GX_HIP(hipStreamSynchronize(s));
+  return (int64_t)lastx + (int64_t)last;
+}
+
+int64_t exclusive_scan(int64_t* data, int64_t n, int64_t* tmp, hipStream_t s) {
+  return scan_impl<int64_t>(data, n, tmp, s);
+}
+int64_t exclusive_scan32(int32_t* data, int64_t n, int64_t* tmp, hipStream_t s) {
+  return scan_impl<int32_t>(data, n, tmp, s);
+}
+
+}  // namespace gx
+
+extern "C" {
+
+gx_status gx_create(gx_ctx** out, int32_t device, void* hip_stream) {
+  if (!out) return GX_EINVAL;
+  *out = nullptr;
+  gx_ctx* c = nullptr;
+  try {
+    int ndev = 0;
+    GX_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return GX_EINVAL;
+    c = new gx_ctx();
+    c->device = device;
+    GX_HIP(hipSetDevice(device));
+    if (hip_stream) {
+      c->stream = (hipStream_t)hip_stream;
+    } else {
+      GX_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+  } catch (const gx::Error& e) {
+    delete c;
+    return e.code;
+  }
+  *out = c;
+  return GX_OK;
+}
+
+void gx_destroy(gx_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* gx_last_error(const gx_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+const char* gx_version(void) { return "gx 0.1 (gfx950)"; }
+
+gx_status gx_phase_times(gx_ctx* c, double* ms) {
+  if (!c) return GX_EINVAL;
+  if (ms)
+    for (int i = 0; i < 8; ++i) ms[i] = c->phase_ms[i];
+  return GX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,226 @@
+// Internal declarations shared by the gx HIP sources (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/gx.h"
+
+namespace gx {
+
+struct Error : std::runtime_error {
+  gx_status code;
+  Error(gx_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define GX_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      throw ::gx::Error(e_ == hipErrorOutOfMemory ? GX_ENOMEM : GX_EHIP,              \
+                        std::string(#call) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+#define GX_REQUIRE(cond, msg)                                                         \
+  do {                                                                                \
+    if (!(cond)) throw ::gx::Error(GX_EINVAL, msg);                                   \
+  } while (0)
+
+// Owning device buffer.
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t count) { alloc(count); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count) {
+      hipError_t e = hipMalloc(&p, count * sizeof(T));
+      if (e != hipSuccess) {
+        p = nullptr;
+        n = 0;
+        throw Error(GX_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) +
+                                   " bytes failed: " + hipGetErrorString(e));
+      }
+    }
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+  operator T*() const { return p; }
+};
+
+template <class T>
+inline void zero(DevBuf<T>& b, hipStream_t s) {
+  if (b.n) GX_HIP(hipMemsetAsync(b.p, 0, b.bytes(), s));
+}
+template <class T>
+inline void to_dev(T* dst, const T* src, size_t n, hipStream_t s) {
+  if (n) GX_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+}
+template <class T>
+inline void to_host(T* dst, const T* src, size_t n, hipStream_t s) {
+  if (n) GX_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, s));
+  GX_HIP(hipStreamSynchronize(s));
+}
+
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Exclusive prefix sum of n int64 values in place; returns the total.  tmp must hold
+// scan_tmp_size(n) elements.
+size_t scan_tmp_size(int64_t n);
+int64_t exclusive_scan(int64_t* data, int64_t n, int64_t* tmp, hipStream_t s);
+int64_t exclusive_scan32(int32_t* data, int64_t n, int64_t* tmp, hipStream_t s);
+
+__device__ inline double wave_sum_d(double s) {
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  return s;
+}
+
+struct BandView {
+  const int64_t* B;
+  const int64_t* ld;
+  const int64_t* off;
+};
+
+// ------------------------------------------------------------------------------------
+// Decomposition and preconditioner state.
+struct BandSet {
+  // Banded lower factors of a batch of SPD matrices, row-major band storage:
+  // entry (r, c), r - B <= c <= r, of matrix j lives at off[j] + r * ld[j] + (c - r + B).
+  int n_mat = 0;
+  std::vector<int64_t> n, B, ld, off;          // host copies
+  DevBuf<int64_t> d_n, d_B, d_ld, d_off;       // device copies
+  int64_t total = 0;                           // stored entries
+  int max_n = 0, max_B = 0;
+  DevBuf<double> v64;                          // FP64 storage (precision FP64)
+  DevBuf<float> v32;                           // FP32 storage (mixed precision)
+  bool fp32 = false;
+};
+
+struct Schwarz {
+  int n_sub = 0, W = 0;                        // subdomains, 64-bit mask words
+  DevBuf<uint64_t> elem_mask, node_or, node_and;
+  // per subdomain node lists (interior I, Neumann D), concatenated, with offsets
+  std::vector<int64_t> nI, nD, offI, offD, nE, offE;
+  DevBuf<int64_t> d_offI, d_offD, d_nI, d_nD, d_offE, d_nE;
+  DevBuf<int32_t> I_nodes, D_nodes, E_list;
+  DevBuf<int32_t> I_loc, D_loc;                // [n_sub * n_nodes], -1 when absent
+  DevBuf<int32_t> node_cnt;                    // subdomains holding the node as interior
+  BandSet A;                                   // interior factors L_j
+  DevBuf<double> dg;                           // diagonal of K (scaling of FP32 factors)
+  std::vector<int64_t> xoff;                   // local vector segment of each subdomain
+  DevBuf<int64_t> d_xoff;
+  // coarse space
+  bool two_level = false;
+  std::vector<int32_t> nev;
+  std::vector<int64_t> z_off;                  // offset of Z_j (row-major nI_j*3 x nev_j)
+  DevBuf<int64_t> d_z_off;
+  DevBuf<int32_t> d_nev, d_c_off;              // coarse column offset of each subdomain
+  std::vector<int32_t> c_off;
+  int64_t n0 = 0;
+  DevBuf<double> Z;
+  BandSet C;                                   // Cholesky factor of K_0 (full band)
+  DevBuf<int64_t> d_c_xoff;
+  std::vector<std::vector<double>> lam;        // eigenvalues kept per subdomain
+  // work vectors for applying P
+  DevBuf<double> wr64, wx64;                   // gathered local rhs / solution (FP64)
+  DevBuf<float> wr32;                          // FP32 local work
+  DevBuf<double> y0, y0b;                      // coarse rhs / solution
+  DevBuf<double> y0part;                       // per-subdomain partial restriction
+  int precision = GX_FP64;
+};
+
+}  // namespace gx
+
+struct gx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  // mesh copy
+  int64_t n_nodes = 0, n_elems = 0;
+  gx::DevBuf<double> xyz;
+  gx::DevBuf<int32_t> conn, elayer;
+  gx::DevBuf<int32_t> ne_ptr, ne_idx;          // node -> element incidence (sorted)
+  gx::DevBuf<uint8_t> fixed;                   // per DOF: 1 if clamped
+  // element matrices, block-major: Ke[((e * 20 + a) * 20 + b) * 9 + 3 i + k]
+  gx::DevBuf<double> Ke;
+  // K: 3x3-block CSR
+  gx::DevBuf<int32_t> row_ptr, col;
+  gx::DevBuf<double> val;
+  int64_t nnzb = 0;
+  bool assembled = false;
+  // preconditioner
+  gx::Schwarz sw;
+  bool setup_done = false;
+  // PCG work vectors
+  gx::DevBuf<double> r, z, p, q, bm, red;
+  int32_t pcg_iters = 0;
+  double phase_ms[8] = {0};
+};
+
+namespace gx {
+// implemented in the respective .hip files
+void build_node_elem(gx_ctx* c);
+void spmv(gx_ctx* c, const double* x, double* y);
+void geneo_setup(gx_ctx* c, const gx_geneo_opts* o, int32_t* nev_out, int64_t* n0_out);
+void precond_apply(gx_ctx* c, const double* r, double* z);
+void dd_build(gx_ctx* c, const int32_t* part, int n_sub, int overlap);
+void interior_factors(gx_ctx* c, int precision);
+void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o);
+void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<int64_t>& B,
+                 bool fp32, hipStream_t st);
+void band_factor(BandSet& bs, hipStream_t st);
+void band_solve(BandSet& bs, const int64_t* d_xoff, double* x64, float* x32, hipStream_t st);
+struct Timer {
+  hipStream_t s;
+  std::chrono::steady_clock::time_point t0;
+  explicit Timer(hipStream_t st) : s(st) {
+    (void)hipStreamSynchronize(s);
+    t0 = std::chrono::steady_clock::now();
+  }
+  double ms() {
+    (void)hipStreamSynchronize(s);
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+        .count();
+  }
+};
+}  // namespace gx
+
+#define GX_API_BEGIN(ctx)                                                             \
+  if (!(ctx)) return GX_EINVAL;                                                       \
+  try {                                                                               \
+    (ctx)->err.clear();                                                               \
+    GX_HIP(hipSetDevice((ctx)->device));
+
+#define GX_API_END(ctx)                                                               \
+  }                                                                                   \
+  catch (const ::gx::Error& e_) {                                                     \
+    (ctx)->err = e_.what();                                                           \
+    return e_.code;                                                                   \
+  }                                                                                   \
+  catch (const std::exception& e_) {                                                  \
+    (ctx)->err = e_.what();                                                           \
+    return GX_EINVAL;                                                                 \
+  }                                                                                   \
+  return GX_OK;
