@@ -1,0 +1,138 @@
+"""Benchmark: AS-GenEO preconditioned CG on a 3M-DOF flat laminate, one MI355X.
+
+One step = the whole path on one synthetic laminate: device mesh generation, element
+assembly of K and f, overlapping decomposition, GenEO eigensolves and coarse space,
+subdomain factorisations, and the PCG solve to rtol 1e-8.  Prints one JSON line.
+
+Workload (the configuration the metric is quoted on): flat 50 x 50 mm laminate, 12 plies
+[0/45/90/-45/0/45]s, 0.25 mm plies with 4 element layers and 0.05 mm resin interfaces with
+1, 64 x 64 x 59 serendipity hexahedra, 3,005,925 DOFs (2,971,200 free), clamped at x = 0,
+1 MPa traction at x = 50; 8 x 8 subdomains, overlap 2, GenEO threshold 0.1.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Solve time per 1M DOFs at rtol 1e-8 (FP64 vs mixed); CG iters; SpMV GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def run_step(gx, torch, cfg, precision):
+    s = gx.Solver(stream=torch.cuda.current_stream())
+    s.laminate(cfg)
+    f = s.assemble()
+    sv = cfg["solver"]
+    part = s.partition(cfg, sv["px"], sv["py"])
+    nev, n0 = s.geneo_setup(part, sv["px"] * sv["py"], overlap=sv["overlap"], tau=sv["tau"],
+                            nev=sv["nev"], nev_max=sv["nev_max"], precision=precision)
+    out = s.pcg(f, rtol=sv["rtol"], maxit=2000)
+    return s, out, nev, n0
+
+
+def cpu_baseline(budget_s=30.0):
+    """The oracle (plain CPU FP64) on a bounded sample of the same workload: the cfg1 layup
+    and element layering on a 12 x 12 in-plane mesh split into 2 x 2 subdomains with the
+    same overlap and threshold, timed end to end with one BLAS thread."""
+    import workloads
+    from threadpoolctl import threadpool_limits
+    from oracle import pcg
+    cfg = workloads.cfg1(nx=12, ny=12, px=2, py=2)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        R = pcg.solve(cfg, rtol=cfg["solver"]["rtol"])
+        t = time.perf_counter() - t0
+    n = R["prob"].n
+    return {"value": t / (n / 1e6), "unit": "s/MDOF", "cores": 1, "kind": "oracle",
+            "sample": f"{cfg['name']}: {n} free DOFs, 2x2 subdomains, overlap 2, tau 0.1, "
+                      f"{R['iters']} PCG iterations, {t:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--small", action="store_true", help="reduced 24x24 workload (testing)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import paper_1707_04228_amd as gx
+    import workloads
+
+    cfg = workloads.cfg1(nx=24, ny=24, px=3, py=3) if args.small else workloads.cfg1()
+    prec = gx.GX_MIXED if args.precision == "mixed" else gx.GX_FP64
+    for _ in range(args.warmup):
+        s, out, nev, n0 = run_step(gx, torch, cfg, prec)
+        print(f"# warmup: {out['iters']} iterations, relres {out['relres']:.2e}", flush=True)
+        del s
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for k in range(args.steps):
+        s, out, nev, n0 = run_step(gx, torch, cfg, prec)
+        results.append((out["iters"], out["relres"], s.phase_times()))
+        if k + 1 < args.steps:
+            del s
+        print(f"# step {k}: {out['iters']} iterations", flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = 1e3 * dt / args.steps
+    n_free = int(3 * s.mesh["n_nodes"] - 3 * s.mesh["clamped"].numel())
+    # live kernel measurements on the library's stream (HIP events)
+    spmv_ms, spmv_bytes = s.kernel_time(0, reps=20)
+    solve_ms, solve_bytes = s.kernel_time(1, reps=5)
+    pre_ms, _ = s.kernel_time(2, reps=5)
+    phases = results[-1][2]
+    spmv_gbs = spmv_bytes / (spmv_ms * 1e-3) / 1e9
+    solve_gbs = solve_bytes / (solve_ms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": (ms_step / 1e3) / (n_free / 1e6),
+        "unit": "s/MDOF",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == gx.GX_FP64 else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"] + " flat 50x50 mm [0/45/90/-45/0/45]s laminate, "
+                               "20-node serendipity hexes, 8x8 subdomains, overlap 2, "
+                               "GenEO tau 0.1, rtol 1e-8",
+                   "n_dofs": int(3 * s.mesh["n_nodes"]), "n_free_dofs": n_free,
+                   "precision": args.precision},
+        "cg_iters": results[-1][0],
+        "relres": results[-1][1],
+        "n0": int(n0),
+        "spmv_GBps": spmv_gbs,
+        "spmv_ms": spmv_ms,
+        "subdomain_solve_GBps": solve_gbs,
+        "subdomain_solve_ms": solve_ms,
+        "precond_apply_ms": pre_ms,
+        "phases_ms": phases,
+        "roofline": {"bound": "hbm", "kernel": "k_band_solve (subdomain forward+backward)",
+                     "achieved": solve_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": solve_gbs / HBM_PEAK_GBS, "traffic": None},
+        "spmv_roofline": {"bound": "hbm", "kernel": "k_spmv", "achieved": spmv_gbs,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": spmv_gbs / HBM_PEAK_GBS},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

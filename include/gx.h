@@ -226,6 +226,14 @@ gx_status gx_precond_apply(gx_ctx* ctx, const double* r, double* z);
 gx_status gx_pcg_solve(gx_ctx* ctx, const double* b, double* x, double rtol, int32_t maxit,
                        int32_t* iters_out, double* relres_out, double* hist);
 
+/* Measurement of one library kernel with HIP events on the context's stream: the average
+ * duration over `reps` launches (ms) and the algorithmic bytes one launch must move
+ * (bytes, 0 when not defined).  which: 0 = block-CSR product y = K x; 1 = the batched
+ * subdomain band solves of one preconditioner application (forward and backward);
+ * 2 = one whole preconditioner application; 3 = the coarse solve. */
+gx_status gx_kernel_time(gx_ctx* ctx, int32_t which, int32_t reps, double* avg_ms,
+                         double* bytes);
+
 /* Time spent in the last call of each phase, milliseconds (host [8], may be NULL):
  * assemble, decomposition, local factors, eigensolves, coarse, pcg, precond total in pcg,
  * spmv total in pcg. */

@@ -94,7 +94,8 @@ for _name, _args in [("gx_geneo_setup", [vp, C.POINTER(GeneoOpts), i32p, i64p]),
                      ("gx_subdomain_info", [vp, i64p, i64p, i64p]),
                      ("gx_geneo_eigenvalues", [vp, C.c_int32, f64p]),
                      ("gx_precond_apply", [vp, vp, vp]),
-                     ("gx_pcg_solve", [vp, vp, vp, C.c_double, C.c_int32, i32p, f64p, f64p])]:
+                     ("gx_pcg_solve", [vp, vp, vp, C.c_double, C.c_int32, i32p, f64p, f64p]),
+                     ("gx_kernel_time", [vp, C.c_int32, C.c_int32, f64p, f64p])]:
     if hasattr(lib, _name):
         _sig(_name, _args)
 
@@ -102,7 +103,7 @@ EXPORTS = ["gx_create", "gx_destroy", "gx_last_error", "gx_version", "gx_laminat
            "gx_laminate_mesh", "gx_laminate_partition", "gx_laminate_traction",
            "gx_assemble", "gx_matrix_info", "gx_matrix_copy", "gx_spmv", "gx_geneo_setup",
            "gx_subdomain_info", "gx_geneo_eigenvalues", "gx_precond_apply", "gx_pcg_solve",
-           "gx_phase_times"]
+           "gx_phase_times", "gx_kernel_time"]
 
 
 class GxError(RuntimeError):
@@ -167,7 +168,7 @@ class Solver:
         self.nev = None
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.gx_destroy(self.h)
             self.h = None
 
@@ -308,6 +309,12 @@ class Solver:
         if history:
             out["hist"] = hist[: it.value + 1]
         return out
+
+    def kernel_time(self, which, reps=5):
+        """(average ms, algorithmic bytes per launch) of library kernel `which`."""
+        ms, b = C.c_double(), C.c_double()
+        self._check(lib.gx_kernel_time(self.h, which, reps, C.byref(ms), C.byref(b)))
+        return ms.value, b.value
 
     def phase_times(self):
         t = np.zeros(8)

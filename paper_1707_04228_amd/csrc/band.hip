@@ -189,18 +189,25 @@ void band_factor(BandSet& bs, hipStream_t st) {
 // ---------------------------------------------------------------------------------------
 // Solves.  x (vector of matrix j at xoff[j]) is overwritten: forward then backward.
 
+// Column blockIdx.y of matrix j's right-hand sides, stored with row stride `stride` at
+// xoff[j] (stride 1 and one column for the preconditioner; row-major blocks of columns for
+// the eigensolver).  Matrices with active[j] == 0 are skipped.
 template <class T, class V>
 __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve(BandArgs a, const T* v,
-                                                             const int64_t* xoff, V* xall) {
+                                                             const int64_t* xoff, V* xall,
+                                                             int stride,
+                                                             const int32_t* active) {
   __shared__ double win[WIN];
   __shared__ double tri[SB][SB + 1];
   __shared__ double acc[SB];
   __shared__ double part[SOLVE_THREADS / 64][SB];
   const int j = blockIdx.x;
+  if (active && !active[j]) return;
   const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
   const T* base = v + a.off[j];
-  V* x = xall + xoff[j];
+  V* xv = xall + xoff[j] + blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#define x(i) xv[(int64_t)(i) * stride]
   constexpr int NW = SOLVE_THREADS / 64;
   constexpr int64_t MSK = WIN - 1;
   // ---- forward: L y = b
@@ -213,7 +220,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve(BandArgs a, const 
       double s = 0.0;
       for (int64_t c = cs + lane; c < i0; c += 64) s += (double)row[c] * win[c & MSK];
       s = wave_sum_d(s);
-      if (lane == 0) acc[ii] = (double)x[i] - s;
+      if (lane == 0) acc[ii] = (double)x(i) - s;
       for (int l = lane; l < SB; l += 64)
         tri[ii][l] = (l <= ii && i - (i0 + l) <= B) ? (double)row[i0 + l] : 0.0;
     }
@@ -227,7 +234,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve(BandArgs a, const 
       }
       if (lane < nb) {
         win[(i0 + lane) & MSK] = y_l;
-        x[i0 + lane] = (V)y_l;
+        x(i0 + lane) = (V)y_l;
       }
     }
     __syncthreads();
@@ -253,7 +260,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve(BandArgs a, const 
     if (wave == 0) {
       double t = 0.0;
       for (int w = 0; w < NW; ++w) t += part[w][lane];
-      double a_l = lane < nb ? (double)x[i0 + lane] - t : 0.0, x_l = 0.0;
+      double a_l = lane < nb ? (double)x(i0 + lane) - t : 0.0, x_l = 0.0;
       for (int cc = nb - 1; cc >= 0; --cc) {
         const double xc = __shfl(a_l, cc) / tri[cc][cc];
         if (lane == cc) x_l = xc;
@@ -261,22 +268,27 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve(BandArgs a, const 
       }
       if (lane < nb) {
         win[(i0 + lane) & MSK] = x_l;
-        x[i0 + lane] = (V)x_l;
+        x(i0 + lane) = (V)x_l;
       }
     }
     __syncthreads();
   }
+#undef x
 }
 
-void band_solve(BandSet& bs, const int64_t* d_xoff, double* x64, float* x32, hipStream_t st) {
+void band_solve(BandSet& bs, const int64_t* d_xoff, double* x64, float* x32, hipStream_t st,
+                int ncol, const int32_t* active) {
   GX_REQUIRE(bs.max_B + SB <= WIN, "band too wide for the solve window");
   BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p};
-  if (bs.fp32)
-    hipLaunchKernelGGL((k_band_solve<float, float>), dim3(bs.n_mat), dim3(SOLVE_THREADS), 0,
-                       st, a, bs.v32.p, d_xoff, x32);
+  if (bs.fp32 && x32)
+    hipLaunchKernelGGL((k_band_solve<float, float>), dim3(bs.n_mat, ncol), dim3(SOLVE_THREADS),
+                       0, st, a, bs.v32.p, d_xoff, x32, ncol, active);
+  else if (bs.fp32)
+    hipLaunchKernelGGL((k_band_solve<float, double>), dim3(bs.n_mat, ncol),
+                       dim3(SOLVE_THREADS), 0, st, a, bs.v32.p, d_xoff, x64, ncol, active);
   else
-    hipLaunchKernelGGL((k_band_solve<double, double>), dim3(bs.n_mat), dim3(SOLVE_THREADS), 0,
-                       st, a, bs.v64.p, d_xoff, x64);
+    hipLaunchKernelGGL((k_band_solve<double, double>), dim3(bs.n_mat, ncol),
+                       dim3(SOLVE_THREADS), 0, st, a, bs.v64.p, d_xoff, x64, ncol, active);
   GX_HIP(hipGetLastError());
 }
 

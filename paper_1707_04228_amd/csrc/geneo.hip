@@ -1,7 +1,782 @@
-// GenEO coarse space and the setup entry point of the two-level Schwarz preconditioner.
+// GenEO coarse space (section 2.3) and the setup entry point of the preconditioner.
+//
+// In every subdomain j the lowest-energy modes of the local generalised eigenproblem
+//     A_j^N p = lambda X_j A_j^o X_j p
+// are computed (A^N: stiffness of the subdomain's elements on all DOFs of its nodes;
+// A^o: the same over the elements that also lie in another subdomain; X_j: partition of
+// unity, zero off the interior).  Their partition-of-unity images span the coarse space;
+// K_0 = Z^T K Z is factored once and solved in every preconditioner application.
+//
+// Eigensolver: block shift-invert subspace iteration with Rayleigh-Ritz for the largest
+// mu of B p = mu M p, M = A^N + sigma B (lambda = 1/mu - sigma).  M is assembled in band
+// storage directly from the element matrices and factored by the batched band Cholesky;
+// B products are gathers over the stored element matrices of the overlap elements.
+// With Y = M^-1 B X the M-products come for free (M Y = B X), so each iteration needs one
+// multi-column band solve, one B product, two Gram matrices and a small dense eigenproblem
+// (parallel cyclic Jacobi in LDS).  Eigen-residuals and the threshold test are FP64.
 #include <cmath>
 
 #include "gx_internal.h"
+
+namespace gx {
+
+constexpr int MAXM = 40;                       // eigensolver block size limit
+
+__device__ inline bool has_bit(const uint64_t* mask, int64_t item, int W, int j) {
+  return (mask[item * W + j / 64] >> (j % 64)) & 1ull;
+}
+__device__ inline int popc_mask(const uint64_t* mask, int64_t item, int W) {
+  int c = 0;
+  for (int w = 0; w < W; ++w) c += __popcll(mask[item * W + w]);
+  return c;
+}
+// partition-of-unity weight of node n in subdomain j (zero off the interior)
+__device__ inline double pou(const int32_t* I_loc, const int32_t* cnt, int64_t N, int j,
+                             int64_t n) {
+  return I_loc[(int64_t)j * N + n] >= 0 ? 1.0 / cnt[n] : 0.0;
+}
+
+struct GeneoDev {
+  const int32_t* conn;
+  const int32_t* ne_ptr;
+  const int32_t* ne_idx;
+  const double* Ke;
+  const uint8_t* fixed;
+  const uint64_t* emask;
+  int W;
+  int64_t N;
+  const int32_t* D_nodes;
+  const int64_t* offD;
+  const int64_t* nD;
+  const int32_t* D_loc;
+  const int32_t* I_loc;
+  const int32_t* cnt;
+};
+
+// M_j = A^N + sigma X A^o X in band storage over the Neumann DOFs; clamped DOFs -> identity
+__global__ void __launch_bounds__(64) k_neumann_fill(GeneoDev g, double sigma, BandView bv,
+                                                     double* v) {
+  const int j = blockIdx.y;
+  const int64_t ln = blockIdx.x;
+  if (ln >= g.nD[j]) return;
+  const int64_t n = g.D_nodes[g.offD[j] + ln];
+  const int64_t B = bv.B[j], ld = bv.ld[j];
+  double* base = v + bv.off[j];
+  for (int64_t i = threadIdx.x; i < 3 * ld; i += 64) base[3 * ln * ld + i] = 0.0;
+  __syncthreads();
+  const double xn = pou(g.I_loc, g.cnt, g.N, j, n);
+  for (int k = g.ne_ptr[n]; k < g.ne_ptr[n + 1]; ++k) {
+    const int64_t e = g.ne_idx[k];
+    if (!has_bit(g.emask, e, g.W, j)) continue;
+    const bool over = popc_mask(g.emask, e, g.W) >= 2;
+    int a = 0;
+    while (a < 19 && g.conn[20 * e + a] != n) ++a;
+    for (int t = threadIdx.x; t < 180; t += 64) {
+      const int b = t / 9, comp = t - 9 * (t / 9);
+      const int i = comp / 3, kk = comp - 3 * (comp / 3);
+      const int64_t m = g.conn[20 * e + b];
+      const int64_t lm = g.D_loc[(int64_t)j * g.N + m];
+      const int64_t row = 3 * ln + i, col = 3 * lm + kk;
+      if (col > row) continue;
+      const double w = over ? 1.0 + sigma * xn * pou(g.I_loc, g.cnt, g.N, j, m) : 1.0;
+      base[row * ld + (col - row + B)] += w * g.Ke[((e * 20 + a) * 20 + b) * 9 + comp];
+    }
+    __syncthreads();
+  }
+  for (int64_t t = threadIdx.x; t < 3 * ld; t += 64) {
+    const int64_t row = 3 * ln + t / ld, col = row - B + t % ld;
+    if (col < 0) continue;
+    const int64_t gr = 3 * n + row % 3;
+    const int64_t gc = 3 * (int64_t)g.D_nodes[g.offD[j] + col / 3] + col % 3;
+    if (g.fixed[gr] || g.fixed[gc]) base[3 * ln * ld + t] = (row == col) ? 1.0 : 0.0;
+  }
+}
+
+// Y = X_j A^o X_j X for the m columns of subdomain j (row-major, lane = column)
+__global__ void __launch_bounds__(64) k_bmul(GeneoDev g, int m, const int64_t* voff,
+                                             const int32_t* active, const double* X,
+                                             double* Y) {
+  const int j = blockIdx.y;
+  const int64_t ln = blockIdx.x;
+  if (ln >= g.nD[j] || !active[j]) return;
+  const int lane = threadIdx.x;
+  const int64_t n = g.D_nodes[g.offD[j] + ln];
+  const double* Xj = X + voff[j];
+  double y0 = 0, y1 = 0, y2 = 0;
+  const double xn = pou(g.I_loc, g.cnt, g.N, j, n);
+  if (xn != 0.0 && lane < m) {
+    for (int k = g.ne_ptr[n]; k < g.ne_ptr[n + 1]; ++k) {
+      const int64_t e = g.ne_idx[k];
+      if (!has_bit(g.emask, e, g.W, j) || popc_mask(g.emask, e, g.W) < 2) continue;
+      int a = 0;
+      while (a < 19 && g.conn[20 * e + a] != n) ++a;
+      for (int b = 0; b < 20; ++b) {
+        const int64_t mm = g.conn[20 * e + b];
+        const double w = xn * pou(g.I_loc, g.cnt, g.N, j, mm);
+        if (w == 0.0) continue;
+        const int64_t lm = g.D_loc[(int64_t)j * g.N + mm];
+        const double* kb = g.Ke + ((e * 20 + a) * 20 + b) * 9;
+        const double x0 = g.fixed[3 * mm] ? 0.0 : Xj[(3 * lm) * m + lane];
+        const double x1 = g.fixed[3 * mm + 1] ? 0.0 : Xj[(3 * lm + 1) * m + lane];
+        const double x2 = g.fixed[3 * mm + 2] ? 0.0 : Xj[(3 * lm + 2) * m + lane];
+        y0 += w * (kb[0] * x0 + kb[1] * x1 + kb[2] * x2);
+        y1 += w * (kb[3] * x0 + kb[4] * x1 + kb[5] * x2);
+        y2 += w * (kb[6] * x0 + kb[7] * x1 + kb[8] * x2);
+      }
+    }
+  }
+  if (lane < m) {
+    double* Yj = Y + voff[j];
+    Yj[(3 * ln) * m + lane] = g.fixed[3 * n] ? 0.0 : y0;
+    Yj[(3 * ln + 1) * m + lane] = g.fixed[3 * n + 1] ? 0.0 : y1;
+    Yj[(3 * ln + 2) * m + lane] = g.fixed[3 * n + 2] ? 0.0 : y2;
+  }
+}
+
+// deterministic pseudo-random start block (splitmix64 of the entry index), zero on clamps
+__global__ void k_rand_init(GeneoDev g, int m, const int64_t* voff, double* X) {
+  const int j = blockIdx.y;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 3 * g.nD[j] * m) return;
+  const int64_t row = r / m;
+  const int64_t n = g.D_nodes[g.offD[j] + row / 3];
+  uint64_t z = (uint64_t)r + 0x9E3779B97F4A7C15ull * (uint64_t)(j + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+  X[voff[j] + r] = g.fixed[3 * n + row % 3] ? 0.0 : u;
+}
+
+__global__ void k_copy_active(int64_t n_rows_max, const int64_t* nrows, int m,
+                              const int64_t* voff, const int32_t* active, const double* src,
+                              double* dst) {
+  const int j = blockIdx.y;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (!active[j] || r >= 3 * nrows[j] * m) return;
+  dst[voff[j] + r] = src[voff[j] + r];
+}
+
+// Gram partials G_U[a][b] = sum_i U[i][a] V1[i][b] and G_2 = sum_i U[i][a] V2[i][b] over a
+// chunk of rows; chunk partials are reduced in a fixed order afterwards
+constexpr int GCH = 4096;
+constexpr int GROWS = 32;
+__global__ void __launch_bounds__(256) k_gram(const int64_t* nrows, int m, const int64_t* voff,
+                                              const int32_t* active, const double* U,
+                                              const double* V1, const double* V2,
+                                              int64_t nch_max, double* part) {
+  __shared__ double su[GROWS][MAXM], s1[GROWS][MAXM], s2[GROWS][MAXM];
+  const int j = blockIdx.y;
+  if (!active[j]) return;
+  const int64_t n3 = 3 * nrows[j];
+  const int64_t r0 = (int64_t)blockIdx.x * GCH;
+  constexpr int EPT = (MAXM * MAXM + 255) / 256;
+  double a1[EPT], a2[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) a1[q] = a2[q] = 0.0;
+  const double* Uj = U + voff[j];
+  const double* V1j = V1 + voff[j];
+  const double* V2j = V2 + voff[j];
+  for (int64_t rb = r0; rb < min(n3, r0 + GCH); rb += GROWS) {
+    for (int t = threadIdx.x; t < GROWS * m; t += 256) {
+      const int rr = t / m, cc = t % m;
+      const int64_t row = rb + rr;
+      const bool ok = row < n3;
+      su[rr][cc] = ok ? Uj[row * m + cc] : 0.0;
+      s1[rr][cc] = ok ? V1j[row * m + cc] : 0.0;
+      s2[rr][cc] = ok ? V2j[row * m + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (e < m * m) {
+        const int a = e / m, b = e % m;
+        double t1 = 0, t2 = 0;
+        for (int rr = 0; rr < GROWS; ++rr) {
+          t1 += su[rr][a] * s1[rr][b];
+          t2 += su[rr][a] * s2[rr][b];
+        }
+        a1[q] += t1;
+        a2[q] += t2;
+      }
+    }
+    __syncthreads();
+  }
+  double* pj = part + ((int64_t)j * nch_max + blockIdx.x) * 2 * MAXM * MAXM;
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    if (e < m * m) {
+      pj[e] = a1[q];
+      pj[MAXM * MAXM + e] = a2[q];
+    }
+  }
+}
+
+__global__ void k_gram_sum(const int64_t* nrows, int m, const int32_t* active,
+                           int64_t nch_max, const double* part, double* G) {
+  const int j = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!active[j] || e >= 2 * MAXM * MAXM) return;
+  const int64_t nch = (3 * nrows[j] + GCH - 1) / GCH;
+  double s = 0.0;
+  for (int64_t k = 0; k < nch; ++k) s += part[((int64_t)j * nch_max + k) * 2 * MAXM * MAXM + e];
+  G[(int64_t)j * 2 * MAXM * MAXM + e] = s;
+}
+
+// Small dense Rayleigh-Ritz per subdomain: G_B c = mu G_M c, largest mu first.
+// G layout: [G_M (m x m, ld m) | G_B] inside a 2 MAXM^2 slot.  Output: c (m x m row-major,
+// column b = b-th Ritz vector) and theta_b = 1 / mu_b.
+__global__ void __launch_bounds__(256) k_rayleigh_ritz(int m, const int32_t* active,
+                                                       const double* G, double* Cout,
+                                                       double* theta, int* err) {
+  __shared__ double L[MAXM][MAXM + 1], H[MAXM][MAXM + 1], T[MAXM][MAXM + 1],
+      V[MAXM][MAXM + 1];
+  __shared__ double dsc[MAXM], rc[MAXM / 2 + 1], rs[MAXM / 2 + 1], mu[MAXM];
+  __shared__ int rp[MAXM / 2 + 1], rq[MAXM / 2 + 1], perm[MAXM];
+  __shared__ double offn;
+  const int j = blockIdx.x;
+  if (!active[j]) return;
+  const int t = threadIdx.x;
+  const double* Gj = G + (int64_t)j * 2 * MAXM * MAXM;
+  for (int e = t; e < m * m; e += 256) {
+    const int a = e / m, b = e % m;
+    L[a][b] = 0.5 * (Gj[a * m + b] + Gj[b * m + a]);
+    T[a][b] = 0.5 * (Gj[MAXM * MAXM + a * m + b] + Gj[MAXM * MAXM + b * m + a]);
+  }
+  __syncthreads();
+  if (t < m) dsc[t] = L[t][t] > 0 ? 1.0 / sqrt(L[t][t]) : 0.0;
+  __syncthreads();
+  for (int e = t; e < m * m; e += 256) {
+    const int a = e / m, b = e % m;
+    L[a][b] *= dsc[a] * dsc[b];
+    T[a][b] *= dsc[a] * dsc[b];
+  }
+  __syncthreads();
+  // Cholesky of the scaled M-Gram (lower, in place)
+  for (int i = 0; i < m; ++i) {
+    if (t == 0) {
+      double d = L[i][i];
+      if (!(d > 1e-13)) {
+        atomicOr(err, 1);
+        d = 1.0;
+      }
+      L[i][i] = sqrt(d);
+    }
+    __syncthreads();
+    for (int r = i + 1 + t; r < m; r += 256) L[r][i] /= L[i][i];
+    __syncthreads();
+    const int mm = m - i - 1;
+    for (int e = t; e < mm * mm; e += 256) {
+      const int r = i + 1 + e / mm, s = i + 1 + e % mm;
+      if (s <= r) L[r][s] -= L[r][i] * L[s][i];
+    }
+    __syncthreads();
+  }
+  // H = L^-1 G_B L^-T: first W = L^-1 G_B (column k by thread k), then H = L^-1 W^T
+  if (t < m) {
+    for (int i = 0; i < m; ++i) {
+      double s = T[i][t];
+      for (int l = 0; l < i; ++l) s -= L[i][l] * H[l][t];
+      H[i][t] = s / L[i][i];
+    }
+  }
+  __syncthreads();
+  if (t < m) {
+    for (int i = 0; i < m; ++i) {
+      double s = H[t][i];
+      for (int l = 0; l < i; ++l) s -= L[i][l] * T[l][t];
+      T[i][t] = s / L[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < m * m; e += 256) {
+    const int a = e / m, b = e % m;
+    H[a][b] = 0.5 * (T[a][b] + T[b][a]);
+    V[a][b] = (a == b) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // parallel cyclic Jacobi, round-robin pairing (one index is a dummy when m is odd)
+  const int me = m + (m & 1);
+  const int np = me / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (t == 0) {
+      double off = 0.0, all = 0.0;
+      for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) {
+          all += H[a][b] * H[a][b];
+          if (a != b) off += H[a][b] * H[a][b];
+        }
+      offn = (off <= 1e-30 * all) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (offn != 0.0) break;
+    for (int round = 0; round < me - 1; ++round) {
+      if (t < np) {
+        int p, q;
+        if (t == 0) {
+          p = me - 1;
+          q = round;
+        } else {
+          p = (round + t) % (me - 1);
+          q = (round - t + (me - 1)) % (me - 1);
+        }
+        if (p > q) { const int tmp = p; p = q; q = tmp; }
+        double c = 1.0, s = 0.0;
+        if (q < m && H[p][q] != 0.0) {
+          const double th = (H[q][q] - H[p][p]) / (2.0 * H[p][q]);
+          const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(tt * tt + 1.0);
+          s = tt * c;
+        }
+        rp[t] = p;
+        rq[t] = q < m ? q : p;
+        rc[t] = c;
+        rs[t] = s;
+      }
+      __syncthreads();
+      for (int e = t; e < np * m; e += 256) {      // rows: H <- P^T H
+        const int k = e / m, col = e % m;
+        const int p = rp[k], q = rq[k];
+        if (p == q) continue;
+        const double c = rc[k], s = rs[k];
+        const double hp = H[p][col], hq = H[q][col];
+        H[p][col] = c * hp - s * hq;
+        H[q][col] = s * hp + c * hq;
+      }
+      __syncthreads();
+      for (int e = t; e < np * m; e += 256) {      // columns: H <- H P, V <- V P
+        const int k = e / m, row = e % m;
+        const int p = rp[k], q = rq[k];
+        if (p == q) continue;
+        const double c = rc[k], s = rs[k];
+        const double hp = H[row][p], hq = H[row][q];
+        H[row][p] = c * hp - s * hq;
+        H[row][q] = s * hp + c * hq;
+        const double vp = V[row][p], vq = V[row][q];
+        V[row][p] = c * vp - s * vq;
+        V[row][q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+  // order by decreasing mu
+  if (t == 0) {
+    for (int a = 0; a < m; ++a) {
+      mu[a] = H[a][a];
+      perm[a] = a;
+    }
+    for (int a = 0; a < m; ++a)
+      for (int b = a + 1; b < m; ++b)
+        if (mu[perm[b]] > mu[perm[a]]) {
+          const int tmp = perm[a];
+          perm[a] = perm[b];
+          perm[b] = tmp;
+        }
+  }
+  __syncthreads();
+  // c = D L^-T V (column b = Ritz vector of the b-th largest mu)
+  if (t < m) {
+    const int src = perm[t];
+    for (int i = m - 1; i >= 0; --i) {
+      double s = V[i][src];
+      for (int l = i + 1; l < m; ++l) s -= L[l][i] * T[l][t];
+      T[i][t] = s / L[i][i];
+    }
+    theta[(int64_t)j * MAXM + t] = 1.0 / mu[src];
+  }
+  __syncthreads();
+  for (int e = t; e < m * m; e += 256) {
+    const int a = e / m, b = e % m;
+    Cout[(int64_t)j * MAXM * MAXM + a * m + b] = dsc[a] * T[a][b];
+  }
+}
+
+// out[i][b] = sum_a in[i][a] c[a][b] (row-major blocks of m columns)
+__global__ void __launch_bounds__(256) k_rotate(const int64_t* nrows, int m,
+                                                const int64_t* voff, const int32_t* active,
+                                                const double* Cm, const double* in,
+                                                double* out) {
+  __shared__ double c[MAXM][MAXM];
+  const int j = blockIdx.y;
+  if (!active[j]) return;
+  for (int e = threadIdx.x; e < m * m; e += 256) c[e / m][e % m] = Cm[(int64_t)j * MAXM * MAXM + e];
+  __syncthreads();
+  const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  const int b = threadIdx.x % 64;
+  if (row >= 3 * nrows[j] || b >= m) return;
+  const double* ir = in + voff[j] + row * m;
+  double s = 0.0;
+  for (int a = 0; a < m; ++a) s += ir[a] * c[a][b];
+  out[voff[j] + row * m + b] = s;
+}
+
+// per column: ||MX - theta BX||^2 and ||MX||^2 (chunk partials, then fixed-order sums)
+__global__ void __launch_bounds__(256) k_resid(const int64_t* nrows, int m,
+                                               const int64_t* voff, const int32_t* active,
+                                               const double* theta, const double* MX,
+                                               const double* BX, int64_t nch_max,
+                                               double* part) {
+  __shared__ double red[4][2][64];
+  const int j = blockIdx.y;
+  if (!active[j]) return;
+  const int64_t n3 = 3 * nrows[j];
+  const int b = threadIdx.x % 64, rg = threadIdx.x / 64;
+  double r2 = 0, m2 = 0;
+  if (b < m) {
+    const double th = theta[(int64_t)j * MAXM + b];
+    const int64_t r0 = (int64_t)blockIdx.x * GCH;
+    for (int64_t row = r0 + rg; row < min(n3, r0 + GCH); row += 4) {
+      const double mx = MX[voff[j] + row * m + b];
+      const double d = mx - th * BX[voff[j] + row * m + b];
+      r2 += d * d;
+      m2 += mx * mx;
+    }
+  }
+  red[rg][0][b] = r2;
+  red[rg][1][b] = m2;
+  __syncthreads();
+  if (rg == 0 && b < m) {
+    double* pj = part + ((int64_t)j * nch_max + blockIdx.x) * 2 * MAXM;
+    pj[b] = red[0][0][b] + red[1][0][b] + red[2][0][b] + red[3][0][b];
+    pj[MAXM + b] = red[0][1][b] + red[1][1][b] + red[2][1][b] + red[3][1][b];
+  }
+}
+
+__global__ void k_resid_sum(const int64_t* nrows, const int32_t* active, int64_t nch_max,
+                            const double* part, double* out) {
+  const int j = blockIdx.x;
+  const int e = threadIdx.x;
+  if (!active[j] || e >= 2 * MAXM) return;
+  const int64_t nch = (3 * nrows[j] + GCH - 1) / GCH;
+  double s = 0.0;
+  for (int64_t k = 0; k < nch; ++k) s += part[((int64_t)j * nch_max + k) * 2 * MAXM + e];
+  out[(int64_t)j * 2 * MAXM + e] = s;
+}
+
+// ---------------------------------------------------------------------------------------
+// coarse space
+struct CoarseDev {
+  const int32_t* I_nodes;
+  const int64_t* offI;
+  const int64_t* nI;
+  const int64_t* zoff;        // Z_j column-major, 3 nI_j rows
+  const int32_t* nev;
+  const int32_t* coff;
+};
+
+__global__ void k_build_Z(GeneoDev g, CoarseDev cd, int m, const int64_t* voff,
+                          const double* X, double* Z) {
+  const int j = blockIdx.y;
+  const int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n3 = 3 * cd.nI[j];
+  if (li >= n3) return;
+  const int64_t n = cd.I_nodes[cd.offI[j] + li / 3];
+  const int64_t ld = 3 * (int64_t)g.D_loc[(int64_t)j * g.N + n] + li % 3;
+  const double w = g.fixed[3 * n + li % 3] ? 0.0 : 1.0 / g.cnt[n];
+  for (int a = 0; a < cd.nev[j]; ++a)
+    Z[cd.zoff[j] + (int64_t)a * n3 + li] = w * X[voff[j] + ld * m + a];
+}
+
+// V_j = K R_j^T Z_j on the Neumann rows of j (row-major, nev_j columns, lane = column)
+__global__ void __launch_bounds__(64) k_coarse_V(GeneoDev g, CoarseDev cd, const int32_t* rp,
+                                                 const int32_t* col, const double* val,
+                                                 const double* Z, const int64_t* vcoff,
+                                                 double* Vc) {
+  const int j = blockIdx.y;
+  const int64_t ln = blockIdx.x;
+  if (ln >= g.nD[j]) return;
+  const int a = threadIdx.x, m = cd.nev[j];
+  if (a >= m) return;
+  const int64_t n = g.D_nodes[g.offD[j] + ln];
+  const int64_t n3 = 3 * cd.nI[j];
+  const double* Zj = Z + cd.zoff[j] + (int64_t)a * n3;
+  double y0 = 0, y1 = 0, y2 = 0;
+  for (int k = rp[n]; k < rp[n + 1]; ++k) {
+    const int64_t mm = col[k];
+    const int64_t li = g.I_loc[(int64_t)j * g.N + mm];
+    if (li < 0) continue;
+    const double* kb = val + (int64_t)k * 9;
+    const double z0 = Zj[3 * li], z1 = Zj[3 * li + 1], z2 = Zj[3 * li + 2];
+    y0 += kb[0] * z0 + kb[1] * z1 + kb[2] * z2;
+    y1 += kb[3] * z0 + kb[4] * z1 + kb[5] * z2;
+    y2 += kb[6] * z0 + kb[7] * z1 + kb[8] * z2;
+  }
+  double* o = Vc + vcoff[j];
+  o[(3 * ln) * m + a] = y0;
+  o[(3 * ln + 1) * m + a] = y1;
+  o[(3 * ln + 2) * m + a] = y2;
+}
+
+__global__ void k_pair_adjacency(const uint64_t* nand, const uint64_t* nor, int W, int64_t N,
+                                 int n_sub, int32_t* adj) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  for (int wk = 0; wk < W; ++wk) {
+    uint64_t bk = nand[n * W + wk];
+    while (bk) {
+      const int k = wk * 64 + __ffsll((unsigned long long)bk) - 1;
+      bk &= bk - 1;
+      for (int wj = 0; wj < W; ++wj) {
+        uint64_t bj = nor[n * W + wj];
+        while (bj) {
+          const int jj = wj * 64 + __ffsll((unsigned long long)bj) - 1;
+          bj &= bj - 1;
+          adj[(int64_t)k * n_sub + jj] = 1;
+        }
+      }
+    }
+  }
+}
+
+// K_0 block (k, j) = sum over nodes in I_k and D_j of Z_k^T V_j
+__global__ void __launch_bounds__(256) k_coarse_pair(GeneoDev g, CoarseDev cd, int n_sub,
+                                                     const int32_t* adj, const double* Z,
+                                                     const double* Vc, const int64_t* vcoff,
+                                                     int64_t n0, double* K0) {
+  const int k = blockIdx.x, j = blockIdx.y;
+  if (!adj[(int64_t)k * n_sub + j]) return;
+  const int mk = cd.nev[k], mj = cd.nev[j];
+  if (mk == 0 || mj == 0) return;
+  constexpr int EPT = (MAXM * MAXM + 255) / 256;
+  double acc[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) acc[q] = 0.0;
+  const int64_t nIk = cd.nI[k], n3k = 3 * nIk;
+  const double* Zk = Z + cd.zoff[k];
+  const double* Vj = Vc + vcoff[j];
+  for (int64_t ln = 0; ln < nIk; ++ln) {
+    const int64_t n = cd.I_nodes[cd.offI[k] + ln];
+    const int64_t ldj = g.D_loc[(int64_t)j * g.N + n];
+    if (ldj < 0) continue;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (e < mk * mj) {
+        const int b = e / mj, a = e % mj;
+        double s = 0.0;
+        for (int c = 0; c < 3; ++c)
+          s += Zk[(int64_t)b * n3k + 3 * ln + c] * Vj[(3 * ldj + c) * mj + a];
+        acc[q] += s;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    if (e < mk * mj) {
+      const int b = e / mj, a = e % mj;
+      K0[(int64_t)(cd.coff[k] + b) * n0 + cd.coff[j] + a] = acc[q];
+    }
+  }
+}
+
+// symmetrise K_0 into full band storage (B = n0 - 1, ld = n0)
+__global__ void k_coarse_fill(int64_t n0, const double* K0, double* band) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n0 * n0) return;
+  const int64_t r = e / n0, c = e % n0;
+  if (c > r) return;
+  band[r * n0 + (c - r + n0 - 1)] = 0.5 * (K0[r * n0 + c] + K0[c * n0 + r]);
+}
+
+void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
+  Schwarz& sw = c->sw;
+  hipStream_t s = c->stream;
+  const int n_sub = sw.n_sub;
+  const int64_t N = c->n_nodes;
+  const double tau = o->tau > 0 ? o->tau : 0.1;
+  const int nev_max = o->nev_max > 0 ? o->nev_max : 32;
+  std::vector<int> want(n_sub, o->nev > 0 ? o->nev : 0);
+  if (o->nev_per_sub)
+    for (int j = 0; j < n_sub; ++j) want[j] = o->nev_per_sub[j];
+  const bool fixed_count = o->nev > 0 || o->nev_per_sub;
+  int mwant = fixed_count ? 0 : nev_max;
+  for (int j = 0; j < n_sub; ++j) mwant = std::max(mwant, want[j]);
+  GX_REQUIRE(mwant >= 1 && mwant + 2 <= MAXM, "requested modes exceed the eigensolver block");
+  const int m = std::min(MAXM, mwant + 8);
+  const double sigma = fixed_count ? 1e-4 * tau : 1e-3 * tau;
+  const double tol = o->eig_tol > 0 ? o->eig_tol : 1e-10;
+  const int maxit = o->eig_maxit > 0 ? o->eig_maxit : 200;
+  for (int j = 0; j < n_sub; ++j)
+    GX_REQUIRE(3 * sw.nD[j] >= m, "subdomain too small for the eigensolver block");
+  Timer te(s);
+  GeneoDev g{c->conn.p, c->ne_ptr.p, c->ne_idx.p, c->Ke.p, c->fixed.p, sw.elem_mask.p, sw.W,
+             N, sw.D_nodes.p, sw.d_offD.p, sw.d_nD.p, sw.D_loc.p, sw.I_loc.p, sw.node_cnt.p};
+  int64_t maxD = 0;
+  for (int j = 0; j < n_sub; ++j) maxD = std::max(maxD, sw.nD[j]);
+  // Neumann pencil M = A^N + sigma B in band storage, factored
+  BandSet Mb;
+  {
+    std::vector<int64_t> n3(n_sub), B =
+        list_bandwidth(c, sw.D_nodes.p, sw.d_offD.p, sw.d_nD.p, sw.D_loc.p, sw.nD);
+    for (int j = 0; j < n_sub; ++j) n3[j] = 3 * sw.nD[j];
+    band_layout(Mb, n3, B, false, s);
+    BandView bv{Mb.d_B.p, Mb.d_ld.p, Mb.d_off.p};
+    hipLaunchKernelGGL(k_neumann_fill, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g, sigma,
+                       bv, Mb.v64.p);
+    GX_HIP(hipGetLastError());
+    band_factor(Mb, s);
+  }
+  // eigen work blocks, row-major (3 nD_j x m) per subdomain
+  std::vector<int64_t> voff(n_sub + 1, 0);
+  for (int j = 0; j < n_sub; ++j) voff[j + 1] = voff[j] + 3 * sw.nD[j] * m;
+  const int64_t tot = voff[n_sub];
+  DevBuf<int64_t> d_voff(n_sub + 1);
+  to_dev(d_voff.p, voff.data(), n_sub + 1, s);
+  DevBuf<double> X(tot), BX(tot), Y(tot), BY(tot), T(tot);
+  DevBuf<int32_t> active(n_sub);
+  std::vector<int32_t> act(n_sub, 1);
+  to_dev(active.p, act.data(), n_sub, s);
+  int64_t nch_max = 0;
+  for (int j = 0; j < n_sub; ++j) nch_max = std::max(nch_max, (3 * sw.nD[j] + GCH - 1) / GCH);
+  DevBuf<double> gpart((size_t)n_sub * nch_max * 2 * MAXM * MAXM), G((size_t)n_sub * 2 * MAXM * MAXM);
+  DevBuf<double> Cm((size_t)n_sub * MAXM * MAXM), theta((size_t)n_sub * MAXM);
+  DevBuf<double> rpart((size_t)n_sub * nch_max * 2 * MAXM), rsum((size_t)n_sub * 2 * MAXM);
+  DevBuf<int> err(1);
+  zero(err, s);
+  const dim3 growD((unsigned)maxD, n_sub);
+  const dim3 gvec(nblocks(3 * maxD * m, 256), n_sub);
+  const dim3 grows(nblocks(3 * maxD, 4), n_sub);
+  const dim3 gch((unsigned)nch_max, n_sub);
+  hipLaunchKernelGGL(k_rand_init, gvec, dim3(256), 0, s, g, m, d_voff.p, X.p);
+  hipLaunchKernelGGL(k_bmul, growD, dim3(64), 0, s, g, m, d_voff.p, active.p, X.p, BX.p);
+  std::vector<double> h_theta((size_t)n_sub * MAXM), h_res((size_t)n_sub * 2 * MAXM);
+  std::vector<double> lam_final((size_t)n_sub * MAXM, 0.0);
+  int it = 0;
+  int n_active = n_sub;
+  for (; it < maxit && n_active > 0; ++it) {
+    hipLaunchKernelGGL(k_copy_active, gvec, dim3(256), 0, s, 3 * maxD * m, sw.d_nD.p, m,
+                       d_voff.p, active.p, BX.p, Y.p);
+    band_solve(Mb, d_voff.p, Y.p, nullptr, s, m, active.p);
+    hipLaunchKernelGGL(k_bmul, growD, dim3(64), 0, s, g, m, d_voff.p, active.p, Y.p, BY.p);
+    hipLaunchKernelGGL(k_gram, gch, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p, active.p, Y.p,
+                       BX.p, BY.p, nch_max, gpart.p);
+    hipLaunchKernelGGL(k_gram_sum, dim3(nblocks(2 * MAXM * MAXM, 256), n_sub), dim3(256), 0,
+                       s, sw.d_nD.p, m, active.p, nch_max, gpart.p, G.p);
+    hipLaunchKernelGGL(k_rayleigh_ritz, dim3(n_sub), dim3(256), 0, s, m, active.p, G.p, Cm.p,
+                       theta.p, err.p);
+    hipLaunchKernelGGL(k_rotate, grows, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p, active.p,
+                       Cm.p, Y.p, T.p);             // new X
+    hipLaunchKernelGGL(k_rotate, grows, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p, active.p,
+                       Cm.p, BX.p, Y.p);            // M X_new
+    hipLaunchKernelGGL(k_rotate, grows, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p, active.p,
+                       Cm.p, BY.p, BX.p);           // B X_new
+    hipLaunchKernelGGL(k_resid, gch, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p, active.p,
+                       theta.p, Y.p, BX.p, nch_max, rpart.p);
+    hipLaunchKernelGGL(k_resid_sum, dim3(n_sub), dim3(2 * MAXM), 0, s, sw.d_nD.p, active.p,
+                       nch_max, rpart.p, rsum.p);
+    // new X into X for the active subdomains
+    hipLaunchKernelGGL(k_copy_active, gvec, dim3(256), 0, s, 3 * maxD * m, sw.d_nD.p, m,
+                       d_voff.p, active.p, T.p, X.p);
+    GX_HIP(hipGetLastError());
+    to_host(h_theta.data(), theta.p, h_theta.size(), s);
+    to_host(h_res.data(), rsum.p, h_res.size(), s);
+    int herr = 0;
+    to_host(&herr, err.p, 1, s);
+    if (herr) throw Error(GX_ENOCONV, "GenEO eigensolver: basis lost rank");
+    for (int j = 0; j < n_sub; ++j) {
+      if (!act[j]) continue;
+      // wanted pairs: the fixed count, or those below 1.5 tau (the test margin)
+      int w = 0;
+      if (fixed_count) {
+        w = want[j];
+      } else {
+        while (w < m - 2 && h_theta[j * MAXM + w] - sigma < 1.5 * tau) ++w;
+        w = std::min(w + 1, m - 2);               // one pair beyond the margin as well
+      }
+      bool ok = true;
+      for (int a = 0; a < w; ++a) {
+        const double r = std::sqrt(h_res[j * 2 * MAXM + a]);
+        const double nm = std::sqrt(h_res[j * 2 * MAXM + MAXM + a]);
+        if (!(r <= tol * nm)) ok = false;
+      }
+      if (ok) {
+        act[j] = 0;
+        --n_active;
+        for (int a = 0; a < m; ++a) lam_final[j * MAXM + a] = h_theta[j * MAXM + a] - sigma;
+      }
+    }
+    to_dev(active.p, act.data(), n_sub, s);
+  }
+  if (n_active > 0)
+    throw Error(GX_ENOCONV, "GenEO eigensolver did not converge in " + std::to_string(maxit) +
+                                " iterations");
+  // selection
+  sw.nev.assign(n_sub, 0);
+  sw.lam.assign(n_sub, {});
+  for (int j = 0; j < n_sub; ++j) {
+    int k = 0;
+    if (fixed_count)
+      k = want[j];
+    else
+      while (k < nev_max && k < m - 2 && lam_final[j * MAXM + k] < tau) ++k;
+    sw.nev[j] = k;
+    for (int a = 0; a < k; ++a) sw.lam[j].push_back(lam_final[j * MAXM + a]);
+  }
+  c->phase_ms[3] = te.ms();
+  c->eig_iters = it;
+  Timer tc(s);
+  // coarse basis Z_j (column-major on I_j) and K_0
+  sw.c_off.assign(n_sub + 1, 0);
+  sw.z_off.assign(n_sub + 1, 0);
+  for (int j = 0; j < n_sub; ++j) {
+    sw.c_off[j + 1] = sw.c_off[j] + sw.nev[j];
+    sw.z_off[j + 1] = sw.z_off[j] + 3 * sw.nI[j] * sw.nev[j];
+  }
+  sw.n0 = sw.c_off[n_sub];
+  if (sw.n0 == 0) {
+    sw.two_level = false;
+    c->phase_ms[4] = tc.ms();
+    return;
+  }
+  GX_REQUIRE(sw.n0 + 64 <= 4096, "coarse space too large for the coarse solve window");
+  sw.d_nev.alloc(n_sub);
+  sw.d_c_off.alloc(n_sub + 1);
+  sw.d_z_off.alloc(n_sub + 1);
+  to_dev(sw.d_nev.p, sw.nev.data(), n_sub, s);
+  to_dev(sw.d_c_off.p, sw.c_off.data(), n_sub + 1, s);
+  to_dev(sw.d_z_off.p, sw.z_off.data(), n_sub + 1, s);
+  sw.Z.alloc(std::max<int64_t>(sw.z_off[n_sub], 1));
+  CoarseDev cd{sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p, sw.d_z_off.p, sw.d_nev.p, sw.d_c_off.p};
+  int64_t maxI = 0;
+  for (int j = 0; j < n_sub; ++j) maxI = std::max(maxI, sw.nI[j]);
+  hipLaunchKernelGGL(k_build_Z, dim3(nblocks(3 * maxI, 256), n_sub), dim3(256), 0, s, g, cd, m,
+                     d_voff.p, X.p, sw.Z.p);
+  std::vector<int64_t> vco(n_sub + 1, 0);
+  for (int j = 0; j < n_sub; ++j) vco[j + 1] = vco[j] + 3 * sw.nD[j] * sw.nev[j];
+  DevBuf<int64_t> d_vco(n_sub + 1);
+  to_dev(d_vco.p, vco.data(), n_sub + 1, s);
+  DevBuf<double> Vc(std::max<int64_t>(vco[n_sub], 1));
+  hipLaunchKernelGGL(k_coarse_V, growD, dim3(64), 0, s, g, cd, c->row_ptr.p, c->col.p,
+                     c->val.p, sw.Z.p, d_vco.p, Vc.p);
+  DevBuf<int32_t> adj((size_t)n_sub * n_sub);
+  zero(adj, s);
+  hipLaunchKernelGGL(k_pair_adjacency, dim3(nblocks(N, 256)), dim3(256), 0, s, sw.node_and.p,
+                     sw.node_or.p, sw.W, N, n_sub, adj.p);
+  const int64_t n0 = sw.n0;
+  DevBuf<double> K0(n0 * n0);
+  zero(K0, s);
+  hipLaunchKernelGGL(k_coarse_pair, dim3(n_sub, n_sub), dim3(256), 0, s, g, cd, n_sub, adj.p,
+                     sw.Z.p, Vc.p, d_vco.p, n0, K0.p);
+  band_layout(sw.C, {n0}, {n0 - 1}, false, s);
+  zero(sw.C.v64, s);
+  hipLaunchKernelGGL(k_coarse_fill, dim3(nblocks(n0 * n0, 256)), dim3(256), 0, s, n0, K0.p,
+                     sw.C.v64.p);
+  GX_HIP(hipGetLastError());
+  band_factor(sw.C, s);
+  const int64_t zero64 = 0;
+  sw.d_c_xoff.alloc(1);
+  to_dev(sw.d_c_xoff.p, &zero64, 1, s);
+  const int64_t nchr = (3 * maxI + 1023) / 1024;
+  sw.y0.alloc(n0);
+  sw.y0part.alloc(n0 * nchr);
+  GX_HIP(hipStreamSynchronize(s));
+  c->phase_ms[4] = tc.ms();
+}
+
+}  // namespace gx
 
 using namespace gx;
 
@@ -15,17 +790,20 @@ gx_status gx_geneo_setup(gx_ctx* c, const gx_geneo_opts* o, int32_t* nev_out,
   GX_REQUIRE(o->n_sub >= 1 && o->n_sub <= 4096, "n_sub out of range");
   GX_REQUIRE(o->overlap >= 1 && o->overlap <= 16, "overlap must be in [1, 16]");
   GX_REQUIRE(o->precision == GX_FP64 || o->precision == GX_MIXED, "bad precision");
+  GX_REQUIRE(o->nev_max <= 32, "nev_max must be <= 32");
   c->setup_done = false;
   c->sw = Schwarz();
   Timer t1(c->stream);
   dd_build(c, o->elem_part, o->n_sub, o->overlap);
   c->phase_ms[1] = t1.ms();
+  c->phase_ms[3] = c->phase_ms[4] = 0;
+  // the Neumann factors of the eigensolver are released before the interior factors are
+  // built, so the two never occupy device memory together
+  c->sw.two_level = o->coarse != 0;
+  if (c->sw.two_level) geneo_coarse(c, o);
   Timer t2(c->stream);
   interior_factors(c, o->precision);
   c->phase_ms[2] = t2.ms();
-  c->phase_ms[3] = c->phase_ms[4] = 0;
-  c->sw.two_level = o->coarse != 0;
-  if (c->sw.two_level) geneo_coarse(c, o);
   if (nev_out)
     for (int j = 0; j < o->n_sub; ++j) nev_out[j] = c->sw.two_level ? c->sw.nev[j] : 0;
   if (n0_out) *n0_out = c->sw.two_level ? c->sw.n0 : 0;
@@ -53,10 +831,3 @@ gx_status gx_geneo_eigenvalues(gx_ctx* c, int32_t j, double* lam) {
 }
 
 }  // extern "C"
-
-namespace gx {
-void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
-  (void)o;
-  throw Error(GX_EINVAL, "coarse space not available in this build");
-}
-}  // namespace gx

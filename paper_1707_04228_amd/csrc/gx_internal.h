@@ -176,6 +176,7 @@ struct gx_ctx {
   // PCG work vectors
   gx::DevBuf<double> r, z, p, q, bm, red;
   int32_t pcg_iters = 0;
+  int32_t eig_iters = 0;
   double phase_ms[8] = {0};
 };
 
@@ -188,10 +189,14 @@ void precond_apply(gx_ctx* c, const double* r, double* z);
 void dd_build(gx_ctx* c, const int32_t* part, int n_sub, int overlap);
 void interior_factors(gx_ctx* c, int precision);
 void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o);
+std::vector<int64_t> list_bandwidth(gx_ctx* c, const int32_t* list, const int64_t* d_off,
+                                    const int64_t* d_cnt, const int32_t* loc,
+                                    const std::vector<int64_t>& cnt);
 void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<int64_t>& B,
                  bool fp32, hipStream_t st);
 void band_factor(BandSet& bs, hipStream_t st);
-void band_solve(BandSet& bs, const int64_t* d_xoff, double* x64, float* x32, hipStream_t st);
+void band_solve(BandSet& bs, const int64_t* d_xoff, double* x64, float* x32, hipStream_t st,
+                int ncol = 1, const int32_t* active = nullptr);
 struct Timer {
   hipStream_t s;
   std::chrono::steady_clock::time_point t0;

@@ -89,6 +89,11 @@ __global__ void k_zero_fixed(int64_t n, const uint8_t* fixed, double* x) {
   if (i < n && fixed[i]) x[i] = 0.0;
 }
 
+__global__ void k_fill_ones(int64_t n, const uint8_t* fixed, double* x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = fixed[i] ? 0.0 : 1.0 + 1e-3 * (double)(i % 7);
+}
+
 static void dot(gx_ctx* c, const double* a, const double* b, int dst, int mode) {
   const int64_t n = 3 * c->n_nodes;
   hipLaunchKernelGGL(k_dot, dim3(RG), dim3(RB), 0, c->stream, n, a, b, c->red.p + S_N);
@@ -223,6 +228,53 @@ gx_status gx_pcg_solve(gx_ctx* c, const double* b, double* x, double rtol, int32
   c->phase_ms[7] = t_spmv;
   c->pcg_iters = it;
   return st;
+  GX_API_END(c)
+}
+
+gx_status gx_kernel_time(gx_ctx* c, int32_t which, int32_t reps, double* avg_ms,
+                         double* bytes) {
+  GX_API_BEGIN(c)
+  GX_REQUIRE(reps >= 1 && which >= 0 && which <= 3, "bad kernel id or repetition count");
+  if (!c->assembled) throw Error(GX_ESTATE, "matrix not assembled");
+  if (which >= 1 && !c->setup_done) throw Error(GX_ESTATE, "preconditioner not set up");
+  if (which == 3 && !(c->sw.two_level && c->sw.n0 > 0)) throw Error(GX_ESTATE, "no coarse space");
+  hipStream_t s = c->stream;
+  const int64_t n = 3 * c->n_nodes;
+  if (c->r.n != (size_t)n) {
+    c->r.alloc(n);
+    c->z.alloc(n);
+    c->p.alloc(n);
+    c->q.alloc(n);
+    c->bm.alloc(n);
+    c->red.alloc(S_N + RG);
+  }
+  hipLaunchKernelGGL(k_fill_ones, dim3(nblocks(n, 256)), dim3(256), 0, s, n, c->fixed.p,
+                     c->r.p);
+  GX_HIP(hipMemcpyAsync(c->p.p, c->r.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  EventPair ev;
+  double tot = 0.0, b = 0.0;
+  Schwarz& sw = c->sw;
+  for (int k = 0; k < reps; ++k) {
+    if (which == 1) precond_apply(c, c->r.p, c->z.p);   // refills the local right-hand sides
+    GX_HIP(hipEventRecord(ev.a, s));
+    if (which == 0) spmv(c, c->p.p, c->q.p);
+    if (which == 1) band_solve(sw.A, sw.d_xoff.p, sw.wr64.p, sw.wr32.p, s);
+    if (which == 2) precond_apply(c, c->r.p, c->z.p);
+    if (which == 3) band_solve(sw.C, sw.d_c_xoff.p, sw.y0.p, nullptr, s);
+    GX_HIP(hipEventRecord(ev.b, s));
+    GX_HIP(hipGetLastError());
+    GX_HIP(hipEventSynchronize(ev.b));
+    tot += ev.ms();
+  }
+  if (which == 0) b = (double)c->nnzb * (72 + 4) + (double)c->n_nodes * (4 + 24 + 24);
+  if (which == 1 || which == 3) {
+    const BandSet& bs = which == 1 ? sw.A : sw.C;
+    const double w = bs.fp32 ? 4.0 : 8.0;
+    for (int j = 0; j < bs.n_mat; ++j)
+      b += 2.0 * w * (double)bs.n[j] * (double)(bs.B[j] + 1) + 4.0 * w * (double)bs.n[j];
+  }
+  if (avg_ms) *avg_ms = tot / reps;
+  if (bytes) *bytes = b;
   GX_API_END(c)
 }
 

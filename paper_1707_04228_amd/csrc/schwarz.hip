@@ -259,6 +259,26 @@ __global__ void k_diag(const int32_t* rp, const int32_t* col, const double* val,
       for (int a = 0; a < 3; ++a) dg[3 * n + a] = val[(int64_t)k * 9 + 4 * a];
 }
 
+// Half bandwidth (in DOFs) of K restricted to each subdomain's node list, in list order.
+std::vector<int64_t> list_bandwidth(gx_ctx* c, const int32_t* list, const int64_t* d_off,
+                                    const int64_t* d_cnt, const int32_t* loc,
+                                    const std::vector<int64_t>& cnt) {
+  hipStream_t s = c->stream;
+  const int n_sub = (int)cnt.size();
+  int64_t mx = 0;
+  for (int64_t v : cnt) mx = std::max(mx, v);
+  DevBuf<int32_t> bw(n_sub);
+  zero(bw, s);
+  hipLaunchKernelGGL(k_band_width, dim3(nblocks(mx, 256), n_sub), dim3(256), 0, s,
+                     c->row_ptr.p, c->col.p, list, d_off, d_cnt, loc, c->n_nodes, bw.p);
+  GX_HIP(hipGetLastError());
+  std::vector<int32_t> hb(n_sub);
+  to_host(hb.data(), bw.p, n_sub, s);
+  std::vector<int64_t> B(n_sub);
+  for (int j = 0; j < n_sub; ++j) B[j] = 3 * (int64_t)hb[j] + 2;
+  return B;
+}
+
 void interior_factors(gx_ctx* c, int precision) {
   Schwarz& sw = c->sw;
   hipStream_t s = c->stream;
@@ -266,19 +286,9 @@ void interior_factors(gx_ctx* c, int precision) {
   const int n_sub = sw.n_sub;
   int64_t maxI = 0;
   for (int j = 0; j < n_sub; ++j) maxI = std::max(maxI, sw.nI[j]);
-  DevBuf<int32_t> bw(n_sub);
-  zero(bw, s);
-  hipLaunchKernelGGL(k_band_width, dim3(nblocks(maxI, 256), n_sub), dim3(256), 0, s,
-                     c->row_ptr.p, c->col.p, sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p,
-                     sw.I_loc.p, N, bw.p);
-  GX_HIP(hipGetLastError());
-  std::vector<int32_t> hb(n_sub);
-  to_host(hb.data(), bw.p, n_sub, s);
-  std::vector<int64_t> n(n_sub), B(n_sub);
-  for (int j = 0; j < n_sub; ++j) {
-    n[j] = 3 * sw.nI[j];
-    B[j] = 3 * (int64_t)hb[j] + 2;
-  }
+  std::vector<int64_t> n(n_sub), B =
+      list_bandwidth(c, sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, sw.nI);
+  for (int j = 0; j < n_sub; ++j) n[j] = 3 * sw.nI[j];
   sw.precision = precision;
   const bool fp32 = precision == GX_MIXED;
   band_layout(sw.A, n, B, fp32, s);

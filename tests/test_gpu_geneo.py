@@ -1,0 +1,57 @@
+"""GPU parity of the GenEO coarse space and the two-level preconditioner (section 2.3).
+
+* GenEO eigenvalues of every subdomain equal the oracle's (ARPACK shift-invert on the same
+  pencil) to 1e-8 relative (+1e-10 absolute for the zero rigid-body modes);
+* the number of selected modes (fixed count, or the threshold tau) and the coarse
+  dimension equal the oracle's;
+* P r equals the oracle's two-level P r to 1e-8 relative (the coarse space is a span: two
+  correct eigensolvers agree on it up to their eigen-residual over the spectral gap);
+* two-level PCG: iteration count +-1 against the oracle, and the checks of the one-level
+  test on the solution.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_helpers import rel_err
+from test_gpu_schwarz import _setup, check_solution
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gx():
+    import paper_1707_04228_amd as gx
+    return gx
+
+
+def _strip():
+    cfg = workloads.small_flat(nx=16, ny=2, length=16.0, width=2.0)
+    cfg["name"] = "strip_16x2_tau"
+    cfg["solver"].update(px=4, py=1, overlap=1, nev=0, tau=0.1)
+    return cfg
+
+
+TWO_LEVEL = [workloads.cfg0(), _strip(), workloads.small_lsection(nx=12, ny=2)]
+
+
+@pytest.mark.parametrize("cfg", TWO_LEVEL, ids=lambda c: c["name"])
+def test_geneo_two_level(gx, cfg):
+    import torch
+    from oracle import pcg
+    R = pcg.solve(cfg, rtol=1e-8)
+    prob, co = R["prob"], R["coarse"]
+    s, f, part = _setup(gx, cfg, coarse=True)
+    assert list(s.nev) == co.nev
+    assert s.n0 == co.n0
+    for j in range(len(co.nev)):
+        lg, lo = s.eigenvalues(j), co.lams[j]
+        assert np.all(np.abs(lg - lo) <= 1e-8 * np.abs(lo) + 1e-10), (j, lg, lo)
+    rng = np.random.default_rng(12)
+    r = rng.standard_normal(prob.n)
+    z = s.precond(torch.tensor(prob.to_full(r), device="cuda")).cpu().numpy()
+    zo = R["P"].apply(r)
+    assert rel_err(z[prob.free], zo) <= 1e-8
+    out = s.pcg(f, rtol=1e-8, maxit=500, history=True)
+    assert abs(out["iters"] - R["iters"]) <= 1
+    check_solution(s, f, prob, out, R["hist"])
