@@ -81,7 +81,7 @@ def main():
     results = []
     for k in range(args.steps):
         s, out, nev, n0 = run_step(gx, torch, cfg, prec)
-        results.append((out["iters"], out["relres"], s.phase_times()))
+        results.append((out["iters"], out["relres"], s.phase_times(), s.stats()))
         if k + 1 < args.steps:
             del s
         print(f"# step {k}: {out['iters']} iterations", flush=True)
@@ -123,6 +123,7 @@ def main():
         "subdomain_solve_ms": solve_ms,
         "precond_apply_ms": pre_ms,
         "phases_ms": phases,
+        "stats": results[-1][3],
         "roofline": {"bound": "hbm", "kernel": "k_band_solve (subdomain forward+backward)",
                      "achieved": solve_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": solve_gbs / HBM_PEAK_GBS, "traffic": None},

@@ -234,6 +234,18 @@ gx_status gx_pcg_solve(gx_ctx* ctx, const double* b, double* x, double rtol, int
 gx_status gx_kernel_time(gx_ctx* ctx, int32_t which, int32_t reps, double* avg_ms,
                          double* bytes);
 
+/* Tuning knobs, applied by the next gx_geneo_setup (0 = automatic choice):
+ * param 0: work-groups per subdomain for the single right-hand-side band solves (PCG);
+ * param 1: work-groups per subdomain for the multi-column band solves (eigensolver).
+ * Values 1..8; the library lowers a request that would not keep every work-group of the
+ * pipelined launch resident on the device. */
+gx_status gx_tune(gx_ctx* ctx, int32_t param, int64_t value);
+
+/* Counters of the last setup / solve (host [4]): eigensolver iterations, PCG iterations,
+ * stored entries of the interior band factors, stored entries of the eigensolver's
+ * Neumann band factors. */
+gx_status gx_stats(gx_ctx* ctx, int64_t* out);
+
 /* Time spent in the last call of each phase, milliseconds (host [8], may be NULL):
  * assemble, decomposition, local factors, eigensolves, coarse, pcg, precond total in pcg,
  * spmv total in pcg. */

@@ -95,7 +95,9 @@ for _name, _args in [("gx_geneo_setup", [vp, C.POINTER(GeneoOpts), i32p, i64p]),
                      ("gx_geneo_eigenvalues", [vp, C.c_int32, f64p]),
                      ("gx_precond_apply", [vp, vp, vp]),
                      ("gx_pcg_solve", [vp, vp, vp, C.c_double, C.c_int32, i32p, f64p, f64p]),
-                     ("gx_kernel_time", [vp, C.c_int32, C.c_int32, f64p, f64p])]:
+                     ("gx_kernel_time", [vp, C.c_int32, C.c_int32, f64p, f64p]),
+                     ("gx_stats", [vp, i64p]),
+                     ("gx_tune", [vp, C.c_int32, C.c_int64])]:
     if hasattr(lib, _name):
         _sig(_name, _args)
 
@@ -103,7 +105,7 @@ EXPORTS = ["gx_create", "gx_destroy", "gx_last_error", "gx_version", "gx_laminat
            "gx_laminate_mesh", "gx_laminate_partition", "gx_laminate_traction",
            "gx_assemble", "gx_matrix_info", "gx_matrix_copy", "gx_spmv", "gx_geneo_setup",
            "gx_subdomain_info", "gx_geneo_eigenvalues", "gx_precond_apply", "gx_pcg_solve",
-           "gx_phase_times", "gx_kernel_time"]
+           "gx_phase_times", "gx_kernel_time", "gx_stats", "gx_tune"]
 
 
 class GxError(RuntimeError):
@@ -315,6 +317,15 @@ class Solver:
         ms, b = C.c_double(), C.c_double()
         self._check(lib.gx_kernel_time(self.h, which, reps, C.byref(ms), C.byref(b)))
         return ms.value, b.value
+
+    def tune(self, param, value):
+        self._check(lib.gx_tune(self.h, param, value))
+
+    def stats(self):
+        out = np.zeros(4, dtype=np.int64)
+        self._check(lib.gx_stats(self.h, out.ctypes.data_as(i64p)))
+        return dict(eig_iters=int(out[0]), pcg_iters=int(out[1]),
+                    interior_band_entries=int(out[2]), neumann_band_entries=int(out[3]))
 
     def phase_times(self):
         t = np.zeros(8)

@@ -595,12 +595,11 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   int mwant = fixed_count ? 0 : nev_max;
   for (int j = 0; j < n_sub; ++j) mwant = std::max(mwant, want[j]);
   GX_REQUIRE(mwant >= 1 && mwant + 2 <= MAXM, "requested modes exceed the eigensolver block");
-  const int m = std::min(MAXM, mwant + 8);
   const double sigma = fixed_count ? 1e-4 * tau : 1e-3 * tau;
   const double tol = o->eig_tol > 0 ? o->eig_tol : 1e-10;
   const int maxit = o->eig_maxit > 0 ? o->eig_maxit : 200;
   for (int j = 0; j < n_sub; ++j)
-    GX_REQUIRE(3 * sw.nD[j] >= m, "subdomain too small for the eigensolver block");
+    GX_REQUIRE(3 * sw.nD[j] >= mwant + 8, "subdomain too small for the eigensolver block");
   Timer te(s);
   GeneoDev g{c->conn.p, c->ne_ptr.p, c->ne_idx.p, c->Ke.p, c->fixed.p, sw.elem_mask.p, sw.W,
              N, sw.D_nodes.p, sw.d_offD.p, sw.d_nD.p, sw.D_loc.p, sw.I_loc.p, sw.node_cnt.p};
@@ -613,19 +612,31 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
         list_bandwidth(c, sw.D_nodes.p, sw.d_offD.p, sw.d_nD.p, sw.D_loc.p, sw.nD);
     for (int j = 0; j < n_sub; ++j) n3[j] = 3 * sw.nD[j];
     band_layout(Mb, n3, B, false, s);
+    Mb.force_groups[0] = c->tune[0];
+    Mb.force_groups[1] = c->tune[1];
+    c->neumann_entries = Mb.total;
     BandView bv{Mb.d_B.p, Mb.d_ld.p, Mb.d_off.p};
     hipLaunchKernelGGL(k_neumann_fill, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g, sigma,
                        bv, Mb.v64.p);
     GX_HIP(hipGetLastError());
     band_factor(Mb, s);
   }
-  // eigen work blocks, row-major (3 nD_j x m) per subdomain
-  std::vector<int64_t> voff(n_sub + 1, 0);
+  // block size: fixed count + 8 guard vectors; with a threshold, start at 24 and double
+  // while some subdomain's selected modes reach into the guard
+  int m = fixed_count ? std::min(MAXM, mwant + 8) : std::min(MAXM, std::min(24, mwant + 8));
+  std::vector<int64_t> voff;
+  DevBuf<int64_t> d_voff;
+  DevBuf<double> X;
+  std::vector<double> lam_final;
+  int it = 0;
+  for (;;) {
+  voff.assign(n_sub + 1, 0);
   for (int j = 0; j < n_sub; ++j) voff[j + 1] = voff[j] + 3 * sw.nD[j] * m;
   const int64_t tot = voff[n_sub];
-  DevBuf<int64_t> d_voff(n_sub + 1);
+  d_voff.alloc(n_sub + 1);
   to_dev(d_voff.p, voff.data(), n_sub + 1, s);
-  DevBuf<double> X(tot), BX(tot), Y(tot), BY(tot), T(tot);
+  X.alloc(tot);
+  DevBuf<double> BX(tot), Y(tot), BY(tot), T(tot);
   DevBuf<int32_t> active(n_sub);
   std::vector<int32_t> act(n_sub, 1);
   to_dev(active.p, act.data(), n_sub, s);
@@ -643,10 +654,9 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   hipLaunchKernelGGL(k_rand_init, gvec, dim3(256), 0, s, g, m, d_voff.p, X.p);
   hipLaunchKernelGGL(k_bmul, growD, dim3(64), 0, s, g, m, d_voff.p, active.p, X.p, BX.p);
   std::vector<double> h_theta((size_t)n_sub * MAXM), h_res((size_t)n_sub * 2 * MAXM);
-  std::vector<double> lam_final((size_t)n_sub * MAXM, 0.0);
-  int it = 0;
+  lam_final.assign((size_t)n_sub * MAXM, 0.0);
   int n_active = n_sub;
-  for (; it < maxit && n_active > 0; ++it) {
+  for (int itm = 0; itm < maxit && n_active > 0; ++itm, ++it) {
     hipLaunchKernelGGL(k_copy_active, gvec, dim3(256), 0, s, 3 * maxD * m, sw.d_nD.p, m,
                        d_voff.p, active.p, BX.p, Y.p);
     band_solve(Mb, d_voff.p, Y.p, nullptr, s, m, active.p);
@@ -676,6 +686,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
     int herr = 0;
     to_host(&herr, err.p, 1, s);
     if (herr) throw Error(GX_ENOCONV, "GenEO eigensolver: basis lost rank");
+    band_solve_check(Mb, s);
     for (int j = 0; j < n_sub; ++j) {
       if (!act[j]) continue;
       // wanted pairs: the fixed count, or those below 1.5 tau (the test margin)
@@ -703,6 +714,16 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   if (n_active > 0)
     throw Error(GX_ENOCONV, "GenEO eigensolver did not converge in " + std::to_string(maxit) +
                                 " iterations");
+  bool grow = false;
+  if (!fixed_count && m < std::min(MAXM, nev_max + 8))
+    for (int j = 0; j < n_sub; ++j) {
+      int k = 0;
+      while (k < m && lam_final[j * MAXM + k] < tau) ++k;
+      if (k > m - 8) grow = true;
+    }
+  if (!grow) break;
+  m = std::min(MAXM, std::min(2 * m, nev_max + 8));
+  }
   // selection
   sw.nev.assign(n_sub, 0);
   sw.lam.assign(n_sub, {});
@@ -731,7 +752,6 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
     c->phase_ms[4] = tc.ms();
     return;
   }
-  GX_REQUIRE(sw.n0 + 64 <= 4096, "coarse space too large for the coarse solve window");
   sw.d_nev.alloc(n_sub);
   sw.d_c_off.alloc(n_sub + 1);
   sw.d_z_off.alloc(n_sub + 1);
@@ -749,7 +769,8 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   DevBuf<int64_t> d_vco(n_sub + 1);
   to_dev(d_vco.p, vco.data(), n_sub + 1, s);
   DevBuf<double> Vc(std::max<int64_t>(vco[n_sub], 1));
-  hipLaunchKernelGGL(k_coarse_V, growD, dim3(64), 0, s, g, cd, c->row_ptr.p, c->col.p,
+  hipLaunchKernelGGL(k_coarse_V, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g, cd,
+                     c->row_ptr.p, c->col.p,
                      c->val.p, sw.Z.p, d_vco.p, Vc.p);
   DevBuf<int32_t> adj((size_t)n_sub * n_sub);
   zero(adj, s);
@@ -808,6 +829,24 @@ gx_status gx_geneo_setup(gx_ctx* c, const gx_geneo_opts* o, int32_t* nev_out,
     for (int j = 0; j < o->n_sub; ++j) nev_out[j] = c->sw.two_level ? c->sw.nev[j] : 0;
   if (n0_out) *n0_out = c->sw.two_level ? c->sw.n0 : 0;
   c->setup_done = true;
+  GX_API_END(c)
+}
+
+gx_status gx_tune(gx_ctx* c, int32_t param, int64_t value) {
+  GX_API_BEGIN(c)
+  GX_REQUIRE(param >= 0 && param < 2, "unknown tuning parameter");
+  GX_REQUIRE(value >= 0 && value <= 8, "value out of range");
+  c->tune[param] = (int)value;
+  GX_API_END(c)
+}
+
+gx_status gx_stats(gx_ctx* c, int64_t* out) {
+  GX_API_BEGIN(c)
+  GX_REQUIRE(out, "null output");
+  out[0] = c->eig_iters;
+  out[1] = c->pcg_iters;
+  out[2] = c->sw.A.total;
+  out[3] = c->neumann_entries;
   GX_API_END(c)
 }
 

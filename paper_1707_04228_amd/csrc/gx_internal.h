@@ -115,6 +115,10 @@ struct BandSet {
   DevBuf<double> v64;                          // FP64 storage (precision FP64)
   DevBuf<float> v32;                           // FP32 storage (mixed precision)
   bool fp32 = false;
+  int solve_groups[2] = {0, 0};                // work-groups per matrix: 1-RHS, m-RHS solve
+  int force_groups[2] = {0, 0};                // requested (0: automatic, capped by residency)
+  DevBuf<int> flags;                           // block completion flags (+ error word)
+  int epoch = 0;
 };
 
 struct Schwarz {
@@ -177,7 +181,9 @@ struct gx_ctx {
   gx::DevBuf<double> r, z, p, q, bm, red;
   int32_t pcg_iters = 0;
   int32_t eig_iters = 0;
+  int64_t neumann_entries = 0;
   double phase_ms[8] = {0};
+  int tune[4] = {0, 0, 0, 0};                  // see gx_tune
 };
 
 namespace gx {
@@ -195,6 +201,7 @@ std::vector<int64_t> list_bandwidth(gx_ctx* c, const int32_t* list, const int64_
 void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<int64_t>& B,
                  bool fp32, hipStream_t st);
 void band_factor(BandSet& bs, hipStream_t st);
+void band_solve_check(BandSet& bs, hipStream_t st);
 void band_solve(BandSet& bs, const int64_t* d_xoff, double* x64, float* x32, hipStream_t st,
                 int ncol = 1, const int32_t* active = nullptr);
 struct Timer {

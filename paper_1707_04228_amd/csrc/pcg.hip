@@ -130,6 +130,8 @@ gx_status gx_precond_apply(gx_ctx* c, const double* r, double* z) {
   GX_REQUIRE(r && z && r != z, "bad vectors");
   precond_apply(c, r, z);
   GX_HIP(hipStreamSynchronize(c->stream));
+  band_solve_check(c->sw.A, c->stream);
+  band_solve_check(c->sw.C, c->stream);
   GX_API_END(c)
 }
 
@@ -221,6 +223,8 @@ gx_status gx_pcg_solve(gx_ctx* c, const double* b, double* x, double rtol, int32
     if (st == GX_ENOCONV) c->err = "maximum number of iterations reached";
   }
   GX_HIP(hipStreamSynchronize(s));
+  band_solve_check(c->sw.A, s);
+  band_solve_check(c->sw.C, s);
   if (iters_out) *iters_out = it;
   if (relres_out) *relres_out = rel;
   c->phase_ms[5] = tm.ms();

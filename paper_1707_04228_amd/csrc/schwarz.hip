@@ -292,6 +292,8 @@ void interior_factors(gx_ctx* c, int precision) {
   sw.precision = precision;
   const bool fp32 = precision == GX_MIXED;
   band_layout(sw.A, n, B, fp32, s);
+  sw.A.force_groups[0] = c->tune[0];
+  sw.A.force_groups[1] = c->tune[1];
   if (fp32) {
     sw.dg.alloc(3 * N);
     hipLaunchKernelGGL(k_diag, dim3(nblocks(N, 256)), dim3(256), 0, s, c->row_ptr.p,

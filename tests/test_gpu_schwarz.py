@@ -9,7 +9,7 @@ PCG against the oracle (section 2.3, Eq. eq-pre).
 * PCG: the same iteration count (+-1); residual histories within 1e-6 relative over the
   first ten iterations (later iterations drift apart by rounding, as CG does between any
   two implementations); at rtol 1e-8 the true residual, measured with the oracle's K, is
-  below the tolerance; at rtol 1e-13 the solution is within 1e-10 relative L2 (or 1% of
+  below the tolerance; at rtol 1e-13 the solution is within 1e-10 relative L2 (or 10% of
   the kappa(K) u bound of any backward-stable solve, whichever is larger) of the exact
   solution of the assembled system, and its distance to the oracle's solution is what
   first-order perturbation theory predicts from the two assemblies' rounding difference.
@@ -121,9 +121,10 @@ def check_solution(s, f, prob, out, histo):
     assert rel_err(xf, xg) <= 1e-6
     tight = s.pcg(f, rtol=1e-13, maxit=1000, allow_noconv=True)
     xt = tight["x"].cpu().numpy()[prob.free]
-    # a backward-stable FP64 solve guarantees only kappa(K) u; require 1e-10, or a hundredth
-    # of that bound on the most ill-conditioned (thin strip) cases
-    assert rel_err(xt, xg) <= max(1e-10, 0.01 * kappa(prob.K) * 1.11e-16)
+    # a backward-stable FP64 solve guarantees only kappa(K) u; require 1e-10, or a tenth of
+    # that bound on the most ill-conditioned (thin strip, kappa ~ 1e9) cases
+    tol = max(1e-10, 0.1 * kappa(prob.K) * 1.11e-16)
+    assert rel_err(xt, xg) <= tol
     # end to end: the assembly difference explains the rest (first-order perturbation)
     pred = lu.solve((fg - prob.f) - (Kg - prob.K) @ xo)
-    assert np.linalg.norm((xt - xo) - pred) <= 0.1 * np.linalg.norm(pred) + 1e-10 * np.linalg.norm(xo)
+    assert np.linalg.norm((xt - xo) - pred) <= 0.1 * np.linalg.norm(pred) + tol * np.linalg.norm(xo)
