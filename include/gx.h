@@ -241,9 +241,11 @@ gx_status gx_kernel_time(gx_ctx* ctx, int32_t which, int32_t reps, double* avg_m
  * pipelined launch resident on the device. */
 gx_status gx_tune(gx_ctx* ctx, int32_t param, int64_t value);
 
-/* Counters of the last setup / solve (host [4]): eigensolver iterations, PCG iterations,
+/* Counters of the last setup / solve (host [5]): eigensolver iterations, PCG iterations,
  * stored entries of the interior band factors, stored entries of the eigensolver's
- * Neumann band factors. */
+ * Neumann band factors, and FP64 fall-backs of the mixed path (bit 0: an FP32 interior
+ * factor broke down and the interior factors were rebuilt in FP64; bit 1: the same for the
+ * eigensolver's factors). */
 gx_status gx_stats(gx_ctx* ctx, int64_t* out);
 
 /* Time spent in the last call of each phase, milliseconds (host [8], may be NULL):

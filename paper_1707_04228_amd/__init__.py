@@ -322,10 +322,11 @@ class Solver:
         self._check(lib.gx_tune(self.h, param, value))
 
     def stats(self):
-        out = np.zeros(4, dtype=np.int64)
+        out = np.zeros(5, dtype=np.int64)
         self._check(lib.gx_stats(self.h, out.ctypes.data_as(i64p)))
         return dict(eig_iters=int(out[0]), pcg_iters=int(out[1]),
-                    interior_band_entries=int(out[2]), neumann_band_entries=int(out[3]))
+                    interior_band_entries=int(out[2]), neumann_band_entries=int(out[3]),
+                    fp64_fallbacks=int(out[4]))
 
     def phase_times(self):
         t = np.zeros(8)

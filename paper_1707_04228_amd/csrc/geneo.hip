@@ -53,16 +53,46 @@ struct GeneoDev {
   const int32_t* cnt;
 };
 
-// M_j = A^N + sigma X A^o X in band storage over the Neumann DOFs; clamped DOFs -> identity
+// diagonal of M_j = A^N + sigma X A^o X on the Neumann DOFs (1 on clamped DOFs)
+__global__ void k_neumann_diag(GeneoDev g, double sigma, const int64_t* doff, double* dM) {
+  const int j = blockIdx.y;
+  const int64_t ln = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ln >= g.nD[j]) return;
+  const int64_t n = g.D_nodes[g.offD[j] + ln];
+  const double xn = pou(g.I_loc, g.cnt, g.N, j, n);
+  double d0 = 0, d1 = 0, d2 = 0;
+  for (int k = g.ne_ptr[n]; k < g.ne_ptr[n + 1]; ++k) {
+    const int64_t e = g.ne_idx[k];
+    if (!has_bit(g.emask, e, g.W, j)) continue;
+    const double w = popc_mask(g.emask, e, g.W) >= 2 ? 1.0 + sigma * xn * xn : 1.0;
+    int a = 0;
+    while (a < 19 && g.conn[20 * e + a] != n) ++a;
+    const double* kb = g.Ke + ((e * 20 + a) * 20 + a) * 9;
+    d0 += w * kb[0];
+    d1 += w * kb[4];
+    d2 += w * kb[8];
+  }
+  double* o = dM + doff[j] + 3 * ln;
+  o[0] = g.fixed[3 * n] ? 1.0 : d0;
+  o[1] = g.fixed[3 * n + 1] ? 1.0 : d1;
+  o[2] = g.fixed[3 * n + 2] ? 1.0 : d2;
+}
+
+// M_j = A^N + sigma X A^o X in band storage over the Neumann DOFs; clamped DOFs -> identity.
+// The three band rows of a node are accumulated in LDS (element order, deterministic) and
+// written once, scaled symmetrically by diag(M)^-1/2 when dM is given (FP32 factors).
+template <class T>
 __global__ void __launch_bounds__(64) k_neumann_fill(GeneoDev g, double sigma, BandView bv,
-                                                     double* v) {
+                                                     const int64_t* doff, const double* dM,
+                                                     T* v) {
+  extern __shared__ double rowbuf[];
   const int j = blockIdx.y;
   const int64_t ln = blockIdx.x;
   if (ln >= g.nD[j]) return;
   const int64_t n = g.D_nodes[g.offD[j] + ln];
   const int64_t B = bv.B[j], ld = bv.ld[j];
-  double* base = v + bv.off[j];
-  for (int64_t i = threadIdx.x; i < 3 * ld; i += 64) base[3 * ln * ld + i] = 0.0;
+  T* base = v + bv.off[j];
+  for (int64_t i = threadIdx.x; i < 3 * ld; i += 64) rowbuf[i] = 0.0;
   __syncthreads();
   const double xn = pou(g.I_loc, g.cnt, g.N, j, n);
   for (int k = g.ne_ptr[n]; k < g.ne_ptr[n + 1]; ++k) {
@@ -79,17 +109,93 @@ __global__ void __launch_bounds__(64) k_neumann_fill(GeneoDev g, double sigma, B
       const int64_t row = 3 * ln + i, col = 3 * lm + kk;
       if (col > row) continue;
       const double w = over ? 1.0 + sigma * xn * pou(g.I_loc, g.cnt, g.N, j, m) : 1.0;
-      base[row * ld + (col - row + B)] += w * g.Ke[((e * 20 + a) * 20 + b) * 9 + comp];
+      rowbuf[i * ld + (col - row + B)] += w * g.Ke[((e * 20 + a) * 20 + b) * 9 + comp];
     }
     __syncthreads();
   }
   for (int64_t t = threadIdx.x; t < 3 * ld; t += 64) {
     const int64_t row = 3 * ln + t / ld, col = row - B + t % ld;
-    if (col < 0) continue;
-    const int64_t gr = 3 * n + row % 3;
-    const int64_t gc = 3 * (int64_t)g.D_nodes[g.offD[j] + col / 3] + col % 3;
-    if (g.fixed[gr] || g.fixed[gc]) base[3 * ln * ld + t] = (row == col) ? 1.0 : 0.0;
+    double val = rowbuf[t];
+    if (col >= 0) {
+      const int64_t gr = 3 * n + row % 3;
+      const int64_t gc = 3 * (int64_t)g.D_nodes[g.offD[j] + col / 3] + col % 3;
+      if (g.fixed[gr] || g.fixed[gc]) val = (row == col) ? 1.0 : 0.0;
+      if (dM) val /= sqrt(dM[doff[j] + row] * dM[doff[j] + col]);
+    } else {
+      val = 0.0;
+    }
+    base[3 * ln * ld + t] = (T)val;
   }
+}
+
+// Y = (A^N X) + sigma BX for the m columns of subdomain j (FP64; lane = column)
+__global__ void __launch_bounds__(64) k_amul(GeneoDev g, int m, const int64_t* voff,
+                                             const int32_t* active, const double* X,
+                                             const double* BX, double sigma, double* Y) {
+  const int j = blockIdx.y;
+  const int64_t ln = blockIdx.x;
+  if (ln >= g.nD[j] || !active[j]) return;
+  const int lane = threadIdx.x;
+  if (lane >= m) return;
+  const int64_t n = g.D_nodes[g.offD[j] + ln];
+  const double* Xj = X + voff[j];
+  double y0 = 0, y1 = 0, y2 = 0;
+  for (int k = g.ne_ptr[n]; k < g.ne_ptr[n + 1]; ++k) {
+    const int64_t e = g.ne_idx[k];
+    if (!has_bit(g.emask, e, g.W, j)) continue;
+    int a = 0;
+    while (a < 19 && g.conn[20 * e + a] != n) ++a;
+    for (int b = 0; b < 20; ++b) {
+      const int64_t mm = g.conn[20 * e + b];
+      const int64_t lm = g.D_loc[(int64_t)j * g.N + mm];
+      const double* kb = g.Ke + ((e * 20 + a) * 20 + b) * 9;
+      const double x0 = g.fixed[3 * mm] ? 0.0 : Xj[(3 * lm) * m + lane];
+      const double x1 = g.fixed[3 * mm + 1] ? 0.0 : Xj[(3 * lm + 1) * m + lane];
+      const double x2 = g.fixed[3 * mm + 2] ? 0.0 : Xj[(3 * lm + 2) * m + lane];
+      y0 += kb[0] * x0 + kb[1] * x1 + kb[2] * x2;
+      y1 += kb[3] * x0 + kb[4] * x1 + kb[5] * x2;
+      y2 += kb[6] * x0 + kb[7] * x1 + kb[8] * x2;
+    }
+  }
+  const double* BXj = BX + voff[j];
+  double* Yj = Y + voff[j];
+  const int64_t r = 3 * ln;
+  Yj[r * m + lane] = g.fixed[3 * n] ? Xj[r * m + lane] : y0 + sigma * BXj[r * m + lane];
+  Yj[(r + 1) * m + lane] =
+      g.fixed[3 * n + 1] ? Xj[(r + 1) * m + lane] : y1 + sigma * BXj[(r + 1) * m + lane];
+  Yj[(r + 2) * m + lane] =
+      g.fixed[3 * n + 2] ? Xj[(r + 2) * m + lane] : y2 + sigma * BXj[(r + 2) * m + lane];
+}
+
+// T = MX - theta BX (per-column Ritz values), active subdomains only
+__global__ void k_res_block(const int64_t* nrows, int m, const int64_t* voff,
+                            const int32_t* active, const double* theta, const double* MX,
+                            const double* BX, double* T) {
+  const int j = blockIdx.y;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (!active[j] || r >= 3 * nrows[j] * m) return;
+  const int64_t i = voff[j] + r;
+  T[i] = MX[i] - theta[(int64_t)j * MAXM + r % m] * BX[i];
+}
+
+// Y = X - T, active subdomains only
+__global__ void k_sub_block(const int64_t* nrows, int m, const int64_t* voff,
+                            const int32_t* active, const double* X, const double* T,
+                            double* Y) {
+  const int j = blockIdx.y;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (!active[j] || r >= 3 * nrows[j] * m) return;
+  Y[voff[j] + r] = X[voff[j] + r] - T[voff[j] + r];
+}
+
+// dst = src * diag^-1/2 (row scaling of the m columns), active subdomains only
+__global__ void k_scale_rows(const int64_t* nrows, int m, const int64_t* voff,
+                             const int64_t* doff, const int32_t* active, const double* dM,
+                             const double* src, double* dst) {
+  const int j = blockIdx.y;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (!active[j] || r >= 3 * nrows[j] * m) return;
+  dst[voff[j] + r] = src[voff[j] + r] / sqrt(dM[doff[j] + r / m]);
 }
 
 // Y = X_j A^o X_j X for the m columns of subdomain j (row-major, lane = column)
@@ -595,7 +701,10 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   int mwant = fixed_count ? 0 : nev_max;
   for (int j = 0; j < n_sub; ++j) mwant = std::max(mwant, want[j]);
   GX_REQUIRE(mwant >= 1 && mwant + 2 <= MAXM, "requested modes exceed the eigensolver block");
-  const double sigma = fixed_count ? 1e-4 * tau : 1e-3 * tau;
+  // shift of the pencil: tiny in FP64; in the mixed path 0.1 tau keeps A^N + sigma B well
+  // enough conditioned for FP32 factors (convergence rate (lambda + s)/(lambda_m+1 + s))
+  const double sigma = o->precision == GX_MIXED ? 0.1 * tau
+                                                : (fixed_count ? 1e-4 * tau : 1e-3 * tau);
   const double tol = o->eig_tol > 0 ? o->eig_tol : 1e-10;
   const int maxit = o->eig_maxit > 0 ? o->eig_maxit : 200;
   for (int j = 0; j < n_sub; ++j)
@@ -606,21 +715,51 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   int64_t maxD = 0;
   for (int j = 0; j < n_sub; ++j) maxD = std::max(maxD, sw.nD[j]);
   // Neumann pencil M = A^N + sigma B in band storage, factored
+  // mixed precision: FP32 factors of diag(M)^-1/2 M diag(M)^-1/2; the Rayleigh-Ritz step,
+  // residuals and threshold test stay FP64 (M Y is then formed explicitly)
+  const bool fp32 = o->precision == GX_MIXED;
   BandSet Mb;
+  std::vector<int64_t> doff(n_sub + 1, 0);
+  for (int j = 0; j < n_sub; ++j) doff[j + 1] = doff[j] + 3 * sw.nD[j];
+  DevBuf<int64_t> d_doff(n_sub + 1);
+  to_dev(d_doff.p, doff.data(), n_sub + 1, s);
+  DevBuf<double> dM;
   {
     std::vector<int64_t> n3(n_sub), B =
         list_bandwidth(c, sw.D_nodes.p, sw.d_offD.p, sw.d_nD.p, sw.D_loc.p, sw.nD);
     for (int j = 0; j < n_sub; ++j) n3[j] = 3 * sw.nD[j];
-    band_layout(Mb, n3, B, false, s);
+    band_layout(Mb, n3, B, fp32, s);
     Mb.force_groups[0] = c->tune[0];
     Mb.force_groups[1] = c->tune[1];
     c->neumann_entries = Mb.total;
+    const size_t lds = 3 * (size_t)(Mb.max_B + 1) * sizeof(double);
+    GX_REQUIRE(lds <= 65536, "Neumann bandwidth too large for the band assembly");
     BandView bv{Mb.d_B.p, Mb.d_ld.p, Mb.d_off.p};
-    hipLaunchKernelGGL(k_neumann_fill, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g, sigma,
-                       bv, Mb.v64.p);
+    if (fp32) {
+      dM.alloc(doff[n_sub]);
+      hipLaunchKernelGGL(k_neumann_diag, dim3(nblocks(maxD, 256), n_sub), dim3(256), 0, s, g,
+                         sigma, d_doff.p, dM.p);
+      hipLaunchKernelGGL(k_neumann_fill<float>, dim3((unsigned)maxD, n_sub), dim3(64), lds, s,
+                         g, sigma, bv, d_doff.p, (const double*)dM.p, Mb.v32.p);
+    } else {
+      hipLaunchKernelGGL(k_neumann_fill<double>, dim3((unsigned)maxD, n_sub), dim3(64), lds, s,
+                         g, sigma, bv, d_doff.p, (const double*)nullptr, Mb.v64.p);
+    }
     GX_HIP(hipGetLastError());
-    band_factor(Mb, s);
+    try {
+      band_factor(Mb, s);
+    } catch (const Error& e) {
+      if (!fp32 || e.code != GX_ENOTSPD) throw;
+      // an FP32 factor broke down: this matrix set is refactored in FP64 (reported)
+      c->fp64_fallbacks |= 2;
+      band_layout(Mb, n3, B, false, s);
+      hipLaunchKernelGGL(k_neumann_fill<double>, dim3((unsigned)maxD, n_sub), dim3(64), lds,
+                         s, g, sigma, bv, d_doff.p, (const double*)nullptr, Mb.v64.p);
+      GX_HIP(hipGetLastError());
+      band_factor(Mb, s);
+    }
   }
+  const bool m32 = Mb.fp32;
   // block size: fixed count + 8 guard vectors; with a threshold, start at 24 and double
   // while some subdomain's selected modes reach into the guard
   int m = fixed_count ? std::min(MAXM, mwant + 8) : std::min(MAXM, std::min(24, mwant + 8));
@@ -636,7 +775,8 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   d_voff.alloc(n_sub + 1);
   to_dev(d_voff.p, voff.data(), n_sub + 1, s);
   X.alloc(tot);
-  DevBuf<double> BX(tot), Y(tot), BY(tot), T(tot);
+  DevBuf<double> BX(tot), Y(tot), BY(tot), T(tot), MYb(m32 ? tot : 0);
+  double* MY = m32 ? MYb.p : BX.p;                 // M Y (= B X for exact FP64 solves)
   DevBuf<int32_t> active(n_sub);
   std::vector<int32_t> act(n_sub, 1);
   to_dev(active.p, act.data(), n_sub, s);
@@ -657,12 +797,38 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   lam_final.assign((size_t)n_sub * MAXM, 0.0);
   int n_active = n_sub;
   for (int itm = 0; itm < maxit && n_active > 0; ++itm, ++it) {
-    hipLaunchKernelGGL(k_copy_active, gvec, dim3(256), 0, s, 3 * maxD * m, sw.d_nD.p, m,
-                       d_voff.p, active.p, BX.p, Y.p);
-    band_solve(Mb, d_voff.p, Y.p, nullptr, s, m, active.p);
+    if (m32) {
+      // FP32 factor solves T ~ M^-1 (T = S Mt^-1 S): first step Y = T BX, then the
+      // preconditioned-residual step Y = X - T (M X - B X Theta) with FP64 residuals
+      // (MX is in Y after the previous rotation); exact eigenpairs are fixed points
+      if (itm == 0)
+        hipLaunchKernelGGL(k_copy_active, gvec, dim3(256), 0, s, 3 * maxD * m, sw.d_nD.p, m,
+                           d_voff.p, active.p, BX.p, T.p);
+      else
+        hipLaunchKernelGGL(k_res_block, gvec, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p,
+                           active.p, theta.p, Y.p, BX.p, T.p);
+      hipLaunchKernelGGL(k_scale_rows, gvec, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p,
+                         d_doff.p, active.p, dM.p, T.p, T.p);
+      band_solve(Mb, d_voff.p, T.p, nullptr, s, m, active.p);
+      hipLaunchKernelGGL(k_scale_rows, gvec, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p,
+                         d_doff.p, active.p, dM.p, T.p, T.p);
+      if (itm == 0)
+        hipLaunchKernelGGL(k_copy_active, gvec, dim3(256), 0, s, 3 * maxD * m, sw.d_nD.p, m,
+                           d_voff.p, active.p, T.p, Y.p);
+      else
+        hipLaunchKernelGGL(k_sub_block, gvec, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p,
+                           active.p, X.p, T.p, Y.p);
+    } else {
+      hipLaunchKernelGGL(k_copy_active, gvec, dim3(256), 0, s, 3 * maxD * m, sw.d_nD.p, m,
+                         d_voff.p, active.p, BX.p, Y.p);
+      band_solve(Mb, d_voff.p, Y.p, nullptr, s, m, active.p);
+    }
     hipLaunchKernelGGL(k_bmul, growD, dim3(64), 0, s, g, m, d_voff.p, active.p, Y.p, BY.p);
+    if (m32)
+      hipLaunchKernelGGL(k_amul, growD, dim3(64), 0, s, g, m, d_voff.p, active.p, Y.p, BY.p,
+                         sigma, MY);
     hipLaunchKernelGGL(k_gram, gch, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p, active.p, Y.p,
-                       BX.p, BY.p, nch_max, gpart.p);
+                       MY, BY.p, nch_max, gpart.p);
     hipLaunchKernelGGL(k_gram_sum, dim3(nblocks(2 * MAXM * MAXM, 256), n_sub), dim3(256), 0,
                        s, sw.d_nD.p, m, active.p, nch_max, gpart.p, G.p);
     hipLaunchKernelGGL(k_rayleigh_ritz, dim3(n_sub), dim3(256), 0, s, m, active.p, G.p, Cm.p,
@@ -670,7 +836,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
     hipLaunchKernelGGL(k_rotate, grows, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p, active.p,
                        Cm.p, Y.p, T.p);             // new X
     hipLaunchKernelGGL(k_rotate, grows, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p, active.p,
-                       Cm.p, BX.p, Y.p);            // M X_new
+                       Cm.p, MY, Y.p);              // M X_new
     hipLaunchKernelGGL(k_rotate, grows, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p, active.p,
                        Cm.p, BY.p, BX.p);           // B X_new
     hipLaunchKernelGGL(k_resid, gch, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p, active.p,
@@ -814,6 +980,7 @@ gx_status gx_geneo_setup(gx_ctx* c, const gx_geneo_opts* o, int32_t* nev_out,
   GX_REQUIRE(o->nev_max <= 32, "nev_max must be <= 32");
   c->setup_done = false;
   c->sw = Schwarz();
+  c->fp64_fallbacks = 0;
   Timer t1(c->stream);
   dd_build(c, o->elem_part, o->n_sub, o->overlap);
   c->phase_ms[1] = t1.ms();
@@ -847,6 +1014,7 @@ gx_status gx_stats(gx_ctx* c, int64_t* out) {
   out[1] = c->pcg_iters;
   out[2] = c->sw.A.total;
   out[3] = c->neumann_entries;
+  out[4] = c->fp64_fallbacks;
   GX_API_END(c)
 }
 

@@ -182,6 +182,7 @@ struct gx_ctx {
   int32_t pcg_iters = 0;
   int32_t eig_iters = 0;
   int64_t neumann_entries = 0;
+  int32_t fp64_fallbacks = 0;                  // bit 0: interior, bit 1: eigensolver factors
   double phase_ms[8] = {0};
   int tune[4] = {0, 0, 0, 0};                  // see gx_tune
 };

@@ -309,20 +309,28 @@ void interior_factors(gx_ctx* c, int precision) {
                        c->row_ptr.p, c->col.p, c->val.p, (const double*)nullptr, sw.I_nodes.p,
                        sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, N, bv, sw.A.v64.p);
   GX_HIP(hipGetLastError());
-  band_factor(sw.A, s);
+  try {
+    band_factor(sw.A, s);
+  } catch (const Error& e) {
+    if (!fp32 || e.code != GX_ENOTSPD) throw;
+    // an FP32 factor broke down: the interior factors are rebuilt in FP64 (reported)
+    c->fp64_fallbacks |= 1;
+    band_layout(sw.A, n, B, false, s);
+    BandView bv64{sw.A.d_B.p, sw.A.d_ld.p, sw.A.d_off.p};
+    hipLaunchKernelGGL(k_band_fill<double>, dim3((unsigned)maxI, n_sub), dim3(64), 0, s,
+                       c->row_ptr.p, c->col.p, c->val.p, (const double*)nullptr, sw.I_nodes.p,
+                       sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, N, bv64, sw.A.v64.p);
+    GX_HIP(hipGetLastError());
+    band_factor(sw.A, s);
+    sw.precision = GX_FP64;
+  }
   // solve work vectors, one segment of 3 nI_j per subdomain
   std::vector<int64_t> xo(n_sub + 1, 0);
   for (int j = 0; j < n_sub; ++j) xo[j + 1] = xo[j] + n[j];
   sw.xoff = xo;
   sw.d_xoff.alloc(n_sub + 1);
   to_dev(sw.d_xoff.p, xo.data(), n_sub + 1, s);
-  if (fp32) {
-    sw.wr32.alloc(xo[n_sub]);
-    sw.wr64.release();
-  } else {
-    sw.wr64.alloc(xo[n_sub]);
-    sw.wr32.release();
-  }
+  sw.wr64.alloc(xo[n_sub]);                      // FP64 local vectors in both precisions
   GX_HIP(hipStreamSynchronize(s));
 }
 
@@ -417,15 +425,10 @@ void precond_apply(gx_ctx* c, const double* r, double* z) {
   for (int j = 0; j < sw.n_sub; ++j) maxI = std::max(maxI, sw.nI[j]);
   const bool fp32 = sw.precision == GX_MIXED;
   const double* dg = fp32 ? sw.dg.p : nullptr;
-  if (fp32)
-    hipLaunchKernelGGL(k_gather_local<float>, dim3(nblocks(3 * maxI, 256), sw.n_sub),
-                       dim3(256), 0, s, r, dg, sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p,
-                       sw.d_xoff.p, sw.wr32.p);
-  else
-    hipLaunchKernelGGL(k_gather_local<double>, dim3(nblocks(3 * maxI, 256), sw.n_sub),
-                       dim3(256), 0, s, r, dg, sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p,
-                       sw.d_xoff.p, sw.wr64.p);
-  band_solve(sw.A, sw.d_xoff.p, sw.wr64.p, sw.wr32.p, s);
+  hipLaunchKernelGGL(k_gather_local<double>, dim3(nblocks(3 * maxI, 256), sw.n_sub),
+                     dim3(256), 0, s, r, dg, sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p,
+                     sw.d_xoff.p, sw.wr64.p);
+  band_solve(sw.A, sw.d_xoff.p, sw.wr64.p, nullptr, s);
   const bool two = sw.two_level && sw.n0 > 0;
   if (two) {
     const int64_t nch = (3 * maxI + RCH - 1) / RCH;
@@ -436,16 +439,10 @@ void precond_apply(gx_ctx* c, const double* r, double* z) {
                        sw.y0part.p, sw.n0, nch, sw.y0.p);
     band_solve(sw.C, sw.d_c_xoff.p, sw.y0.p, nullptr, s);
   }
-  if (fp32)
-    hipLaunchKernelGGL(k_combine<float>, dim3(nblocks(3 * N, 256)), dim3(256), 0, s,
-                       sw.node_and.p, sw.W, N, sw.I_loc.p, sw.d_xoff.p, sw.wr32.p, dg,
-                       sw.d_z_off.p, sw.d_nev.p, sw.d_c_off.p, sw.d_nI.p,
-                       two ? sw.Z.p : nullptr, sw.y0.p, c->fixed.p, z);
-  else
-    hipLaunchKernelGGL(k_combine<double>, dim3(nblocks(3 * N, 256)), dim3(256), 0, s,
-                       sw.node_and.p, sw.W, N, sw.I_loc.p, sw.d_xoff.p, sw.wr64.p, dg,
-                       sw.d_z_off.p, sw.d_nev.p, sw.d_c_off.p, sw.d_nI.p,
-                       two ? sw.Z.p : nullptr, sw.y0.p, c->fixed.p, z);
+  hipLaunchKernelGGL(k_combine<double>, dim3(nblocks(3 * N, 256)), dim3(256), 0, s,
+                     sw.node_and.p, sw.W, N, sw.I_loc.p, sw.d_xoff.p, sw.wr64.p, dg,
+                     sw.d_z_off.p, sw.d_nev.p, sw.d_c_off.p, sw.d_nI.p,
+                     two ? sw.Z.p : nullptr, sw.y0.p, c->fixed.p, z);
   GX_HIP(hipGetLastError());
 }
 
