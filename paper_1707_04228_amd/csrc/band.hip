@@ -9,12 +9,11 @@
 // Storage of matrix j: entry (r, c), r - B_j <= c <= r, at off_j + r * ld_j + (c - r + B_j).
 //
 // Factorisation: right-looking, block columns of NB; per step one kernel factors the
-// diagonal block in LDS, one solves the panel rows, one updates the trailing window with
-// 32x32 tiles.  Matrices of different size and bandwidth run in the same launches.
+// diagonal block in LDS (and keeps its inverse for the solves), one solves the panel rows,
+// one updates the trailing window with 64x64 tiles.  Matrices of different size and
+// bandwidth run in the same launches.
 //
-// Solves: one work-group per matrix streams the band once forward (L y = b) and once
-// backward (L^T x = y); a ring buffer in LDS holds the last B solved values, the 64x64
-// diagonal triangle of each block is solved by one wavefront with lane shuffles.
+// Solves: see the comment above the solve kernels.
 #include "gx_internal.h"
 
 namespace gx {
@@ -34,7 +33,7 @@ struct BandArgs {
 // Diagonal block of step c0: Cholesky in LDS, written back; its inverse goes to inv[j].
 template <class T>
 __global__ void __launch_bounds__(256) k_potrf(BandArgs a, T* v, int64_t c0, double* inv,
-                                               int* err) {
+                                               T* dinv, const int64_t* boff, int* err) {
   __shared__ double D[NB][NB + 1];
   __shared__ double Li[NB][NB + 1];
   const int j = blockIdx.x;
@@ -90,9 +89,11 @@ __global__ void __launch_bounds__(256) k_potrf(BandArgs a, T* v, int64_t c0, dou
   }
   __syncthreads();
   double* ij = inv + (int64_t)j * NB * NB;
+  T* dj = dinv + boff[j] + (c0 / NB) * NB * NB;   // kept for the triangular solves
   for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
     const int i = idx / NB, l = idx % NB;
     ij[idx] = Li[i][l];
+    dj[idx] = (T)Li[i][l];
     if (i < nb && l <= i && i - l <= B) base[(c0 + i) * ld + (l - i + B)] = (T)D[i][l];
   }
 }
@@ -233,7 +234,7 @@ __global__ void __launch_bounds__(256) k_syrk(BandArgs a, T* v, int64_t c0) {
 }
 
 template <class T>
-void band_factor_t(BandSet& bs, T* v, hipStream_t st, int* err) {
+void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, int* err) {
   BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p};
   DevBuf<double> inv((size_t)bs.n_mat * NB * NB);
   const int64_t steps = (bs.max_n + NB - 1) / NB;
@@ -242,7 +243,8 @@ void band_factor_t(BandSet& bs, T* v, hipStream_t st, int* err) {
   const unsigned trsm_blocks = (unsigned)((bs.max_B + TS - 1) / TS);
   for (int64_t k = 0; k < steps; ++k) {
     const int64_t c0 = k * NB;
-    hipLaunchKernelGGL(k_potrf<T>, dim3(bs.n_mat), dim3(256), 0, st, a, v, c0, inv.p, err);
+    hipLaunchKernelGGL(k_potrf<T>, dim3(bs.n_mat), dim3(256), 0, st, a, v, c0, inv.p, dinv,
+                       bs.d_boff.p, err);
     if (bs.max_B > 0) {
       hipLaunchKernelGGL(k_trsm<T>, dim3(trsm_blocks, bs.n_mat), dim3(256), 0, st, a, v, c0,
                          inv.p);
@@ -257,182 +259,43 @@ void band_factor(BandSet& bs, hipStream_t st) {
   DevBuf<int> err(1);
   zero(err, st);
   if (bs.fp32)
-    band_factor_t<float>(bs, bs.v32.p, st, err.p);
+    band_factor_t<float>(bs, bs.v32.p, bs.dinv32.p, st, err.p);
   else
-    band_factor_t<double>(bs, bs.v64.p, st, err.p);
+    band_factor_t<double>(bs, bs.v64.p, bs.dinv64.p, st, err.p);
   int h = 0;
   to_host(&h, err.p, 1, st);
   if (h) throw Error(GX_ENOTSPD, "non-positive pivot in a banded Cholesky factorisation");
 }
 
 // ---------------------------------------------------------------------------------------
-// Solves.  NC right-hand-side columns per work-group, stored row-major with row stride
-// `stride` at xoff[j] (+ NC * blockIdx.y); overwritten: forward (L y = b), then backward
-// (L^T x = y).  8 wavefronts: in the forward dot phase wave w owns rows 8w..8w+7 of the
-// 64-row block, so every loaded solution value serves 8 band rows; in the backward phase
-// lanes own the block's 64 columns and waves split the band rows below it; the 64x64
-// diagonal triangle of each block is solved per column by one wave with lane shuffles.
-// Solution values written earlier by the work-group are read back through global memory
-// (same work-group, ordered by the barriers).
+// Solves: forward L y = b, then backward L^T x = y, in place on FP64 right-hand sides.
+// A matrix is swept in blocks of 64 rows.  The coupling between consecutive blocks runs
+// through the explicit inverse of each 64x64 diagonal block (kept by the factorisation),
+// so the serial part of a block is one small product, not a 64-step substitution.
+//
+// G work-groups share a matrix: block k belongs to work-group k mod G in the forward sweep
+// and to (nblk - 1 - k) mod G in the backward sweep.  A work-group first adds the
+// contributions of the blocks that are complete by construction (its own previous block
+// and everything before it), then waits - bounded spin, acquire - for the predecessor
+// block (which waited for its own predecessor, so all earlier blocks are complete), adds
+// the at most G - 1 blocks that were in flight, applies the inverse diagonal block and
+// publishes the block with a release store of the launch epoch.  A timed-out wait raises
+// err and proceeds, so every wave always reaches the end of the kernel.
 constexpr int SW = SOLVE_THREADS / 64;           // waves per work-group (8)
 constexpr int RPW = SB / SW;                      // forward rows per wave (8)
+constexpr int GMAX = 4;                           // work-groups per matrix, 1-RHS solve
+constexpr int DL = SB * SB / SOLVE_THREADS;       // inverse-block entries per thread (8)
+constexpr int64_t SPIN_LIMIT = (int64_t)1 << 22;
+constexpr int64_t BAND_PAD = 1024;               // trailing entries of a band allocation
 
-// the 64x64 diagonal triangle of a solve block into LDS (rows 8w..8w+7 per wave; all
-// loads issued before the stores); rows past the end of the matrix become identity
-template <class T>
-__device__ inline void load_tri(double (&tri)[SB][SB + 1], const T* base, int64_t B,
-                                int64_t ld, int64_t i0, int nb, int lane, int wave) {
-  double v[RPW];
-#pragma unroll
-  for (int r = 0; r < RPW; ++r) {
-    const int ii = RPW * wave + r;
-    const int64_t i = i0 + ii;
-    v[r] = (ii < nb && lane <= ii && i - (i0 + lane) <= B)
-               ? (double)base[i * ld + (i0 + lane - i + B)]
-               : (lane == ii ? 1.0 : 0.0);
-  }
-#pragma unroll
-  for (int r = 0; r < RPW; ++r) tri[RPW * wave + r][lane] = v[r];
-}
-
-template <class T, class V, int NC>
-__global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve(BandArgs a, const T* v,
-                                                             const int64_t* xoff, V* xall,
-                                                             int stride, int ncol,
-                                                             const int32_t* active) {
-  __shared__ double tri[SB][SB + 1];
-  __shared__ double acc[SB][NC];
-  __shared__ double part[SW][SB][NC];
-  const int j = blockIdx.x;
-  if (active && !active[j]) return;
-  const int col0 = blockIdx.y * NC;
-  const int nc = min(NC, ncol - col0);
-  const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
-  const T* base = v + a.off[j];
-  V* xv = xall + xoff[j] + col0;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#define X(i, c) xv[(int64_t)(i) * stride + (c)]
-  // ---- forward: L y = b
-  for (int64_t i0 = 0; i0 < n; i0 += SB) {
-    const int nb = (int)min<int64_t>(SB, n - i0);
-    constexpr int RH = NC == 1 ? RPW : 4;           // rows accumulated per pass
-    for (int h = 0; h < RPW / RH; ++h) {
-      const int64_t ifirst = i0 + RPW * wave + RH * h;
-      double s[RH][NC];
-#pragma unroll
-      for (int r = 0; r < RH; ++r)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) s[r][c] = 0.0;
-      if (ifirst < n) {
-        for (int64_t cc = max<int64_t>(ifirst - B, 0) + lane; cc < i0; cc += 64) {
-          double y[NC];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) y[c] = c < nc ? (double)X(cc, c) : 0.0;
-#pragma unroll
-          for (int r = 0; r < RH; ++r) {
-            const int64_t i = ifirst + r;
-            const double l =
-                (i < n && cc >= i - B) ? (double)base[i * ld + (cc - i + B)] : 0.0;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) s[r][c] += l * y[c];
-          }
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < RH; ++r)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) s[r][c] = wave_sum_d(s[r][c]);
-      if (lane == 0) {
-#pragma unroll
-        for (int r = 0; r < RH; ++r) {
-          const int64_t i = ifirst + r;
-#pragma unroll
-          for (int c = 0; c < NC; ++c)
-            acc[RPW * wave + RH * h + r][c] = (i < n && c < nc) ? (double)X(i, c) - s[r][c] : 0.0;
-        }
-      }
-    }
-    load_tri<T>(tri, base, B, ld, i0, nb, lane, wave);
-    __syncthreads();
-    if (wave < nc) {
-      double a_l = acc[lane][wave], y_l = 0.0;
-      for (int k = 0; k < nb; ++k) {
-        const double yk = __shfl(a_l, k) / tri[k][k];
-        if (lane == k) y_l = yk;
-        if (lane > k) a_l -= tri[lane][k] * yk;
-      }
-      if (lane < nb) X(i0 + lane, wave) = (V)y_l;
-    }
-    __syncthreads();
-  }
-  // ---- backward: L^T x = y
-  const int64_t nblk = (n + SB - 1) / SB;
-  for (int64_t kb = nblk - 1; kb >= 0; --kb) {
-    const int64_t i0 = kb * SB;
-    const int nb = (int)min<int64_t>(SB, n - i0);
-    const int64_t rend = min<int64_t>(n, i0 + nb + B);
-    const int64_t cidx = i0 + lane;
-    double s[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) s[c] = 0.0;
-    int64_t r = i0 + nb + wave;
-    constexpr int UB = NC == 1 ? 4 : 1;           // rows in flight per lane
-    if (UB > 1) {
-      for (; r + (UB - 1) * SW < rend; r += UB * SW) {
-        double l[UB], xr[UB][NC];
-#pragma unroll
-        for (int u = 0; u < UB; ++u) {
-          const int64_t rr = r + u * SW;
-          l[u] = (lane < nb && rr - B <= cidx) ? (double)base[rr * ld + (cidx - rr + B)] : 0.0;
-#pragma unroll
-          for (int c = 0; c < NC; ++c) xr[u][c] = c < nc ? (double)X(rr, c) : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < UB; ++u)
-#pragma unroll
-          for (int c = 0; c < NC; ++c) s[c] += l[u] * xr[u][c];
-      }
-    }
-    for (; r < rend; r += SW) {
-      const double l = (lane < nb && r - B <= cidx) ? (double)base[r * ld + (cidx - r + B)] : 0.0;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) s[c] += l * (c < nc ? (double)X(r, c) : 0.0);
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) part[wave][lane][c] = s[c];
-    load_tri<T>(tri, base, B, ld, i0, nb, lane, wave);
-    __syncthreads();
-    if (wave < nc) {
-      double t = 0.0;
-      for (int w = 0; w < SW; ++w) t += part[w][lane][wave];
-      double a_l = lane < nb ? (double)X(i0 + lane, wave) - t : 0.0, x_l = 0.0;
-      for (int k = nb - 1; k >= 0; --k) {
-        const double xk = __shfl(a_l, k) / tri[k][k];
-        if (lane == k) x_l = xk;
-        if (lane < k) a_l -= tri[k][lane] * xk;
-      }
-      if (lane < nb) X(i0 + lane, wave) = (V)x_l;
-    }
-    __syncthreads();
-  }
-#undef X
-}
-
-// ---------------------------------------------------------------------------------------
-// One right-hand side per matrix, G work-groups per matrix.  Block k of 64 rows belongs to
-// work-group k mod G (forward) / (nblk - 1 - k) mod G (backward).  A work-group first adds
-// the contributions of blocks that are complete by construction (its own previous block
-// and everything before it), then waits - bounded spin, acquire - for the at most G - 1
-// blocks still in flight, solves its diagonal triangle and publishes the block with a
-// release store of the launch epoch.  A timed-out wait raises err and proceeds, so every
-// wave always reaches the end of the kernel.
-constexpr int64_t SPIN_LIMIT = (int64_t)1 << 24;
-
+// Once any wait of the launch has timed out, every later wait gives up at once, so a
+// broken pipeline costs one time-out, not one per block.
 __device__ inline void wait_flag(const int* f, int epoch, int* err) {
   if (threadIdx.x == 0) {
     int64_t spins = 0;
     while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-      if (++spins > SPIN_LIMIT) {
+      if ((++spins & 255) == 0 &&
+          (spins > SPIN_LIMIT || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
         atomicOr(err, 2);
         break;
       }
@@ -446,11 +309,51 @@ __device__ inline void post_flag(int* f, int epoch) {
   __hip_atomic_store(f, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <class T, class V>
-__global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_mw(
-    BandArgs a, const T* v, const int64_t* xoff, V* xall, int G, int n_pad, int n_mat,
-    int* fflag, int* bflag, int64_t nblk_max, int epoch, int* err) {
-  __shared__ double tri[SB][SB + 1];
+// Band entry (r, c) loaded from a clamped, always valid address; the caller masks entries
+// outside the band.  The loads are unconditional so that a wave issues all of them before
+// it waits for any.
+template <class T>
+__device__ inline T band_raw(const T* base, int64_t n, int64_t B, int64_t ld, int64_t r,
+                             int64_t c) {
+  const int64_t rc = min(r, n - 1);
+  const int64_t o = min(max(c - rc + B, (int64_t)0), B);
+  return base[rc * ld + o];
+}
+
+// s[r] summed over the 64 lanes; lane l receives the total of row l >> 3
+__device__ inline double reduce_rows8(const double (&s)[RPW], int lane) {
+  double t4[4], t2[2];
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double send = b5 ? s[r] : s[r + 4];
+    t4[r] = (b5 ? s[r + 4] : s[r]) + __shfl_xor(send, 32);
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const double send = b4 ? t4[r] : t4[r + 2];
+    t2[r] = (b4 ? t4[r + 2] : t4[r]) + __shfl_xor(send, 16);
+  }
+  double t = (b3 ? t2[1] : t2[0]) + __shfl_xor(b3 ? t2[0] : t2[1], 8);
+  t += __shfl_xor(t, 4);
+  t += __shfl_xor(t, 2);
+  t += __shfl_xor(t, 1);
+  return t;
+}
+
+// ---- one right-hand side per matrix
+// Loads are unconditional: rows past the end of the matrix are clamped to its last row, a
+// lane whose column lies outside the band reads a neighbouring entry (the band storage
+// carries BAND_PAD zero entries after the last row), and masks are applied by multiplying
+// with 0 or 1, so that a wave issues all loads of a step before it waits for any.
+// Blocks in flight are added oldest first, each after its own flag; the entries of the
+// predecessor block - the last to complete - are loaded before the waits.
+template <class T>
+__global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
+    BandArgs a, const T* v, const T* dinv, const int64_t* boff, const int64_t* xoff,
+    double* xall, int G, int n_pad, int n_mat, int* fflag, int* bflag, int64_t nblk_max,
+    int epoch, int* err) {
+  __shared__ double Di[SB][SB + 1];
   __shared__ double acc[SB];
   __shared__ double part[SW][SB];
   const int g = blockIdx.x / n_pad, j = blockIdx.x % n_pad;
@@ -458,328 +361,421 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_mw(
   const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
   if (n == 0) return;
   const T* base = v + a.off[j];
-  V* x = xall + xoff[j];
+  const T* dv = dinv + boff[j];
+  double* x = xall + xoff[j];
   int* ff = fflag + (int64_t)j * nblk_max;
   int* bf = bflag + (int64_t)j * nblk_max;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t nblk = (n + SB - 1) / SB;
-  // ---- forward
+  constexpr int U = sizeof(T) == 8 ? 4 : 8;       // 64-column steps in flight per wave
+  constexpr int UB = 16;                           // band rows in flight per wave (backward)
+  // ---- forward: wave w owns rows 8w..8w+7 of the block, lanes run along the columns
   for (int64_t k = g; k < nblk; k += G) {
     const int64_t i0 = k * SB;
     const int nb = (int)min<int64_t>(SB, n - i0);
-    const int64_t done_end = max<int64_t>(k - G + 1, 0) * SB;   // columns known complete
+    const int64_t kdone = max<int64_t>(k - G + 1, 0);        // column blocks < kdone complete
+    const int64_t done_end = kdone * SB;
     const int64_t ifirst = i0 + RPW * wave;
+    const T* rp[RPW];                              // rp[r][c] = entry (row, c)
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int64_t rc = min<int64_t>(ifirst + r, n - 1);
+      rp[r] = base + rc * ld - rc + B;
+    }
     double s[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) s[r] = 0.0;
-    for (int64_t cc = max<int64_t>(ifirst - B, 0) + lane; cc < done_end; cc += 64) {
-      const double y = (double)x[cc];
+    for (int64_t c0 = max<int64_t>(ifirst - B, 0) + lane; c0 < done_end + lane; c0 += 64 * U) {
+      T l[U][RPW];
+      double xv[U];
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) {
-        const int64_t i = ifirst + r;
-        const double l = (i < n && cc >= i - B) ? (double)base[i * ld + (cc - i + B)] : 0.0;
-        s[r] += l * y;
+      for (int u = 0; u < U; ++u) {
+        xv[u] = x[min<int64_t>(c0 + 64 * u, done_end - 1)];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) l[u][r] = rp[r][c0 + 64 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t cc = c0 + 64 * u;
+        const double xu = cc < done_end ? xv[u] : 0.0;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r)
+          s[r] += (double)l[u][r] * (cc >= ifirst + r - B ? xu : 0.0);
       }
     }
-    load_tri<T>(tri, base, B, ld, i0, nb, lane, wave);
-    for (int64_t kk = max<int64_t>(k - G + 1, 0); kk < k; ++kk) {   // blocks in flight
+    T pf[RPW], dd[DL];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) pf[r] = rp[r][i0 - SB + lane];
+#pragma unroll
+    for (int u = 0; u < DL; ++u) dd[u] = dv[k * SB * SB + threadIdx.x + SOLVE_THREADS * u];
+    for (int64_t kk = kdone; kk < k - 1; ++kk) {   // older blocks in flight (G > 2)
       wait_flag(ff + kk, epoch, err);
       const int64_t cc = kk * SB + lane;
-      const double y = (double)x[cc];
+      const double xu = x[cc];
+      T l[RPW];
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) {
-        const int64_t i = ifirst + r;
-        const double l = (i < n && cc >= i - B) ? (double)base[i * ld + (cc - i + B)] : 0.0;
-        s[r] += l * y;
-      }
+      for (int r = 0; r < RPW; ++r) l[r] = rp[r][cc];
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) s[r] += (double)l[r] * (cc >= ifirst + r - B ? xu : 0.0);
+    }
+    if (k >= 1 && k - 1 >= kdone) {                // the predecessor block (G > 1)
+      wait_flag(ff + k - 1, epoch, err);
+      const int64_t cc = i0 - SB + lane;
+      const double xu = x[cc];
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) s[r] += (double)pf[r] * (cc >= ifirst + r - B ? xu : 0.0);
     }
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) s[r] = wave_sum_d(s[r]);
-    if (lane == 0)
-#pragma unroll
-      for (int r = 0; r < RPW; ++r) {
-        const int64_t i = ifirst + r;
-        acc[RPW * wave + r] = i < n ? (double)x[i] - s[r] : 0.0;
-      }
+    for (int u = 0; u < DL; ++u) {
+      const int idx = threadIdx.x + SOLVE_THREADS * u;
+      Di[idx / SB][idx % SB] = (double)dd[u];
+    }
+    const double tot = reduce_rows8(s, lane);
+    if ((lane & 7) == 0) {
+      const int ii = RPW * wave + (lane >> 3);
+      acc[ii] = ii < nb ? x[i0 + ii] - tot : 0.0;
+    }
     __syncthreads();
     if (wave == 0) {
-      double a_l = acc[lane], y_l = 0.0;
-      for (int q = 0; q < nb; ++q) {
-        const double yq = __shfl(a_l, q) / tri[q][q];
-        if (lane == q) y_l = yq;
-        if (lane > q) a_l -= tri[lane][q] * yq;
-      }
-      if (lane < nb) x[i0 + lane] = (V)y_l;
-      if (lane == 0) post_flag(ff + k, epoch);
+      double y[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+      for (int q = 0; q < SB; q += 4)
+#pragma unroll
+        for (int h = 0; h < 4; ++h) y[h] += Di[lane][q + h] * acc[q + h];
+      if (lane < nb) x[i0 + lane] = (y[0] + y[1]) + (y[2] + y[3]);
+      if (G > 1 && lane == 0) post_flag(ff + k, epoch);
     }
     __syncthreads();
   }
-  // ---- backward
+  // ---- backward: lanes own the block's 64 columns, waves split the band rows below it;
+  // entry (r, c) = cb[r * rs + c]
+  const T* cb = base + B;
+  const int64_t rs = ld - 1;
   for (int64_t t = g; t < nblk; t += G) {
     const int64_t kb = nblk - 1 - t;
     const int64_t i0 = kb * SB;
     const int nb = (int)min<int64_t>(SB, n - i0);
     const int64_t rend = min<int64_t>(n, i0 + nb + B);
-    const int64_t inflight_end = min<int64_t>(rend, (kb + G) * SB);   // rows of blocks in flight
+    const int64_t kdone = kb + G;                  // row blocks >= kdone complete
+    const int64_t done_beg = min<int64_t>(rend, kdone * SB);
     const int64_t cidx = i0 + lane;
-    wait_flag(ff + kb, epoch, err);                 // this block's forward result
     double sacc = 0.0;
-    int64_t r = inflight_end + wave;
-    for (; r + 3 * SW < rend; r += 4 * SW) {
-      double l[4], xr[4];
+    for (int64_t r0 = done_beg + wave; r0 < rend; r0 += SW * UB) {
+      T l[UB];
+      double xr[UB];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t rr = r + u * SW;
-        l[u] = (lane < nb && rr - B <= cidx) ? (double)base[rr * ld + (cidx - rr + B)] : 0.0;
-        xr[u] = (double)x[rr];
+      for (int u = 0; u < UB; ++u) {
+        const int64_t rr = min<int64_t>(r0 + SW * u, rend - 1);
+        l[u] = cb[rr * rs + cidx];
+        xr[u] = x[rr];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) sacc += l[u] * xr[u];
+      for (int u = 0; u < UB; ++u) {
+        const int64_t rr = r0 + SW * u;
+        sacc += (double)l[u] * ((rr < rend && rr - B <= cidx) ? xr[u] : 0.0);
+      }
     }
-    for (; r < rend; r += SW) {
-      const double l = (lane < nb && r - B <= cidx) ? (double)base[r * ld + (cidx - r + B)] : 0.0;
-      sacc += l * (double)x[r];
-    }
-    load_tri<T>(tri, base, B, ld, i0, nb, lane, wave);
-    for (int64_t kk = kb + 1; kk < min<int64_t>(kb + G, nblk); ++kk) {   // in flight
+    // rows of the blocks in flight: kb + 1 (the last to complete) .. kdone - 1
+    const int64_t kin = min<int64_t>(kdone - 1, (rend - 1) / SB);   // last row block in flight
+    T pf[RPW], dd[DL];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+      pf[r] = cb[min<int64_t>(i0 + SB + wave + SW * r, n - 1) * rs + cidx];
+#pragma unroll
+    for (int u = 0; u < DL; ++u) dd[u] = dv[kb * SB * SB + threadIdx.x + SOLVE_THREADS * u];
+    for (int64_t kk = kin; kk > kb + 1; --kk) {    // older blocks in flight (G > 2)
       wait_flag(bf + kk, epoch, err);
-      for (int64_t rr = kk * SB + wave; rr < min<int64_t>((kk + 1) * SB, rend); rr += SW) {
-        const double l = (lane < nb && rr - B <= cidx) ? (double)base[rr * ld + (cidx - rr + B)] : 0.0;
-        sacc += l * (double)x[rr];
+      T l[RPW];
+      double xr[RPW];
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const int64_t rr = min<int64_t>(kk * SB + wave + SW * r, rend - 1);
+        l[r] = cb[rr * rs + cidx];
+        xr[r] = x[rr];
       }
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const int64_t rr = kk * SB + wave + SW * r;
+        sacc += (double)l[r] * ((rr < rend && rr - B <= cidx) ? xr[r] : 0.0);
+      }
+    }
+    if (G > 1) wait_flag(kb + 1 < nblk ? bf + kb + 1 : ff + kb, epoch, err);
+    if (kb + 1 <= kin) {                           // the block right below (G > 1)
+      double xr[RPW];
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) xr[r] = x[min<int64_t>(i0 + SB + wave + SW * r, rend - 1)];
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const int64_t rr = i0 + SB + wave + SW * r;
+        sacc += (double)pf[r] * ((rr < rend && rr - B <= cidx) ? xr[r] : 0.0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < DL; ++u) {
+      const int idx = threadIdx.x + SOLVE_THREADS * u;
+      Di[idx / SB][idx % SB] = (double)dd[u];
     }
     part[wave][lane] = sacc;
     __syncthreads();
     if (wave == 0) {
       double tsum = 0.0;
+#pragma unroll
       for (int w = 0; w < SW; ++w) tsum += part[w][lane];
-      double a_l = lane < nb ? (double)x[i0 + lane] - tsum : 0.0, x_l = 0.0;
-      for (int q = nb - 1; q >= 0; --q) {
-        const double xq = __shfl(a_l, q) / tri[q][q];
-        if (lane == q) x_l = xq;
-        if (lane < q) a_l -= tri[q][lane] * xq;
-      }
-      if (lane < nb) x[i0 + lane] = (V)x_l;
-      if (lane == 0) post_flag(bf + kb, epoch);
+      acc[lane] = lane < nb ? x[cidx] - tsum : 0.0;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      double y[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+      for (int q = 0; q < SB; q += 4)
+#pragma unroll
+        for (int h = 0; h < 4; ++h) y[h] += Di[q + h][lane] * acc[q + h];
+      if (lane < nb) x[cidx] = (y[0] + y[1]) + (y[2] + y[3]);
+      if (G > 1 && lane == 0) post_flag(bf + kb, epoch);
     }
     __syncthreads();
   }
 }
 
-// ---------------------------------------------------------------------------------------
-// m right-hand sides per matrix (m <= 64, row-major, row stride m), G work-groups per matrix
-// pipelined as in k_band_solve_mw.  The dot products of a 64-row block are a
-// (64 x B) x (B x m) product staged through LDS in 64-column chunks of the band; each
-// thread accumulates 4 rows x 2 columns.  Triangles are solved per column by the waves.
-constexpr int MC = 40;                           // right-hand-side columns per launch, max
+// ---- m right-hand sides per matrix (m <= MC, row-major, row stride m)
+// The block products - a 64-row block of the band against 64 solution rows, and the
+// inverse diagonal block against the block's right-hand side - are 64 x 64 x m and run on
+// FP64 matrix cores (v_mfma_f64_16x16x4: wave w owns row tile w mod 4 and the column
+// tiles w / 4 and w / 4 + 2; lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
+// holds D[4 r + l / 16][l % 16] in accumulator register r).  Band chunks are staged through LDS, the next chunk's loads
+// in flight in registers while the current one is multiplied.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int MC = 48;                            // right-hand sides per launch, at most
+constexpr int YLD = MC + 1;
+constexpr int YL = SB * MC / SOLVE_THREADS;       // solution-chunk entries per thread (6)
 
 template <class T>
-__device__ inline void mc_chunk_fwd(double (&Ab)[SB][SB + 1], double (&Yc)[SB][MC + 1],
-                                    const T* base, const double* x, int64_t n, int64_t B,
-                                    int64_t ld, int64_t i0, int64_t c0, int64_t cend, int m) {
-  // band rows i0..i0+63, columns c0..c0+63 (masked to the band, < cend); Y rows c0..c0+63.
-  // All loads of a thread are issued before any LDS store (one memory round trip).
-  constexpr int LA = SB * SB / SOLVE_THREADS;            // 8
-  constexpr int LY = (SB * MC + SOLVE_THREADS - 1) / SOLVE_THREADS;   // 5
-  double va[LA], vy[LY];
-#pragma unroll
-  for (int u = 0; u < LA; ++u) {
-    const int idx = threadIdx.x + u * SOLVE_THREADS;
-    const int ii = idx / SB, kk = idx % SB;
-    const int64_t i = i0 + ii, c = c0 + kk;
-    va[u] = (i < n && c < cend && c >= i - B) ? (double)base[i * ld + (c - i + B)] : 0.0;
-  }
-#pragma unroll
-  for (int u = 0; u < LY; ++u) {
-    const int idx = threadIdx.x + u * SOLVE_THREADS;
-    const int kk = idx / m, cc = idx - kk * m;
-    const int64_t c = c0 + kk;
-    vy[u] = (idx < SB * m && c < cend) ? x[c * m + cc] : 0.0;
-  }
-#pragma unroll
-  for (int u = 0; u < LA; ++u) {
-    const int idx = threadIdx.x + u * SOLVE_THREADS;
-    Ab[idx / SB][idx % SB] = va[u];
-  }
-#pragma unroll
-  for (int u = 0; u < LY; ++u) {
-    const int idx = threadIdx.x + u * SOLVE_THREADS;
-    if (idx < SB * m) Yc[idx / m][idx - (idx / m) * m] = vy[u];
-  }
-  if (threadIdx.x < SB) Yc[threadIdx.x][MC] = 0.0;
-}
-
-// backward chunk: Ab[rr][cl] = L[r0 + rr][i0 + cl], Yc[rr][col] = x[r0 + rr][col]
-template <class T>
-__device__ inline void mc_chunk_bwd(double (&Ab)[SB][SB + 1], double (&Yc)[SB][MC + 1],
-                                    const T* base, const double* x, int64_t B, int64_t ld,
-                                    int64_t i0, int nb, int64_t r0, int64_t rr_end, int m) {
-  constexpr int LA = SB * SB / SOLVE_THREADS;
-  constexpr int LY = (SB * MC + SOLVE_THREADS - 1) / SOLVE_THREADS;
-  double va[LA], vy[LY];
-#pragma unroll
-  for (int u = 0; u < LA; ++u) {
-    const int idx = threadIdx.x + u * SOLVE_THREADS;
-    const int rr = idx / SB, cl = idx % SB;
-    const int64_t r = r0 + rr, c = i0 + cl;
-    va[u] = (r < rr_end && cl < nb && r - B <= c) ? (double)base[r * ld + (c - r + B)] : 0.0;
-  }
-#pragma unroll
-  for (int u = 0; u < LY; ++u) {
-    const int idx = threadIdx.x + u * SOLVE_THREADS;
-    const int rr = idx / m, cc = idx - rr * m;
-    const int64_t r = r0 + rr;
-    vy[u] = (idx < SB * m && r < rr_end) ? x[r * m + cc] : 0.0;
-  }
-#pragma unroll
-  for (int u = 0; u < LA; ++u) {
-    const int idx = threadIdx.x + u * SOLVE_THREADS;
-    Ab[idx / SB][idx % SB] = va[u];
-  }
-#pragma unroll
-  for (int u = 0; u < LY; ++u) {
-    const int idx = threadIdx.x + u * SOLVE_THREADS;
-    if (idx < SB * m) Yc[idx / m][idx - (idx / m) * m] = vy[u];
-  }
-  if (threadIdx.x < SB) Yc[threadIdx.x][MC] = 0.0;
-}
-
-template <class T>
-__global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_mc(
-    BandArgs a, const T* v, const int64_t* xoff, double* xall, int m, int G, int n_pad,
-    int n_mat, int* fflag, int* bflag, int64_t nblk_max, int epoch, const int32_t* active,
-    int* err) {
-  __shared__ double Ab[SB][SB + 1];               // band chunk; the block's triangle later
-  __shared__ double Yc[SB][MC + 1];               // solution chunk
-  __shared__ double acc[SB][MC + 1];
-  double (&tri)[SB][SB + 1] = Ab;
+__global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_m(
+    BandArgs a, const T* v, const T* dinv, const int64_t* boff, const int64_t* xoff,
+    double* xall, int m, int G, int n_pad, int n_mat, int* fflag, int* bflag,
+    int64_t nblk_max, int epoch, const int32_t* active, int* err) {
+  __shared__ double Ab[SB][SB + 1];               // band chunk; the inverse block later
+  __shared__ double Yc[SB][YLD];                  // solution chunk; the block's rhs later
   const int g = blockIdx.x / n_pad, j = blockIdx.x % n_pad;
   if (j >= n_mat || g >= G) return;
   if (active && !active[j]) return;
   const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
+  if (n == 0) return;
   const T* base = v + a.off[j];
+  const T* dv = dinv + boff[j];
   double* x = xall + xoff[j];
   int* ff = fflag + (int64_t)j * nblk_max;
   int* bf = bflag + (int64_t)j * nblk_max;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int rg = threadIdx.x / 32, slot = threadIdx.x % 32;   // 16 row groups x 32 slots
-  const int slot2 = slot + 32 < MC ? slot + 32 : MC;          // second column (MC: unused)
+  const int li = lane & 15, lk = lane >> 4;        // matrix-core operand coordinates
+  const int rt = wave & 3, ct0 = wave >> 2, ct1 = ct0 + 2;
+  const int nct = (m + 15) / 16;
+  const bool has0 = ct0 < nct, has1 = ct1 < nct;
   const int64_t nblk = (n + SB - 1) / SB;
+  int yr[YL], yc[YL];                              // (row, column) of the staged entries
+#pragma unroll
+  for (int u = 0; u < YL; ++u) {
+    const int idx = threadIdx.x + SOLVE_THREADS * u;
+    yr[u] = idx < SB * m ? idx / m : SB;
+    yc[u] = idx < SB * m ? idx - (idx / m) * m : 0;
+  }
+  for (int idx = threadIdx.x; idx < SB * (YLD - m); idx += SOLVE_THREADS)
+    Yc[idx / (YLD - m)][m + idx % (YLD - m)] = 0.0;   // padding columns stay zero
+  // chunk fetch: forward chunk = band rows i0.. of columns c0..; backward chunk = band rows
+  // r0.. of columns i0..; solution rows of the chunk
+  auto fetch_f = [&](int64_t i0, int64_t c0, T (&fa)[DL], double (&fy)[YL]) {
+#pragma unroll
+    for (int u = 0; u < DL; ++u) {
+      const int idx = threadIdx.x + SOLVE_THREADS * u;
+      fa[u] = band_raw(base, n, B, ld, i0 + idx / SB, c0 + idx % SB);
+    }
+#pragma unroll
+    for (int u = 0; u < YL; ++u) fy[u] = x[min<int64_t>(c0 + yr[u], n - 1) * m + yc[u]];
+  };
+  auto stage_f = [&](int64_t i0, int64_t c0, const T (&fa)[DL], const double (&fy)[YL]) {
+#pragma unroll
+    for (int u = 0; u < DL; ++u) {
+      const int idx = threadIdx.x + SOLVE_THREADS * u;
+      const int64_t i = i0 + idx / SB, c = c0 + idx % SB;
+      Ab[idx / SB][idx % SB] = (i < n && c >= i - B && c <= i) ? (double)fa[u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < YL; ++u)
+      if (yr[u] < SB) Yc[yr[u]][yc[u]] = fy[u];
+  };
+  auto fetch_b = [&](int64_t i0, int64_t r0, T (&fa)[DL], double (&fy)[YL]) {
+#pragma unroll
+    for (int u = 0; u < DL; ++u) {
+      const int idx = threadIdx.x + SOLVE_THREADS * u;
+      fa[u] = band_raw(base, n, B, ld, r0 + idx / SB, i0 + idx % SB);
+    }
+#pragma unroll
+    for (int u = 0; u < YL; ++u) fy[u] = x[min<int64_t>(r0 + yr[u], n - 1) * m + yc[u]];
+  };
+  auto stage_b = [&](int64_t i0, int nb, int64_t r0, const T (&fa)[DL],
+                     const double (&fy)[YL]) {
+#pragma unroll
+    for (int u = 0; u < DL; ++u) {
+      const int idx = threadIdx.x + SOLVE_THREADS * u;
+      const int64_t r = r0 + idx / SB;
+      const int cl = idx % SB;
+      Ab[idx / SB][cl] = (r < n && cl < nb && r - B <= i0 + cl) ? (double)fa[u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < YL; ++u)
+      if (yr[u] < SB) Yc[yr[u]][yc[u]] = r0 + yr[u] < n ? fy[u] : 0.0;
+  };
+  // acc += A Yc over the 64-deep chunk; A = Ab (forward) or Ab^T (backward)
+  auto mma = [&](bool trans, v4d& acc0, v4d& acc1) {
+    if (!has0) return;
+#pragma unroll 4
+    for (int ks = 0; ks < SB / 4; ++ks) {
+      const int kq = 4 * ks + lk;
+      const double av = trans ? Ab[kq][16 * rt + li] : Ab[16 * rt + li][kq];
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Yc[kq][16 * ct0 + li], acc0, 0, 0, 0);
+      if (has1)
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Yc[kq][16 * ct1 + li], acc1, 0, 0, 0);
+    }
+  };
+  // block rhs minus the accumulated sums into Yc (rows < nb), inverse block into Ab
+  auto finish_in = [&](int64_t i0, int nb, const v4d& acc0, const v4d& acc1,
+                       const double (&bb)[2][4], const T (&dd)[DL]) {
+#pragma unroll
+    for (int u = 0; u < DL; ++u) {
+      const int idx = threadIdx.x + SOLVE_THREADS * u;
+      Ab[idx / SB][idx % SB] = (double)dd[u];
+    }
+    if (has0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ii = 16 * rt + 4 * r + lk;
+        const int c0 = 16 * ct0 + li, c1 = 16 * ct1 + li;
+        if (c0 < m) Yc[ii][c0] = ii < nb ? bb[0][r] - acc0[r] : 0.0;
+        if (has1 && c1 < m) Yc[ii][c1] = ii < nb ? bb[1][r] - acc1[r] : 0.0;
+      }
+    }
+  };
+  auto load_rhs = [&](int64_t i0, int nb, double (&bb)[2][4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ii = 16 * rt + 4 * r + lk;
+      const int64_t row = min<int64_t>(i0 + ii, n - 1);
+      bb[0][r] = x[row * m + min(16 * ct0 + li, m - 1)];
+      bb[1][r] = x[row * m + min(16 * ct1 + li, m - 1)];
+    }
+  };
+  auto store_block = [&](int64_t i0, int nb, const v4d& y0, const v4d& y1) {
+    if (has0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ii = 16 * rt + 4 * r + lk;
+        const int c0 = 16 * ct0 + li, c1 = 16 * ct1 + li;
+        if (ii < nb && c0 < m) x[(i0 + ii) * m + c0] = y0[r];
+        if (has1 && ii < nb && c1 < m) x[(i0 + ii) * m + c1] = y1[r];
+      }
+    }
+    // every wave's stores complete before the block is published
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+  };
+  const v4d zero4 = {0.0, 0.0, 0.0, 0.0};
   // ---- forward
   for (int64_t k = g; k < nblk; k += G) {
     const int64_t i0 = k * SB;
     const int nb = (int)min<int64_t>(SB, n - i0);
-    double s[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-    const int64_t cfirst = max<int64_t>(i0 - B, 0);
-    const int64_t done_end = max<int64_t>(k - G + 1, 0) * SB;
-    for (int64_t c0 = cfirst; c0 < i0; c0 += SB) {
-      const int64_t kk = c0 / SB;                       // not block aligned at the start
-      const int64_t cend = min<int64_t>(i0, c0 + SB);
-      if (cend > done_end) {                            // part of a block still in flight
-        const int64_t b0 = max<int64_t>(c0 / SB, done_end / SB);
-        for (int64_t w = b0; w * SB < cend; ++w) wait_flag(ff + w, epoch, err);
-      }
-      (void)kk;
-      mc_chunk_fwd<T>(Ab, Yc, base, x, n, B, ld, i0, c0, cend, m);
+    const int64_t kfirst = max<int64_t>(i0 - B, 0) / SB;
+    const int64_t kdone = max<int64_t>(k - G + 1, 0);          // chunks < kdone complete
+    v4d acc0 = zero4, acc1 = zero4;
+    T fa[DL];
+    double fy[YL];
+    int64_t kk = kfirst;
+    if (kk < kdone) fetch_f(i0, kk * SB, fa, fy);
+    for (; kk < kdone; ++kk) {
       __syncthreads();
-      for (int q = 0; q < SB; ++q) {
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          const double av = Ab[4 * rg + p][q];
-          s[p][0] += av * Yc[q][slot];
-          s[p][1] += av * Yc[q][slot2];
-        }
-      }
+      stage_f(i0, kk * SB, fa, fy);
       __syncthreads();
+      if (kk + 1 < kdone) fetch_f(i0, (kk + 1) * SB, fa, fy);
+      mma(false, acc0, acc1);
     }
+    T dd[DL];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int ii = 4 * rg + p;
-      const int64_t i = i0 + ii;
-      if (slot < m) acc[ii][slot] = i < n ? x[i * m + slot] - s[p][0] : 0.0;
-      if (slot + 32 < m) acc[ii][slot + 32] = i < n ? x[i * m + slot + 32] - s[p][1] : 0.0;
-    }
-    load_tri<T>(tri, base, B, ld, i0, nb, lane, wave);
-    __syncthreads();
-    for (int col = wave; col < m; col += SW) {
-      double a_l = acc[lane][col], y_l = 0.0;
-      for (int q = 0; q < nb; ++q) {
-        const double yq = __shfl(a_l, q) / tri[q][q];
-        if (lane == q) y_l = yq;
-        if (lane > q) a_l -= tri[lane][q] * yq;
-      }
-      if (lane < nb) x[(i0 + lane) * m + col] = y_l;
+    for (int u = 0; u < DL; ++u) dd[u] = dv[k * SB * SB + threadIdx.x + SOLVE_THREADS * u];
+    double bb[2][4];
+    load_rhs(i0, nb, bb);
+    if (G > 1 && k > 0) wait_flag(ff + k - 1, epoch, err);
+    for (kk = max(kfirst, kdone); kk < k; ++kk) {
+      fetch_f(i0, kk * SB, fa, fy);
+      __syncthreads();
+      stage_f(i0, kk * SB, fa, fy);
+      __syncthreads();
+      mma(false, acc0, acc1);
     }
     __syncthreads();
-    if (threadIdx.x == 0) post_flag(ff + k, epoch);
+    finish_in(i0, nb, acc0, acc1, bb, dd);
+    __syncthreads();
+    v4d y0 = zero4, y1 = zero4;
+    mma(false, y0, y1);
+    store_block(i0, nb, y0, y1);
+    if (G > 1 && threadIdx.x == 0) post_flag(ff + k, epoch);
   }
   // ---- backward
   for (int64_t t = g; t < nblk; t += G) {
     const int64_t kb = nblk - 1 - t;
     const int64_t i0 = kb * SB;
     const int nb = (int)min<int64_t>(SB, n - i0);
-    const int64_t rend = min<int64_t>(n, i0 + nb + B);
-    const int64_t done_beg = min<int64_t>(n, (kb + G) * SB);   // rows known complete
-    wait_flag(ff + kb, epoch, err);
-    double s[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-    // chunks of 64 rows from the far end of the band inwards: rows of complete blocks
-    // first, the rows of blocks still in flight (right below this block) last
-    const int64_t nchunk = (rend - (i0 + nb) + SB - 1) / SB;
-    for (int64_t ch = nchunk - 1; ch >= 0; --ch) {
-      const int64_t r0 = i0 + nb + ch * SB;
-      const int64_t rr_end = min<int64_t>(rend, r0 + SB);
-      if (r0 < done_beg)                                // rows of blocks still in flight
-        for (int64_t w = r0 / SB; w * SB < min<int64_t>(rr_end, done_beg); ++w)
-          wait_flag(bf + w, epoch, err);
-      mc_chunk_bwd<T>(Ab, Yc, base, x, B, ld, i0, nb, r0, rr_end, m);
+    const int64_t klast = (min<int64_t>(n, i0 + nb + B) - 1) / SB;   // last row block
+    const int64_t kdone = kb + G;                  // row blocks >= kdone complete
+    v4d acc0 = zero4, acc1 = zero4;
+    T fa[DL];
+    double fy[YL];
+    int64_t kk = klast;
+    if (kk >= kdone) fetch_b(i0, kk * SB, fa, fy);
+    for (; kk >= kdone; --kk) {
       __syncthreads();
-      for (int q = 0; q < SB; ++q) {
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          const double av = Ab[q][4 * rg + p];
-          s[p][0] += av * Yc[q][slot];
-          s[p][1] += av * Yc[q][slot2];
-        }
-      }
+      stage_b(i0, nb, kk * SB, fa, fy);
       __syncthreads();
+      if (kk - 1 >= kdone) fetch_b(i0, (kk - 1) * SB, fa, fy);
+      mma(true, acc0, acc1);
     }
+    T dd[DL];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int cl = 4 * rg + p;
-      const int64_t c = i0 + cl;
-      if (slot < m) acc[cl][slot] = cl < nb ? x[c * m + slot] - s[p][0] : 0.0;
-      if (slot + 32 < m) acc[cl][slot + 32] = cl < nb ? x[c * m + slot + 32] - s[p][1] : 0.0;
+    for (int u = 0; u < DL; ++u) dd[u] = dv[kb * SB * SB + threadIdx.x + SOLVE_THREADS * u];
+    if (G > 1) wait_flag(kb + 1 < nblk ? bf + kb + 1 : ff + kb, epoch, err);
+    for (kk = min(klast, kdone - 1); kk > kb; --kk) {
+      fetch_b(i0, kk * SB, fa, fy);
+      __syncthreads();
+      stage_b(i0, nb, kk * SB, fa, fy);
+      __syncthreads();
+      mma(true, acc0, acc1);
     }
-    load_tri<T>(tri, base, B, ld, i0, nb, lane, wave);
+    double bb[2][4];
+    load_rhs(i0, nb, bb);
     __syncthreads();
-    for (int col = wave; col < m; col += SW) {
-      double a_l = acc[lane][col], x_l = 0.0;
-      for (int q = nb - 1; q >= 0; --q) {
-        const double xq = __shfl(a_l, q) / tri[q][q];
-        if (lane == q) x_l = xq;
-        if (lane < q) a_l -= tri[q][lane] * xq;
-      }
-      if (lane < nb) x[(i0 + lane) * m + col] = x_l;
-    }
+    finish_in(i0, nb, acc0, acc1, bb, dd);
     __syncthreads();
-    if (threadIdx.x == 0) post_flag(bf + kb, epoch);
+    v4d y0 = zero4, y1 = zero4;
+    mma(true, y0, y1);
+    store_block(i0, nb, y0, y1);
+    if (G > 1 && threadIdx.x == 0) post_flag(bf + kb, epoch);
   }
 }
 
-// Work-groups per matrix for the single right-hand-side solve: as many as keep every
-// work-group of the launch resident at once (the waits rely on it), at most 4.
+// Work-groups per matrix: as many as keep every work-group of the launch resident at once
+// (the waits rely on it), with a quarter of the machine in reserve; at most GMAX for one
+// right-hand side, 8 for several.
 static int solve_groups(BandSet& bs, const void* kernel, int which) {
   if (bs.solve_groups[which] > 0) return bs.solve_groups[which];
   int dev = 0, cus = 0, per_cu = 0;
   GX_HIP(hipGetDevice(&dev));
   GX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   GX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, SOLVE_THREADS, 0));
-  // the waits need every work-group of the launch resident: keep a quarter in reserve
   const int64_t capacity = (int64_t)cus * std::max(per_cu, 0) * 3 / 4;
+  const int cap = which == 0 ? GMAX : 8;
   int G = 1;
-  const int top = bs.force_groups[which] > 0 ? std::min(bs.force_groups[which], 8) : 4;
+  const int top = bs.force_groups[which] > 0 ? std::min(bs.force_groups[which], cap)
+                                             : std::min(4, cap);
   for (int c = top; c >= 2; --c)
-    if ((int64_t)bs.n_mat * c <= capacity && bs.max_n >= (int64_t)4 * SB * c) {
+    if ((int64_t)bs.n_mat * c <= capacity && bs.max_n >= (int64_t)2 * SB * c) {
       G = c;
       break;
     }
@@ -787,81 +783,65 @@ static int solve_groups(BandSet& bs, const void* kernel, int which) {
   return G;
 }
 
-void band_solve(BandSet& bs, const int64_t* d_xoff, double* x64, float* x32, hipStream_t st,
-                int ncol, const int32_t* active) {
-  BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p};
-  if (ncol == 1 && !active && !(bs.fp32 && x32)) {
-    const int G = bs.fp32 ? solve_groups(bs, reinterpret_cast<const void*>(
-                                                 &k_band_solve_mw<float, double>), 0)
-                          : solve_groups(bs, reinterpret_cast<const void*>(
-                                                 &k_band_solve_mw<double, double>), 0);
-    if (G > 1) {
-      const int64_t nblk = (bs.max_n + SB - 1) / SB;
-      const int n_pad = (bs.n_mat + 7) / 8 * 8;
-      if (bs.flags.n != (size_t)(2 * n_pad * nblk + 1)) {
-        bs.flags.alloc(2 * n_pad * nblk + 1);
-        zero(bs.flags, st);
-        bs.epoch = 0;
-      }
-      ++bs.epoch;
-      int* fl = bs.flags.p;
-      if (bs.fp32)
-        hipLaunchKernelGGL((k_band_solve_mw<float, double>), dim3(G * n_pad), dim3(SOLVE_THREADS),
-                           0, st, a, bs.v32.p, d_xoff, x64, G, n_pad, bs.n_mat, fl,
-                           fl + n_pad * nblk,
-                           nblk, bs.epoch, fl + 2 * n_pad * nblk);
-      else
-        hipLaunchKernelGGL((k_band_solve_mw<double, double>), dim3(G * n_pad),
-                           dim3(SOLVE_THREADS), 0, st, a, bs.v64.p, d_xoff, x64, G, n_pad,
-                           bs.n_mat, fl, fl + n_pad * nblk, nblk, bs.epoch,
-                           fl + 2 * n_pad * nblk);
-      GX_HIP(hipGetLastError());
-      return;
-    }
+static int* solve_flags(BandSet& bs, hipStream_t st, int64_t& nblk, int& n_pad) {
+  nblk = (bs.max_n + SB - 1) / SB;
+  n_pad = (bs.n_mat + 7) / 8 * 8;                  // all groups of a matrix on one XCD
+  if (bs.flags.n != (size_t)(2 * n_pad * nblk + 1)) {
+    bs.flags.alloc(2 * n_pad * nblk + 1);
+    zero(bs.flags, st);
+    bs.epoch = 0;
   }
-  if (ncol == 1) {
-    const dim3 g(bs.n_mat, 1);
-    if (bs.fp32 && x32)
-      hipLaunchKernelGGL((k_band_solve<float, float, 1>), g, dim3(SOLVE_THREADS), 0, st, a,
-                         bs.v32.p, d_xoff, x32, 1, 1, active);
-    else if (bs.fp32)
-      hipLaunchKernelGGL((k_band_solve<float, double, 1>), g, dim3(SOLVE_THREADS), 0, st, a,
-                         bs.v32.p, d_xoff, x64, 1, 1, active);
-    else
-      hipLaunchKernelGGL((k_band_solve<double, double, 1>), g, dim3(SOLVE_THREADS), 0, st, a,
-                         bs.v64.p, d_xoff, x64, 1, 1, active);
-  } else if (ncol <= MC) {
-    const int G = bs.fp32 ? solve_groups(bs, reinterpret_cast<const void*>(
-                                                 &k_band_solve_mc<float>), 1)
-                          : solve_groups(bs, reinterpret_cast<const void*>(
-                                                 &k_band_solve_mc<double>), 1);
-    const int64_t nblk = (bs.max_n + SB - 1) / SB;
-    const int n_pad = (bs.n_mat + 7) / 8 * 8;
-    if (bs.flags.n != (size_t)(2 * n_pad * nblk + 1)) {
-      bs.flags.alloc(2 * n_pad * nblk + 1);
-      zero(bs.flags, st);
-      bs.epoch = 0;
-    }
-    ++bs.epoch;
-    int* fl = bs.flags.p;
+  ++bs.epoch;
+  return bs.flags.p;
+}
+
+void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, int ncol,
+                const int32_t* active) {
+  GX_REQUIRE(ncol >= 1 && ncol <= MC, "banded solve: unsupported number of right-hand sides");
+  BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p};
+  int64_t nblk = 0;
+  int n_pad = 0;
+  if (ncol == 1 && !active) {
+    const int G = bs.fp32 ? solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_1<float>), 0)
+                          : solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_1<double>), 0);
+    int* fl = solve_flags(bs, st, nblk, n_pad);
     if (bs.fp32)
-      hipLaunchKernelGGL((k_band_solve_mc<float>), dim3(G * n_pad), dim3(SOLVE_THREADS), 0, st,
-                         a, bs.v32.p, d_xoff, x64, ncol, G, n_pad, bs.n_mat, fl,
-                         fl + n_pad * nblk, nblk, bs.epoch, active, fl + 2 * n_pad * nblk);
+      hipLaunchKernelGGL(k_band_solve_1<float>, dim3(G * n_pad), dim3(SOLVE_THREADS), 0, st, a,
+                         bs.v32.p, bs.dinv32.p, bs.d_boff.p, d_xoff, x, G, n_pad, bs.n_mat, fl,
+                         fl + n_pad * nblk, nblk, bs.epoch, fl + 2 * n_pad * nblk);
     else
-      hipLaunchKernelGGL((k_band_solve_mc<double>), dim3(G * n_pad), dim3(SOLVE_THREADS), 0, st,
-                         a, bs.v64.p, d_xoff, x64, ncol, G, n_pad, bs.n_mat, fl,
-                         fl + n_pad * nblk, nblk, bs.epoch, active, fl + 2 * n_pad * nblk);
+      hipLaunchKernelGGL(k_band_solve_1<double>, dim3(G * n_pad), dim3(SOLVE_THREADS), 0, st, a,
+                         bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, G, n_pad, bs.n_mat, fl,
+                         fl + n_pad * nblk, nblk, bs.epoch, fl + 2 * n_pad * nblk);
   } else {
-    const dim3 g(bs.n_mat, (ncol + 7) / 8);
+    const int G = bs.fp32 ? solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_m<float>), 1)
+                          : solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_m<double>), 1);
+    int* fl = solve_flags(bs, st, nblk, n_pad);
     if (bs.fp32)
-      hipLaunchKernelGGL((k_band_solve<float, double, 8>), g, dim3(SOLVE_THREADS), 0, st, a,
-                         bs.v32.p, d_xoff, x64, ncol, ncol, active);
+      hipLaunchKernelGGL(k_band_solve_m<float>, dim3(G * n_pad), dim3(SOLVE_THREADS), 0, st, a,
+                         bs.v32.p, bs.dinv32.p, bs.d_boff.p, d_xoff, x, ncol, G, n_pad,
+                         bs.n_mat, fl, fl + n_pad * nblk, nblk, bs.epoch, active,
+                         fl + 2 * n_pad * nblk);
     else
-      hipLaunchKernelGGL((k_band_solve<double, double, 8>), g, dim3(SOLVE_THREADS), 0, st, a,
-                         bs.v64.p, d_xoff, x64, ncol, ncol, active);
+      hipLaunchKernelGGL(k_band_solve_m<double>, dim3(G * n_pad), dim3(SOLVE_THREADS), 0, st, a,
+                         bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, ncol, G, n_pad,
+                         bs.n_mat, fl, fl + n_pad * nblk, nblk, bs.epoch, active,
+                         fl + 2 * n_pad * nblk);
   }
   GX_HIP(hipGetLastError());
+}
+
+// Algorithmic bytes of one solve: the factor and the inverse diagonal blocks read once per
+// sweep, the FP64 right-hand sides read and written once per sweep.
+double band_solve_bytes(const BandSet& bs, int ncol) {
+  const double w = bs.fp32 ? 4.0 : 8.0;
+  double b = 0.0;
+  for (int j = 0; j < bs.n_mat; ++j) {
+    const double nblk = (double)((bs.n[j] + SB - 1) / SB);
+    b += 2.0 * w * ((double)bs.n[j] * (double)(bs.B[j] + 1) + nblk * SB * SB) +
+         4.0 * 8.0 * (double)bs.n[j] * ncol;
+  }
+  return b;
 }
 
 // Raises if a multi-work-group solve since the last check timed out waiting for a block.
@@ -903,13 +883,25 @@ void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<i
   to_dev(bs.d_B.p, bs.B.data(), n.size(), st);
   to_dev(bs.d_ld.p, bs.ld.data(), n.size(), st);
   to_dev(bs.d_off.p, bs.off.data(), n.size(), st);
+  bs.boff.assign(n.size() + 1, 0);
+  for (size_t j = 0; j < n.size(); ++j)
+    bs.boff[j + 1] = bs.boff[j] + (n[j] + SB - 1) / SB * SB * SB;
+  bs.d_boff.alloc(n.size() + 1);
+  to_dev(bs.d_boff.p, bs.boff.data(), n.size() + 1, st);
   if (fp32) {
     bs.v64.release();
-    bs.v32.alloc(o);
+    bs.dinv64.release();
+    bs.v32.alloc(o + BAND_PAD);
+    GX_HIP(hipMemsetAsync(bs.v32.p + o, 0, BAND_PAD * sizeof(float), st));
+    bs.dinv32.alloc(bs.boff[n.size()]);
   } else {
     bs.v32.release();
-    bs.v64.alloc(o);
+    bs.dinv32.release();
+    bs.v64.alloc(o + BAND_PAD);
+    GX_HIP(hipMemsetAsync(bs.v64.p + o, 0, BAND_PAD * sizeof(double), st));
+    bs.dinv64.alloc(bs.boff[n.size()]);
   }
+  bs.solve_groups[0] = bs.solve_groups[1] = 0;
   GX_HIP(hipStreamSynchronize(st));
 }
 

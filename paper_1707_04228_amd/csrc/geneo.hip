@@ -809,7 +809,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
                            active.p, theta.p, Y.p, BX.p, T.p);
       hipLaunchKernelGGL(k_scale_rows, gvec, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p,
                          d_doff.p, active.p, dM.p, T.p, T.p);
-      band_solve(Mb, d_voff.p, T.p, nullptr, s, m, active.p);
+      band_solve(Mb, d_voff.p, T.p, s, m, active.p);
       hipLaunchKernelGGL(k_scale_rows, gvec, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p,
                          d_doff.p, active.p, dM.p, T.p, T.p);
       if (itm == 0)
@@ -821,7 +821,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
     } else {
       hipLaunchKernelGGL(k_copy_active, gvec, dim3(256), 0, s, 3 * maxD * m, sw.d_nD.p, m,
                          d_voff.p, active.p, BX.p, Y.p);
-      band_solve(Mb, d_voff.p, Y.p, nullptr, s, m, active.p);
+      band_solve(Mb, d_voff.p, Y.p, s, m, active.p);
     }
     hipLaunchKernelGGL(k_bmul, growD, dim3(64), 0, s, g, m, d_voff.p, active.p, Y.p, BY.p);
     if (m32)

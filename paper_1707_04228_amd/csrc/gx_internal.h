@@ -114,6 +114,12 @@ struct BandSet {
   int max_n = 0, max_B = 0;
   DevBuf<double> v64;                          // FP64 storage (precision FP64)
   DevBuf<float> v32;                           // FP32 storage (mixed precision)
+  // inverses of the 64x64 diagonal blocks of the factors (row-major, identity-padded past
+  // the end of a matrix), block b of matrix j at boff[j] + 4096 b; same precision as v
+  std::vector<int64_t> boff;
+  DevBuf<int64_t> d_boff;
+  DevBuf<double> dinv64;
+  DevBuf<float> dinv32;
   bool fp32 = false;
   int solve_groups[2] = {0, 0};                // work-groups per matrix: 1-RHS, m-RHS solve
   int force_groups[2] = {0, 0};                // requested (0: automatic, capped by residency)
@@ -148,7 +154,6 @@ struct Schwarz {
   std::vector<std::vector<double>> lam;        // eigenvalues kept per subdomain
   // work vectors for applying P
   DevBuf<double> wr64, wx64;                   // gathered local rhs / solution (FP64)
-  DevBuf<float> wr32;                          // FP32 local work
   DevBuf<double> y0, y0b;                      // coarse rhs / solution
   DevBuf<double> y0part;                       // per-subdomain partial restriction
   int precision = GX_FP64;
@@ -203,8 +208,9 @@ void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<i
                  bool fp32, hipStream_t st);
 void band_factor(BandSet& bs, hipStream_t st);
 void band_solve_check(BandSet& bs, hipStream_t st);
-void band_solve(BandSet& bs, const int64_t* d_xoff, double* x64, float* x32, hipStream_t st,
-                int ncol = 1, const int32_t* active = nullptr);
+void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, int ncol = 1,
+                const int32_t* active = nullptr);
+double band_solve_bytes(const BandSet& bs, int ncol);
 struct Timer {
   hipStream_t s;
   std::chrono::steady_clock::time_point t0;

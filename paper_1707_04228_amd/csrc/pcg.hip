@@ -262,21 +262,16 @@ gx_status gx_kernel_time(gx_ctx* c, int32_t which, int32_t reps, double* avg_ms,
     if (which == 1) precond_apply(c, c->r.p, c->z.p);   // refills the local right-hand sides
     GX_HIP(hipEventRecord(ev.a, s));
     if (which == 0) spmv(c, c->p.p, c->q.p);
-    if (which == 1) band_solve(sw.A, sw.d_xoff.p, sw.wr64.p, sw.wr32.p, s);
+    if (which == 1) band_solve(sw.A, sw.d_xoff.p, sw.wr64.p, s);
     if (which == 2) precond_apply(c, c->r.p, c->z.p);
-    if (which == 3) band_solve(sw.C, sw.d_c_xoff.p, sw.y0.p, nullptr, s);
+    if (which == 3) band_solve(sw.C, sw.d_c_xoff.p, sw.y0.p, s);
     GX_HIP(hipEventRecord(ev.b, s));
     GX_HIP(hipGetLastError());
     GX_HIP(hipEventSynchronize(ev.b));
     tot += ev.ms();
   }
   if (which == 0) b = (double)c->nnzb * (72 + 4) + (double)c->n_nodes * (4 + 24 + 24);
-  if (which == 1 || which == 3) {
-    const BandSet& bs = which == 1 ? sw.A : sw.C;
-    const double w = bs.fp32 ? 4.0 : 8.0;
-    for (int j = 0; j < bs.n_mat; ++j)
-      b += 2.0 * w * (double)bs.n[j] * (double)(bs.B[j] + 1) + 4.0 * w * (double)bs.n[j];
-  }
+  if (which == 1 || which == 3) b = band_solve_bytes(which == 1 ? sw.A : sw.C, 1);
   if (avg_ms) *avg_ms = tot / reps;
   if (bytes) *bytes = b;
   GX_API_END(c)

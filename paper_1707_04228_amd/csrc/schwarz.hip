@@ -428,7 +428,7 @@ void precond_apply(gx_ctx* c, const double* r, double* z) {
   hipLaunchKernelGGL(k_gather_local<double>, dim3(nblocks(3 * maxI, 256), sw.n_sub),
                      dim3(256), 0, s, r, dg, sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p,
                      sw.d_xoff.p, sw.wr64.p);
-  band_solve(sw.A, sw.d_xoff.p, sw.wr64.p, nullptr, s);
+  band_solve(sw.A, sw.d_xoff.p, sw.wr64.p, s);
   const bool two = sw.two_level && sw.n0 > 0;
   if (two) {
     const int64_t nch = (3 * maxI + RCH - 1) / RCH;
@@ -437,7 +437,7 @@ void precond_apply(gx_ctx* c, const double* r, double* z) {
                        sw.d_c_off.p, nch, sw.Z.p, sw.y0part.p);
     hipLaunchKernelGGL(k_restrict_sum, dim3(nblocks(sw.n0, 256)), dim3(256), 0, s,
                        sw.y0part.p, sw.n0, nch, sw.y0.p);
-    band_solve(sw.C, sw.d_c_xoff.p, sw.y0.p, nullptr, s);
+    band_solve(sw.C, sw.d_c_xoff.p, sw.y0.p, s);
   }
   hipLaunchKernelGGL(k_combine<double>, dim3(nblocks(3 * N, 256)), dim3(256), 0, s,
                      sw.node_and.p, sw.W, N, sw.I_loc.p, sw.d_xoff.p, sw.wr64.p, dg,
