@@ -192,7 +192,8 @@ typedef struct {
   int32_t overlap;           /* element layers of overlap (>= 1) */
   double tau;                /* eigenvalue threshold (used when nev <= 0) */
   int32_t nev;               /* > 0: fixed number of modes per subdomain */
-  int32_t nev_max;           /* cap per subdomain (<= 48) */
+  int32_t nev_max;           /* cap per subdomain (<= 32; at most 30 are kept: the
+                                eigensolver block of 32 holds 2 guard vectors) */
   int32_t precision;         /* GX_FP64, or GX_MIXED: FP32 subdomain factors and solves */
   int32_t coarse;            /* 1: two-level (GenEO); 0: one-level Schwarz */
   const int32_t* nev_per_sub;/* optional host [n_sub]: modes per subdomain (overrides) */
@@ -225,6 +226,21 @@ gx_status gx_precond_apply(gx_ctx* ctx, const double* r, double* z);
  * ------------------------------------------------------------------------------------ */
 gx_status gx_pcg_solve(gx_ctx* ctx, const double* b, double* x, double rtol, int32_t maxit,
                        int32_t* iters_out, double* relres_out, double* hist);
+
+/* The subdomain solver on its own: batched banded Cholesky factorisation and triangular
+ * solves (section 2.4: the local problems are solved exactly by a direct method).
+ * n_mat matrices; matrix j has order n[j] and half bandwidth bw[j] (host arrays) and is
+ * given in row-major band storage: entry (r, c), r - bw[j] <= c <= r, at
+ * off_j + r (bw[j] + 1) + (c - r + bw[j]), off_j = sum over i < j of n[i] (bw[i] + 1)
+ * (device, FP64; copied, the input is not modified).  x (device) holds nrhs right-hand
+ * sides per matrix, row-major n[j] x nrhs, matrices concatenated; overwritten with the
+ * solutions.  nrhs is 1, 8, 16, 24 or 32.  precision GX_MIXED factors and solves with FP32
+ * factors of diag(A)^-1/2 A diag(A)^-1/2 (x stays FP64).  groups > 0 forces the number of
+ * work-groups per matrix (bounded by what stays resident), 0 chooses it.  GX_ENOTSPD on a
+ * non-positive pivot. */
+gx_status gx_band_factor_solve(gx_ctx* ctx, int32_t n_mat, const int64_t* n, const int64_t* bw,
+                               const double* band, int32_t precision, int32_t nrhs,
+                               int32_t groups, double* x);
 
 /* Measurement of one library kernel with HIP events on the context's stream: the average
  * duration over `reps` launches (ms) and the algorithmic bytes one launch must move

@@ -97,7 +97,9 @@ for _name, _args in [("gx_geneo_setup", [vp, C.POINTER(GeneoOpts), i32p, i64p]),
                      ("gx_pcg_solve", [vp, vp, vp, C.c_double, C.c_int32, i32p, f64p, f64p]),
                      ("gx_kernel_time", [vp, C.c_int32, C.c_int32, f64p, f64p]),
                      ("gx_stats", [vp, i64p]),
-                     ("gx_tune", [vp, C.c_int32, C.c_int64])]:
+                     ("gx_tune", [vp, C.c_int32, C.c_int64]),
+                     ("gx_band_factor_solve", [vp, C.c_int32, i64p, i64p, vp, C.c_int32,
+                                               C.c_int32, C.c_int32, vp])]:
     if hasattr(lib, _name):
         _sig(_name, _args)
 
@@ -105,7 +107,7 @@ EXPORTS = ["gx_create", "gx_destroy", "gx_last_error", "gx_version", "gx_laminat
            "gx_laminate_mesh", "gx_laminate_partition", "gx_laminate_traction",
            "gx_assemble", "gx_matrix_info", "gx_matrix_copy", "gx_spmv", "gx_geneo_setup",
            "gx_subdomain_info", "gx_geneo_eigenvalues", "gx_precond_apply", "gx_pcg_solve",
-           "gx_phase_times", "gx_kernel_time", "gx_stats", "gx_tune"]
+           "gx_phase_times", "gx_kernel_time", "gx_stats", "gx_tune", "gx_band_factor_solve"]
 
 
 class GxError(RuntimeError):
@@ -320,6 +322,17 @@ class Solver:
 
     def tune(self, param, value):
         self._check(lib.gx_tune(self.h, param, value))
+
+    def band_factor_solve(self, n, bw, band, x, precision=GX_FP64, groups=0):
+        """Factor the band matrices (row-major band storage, device FP64 tensor `band`) and
+        solve in place for x (device FP64, n[j] x nrhs per matrix, concatenated)."""
+        n = np.ascontiguousarray(n, dtype=np.int64)
+        bw = np.ascontiguousarray(bw, dtype=np.int64)
+        nrhs = x.numel() // int(n.sum())
+        self._check(lib.gx_band_factor_solve(self.h, len(n), n.ctypes.data_as(i64p),
+                                             bw.ctypes.data_as(i64p), _ptr(band), precision,
+                                             nrhs, groups, _ptr(x)))
+        return x
 
     def stats(self):
         out = np.zeros(5, dtype=np.int64)

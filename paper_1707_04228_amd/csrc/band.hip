@@ -404,8 +404,9 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
       }
     }
     T pf[RPW], dd[DL];
+    const int64_t cpred = k > 0 ? i0 - SB + lane : lane;   // block 0 has no predecessor
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) pf[r] = rp[r][i0 - SB + lane];
+    for (int r = 0; r < RPW; ++r) pf[r] = rp[r][cpred];
 #pragma unroll
     for (int u = 0; u < DL; ++u) dd[u] = dv[k * SB * SB + threadIdx.x + SOLVE_THREADS * u];
     for (int64_t kk = kdone; kk < k - 1; ++kk) {   // older blocks in flight (G > 2)
@@ -537,226 +538,198 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
   }
 }
 
-// ---- m right-hand sides per matrix (m <= MC, row-major, row stride m)
+// ---- M right-hand sides per matrix (M a multiple of 8, at most MC; row-major, row
+// stride M)
 // The block products - a 64-row block of the band against 64 solution rows, and the
-// inverse diagonal block against the block's right-hand side - are 64 x 64 x m and run on
-// FP64 matrix cores (v_mfma_f64_16x16x4: wave w owns row tile w mod 4 and the column
-// tiles w / 4 and w / 4 + 2; lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
-// holds D[4 r + l / 16][l % 16] in accumulator register r).  Band chunks are staged through LDS, the next chunk's loads
-// in flight in registers while the current one is multiplied.
+// inverse diagonal block against the block's right-hand side - are 64 x 64 x M and run on
+// FP64 matrix cores: v_mfma_f64_16x16x4, lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and holds D[4 r + l / 16][l % 16] in accumulator register r; wave w
+// of the 4 owns row tile w and all column tiles.  Chunks (64 x 64 of the band plus the
+// matching solution rows) are staged through LDS, the next chunk's loads in flight in
+// registers while the current one is multiplied; two work-groups share a compute unit.
 typedef double v4d __attribute__((ext_vector_type(4)));
-constexpr int MC = 48;                            // right-hand sides per launch, at most
-constexpr int YLD = MC + 1;
-constexpr int YL = SB * MC / SOLVE_THREADS;       // solution-chunk entries per thread (6)
+constexpr int MC = 32;                            // right-hand sides per launch, at most
+constexpr int MT = 256;                           // threads per work-group
+constexpr int AL = SB * SB / MT;                  // band-chunk entries per thread (16)
 
-template <class T>
-__global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_m(
+template <class T, int M>
+__global__ void __launch_bounds__(MT, 2) k_band_solve_m(
     BandArgs a, const T* v, const T* dinv, const int64_t* boff, const int64_t* xoff,
-    double* xall, int m, int G, int n_pad, int n_mat, int* fflag, int* bflag,
-    int64_t nblk_max, int epoch, const int32_t* active, int* err) {
+    double* xall, int G, int n_pad, int n_mat, int* fflag, int* bflag, int64_t nblk_max,
+    int epoch, const int32_t* active, int* err) {
+  constexpr int NCT = (M + 15) / 16;              // column tiles
+  constexpr int MP = 16 * NCT;                    // LDS row stride (zero columns past M)
+  constexpr int YL = SB * M / MT;                 // solution-chunk entries per thread
   __shared__ double Ab[SB][SB + 1];               // band chunk; the inverse block later
-  __shared__ double Yc[SB][YLD];                  // solution chunk; the block's rhs later
+  __shared__ double Yc[SB * MP];                  // solution chunk
   const int g = blockIdx.x / n_pad, j = blockIdx.x % n_pad;
   if (j >= n_mat || g >= G) return;
   if (active && !active[j]) return;
   const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
   if (n == 0) return;
-  const T* base = v + a.off[j];
+  const T* cb = v + a.off[j] + B;                 // entry (r, c) = cb[r * rs + c]
+  const int64_t rs = ld - 1;
   const T* dv = dinv + boff[j];
   double* x = xall + xoff[j];
   int* ff = fflag + (int64_t)j * nblk_max;
   int* bf = bflag + (int64_t)j * nblk_max;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;        // matrix-core operand coordinates
-  const int rt = wave & 3, ct0 = wave >> 2, ct1 = ct0 + 2;
-  const int nct = (m + 15) / 16;
-  const bool has0 = ct0 < nct, has1 = ct1 < nct;
+  const int lane = threadIdx.x & 63, rt = threadIdx.x >> 6;   // wave = row tile
+  const int li = lane & 15, lk = lane >> 4;
   const int64_t nblk = (n + SB - 1) / SB;
-  int yr[YL], yc[YL];                              // (row, column) of the staged entries
+  if (MP > M)
+    for (int idx = threadIdx.x; idx < SB * (MP - M); idx += MT)
+      Yc[(idx / (MP - M)) * MP + M + idx % (MP - M)] = 0.0;
+  // forward chunk kk of block i0: band rows i0.., columns 64 kk..; backward chunk kk:
+  // band rows 64 kk.., columns i0..; both with solution rows 64 kk..
+  auto fetch = [&](bool bwd, int64_t i0, int64_t kk, T (&fa)[AL], double (&fy)[YL]) {
+    const int64_t r0 = (bwd ? kk * SB : i0) + rt;
+    const int64_t c = (bwd ? i0 : kk * SB) + lane;
 #pragma unroll
-  for (int u = 0; u < YL; ++u) {
-    const int idx = threadIdx.x + SOLVE_THREADS * u;
-    yr[u] = idx < SB * m ? idx / m : SB;
-    yc[u] = idx < SB * m ? idx - (idx / m) * m : 0;
-  }
-  for (int idx = threadIdx.x; idx < SB * (YLD - m); idx += SOLVE_THREADS)
-    Yc[idx / (YLD - m)][m + idx % (YLD - m)] = 0.0;   // padding columns stay zero
-  // chunk fetch: forward chunk = band rows i0.. of columns c0..; backward chunk = band rows
-  // r0.. of columns i0..; solution rows of the chunk
-  auto fetch_f = [&](int64_t i0, int64_t c0, T (&fa)[DL], double (&fy)[YL]) {
+    for (int u = 0; u < AL; ++u) fa[u] = cb[min<int64_t>(r0 + 4 * u, n - 1) * rs + c];
+    const int64_t yend = min<int64_t>((int64_t)SB * M, (n - kk * SB) * M);   // rows < n
+    const double* xs = x + kk * SB * M;
 #pragma unroll
-    for (int u = 0; u < DL; ++u) {
-      const int idx = threadIdx.x + SOLVE_THREADS * u;
-      fa[u] = band_raw(base, n, B, ld, i0 + idx / SB, c0 + idx % SB);
-    }
-#pragma unroll
-    for (int u = 0; u < YL; ++u) fy[u] = x[min<int64_t>(c0 + yr[u], n - 1) * m + yc[u]];
+    for (int u = 0; u < YL; ++u) fy[u] = xs[min<int64_t>(threadIdx.x + MT * u, yend - 1)];
   };
-  auto stage_f = [&](int64_t i0, int64_t c0, const T (&fa)[DL], const double (&fy)[YL]) {
+  auto stage = [&](bool bwd, int64_t i0, int nb, int64_t kk, const T (&fa)[AL],
+                   const double (&fy)[YL]) {
+    const int64_t r0 = (bwd ? kk * SB : i0) + rt;
+    const int64_t c = (bwd ? i0 : kk * SB) + lane;
 #pragma unroll
-    for (int u = 0; u < DL; ++u) {
-      const int idx = threadIdx.x + SOLVE_THREADS * u;
-      const int64_t i = i0 + idx / SB, c = c0 + idx % SB;
-      Ab[idx / SB][idx % SB] = (i < n && c >= i - B && c <= i) ? (double)fa[u] : 0.0;
+    for (int u = 0; u < AL; ++u) {
+      const int64_t r = r0 + 4 * u;
+      const bool in = r < n && c <= r && c >= r - B && (!bwd || lane < nb);
+      Ab[rt + 4 * u][lane] = in ? (double)fa[u] : 0.0;
     }
+    const int64_t yend = min<int64_t>((int64_t)SB * M, (n - kk * SB) * M);   // rows < n
 #pragma unroll
-    for (int u = 0; u < YL; ++u)
-      if (yr[u] < SB) Yc[yr[u]][yc[u]] = fy[u];
-  };
-  auto fetch_b = [&](int64_t i0, int64_t r0, T (&fa)[DL], double (&fy)[YL]) {
-#pragma unroll
-    for (int u = 0; u < DL; ++u) {
-      const int idx = threadIdx.x + SOLVE_THREADS * u;
-      fa[u] = band_raw(base, n, B, ld, r0 + idx / SB, i0 + idx % SB);
+    for (int u = 0; u < YL; ++u) {
+      const int idx = threadIdx.x + MT * u;
+      Yc[(idx / M) * MP + idx % M] = idx < yend ? fy[u] : 0.0;
     }
-#pragma unroll
-    for (int u = 0; u < YL; ++u) fy[u] = x[min<int64_t>(r0 + yr[u], n - 1) * m + yc[u]];
   };
-  auto stage_b = [&](int64_t i0, int nb, int64_t r0, const T (&fa)[DL],
-                     const double (&fy)[YL]) {
-#pragma unroll
-    for (int u = 0; u < DL; ++u) {
-      const int idx = threadIdx.x + SOLVE_THREADS * u;
-      const int64_t r = r0 + idx / SB;
-      const int cl = idx % SB;
-      Ab[idx / SB][cl] = (r < n && cl < nb && r - B <= i0 + cl) ? (double)fa[u] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < YL; ++u)
-      if (yr[u] < SB) Yc[yr[u]][yc[u]] = r0 + yr[u] < n ? fy[u] : 0.0;
-  };
-  // acc += A Yc over the 64-deep chunk; A = Ab (forward) or Ab^T (backward)
-  auto mma = [&](bool trans, v4d& acc0, v4d& acc1) {
-    if (!has0) return;
-#pragma unroll 4
+  // acc[ct] += A Yc over the 64-deep chunk; A = Ab (forward) or Ab^T (backward)
+  constexpr int KU = NCT > 2 ? 2 : 4;              // k-steps unrolled (register budget)
+  auto mma = [&](bool trans, v4d (&acc)[NCT]) {
+#pragma unroll KU
     for (int ks = 0; ks < SB / 4; ++ks) {
       const int kq = 4 * ks + lk;
       const double av = trans ? Ab[kq][16 * rt + li] : Ab[16 * rt + li][kq];
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Yc[kq][16 * ct0 + li], acc0, 0, 0, 0);
-      if (has1)
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Yc[kq][16 * ct1 + li], acc1, 0, 0, 0);
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct)
+        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Yc[kq * MP + 16 * ct + li], acc[ct],
+                                                        0, 0, 0);
     }
   };
-  // block rhs minus the accumulated sums into Yc (rows < nb), inverse block into Ab
-  auto finish_in = [&](int64_t i0, int nb, const v4d& acc0, const v4d& acc1,
-                       const double (&bb)[2][4], const T (&dd)[DL]) {
+  // Yc <- rhs - accumulated sums (rows >= nb zero), Ab <- inverse block; the product with
+  // it is the block's solution, stored and published
+  auto finish = [&](bool bwd, int64_t i0, int nb, int64_t blk, const v4d (&acc)[NCT],
+                    int* flag) {
+    T dd[AL];
 #pragma unroll
-    for (int u = 0; u < DL; ++u) {
-      const int idx = threadIdx.x + SOLVE_THREADS * u;
-      Ab[idx / SB][idx % SB] = (double)dd[u];
-    }
-    if (has0) {
+    for (int u = 0; u < AL; ++u) dd[u] = dv[blk * SB * SB + threadIdx.x + MT * u];
+    double bb[NCT][4];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int ii = 16 * rt + 4 * r + lk;
-        const int c0 = 16 * ct0 + li, c1 = 16 * ct1 + li;
-        if (c0 < m) Yc[ii][c0] = ii < nb ? bb[0][r] - acc0[r] : 0.0;
-        if (has1 && c1 < m) Yc[ii][c1] = ii < nb ? bb[1][r] - acc1[r] : 0.0;
+        const int64_t row = min<int64_t>(i0 + 16 * rt + 4 * r + lk, n - 1);
+        bb[ct][r] = x[row * M + min(16 * ct + li, M - 1)];
       }
-    }
-  };
-  auto load_rhs = [&](int64_t i0, int nb, double (&bb)[2][4]) {
+    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int ii = 16 * rt + 4 * r + lk;
-      const int64_t row = min<int64_t>(i0 + ii, n - 1);
-      bb[0][r] = x[row * m + min(16 * ct0 + li, m - 1)];
-      bb[1][r] = x[row * m + min(16 * ct1 + li, m - 1)];
+    for (int u = 0; u < AL; ++u) {
+      const int idx = threadIdx.x + MT * u;
+      Ab[idx >> 6][idx & 63] = (double)dd[u];
     }
-  };
-  auto store_block = [&](int64_t i0, int nb, const v4d& y0, const v4d& y1) {
-    if (has0) {
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int ii = 16 * rt + 4 * r + lk;
-        const int c0 = 16 * ct0 + li, c1 = 16 * ct1 + li;
-        if (ii < nb && c0 < m) x[(i0 + ii) * m + c0] = y0[r];
-        if (has1 && ii < nb && c1 < m) x[(i0 + ii) * m + c1] = y1[r];
+        const int ii = 16 * rt + 4 * r + lk, col = 16 * ct + li;
+        if (col < M) Yc[ii * MP + col] = ii < nb ? bb[ct][r] - acc[ct][r] : 0.0;
       }
-    }
+    __syncthreads();
+    v4d y[NCT];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) y[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+    mma(bwd, y);
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ii = 16 * rt + 4 * r + lk, col = 16 * ct + li;
+        if (ii < nb && col < M) x[(i0 + ii) * M + col] = y[ct][r];
+      }
     // every wave's stores complete before the block is published
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
+    if (G > 1 && threadIdx.x == 0) post_flag(flag, epoch);
   };
-  const v4d zero4 = {0.0, 0.0, 0.0, 0.0};
   // ---- forward
   for (int64_t k = g; k < nblk; k += G) {
     const int64_t i0 = k * SB;
     const int nb = (int)min<int64_t>(SB, n - i0);
     const int64_t kfirst = max<int64_t>(i0 - B, 0) / SB;
     const int64_t kdone = max<int64_t>(k - G + 1, 0);          // chunks < kdone complete
-    v4d acc0 = zero4, acc1 = zero4;
-    T fa[DL];
-    double fy[YL];
-    int64_t kk = kfirst;
-    if (kk < kdone) fetch_f(i0, kk * SB, fa, fy);
-    for (; kk < kdone; ++kk) {
-      __syncthreads();
-      stage_f(i0, kk * SB, fa, fy);
-      __syncthreads();
-      if (kk + 1 < kdone) fetch_f(i0, (kk + 1) * SB, fa, fy);
-      mma(false, acc0, acc1);
-    }
-    T dd[DL];
+    const bool need_wait = G > 1 && k > 0;
+    v4d acc[NCT];
 #pragma unroll
-    for (int u = 0; u < DL; ++u) dd[u] = dv[k * SB * SB + threadIdx.x + SOLVE_THREADS * u];
-    double bb[2][4];
-    load_rhs(i0, nb, bb);
-    if (G > 1 && k > 0) wait_flag(ff + k - 1, epoch, err);
-    for (kk = max(kfirst, kdone); kk < k; ++kk) {
-      fetch_f(i0, kk * SB, fa, fy);
-      __syncthreads();
-      stage_f(i0, kk * SB, fa, fy);
-      __syncthreads();
-      mma(false, acc0, acc1);
+    for (int ct = 0; ct < NCT; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+    T fa[AL];
+    double fy[YL];
+    if (kfirst < k) {
+      if (need_wait && kfirst >= kdone) wait_flag(ff + k - 1, epoch, err);
+      fetch(false, i0, kfirst, fa, fy);
     }
-    __syncthreads();
-    finish_in(i0, nb, acc0, acc1, bb, dd);
-    __syncthreads();
-    v4d y0 = zero4, y1 = zero4;
-    mma(false, y0, y1);
-    store_block(i0, nb, y0, y1);
-    if (G > 1 && threadIdx.x == 0) post_flag(ff + k, epoch);
+    for (int64_t kk = kfirst; kk < k; ++kk) {
+      __syncthreads();
+      stage(false, i0, nb, kk, fa, fy);
+      __syncthreads();
+      if (kk + 1 < k) {
+        if (need_wait && kk + 1 == kdone) wait_flag(ff + k - 1, epoch, err);
+        fetch(false, i0, kk + 1, fa, fy);
+      }
+      mma(false, acc);
+    }
+    finish(false, i0, nb, k, acc, ff + k);
   }
-  // ---- backward
+  // ---- backward: chunks from the far end of the band inwards
   for (int64_t t = g; t < nblk; t += G) {
     const int64_t kb = nblk - 1 - t;
     const int64_t i0 = kb * SB;
     const int nb = (int)min<int64_t>(SB, n - i0);
     const int64_t klast = (min<int64_t>(n, i0 + nb + B) - 1) / SB;   // last row block
     const int64_t kdone = kb + G;                  // row blocks >= kdone complete
-    v4d acc0 = zero4, acc1 = zero4;
-    T fa[DL];
-    double fy[YL];
-    int64_t kk = klast;
-    if (kk >= kdone) fetch_b(i0, kk * SB, fa, fy);
-    for (; kk >= kdone; --kk) {
-      __syncthreads();
-      stage_b(i0, nb, kk * SB, fa, fy);
-      __syncthreads();
-      if (kk - 1 >= kdone) fetch_b(i0, (kk - 1) * SB, fa, fy);
-      mma(true, acc0, acc1);
-    }
-    T dd[DL];
+    int* wflag = kb + 1 < nblk ? bf + kb + 1 : ff + kb;
+    bool waited = G == 1;
+    v4d acc[NCT];
 #pragma unroll
-    for (int u = 0; u < DL; ++u) dd[u] = dv[kb * SB * SB + threadIdx.x + SOLVE_THREADS * u];
-    if (G > 1) wait_flag(kb + 1 < nblk ? bf + kb + 1 : ff + kb, epoch, err);
-    for (kk = min(klast, kdone - 1); kk > kb; --kk) {
-      fetch_b(i0, kk * SB, fa, fy);
-      __syncthreads();
-      stage_b(i0, nb, kk * SB, fa, fy);
-      __syncthreads();
-      mma(true, acc0, acc1);
+    for (int ct = 0; ct < NCT; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+    T fa[AL];
+    double fy[YL];
+    if (klast > kb) {
+      if (!waited && klast < kdone) {
+        wait_flag(wflag, epoch, err);
+        waited = true;
+      }
+      fetch(true, i0, klast, fa, fy);
     }
-    double bb[2][4];
-    load_rhs(i0, nb, bb);
-    __syncthreads();
-    finish_in(i0, nb, acc0, acc1, bb, dd);
-    __syncthreads();
-    v4d y0 = zero4, y1 = zero4;
-    mma(true, y0, y1);
-    store_block(i0, nb, y0, y1);
-    if (G > 1 && threadIdx.x == 0) post_flag(bf + kb, epoch);
+    for (int64_t kk = klast; kk > kb; --kk) {
+      __syncthreads();
+      stage(true, i0, nb, kk, fa, fy);
+      __syncthreads();
+      if (kk - 1 > kb) {
+        if (!waited && kk - 1 < kdone) {
+          wait_flag(wflag, epoch, err);
+          waited = true;
+        }
+        fetch(true, i0, kk - 1, fa, fy);
+      }
+      mma(true, acc);
+    }
+    if (!waited) wait_flag(wflag, epoch, err);
+    finish(true, i0, nb, kb, acc, bf + kb);
   }
 }
 
@@ -768,12 +741,12 @@ static int solve_groups(BandSet& bs, const void* kernel, int which) {
   int dev = 0, cus = 0, per_cu = 0;
   GX_HIP(hipGetDevice(&dev));
   GX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  GX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, SOLVE_THREADS, 0));
+  GX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel,
+                                                      which == 0 ? SOLVE_THREADS : MT, 0));
   const int64_t capacity = (int64_t)cus * std::max(per_cu, 0) * 3 / 4;
   const int cap = which == 0 ? GMAX : 8;
   int G = 1;
-  const int top = bs.force_groups[which] > 0 ? std::min(bs.force_groups[which], cap)
-                                             : std::min(4, cap);
+  const int top = bs.force_groups[which] > 0 ? std::min(bs.force_groups[which], cap) : cap;
   for (int c = top; c >= 2; --c)
     if ((int64_t)bs.n_mat * c <= capacity && bs.max_n >= (int64_t)2 * SB * c) {
       G = c;
@@ -795,9 +768,28 @@ static int* solve_flags(BandSet& bs, hipStream_t st, int64_t& nblk, int& n_pad) 
   return bs.flags.p;
 }
 
+template <int M>
+static void launch_m(BandSet& bs, const BandArgs& a, const int64_t* d_xoff, double* x,
+                     hipStream_t st, const int32_t* active) {
+  const int G = bs.fp32 ? solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_m<float, M>), 1)
+                        : solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_m<double, M>), 1);
+  int64_t nblk = 0;
+  int n_pad = 0;
+  int* fl = solve_flags(bs, st, nblk, n_pad);
+  if (bs.fp32)
+    hipLaunchKernelGGL((k_band_solve_m<float, M>), dim3(G * n_pad), dim3(MT), 0, st, a, bs.v32.p,
+                       bs.dinv32.p, bs.d_boff.p, d_xoff, x, G, n_pad, bs.n_mat, fl,
+                       fl + n_pad * nblk, nblk, bs.epoch, active, fl + 2 * n_pad * nblk);
+  else
+    hipLaunchKernelGGL((k_band_solve_m<double, M>), dim3(G * n_pad), dim3(MT), 0, st, a,
+                       bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, G, n_pad, bs.n_mat, fl,
+                       fl + n_pad * nblk, nblk, bs.epoch, active, fl + 2 * n_pad * nblk);
+}
+
 void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, int ncol,
                 const int32_t* active) {
-  GX_REQUIRE(ncol >= 1 && ncol <= MC, "banded solve: unsupported number of right-hand sides");
+  GX_REQUIRE(ncol == 1 || (ncol % 8 == 0 && ncol <= MC),
+             "banded solve: right-hand sides must be 1, 8, 16, 24 or 32");
   BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p};
   int64_t nblk = 0;
   int n_pad = 0;
@@ -814,19 +806,12 @@ void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, i
                          bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, G, n_pad, bs.n_mat, fl,
                          fl + n_pad * nblk, nblk, bs.epoch, fl + 2 * n_pad * nblk);
   } else {
-    const int G = bs.fp32 ? solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_m<float>), 1)
-                          : solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_m<double>), 1);
-    int* fl = solve_flags(bs, st, nblk, n_pad);
-    if (bs.fp32)
-      hipLaunchKernelGGL(k_band_solve_m<float>, dim3(G * n_pad), dim3(SOLVE_THREADS), 0, st, a,
-                         bs.v32.p, bs.dinv32.p, bs.d_boff.p, d_xoff, x, ncol, G, n_pad,
-                         bs.n_mat, fl, fl + n_pad * nblk, nblk, bs.epoch, active,
-                         fl + 2 * n_pad * nblk);
-    else
-      hipLaunchKernelGGL(k_band_solve_m<double>, dim3(G * n_pad), dim3(SOLVE_THREADS), 0, st, a,
-                         bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, ncol, G, n_pad,
-                         bs.n_mat, fl, fl + n_pad * nblk, nblk, bs.epoch, active,
-                         fl + 2 * n_pad * nblk);
+    switch (ncol) {
+      case 8: launch_m<8>(bs, a, d_xoff, x, st, active); break;
+      case 16: launch_m<16>(bs, a, d_xoff, x, st, active); break;
+      case 24: launch_m<24>(bs, a, d_xoff, x, st, active); break;
+      default: launch_m<32>(bs, a, d_xoff, x, st, active); break;
+    }
   }
   GX_HIP(hipGetLastError());
 }
@@ -904,5 +889,95 @@ void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<i
   bs.solve_groups[0] = bs.solve_groups[1] = 0;
   GX_HIP(hipStreamSynchronize(st));
 }
+
+
+// ---------------------------------------------------------------------------------------
+// Stand-alone factor-and-solve of caller-supplied band matrices (exposed for testing the
+// subdomain solver in isolation).
+__global__ void k_band_import(int64_t total, const double* src, const double* dscale,
+                              const int64_t* off, const int64_t* nn, const int64_t* bw,
+                              const int64_t* doff, int n_mat, float* d32, double* d64) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  int j = 0;
+  while (j + 1 < n_mat && off[j + 1] <= e) ++j;
+  const int64_t B = bw[j], r = (e - off[j]) / (B + 1), c = r + (e - off[j]) % (B + 1) - B;
+  double v = src[e];
+  if (dscale) v *= (c >= 0) ? dscale[doff[j] + r] * dscale[doff[j] + c] : 0.0;
+  if (d32) d32[e] = (float)v;
+  else d64[e] = v;
+}
+
+__global__ void k_band_diag(int64_t rows, const double* src, const int64_t* off,
+                            const int64_t* nn, const int64_t* bw, const int64_t* doff, int n_mat,
+                            double* dscale) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= rows) return;
+  int j = 0;
+  while (j + 1 < n_mat && doff[j + 1] <= q) ++j;
+  const int64_t r = q - doff[j];
+  const double d = src[off[j] + r * (bw[j] + 1) + bw[j]];
+  dscale[q] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
+}
+
+__global__ void k_scale_rhs(int64_t rows, int nrhs, const double* dscale, double* x) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * nrhs) return;
+  x[e] *= dscale[e / nrhs];
+}
+
+}  // namespace gx
+
+extern "C" gx_status gx_band_factor_solve(gx_ctx* c, int32_t n_mat, const int64_t* n,
+                                          const int64_t* bw, const double* band,
+                                          int32_t precision, int32_t nrhs, int32_t groups,
+                                          double* x) {
+  using namespace gx;
+  GX_API_BEGIN(c)
+  GX_REQUIRE(n_mat >= 1 && n && bw && band && x, "bad band matrices");
+  GX_REQUIRE(precision == GX_FP64 || precision == GX_MIXED, "bad precision");
+  GX_REQUIRE(nrhs == 1 || (nrhs % 8 == 0 && nrhs <= MC), "nrhs must be 1, 8, 16, 24 or 32");
+  std::vector<int64_t> nv(n, n + n_mat), bv(bw, bw + n_mat), off(n_mat + 1, 0),
+      doff(n_mat + 1, 0), xoff(n_mat);
+  for (int j = 0; j < n_mat; ++j) {
+    GX_REQUIRE(nv[j] >= 1 && bv[j] >= 0 && bv[j] < nv[j], "bad order or bandwidth");
+    off[j + 1] = off[j] + nv[j] * (bv[j] + 1);
+    doff[j + 1] = doff[j] + nv[j];
+    xoff[j] = doff[j] * nrhs;
+  }
+  hipStream_t s = c->stream;
+  const bool fp32 = precision == GX_MIXED;
+  BandSet bs;
+  band_layout(bs, nv, bv, fp32, s);
+  bs.force_groups[0] = bs.force_groups[1] = groups;
+  DevBuf<int64_t> d_off(n_mat + 1), d_doff(n_mat + 1), d_xoff(n_mat);
+  to_dev(d_off.p, off.data(), n_mat + 1, s);
+  to_dev(d_doff.p, doff.data(), n_mat + 1, s);
+  to_dev(d_xoff.p, xoff.data(), n_mat, s);
+  DevBuf<double> dsc;
+  if (fp32) {
+    dsc.alloc(doff[n_mat]);
+    hipLaunchKernelGGL(k_band_diag, dim3(nblocks(doff[n_mat], 256)), dim3(256), 0, s,
+                       doff[n_mat], band, d_off.p, bs.d_n.p, bs.d_B.p, d_doff.p, n_mat, dsc.p);
+  }
+  hipLaunchKernelGGL(k_band_import, dim3(nblocks(off[n_mat], 256)), dim3(256), 0, s,
+                     off[n_mat], band, fp32 ? dsc.p : nullptr, d_off.p, bs.d_n.p, bs.d_B.p,
+                     d_doff.p, n_mat, fp32 ? bs.v32.p : nullptr, fp32 ? nullptr : bs.v64.p);
+  GX_HIP(hipGetLastError());
+  band_factor(bs, s);
+  if (fp32)
+    hipLaunchKernelGGL(k_scale_rhs, dim3(nblocks(doff[n_mat] * nrhs, 256)), dim3(256), 0, s,
+                       doff[n_mat], nrhs, dsc.p, x);
+  band_solve(bs, d_xoff.p, x, s, nrhs);
+  if (fp32)
+    hipLaunchKernelGGL(k_scale_rhs, dim3(nblocks(doff[n_mat] * nrhs, 256)), dim3(256), 0, s,
+                       doff[n_mat], nrhs, dsc.p, x);
+  GX_HIP(hipGetLastError());
+  band_solve_check(bs, s);
+  GX_HIP(hipStreamSynchronize(s));
+  GX_API_END(c)
+}
+
+namespace gx {
 
 }  // namespace gx

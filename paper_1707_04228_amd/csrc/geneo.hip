@@ -20,7 +20,7 @@
 
 namespace gx {
 
-constexpr int MAXM = 40;                       // eigensolver block size limit
+constexpr int MAXM = 32;                       // eigensolver block size limit (multiple of 8)
 
 __device__ inline bool has_bit(const uint64_t* mask, int64_t item, int W, int j) {
   return (mask[item * W + j / 64] >> (j % 64)) & 1ull;
@@ -518,35 +518,40 @@ __global__ void __launch_bounds__(256) k_rotate(const int64_t* nrows, int m,
   out[voff[j] + row * m + b] = s;
 }
 
-// per column: ||MX - theta BX||^2 and ||MX||^2 (chunk partials, then fixed-order sums)
+// per column: ||MX - theta BX||^2, ||MX||^2 and ||X||^2 (chunk partials, then fixed-order
+// sums)
 __global__ void __launch_bounds__(256) k_resid(const int64_t* nrows, int m,
                                                const int64_t* voff, const int32_t* active,
                                                const double* theta, const double* MX,
-                                               const double* BX, int64_t nch_max,
-                                               double* part) {
-  __shared__ double red[4][2][64];
+                                               const double* BX, const double* X,
+                                               int64_t nch_max, double* part) {
+  __shared__ double red[4][3][64];
   const int j = blockIdx.y;
   if (!active[j]) return;
   const int64_t n3 = 3 * nrows[j];
   const int b = threadIdx.x % 64, rg = threadIdx.x / 64;
-  double r2 = 0, m2 = 0;
+  double r2 = 0, m2 = 0, x2 = 0;
   if (b < m) {
     const double th = theta[(int64_t)j * MAXM + b];
     const int64_t r0 = (int64_t)blockIdx.x * GCH;
     for (int64_t row = r0 + rg; row < min(n3, r0 + GCH); row += 4) {
-      const double mx = MX[voff[j] + row * m + b];
-      const double d = mx - th * BX[voff[j] + row * m + b];
+      const int64_t e = voff[j] + row * m + b;
+      const double mx = MX[e];
+      const double d = mx - th * BX[e];
       r2 += d * d;
       m2 += mx * mx;
+      x2 += X[e] * X[e];
     }
   }
   red[rg][0][b] = r2;
   red[rg][1][b] = m2;
+  red[rg][2][b] = x2;
   __syncthreads();
   if (rg == 0 && b < m) {
-    double* pj = part + ((int64_t)j * nch_max + blockIdx.x) * 2 * MAXM;
-    pj[b] = red[0][0][b] + red[1][0][b] + red[2][0][b] + red[3][0][b];
-    pj[MAXM + b] = red[0][1][b] + red[1][1][b] + red[2][1][b] + red[3][1][b];
+    double* pj = part + ((int64_t)j * nch_max + blockIdx.x) * 3 * MAXM;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      pj[q * MAXM + b] = red[0][q][b] + red[1][q][b] + red[2][q][b] + red[3][q][b];
   }
 }
 
@@ -554,11 +559,11 @@ __global__ void k_resid_sum(const int64_t* nrows, const int32_t* active, int64_t
                             const double* part, double* out) {
   const int j = blockIdx.x;
   const int e = threadIdx.x;
-  if (!active[j] || e >= 2 * MAXM) return;
+  if (!active[j] || e >= 3 * MAXM) return;
   const int64_t nch = (3 * nrows[j] + GCH - 1) / GCH;
   double s = 0.0;
-  for (int64_t k = 0; k < nch; ++k) s += part[((int64_t)j * nch_max + k) * 2 * MAXM + e];
-  out[(int64_t)j * 2 * MAXM + e] = s;
+  for (int64_t k = 0; k < nch; ++k) s += part[((int64_t)j * nch_max + k) * 3 * MAXM + e];
+  out[(int64_t)j * 3 * MAXM + e] = s;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -693,7 +698,8 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   const int n_sub = sw.n_sub;
   const int64_t N = c->n_nodes;
   const double tau = o->tau > 0 ? o->tau : 0.1;
-  const int nev_max = o->nev_max > 0 ? o->nev_max : 32;
+  // at most MAXM - 2 modes per subdomain fit the eigensolver block (two guard vectors)
+  const int nev_max = std::min(o->nev_max > 0 ? o->nev_max : 32, MAXM - 2);
   std::vector<int> want(n_sub, o->nev > 0 ? o->nev : 0);
   if (o->nev_per_sub)
     for (int j = 0; j < n_sub; ++j) want[j] = o->nev_per_sub[j];
@@ -762,7 +768,9 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   const bool m32 = Mb.fp32;
   // block size: fixed count + 8 guard vectors; with a threshold, start at 24 and double
   // while some subdomain's selected modes reach into the guard
-  int m = fixed_count ? std::min(MAXM, mwant + 8) : std::min(MAXM, std::min(24, mwant + 8));
+  // block sizes are multiples of 8 (the multi-right-hand-side solves are built for them)
+  auto round8 = [](int v) { return std::min(MAXM, (v + 7) / 8 * 8); };
+  int m = fixed_count ? round8(mwant + 8) : round8(std::min(24, mwant + 8));
   std::vector<int64_t> voff;
   DevBuf<int64_t> d_voff;
   DevBuf<double> X;
@@ -784,7 +792,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   for (int j = 0; j < n_sub; ++j) nch_max = std::max(nch_max, (3 * sw.nD[j] + GCH - 1) / GCH);
   DevBuf<double> gpart((size_t)n_sub * nch_max * 2 * MAXM * MAXM), G((size_t)n_sub * 2 * MAXM * MAXM);
   DevBuf<double> Cm((size_t)n_sub * MAXM * MAXM), theta((size_t)n_sub * MAXM);
-  DevBuf<double> rpart((size_t)n_sub * nch_max * 2 * MAXM), rsum((size_t)n_sub * 2 * MAXM);
+  DevBuf<double> rpart((size_t)n_sub * nch_max * 3 * MAXM), rsum((size_t)n_sub * 3 * MAXM);
   DevBuf<int> err(1);
   zero(err, s);
   const dim3 growD((unsigned)maxD, n_sub);
@@ -793,7 +801,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   const dim3 gch((unsigned)nch_max, n_sub);
   hipLaunchKernelGGL(k_rand_init, gvec, dim3(256), 0, s, g, m, d_voff.p, X.p);
   hipLaunchKernelGGL(k_bmul, growD, dim3(64), 0, s, g, m, d_voff.p, active.p, X.p, BX.p);
-  std::vector<double> h_theta((size_t)n_sub * MAXM), h_res((size_t)n_sub * 2 * MAXM);
+  std::vector<double> h_theta((size_t)n_sub * MAXM), h_res((size_t)n_sub * 3 * MAXM);
   lam_final.assign((size_t)n_sub * MAXM, 0.0);
   int n_active = n_sub;
   for (int itm = 0; itm < maxit && n_active > 0; ++itm, ++it) {
@@ -840,8 +848,8 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
     hipLaunchKernelGGL(k_rotate, grows, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p, active.p,
                        Cm.p, BY.p, BX.p);           // B X_new
     hipLaunchKernelGGL(k_resid, gch, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p, active.p,
-                       theta.p, Y.p, BX.p, nch_max, rpart.p);
-    hipLaunchKernelGGL(k_resid_sum, dim3(n_sub), dim3(2 * MAXM), 0, s, sw.d_nD.p, active.p,
+                       theta.p, Y.p, BX.p, T.p, nch_max, rpart.p);
+    hipLaunchKernelGGL(k_resid_sum, dim3(n_sub), dim3(3 * MAXM), 0, s, sw.d_nD.p, active.p,
                        nch_max, rpart.p, rsum.p);
     // new X into X for the active subdomains
     hipLaunchKernelGGL(k_copy_active, gvec, dim3(256), 0, s, 3 * maxD * m, sw.d_nD.p, m,
@@ -863,12 +871,16 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
         while (w < m - 2 && h_theta[j * MAXM + w] - sigma < 1.5 * tau) ++w;
         w = std::min(w + 1, m - 2);               // one pair beyond the margin as well
       }
+      // backward-error test: ||M x - theta B x|| <= tol * S ||x||, S = max over the block of
+      // ||M x|| / ||x|| (an estimate of ||M||).  Relative to ||M x|| alone the test cannot
+      // pass for rigid-body modes, whose M x = sigma B x is tiny: rounding sets the floor.
+      const double* rj = h_res.data() + (size_t)j * 3 * MAXM;
+      double S = 0.0;
+      for (int a = 0; a < m; ++a)
+        if (rj[2 * MAXM + a] > 0.0) S = std::max(S, std::sqrt(rj[MAXM + a] / rj[2 * MAXM + a]));
       bool ok = true;
-      for (int a = 0; a < w; ++a) {
-        const double r = std::sqrt(h_res[j * 2 * MAXM + a]);
-        const double nm = std::sqrt(h_res[j * 2 * MAXM + MAXM + a]);
-        if (!(r <= tol * nm)) ok = false;
-      }
+      for (int a = 0; a < w; ++a)
+        if (!(std::sqrt(rj[a]) <= tol * S * std::sqrt(rj[2 * MAXM + a]))) ok = false;
       if (ok) {
         act[j] = 0;
         --n_active;
@@ -888,7 +900,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
       if (k > m - 8) grow = true;
     }
   if (!grow) break;
-  m = std::min(MAXM, std::min(2 * m, nev_max + 8));
+  m = round8(std::min(2 * m, nev_max + 8));
   }
   // selection
   sw.nev.assign(n_sub, 0);

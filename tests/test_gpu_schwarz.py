@@ -29,7 +29,7 @@ def gx():
     return gx
 
 
-def _setup(gx, cfg, coarse, precision=0, nev_per_sub=None):
+def _setup(gx, cfg, coarse, precision=0, nev_per_sub=None, eig_tol=0.0):
     s = gx.Solver()
     s.laminate(cfg)
     f = s.assemble()
@@ -37,7 +37,7 @@ def _setup(gx, cfg, coarse, precision=0, nev_per_sub=None):
     part = s.partition(cfg, sv["px"], sv["py"])
     s.geneo_setup(part, sv["px"] * sv["py"], overlap=sv["overlap"], tau=sv["tau"] or 0.1,
                   nev=sv["nev"] or 0, nev_max=sv["nev_max"], coarse=coarse,
-                  precision=precision, nev_per_sub=nev_per_sub)
+                  precision=precision, nev_per_sub=nev_per_sub, eig_tol=eig_tol)
     return s, f, part
 
 
