@@ -246,7 +246,9 @@ gx_status gx_band_factor_solve(gx_ctx* ctx, int32_t n_mat, const int64_t* n, con
  * duration over `reps` launches (ms) and the algorithmic bytes one launch must move
  * (bytes, 0 when not defined).  which: 0 = block-CSR product y = K x; 1 = the batched
  * subdomain band solves of one preconditioner application (forward and backward);
- * 2 = one whole preconditioner application; 3 = the coarse solve. */
+ * 2 = one whole preconditioner application; 3 = the coarse solve; 4 = the GenEO
+ * eigensolver's multi-right-hand-side band solves, as timed during the last
+ * gx_geneo_setup (average per solve; reps is ignored). */
 gx_status gx_kernel_time(gx_ctx* ctx, int32_t which, int32_t reps, double* avg_ms,
                          double* bytes);
 

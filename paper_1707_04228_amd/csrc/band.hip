@@ -348,7 +348,8 @@ __device__ inline double reduce_rows8(const double (&s)[RPW], int lane) {
 // with 0 or 1, so that a wave issues all loads of a step before it waits for any.
 // Blocks in flight are added oldest first, each after its own flag; the entries of the
 // predecessor block - the last to complete - are loaded before the waits.
-template <class T>
+// COARSE only names the instance used for the coarse matrix apart in profiles.
+template <class T, bool COARSE>
 __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
     BandArgs a, const T* v, const T* dinv, const int64_t* boff, const int64_t* xoff,
     double* xall, int G, int n_pad, int n_mat, int* fflag, int* bflag, int64_t nblk_max,
@@ -794,17 +795,23 @@ void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, i
   int64_t nblk = 0;
   int n_pad = 0;
   if (ncol == 1 && !active) {
-    const int G = bs.fp32 ? solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_1<float>), 0)
-                          : solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_1<double>), 0);
+    const void* kf = bs.fp32 ? reinterpret_cast<const void*>(&k_band_solve_1<float, false>)
+                   : bs.coarse ? reinterpret_cast<const void*>(&k_band_solve_1<double, true>)
+                               : reinterpret_cast<const void*>(&k_band_solve_1<double, false>);
+    const int G = solve_groups(bs, kf, 0);
     int* fl = solve_flags(bs, st, nblk, n_pad);
     if (bs.fp32)
-      hipLaunchKernelGGL(k_band_solve_1<float>, dim3(G * n_pad), dim3(SOLVE_THREADS), 0, st, a,
-                         bs.v32.p, bs.dinv32.p, bs.d_boff.p, d_xoff, x, G, n_pad, bs.n_mat, fl,
-                         fl + n_pad * nblk, nblk, bs.epoch, fl + 2 * n_pad * nblk);
+      hipLaunchKernelGGL((k_band_solve_1<float, false>), dim3(G * n_pad), dim3(SOLVE_THREADS), 0,
+                         st, a, bs.v32.p, bs.dinv32.p, bs.d_boff.p, d_xoff, x, G, n_pad,
+                         bs.n_mat, fl, fl + n_pad * nblk, nblk, bs.epoch, fl + 2 * n_pad * nblk);
+    else if (bs.coarse)
+      hipLaunchKernelGGL((k_band_solve_1<double, true>), dim3(G * n_pad), dim3(SOLVE_THREADS), 0,
+                         st, a, bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, G, n_pad,
+                         bs.n_mat, fl, fl + n_pad * nblk, nblk, bs.epoch, fl + 2 * n_pad * nblk);
     else
-      hipLaunchKernelGGL(k_band_solve_1<double>, dim3(G * n_pad), dim3(SOLVE_THREADS), 0, st, a,
-                         bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, G, n_pad, bs.n_mat, fl,
-                         fl + n_pad * nblk, nblk, bs.epoch, fl + 2 * n_pad * nblk);
+      hipLaunchKernelGGL((k_band_solve_1<double, false>), dim3(G * n_pad), dim3(SOLVE_THREADS), 0,
+                         st, a, bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, G, n_pad,
+                         bs.n_mat, fl, fl + n_pad * nblk, nblk, bs.epoch, fl + 2 * n_pad * nblk);
   } else {
     switch (ncol) {
       case 8: launch_m<8>(bs, a, d_xoff, x, st, active); break;
@@ -818,10 +825,11 @@ void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, i
 
 // Algorithmic bytes of one solve: the factor and the inverse diagonal blocks read once per
 // sweep, the FP64 right-hand sides read and written once per sweep.
-double band_solve_bytes(const BandSet& bs, int ncol) {
+double band_solve_bytes(const BandSet& bs, int ncol, const int32_t* active_host) {
   const double w = bs.fp32 ? 4.0 : 8.0;
   double b = 0.0;
   for (int j = 0; j < bs.n_mat; ++j) {
+    if (active_host && !active_host[j]) continue;
     const double nblk = (double)((bs.n[j] + SB - 1) / SB);
     b += 2.0 * w * ((double)bs.n[j] * (double)(bs.B[j] + 1) + nblk * SB * SB) +
          4.0 * 8.0 * (double)bs.n[j] * ncol;

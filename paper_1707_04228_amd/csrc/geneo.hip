@@ -776,6 +776,9 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   DevBuf<double> X;
   std::vector<double> lam_final;
   int it = 0;
+  EventPair ev;
+  c->mrhs_ms = c->mrhs_bytes = 0.0;
+  c->mrhs_calls = 0;
   for (;;) {
   voff.assign(n_sub + 1, 0);
   for (int j = 0; j < n_sub; ++j) voff[j + 1] = voff[j] + 3 * sw.nD[j] * m;
@@ -817,7 +820,9 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
                            active.p, theta.p, Y.p, BX.p, T.p);
       hipLaunchKernelGGL(k_scale_rows, gvec, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p,
                          d_doff.p, active.p, dM.p, T.p, T.p);
+      GX_HIP(hipEventRecord(ev.a, s));
       band_solve(Mb, d_voff.p, T.p, s, m, active.p);
+      GX_HIP(hipEventRecord(ev.b, s));
       hipLaunchKernelGGL(k_scale_rows, gvec, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p,
                          d_doff.p, active.p, dM.p, T.p, T.p);
       if (itm == 0)
@@ -829,7 +834,9 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
     } else {
       hipLaunchKernelGGL(k_copy_active, gvec, dim3(256), 0, s, 3 * maxD * m, sw.d_nD.p, m,
                          d_voff.p, active.p, BX.p, Y.p);
+      GX_HIP(hipEventRecord(ev.a, s));
       band_solve(Mb, d_voff.p, Y.p, s, m, active.p);
+      GX_HIP(hipEventRecord(ev.b, s));
     }
     hipLaunchKernelGGL(k_bmul, growD, dim3(64), 0, s, g, m, d_voff.p, active.p, Y.p, BY.p);
     if (m32)
@@ -857,6 +864,9 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
     GX_HIP(hipGetLastError());
     to_host(h_theta.data(), theta.p, h_theta.size(), s);
     to_host(h_res.data(), rsum.p, h_res.size(), s);
+    c->mrhs_ms += ev.ms();
+    c->mrhs_bytes += band_solve_bytes(Mb, m, act.data());
+    ++c->mrhs_calls;
     int herr = 0;
     to_host(&herr, err.p, 1, s);
     if (herr) throw Error(GX_ENOCONV, "GenEO eigensolver: basis lost rank");
@@ -960,6 +970,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   hipLaunchKernelGGL(k_coarse_pair, dim3(n_sub, n_sub), dim3(256), 0, s, g, cd, n_sub, adj.p,
                      sw.Z.p, Vc.p, d_vco.p, n0, K0.p);
   band_layout(sw.C, {n0}, {n0 - 1}, false, s);
+  sw.C.coarse = true;
   zero(sw.C.v64, s);
   hipLaunchKernelGGL(k_coarse_fill, dim3(nblocks(n0 * n0, 256)), dim3(256), 0, s, n0, K0.p,
                      sw.C.v64.p);

@@ -124,6 +124,7 @@ struct BandSet {
   int solve_groups[2] = {0, 0};                // work-groups per matrix: 1-RHS, m-RHS solve
   int force_groups[2] = {0, 0};                // requested (0: automatic, capped by residency)
   DevBuf<int> flags;                           // block completion flags (+ error word)
+  bool coarse = false;                         // the coarse matrix (own solve kernel name)
   int epoch = 0;
 };
 
@@ -189,6 +190,9 @@ struct gx_ctx {
   int64_t neumann_entries = 0;
   int32_t fp64_fallbacks = 0;                  // bit 0: interior, bit 1: eigensolver factors
   double phase_ms[8] = {0};
+  // the eigensolver's multi-right-hand-side band solves of the last setup (HIP events)
+  double mrhs_ms = 0.0, mrhs_bytes = 0.0;
+  int64_t mrhs_calls = 0;
   int tune[4] = {0, 0, 0, 0};                  // see gx_tune
 };
 
@@ -210,7 +214,25 @@ void band_factor(BandSet& bs, hipStream_t st);
 void band_solve_check(BandSet& bs, hipStream_t st);
 void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, int ncol = 1,
                 const int32_t* active = nullptr);
-double band_solve_bytes(const BandSet& bs, int ncol);
+double band_solve_bytes(const BandSet& bs, int ncol, const int32_t* active_host = nullptr);
+// HIP event pair on a stream (timing of single launches)
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    GX_HIP(hipEventCreate(&a));
+    GX_HIP(hipEventCreate(&b));
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  float ms() const {
+    float t = 0;
+    GX_HIP(hipEventElapsedTime(&t, a, b));
+    return t;
+  }
+};
+
 struct Timer {
   hipStream_t s;
   std::chrono::steady_clock::time_point t0;

@@ -101,22 +101,6 @@ static void dot(gx_ctx* c, const double* a, const double* b, int dst, int mode) 
                      dst, mode);
 }
 
-struct EventPair {
-  hipEvent_t a = nullptr, b = nullptr;
-  EventPair() {
-    GX_HIP(hipEventCreate(&a));
-    GX_HIP(hipEventCreate(&b));
-  }
-  ~EventPair() {
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
-  }
-  float ms() const {
-    float t = 0;
-    GX_HIP(hipEventElapsedTime(&t, a, b));
-    return t;
-  }
-};
 
 }  // namespace gx
 
@@ -238,7 +222,13 @@ gx_status gx_pcg_solve(gx_ctx* c, const double* b, double* x, double rtol, int32
 gx_status gx_kernel_time(gx_ctx* c, int32_t which, int32_t reps, double* avg_ms,
                          double* bytes) {
   GX_API_BEGIN(c)
-  GX_REQUIRE(reps >= 1 && which >= 0 && which <= 3, "bad kernel id or repetition count");
+  GX_REQUIRE(reps >= 1 && which >= 0 && which <= 4, "bad kernel id or repetition count");
+  if (which == 4) {                                // recorded during the last setup
+    if (!c->setup_done || c->mrhs_calls == 0) throw Error(GX_ESTATE, "no eigensolver solves recorded");
+    if (avg_ms) *avg_ms = c->mrhs_ms / (double)c->mrhs_calls;
+    if (bytes) *bytes = c->mrhs_bytes / (double)c->mrhs_calls;
+    return GX_OK;
+  }
   if (!c->assembled) throw Error(GX_ESTATE, "matrix not assembled");
   if (which >= 1 && !c->setup_done) throw Error(GX_ESTATE, "preconditioner not set up");
   if (which == 3 && !(c->sw.two_level && c->sw.n0 > 0)) throw Error(GX_ESTATE, "no coarse space");
