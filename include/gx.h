@@ -227,6 +227,29 @@ gx_status gx_precond_apply(gx_ctx* ctx, const double* r, double* z);
 gx_status gx_pcg_solve(gx_ctx* ctx, const double* b, double* x, double rtol, int32_t maxit,
                        int32_t* iters_out, double* relres_out, double* hist);
 
+/* ------------------------------------------------------------------------------------
+ * Sensitivities (extension).  Objective J(u, p) = sum over the region's elements and
+ * Gauss points of sigma_33^2 det J w, sigma_33 the normal stress along the laminate normal
+ * of the local frame (the through-thickness stress that drives corner unfolding,
+ * section 3).  region 0: every element; 1: the arc of an L-section (elements whose
+ * s-range centre lies in the arc; every element of a flat laminate).  lam must be the
+ * laminate whose mesh was assembled.
+ * ------------------------------------------------------------------------------------ */
+/* J for the displacement u (device, 3 n_nodes). */
+gx_status gx_objective(gx_ctx* ctx, const gx_laminate* lam, int32_t region, const double* u,
+                       double* J_out);
+/* J and dJ/dp by the adjoint method: K lambda = dJ/du is solved by PCG with the current
+ * preconditioner to rtol (iters_out: its iterations), then
+ * dJ/dp = dJ/dp|_u - lambda^T (dK/dp u - df/dp).  dJdp (host) receives 2 + n_layers
+ * values: [0] wrinkle amplitude, [1] wrinkle wavelength, [2 + k] the modulus E11 of layer
+ * k (E for an isotropic layer), in the units of J per mm and per MPa.  u must solve the
+ * assembled system (e.g. gx_pcg_solve to a tight tolerance).  GX_ENOCONV if the adjoint
+ * solve does not reach rtol in maxit iterations (the outputs are still filled, from its
+ * last iterate); GX_ESTATE before gx_geneo_setup. */
+gx_status gx_adjoint(gx_ctx* ctx, const gx_laminate* lam, int32_t region, const double* u,
+                     double rtol, int32_t maxit, double* J_out, double* dJdp,
+                     int32_t* iters_out);
+
 /* The subdomain solver on its own: batched banded Cholesky factorisation and triangular
  * solves (section 2.4: the local problems are solved exactly by a direct method).
  * n_mat matrices; matrix j has order n[j] and half bandwidth bw[j] (host arrays) and is

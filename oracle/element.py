@@ -75,9 +75,10 @@ def local_frame(J):
     """Orthonormal frame (e1, e2, e3) from the Jacobian columns dx/dxi and dx/deta."""
     t1 = J[..., :, 0]
     t2 = J[..., :, 1]
-    e1 = t1 / np.linalg.norm(t1, axis=-1, keepdims=True)
+    # lengths as sqrt(sum x^2) (not abs): analytic, so complex-step derivatives go through
+    e1 = t1 / np.sqrt(np.sum(t1 * t1, axis=-1, keepdims=True))
     v = t2 - np.sum(t2 * e1, axis=-1, keepdims=True) * e1
-    e2 = v / np.linalg.norm(v, axis=-1, keepdims=True)
+    e2 = v / np.sqrt(np.sum(v * v, axis=-1, keepdims=True))
     e3 = np.cross(e1, e2)
     return np.stack([e1, e2, e3], axis=-2)
 
@@ -119,7 +120,7 @@ def material_at_points(J, Cloc, angle):
 def element_stiffness(X, Cloc, angle, nq=3, chunk=512):
     """K_e for elements with nodes X (E, 20, 3), material Cloc (E, 6, 6), ply angle (E,)."""
     X = np.asarray(X)
-    out = np.empty((X.shape[0], 60, 60), dtype=X.dtype)
+    out = np.empty((X.shape[0], 60, 60), dtype=np.result_type(X, Cloc))
     for s in range(0, X.shape[0], chunk):
         sl = slice(s, s + chunk)
         gp = gauss_point_data(X[sl], nq)
@@ -145,7 +146,7 @@ def face_load(X, face_xi, traction_fn, nq=3):
     t_eta = np.einsum("qa,eai->eqi", dN[:, :, 1], X)
     t_zt = np.einsum("qa,eai->eqi", dN[:, :, 2], X)
     nvec = np.cross(t_eta, t_zt) * np.sign(face_xi)
-    dA = np.linalg.norm(nvec, axis=-1)
+    dA = np.sqrt(np.sum(nvec * nvec, axis=-1))
     nout = nvec / dA[..., None]
     t = traction_fn(xq, nout)
     f = np.einsum("qa,eqi,eq->eai", N, t, dA * wts[None, :])

@@ -50,7 +50,7 @@ def assemble(mesh, Ke, elems=None, n=None):
 
 def load_vector(mesh):
     """Consistent nodal loads on all DOFs (Eq. eq-1 right-hand side)."""
-    f = np.zeros(mesh.n_dofs)
+    f = np.zeros(mesh.n_dofs, dtype=mesh.xyz.dtype)
     le = mesh.load_elements()
     X = mesh.xyz[mesh.conn[le]]
     load = mesh.cfg["load"]
@@ -80,7 +80,7 @@ def _face_load_with_param(Zx, k, T):
     t_eta = np.einsum("qa,eai->eqi", dN[:, :, 1], X)
     t_zt = np.einsum("qa,eai->eqi", dN[:, :, 2], X)
     nvec = np.cross(t_eta, t_zt)
-    dA = np.linalg.norm(nvec, axis=-1)
+    dA = np.sqrt(np.sum(nvec * nvec, axis=-1))
     nout = nvec / dA[..., None]
     t = (k * (zeta - 0.5 * T))[..., None] * nout
     f = np.einsum("qa,eqi,eq->eai", N, t, dA * wts[None, :])
@@ -103,6 +103,6 @@ class Problem:
         self.n = self.K.shape[0]
 
     def to_full(self, u_free):
-        u = np.zeros(self.mesh.n_dofs)
+        u = np.zeros(self.mesh.n_dofs, dtype=np.result_type(u_free, 1.0))
         u[self.free_idx] = u_free
         return u

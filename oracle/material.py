@@ -20,7 +20,7 @@ VOIGT = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
 
 
 def orthotropic_compliance(E1, E2, E3, G12, G13, G23, nu12, nu13, nu23):
-    S = np.zeros((6, 6))
+    S = np.zeros((6, 6), dtype=np.result_type(E1, E2, E3, G12, G13, G23, nu12, nu13, nu23, 1.0))
     S[0, 0], S[1, 1], S[2, 2] = 1.0 / E1, 1.0 / E2, 1.0 / E3
     S[0, 1] = S[1, 0] = -nu12 / E1
     S[0, 2] = S[2, 0] = -nu13 / E1
@@ -100,7 +100,7 @@ def layer_material(cfg, engineering=False):
             if "E1" in L:
                 k["E1"] = L["E1"]
         else:
-            k = isotropic_as_engineering(RESIN["E"], RESIN["nu"])
+            k = isotropic_as_engineering(L.get("E", RESIN["E"]), RESIN["nu"])
         eng.append(k)
         Cs.append(orthotropic_stiffness(**k))
         angs.append(L["angle"])

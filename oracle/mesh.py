@@ -115,8 +115,8 @@ def geometry_map(cfg, s, l, zeta):
     sb = 0.25 * math.pi * rref
     sa = -sb
     rho = R + zh
-    x = np.empty_like(s)
-    z = np.empty_like(s)
+    x = np.empty(s.shape, dtype=np.result_type(s, zh))
+    z = np.empty(s.shape, dtype=np.result_type(s, zh))
     m1 = s < sa
     m3 = s > sb
     m2 = ~(m1 | m3)

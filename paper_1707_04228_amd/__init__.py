@@ -99,7 +99,10 @@ for _name, _args in [("gx_geneo_setup", [vp, C.POINTER(GeneoOpts), i32p, i64p]),
                      ("gx_stats", [vp, i64p]),
                      ("gx_tune", [vp, C.c_int32, C.c_int64]),
                      ("gx_band_factor_solve", [vp, C.c_int32, i64p, i64p, vp, C.c_int32,
-                                               C.c_int32, C.c_int32, vp])]:
+                                               C.c_int32, C.c_int32, vp]),
+                     ("gx_objective", [vp, C.POINTER(Laminate), C.c_int32, vp, f64p]),
+                     ("gx_adjoint", [vp, C.POINTER(Laminate), C.c_int32, vp, C.c_double,
+                                     C.c_int32, f64p, f64p, i32p])]:
     if hasattr(lib, _name):
         _sig(_name, _args)
 
@@ -107,7 +110,8 @@ EXPORTS = ["gx_create", "gx_destroy", "gx_last_error", "gx_version", "gx_laminat
            "gx_laminate_mesh", "gx_laminate_partition", "gx_laminate_traction",
            "gx_assemble", "gx_matrix_info", "gx_matrix_copy", "gx_spmv", "gx_geneo_setup",
            "gx_subdomain_info", "gx_geneo_eigenvalues", "gx_precond_apply", "gx_pcg_solve",
-           "gx_phase_times", "gx_kernel_time", "gx_stats", "gx_tune", "gx_band_factor_solve"]
+           "gx_phase_times", "gx_kernel_time", "gx_stats", "gx_tune", "gx_band_factor_solve",
+           "gx_objective", "gx_adjoint"]
 
 
 class GxError(RuntimeError):
@@ -152,7 +156,7 @@ def plystack_arrays(cfg):
             eng.append([p["E1"], p["E2"], p["E3"], p["G12"], p["G13"], p["G23"],
                         p["nu12"], p["nu13"], p["nu23"]])
         else:
-            eng.append([RESIN["E"], 0, 0, 0, 0, 0, RESIN["nu"], 0, 0])
+            eng.append([L.get("E", RESIN["E"]), 0, 0, 0, 0, 0, RESIN["nu"], 0, 0])
         ang.append(L["angle"])
     return np.array(eng, dtype=np.float64), np.array(ang, dtype=np.float64)
 
@@ -320,6 +324,26 @@ class Solver:
         self._check(lib.gx_kernel_time(self.h, which, reps, C.byref(ms), C.byref(b)))
         return ms.value, b.value
 
+    # ---- sensitivities ------------------------------------------------------------
+    def objective(self, u, cfg=None, region=1):
+        """J = sum over the region of sigma_33^2 (region 1: the L-section arc; 0: all)."""
+        lam, keep = laminate_struct(cfg or self.mesh["cfg"])
+        J = C.c_double()
+        self._check(lib.gx_objective(self.h, C.byref(lam), region, _ptr(u), C.byref(J)))
+        return J.value
+
+    def adjoint(self, u, cfg=None, region=1, rtol=1e-12, maxit=2000, allow_noconv=False):
+        """(J, dJ/dp, adjoint iterations); dJ/dp = [dA, dL_w, dE11 of every layer]."""
+        cfg = cfg or self.mesh["cfg"]
+        lam, keep = laminate_struct(cfg)
+        out = np.zeros(2 + len(cfg["layers"]))
+        J, it = C.c_double(), C.c_int32()
+        code = lib.gx_adjoint(self.h, C.byref(lam), region, _ptr(u), rtol, maxit, C.byref(J),
+                              out.ctypes.data_as(f64p), C.byref(it))
+        if not (code == GX_OK or (allow_noconv and code == GX_ENOCONV)):
+            self._check(code)
+        return J.value, out, it.value
+
     def tune(self, param, value):
         self._check(lib.gx_tune(self.h, param, value))
 
@@ -346,3 +370,71 @@ class Solver:
         lib.gx_phase_times(self.h, t.ctypes.data_as(f64p))
         return dict(zip(["assemble", "decomposition", "local_factors", "eigensolves",
                          "coarse", "pcg", "pcg_precond", "pcg_spmv"], t.tolist()))
+
+
+# ---- differentiable solve --------------------------------------------------------------
+def with_parameters(cfg, params):
+    """Copy of a laminate descriptor with p = [A, L_w, E11 of every layer] applied (E of an
+    isotropic layer)."""
+    import copy
+    c = copy.deepcopy(cfg)
+    p = [float(v) for v in params]
+    c["wrinkle"] = (p[0], p[1])
+    for k, L in enumerate(c["layers"]):
+        L["E1" if L["mat"] == "ply" else "E"] = p[2 + k]
+    return c
+
+
+def parameters_of(cfg):
+    """p = [A, L_w, E11 of every layer] of a descriptor (defaults from the material table)."""
+    from workloads import PLY, RESIN
+    A, Lw = cfg.get("wrinkle", (0.0, 1.0))
+    p = [A, Lw]
+    for L in cfg["layers"]:
+        p.append(L.get("E1", PLY["E1"]) if L["mat"] == "ply" else L.get("E", RESIN["E"]))
+    return np.array(p, dtype=np.float64)
+
+
+def _laminate_objective_fn():
+    import torch
+
+    class LaminateObjective(torch.autograd.Function):
+        """J(p) = sum over the region of sigma_33^2 for the laminate with parameters p
+        (wrinkle amplitude, wavelength, layer moduli): forward = mesh, assembly, GenEO
+        set-up and PCG solve on the device; backward = the adjoint solve with the same
+        preconditioner (gx_adjoint).  p is a CPU float64 tensor; J a CPU scalar."""
+
+        @staticmethod
+        def forward(ctx, p, cfg, region=1, rtol=1e-12, device=0):
+            c = with_parameters(cfg, p.detach().cpu().numpy())
+            s = Solver(device=device)
+            s.laminate(c)
+            f = s.assemble()
+            sv = c["solver"]
+            part = s.partition(c, sv["px"], sv["py"])
+            s.geneo_setup(part, sv["px"] * sv["py"], overlap=sv["overlap"],
+                          tau=sv["tau"] or 0.1, nev=sv["nev"] or 0, nev_max=sv["nev_max"])
+            u = s.pcg(f, rtol=rtol, maxit=5000, allow_noconv=True)["x"]
+            J, g, _ = s.adjoint(u, c, region=region, rtol=rtol, maxit=5000,
+                                allow_noconv=True)
+            s.close()
+            ctx.save_for_backward(torch.tensor(g, dtype=torch.float64))
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            (g,) = ctx.saved_tensors
+            return gJ * g, None, None, None, None
+
+    return LaminateObjective
+
+
+def laminate_objective(p, cfg, region=1, rtol=1e-12, device=0):
+    """Differentiable J(p); see LaminateObjective."""
+    global _LAMINATE_OBJECTIVE
+    if _LAMINATE_OBJECTIVE is None:
+        _LAMINATE_OBJECTIVE = _laminate_objective_fn()
+    return _LAMINATE_OBJECTIVE.apply(p, cfg, region, rtol, device)
+
+
+_LAMINATE_OBJECTIVE = None

@@ -13,59 +13,13 @@
 //   6. consistent face loads from a 3x3 Gauss rule on each loaded face.
 #include <cmath>
 
+#include "element.h"
 #include "gx_internal.h"
 
 namespace gx {
 
 constexpr int MAX_ADJ = 32;        // elements sharing one node
 constexpr int MAX_ROW = 128;       // blocks in one block row of K
-
-// ---------------------------------------------------------------------------------------
-// Serendipity shape functions on the reference cube [-1, 1]^3.
-__device__ __constant__ int8_t c_ref[20][3] = {
-    {-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {1, 1, -1},
-    {-1, -1, 1},  {1, -1, 1},  {-1, 1, 1},  {1, 1, 1},
-    {0, -1, -1},  {0, 1, -1},  {0, -1, 1},  {0, 1, 1},
-    {-1, 0, -1},  {1, 0, -1},  {-1, 0, 1},  {1, 0, 1},
-    {-1, -1, 0},  {1, -1, 0},  {-1, 1, 0},  {1, 1, 0}};
-
-// value and reference gradient of shape function a at (p0, p1, p2)
-__device__ inline void shape_one(int a, double p0, double p1, double p2, double* N,
-                                 double* d) {
-  const double r0 = c_ref[a][0], r1 = c_ref[a][1], r2 = c_ref[a][2];
-  const double f0 = 1 + p0 * r0, f1 = 1 + p1 * r1, f2 = 1 + p2 * r2;
-  if (r0 != 0 && r1 != 0 && r2 != 0) {
-    const double g = p0 * r0 + p1 * r1 + p2 * r2 - 2;
-    *N = 0.125 * f0 * f1 * f2 * g;
-    d[0] = 0.125 * r0 * f1 * f2 * (g + f0);
-    d[1] = 0.125 * r1 * f0 * f2 * (g + f1);
-    d[2] = 0.125 * r2 * f0 * f1 * (g + f2);
-  } else if (r0 == 0) {                          // edge along xi: bubble (1 - xi^2)
-    const double b = 1 - p0 * p0;
-    *N = 0.25 * b * f1 * f2;
-    d[0] = -0.5 * p0 * f1 * f2;
-    d[1] = 0.25 * b * r1 * f2;
-    d[2] = 0.25 * b * f1 * r2;
-  } else if (r1 == 0) {                          // edge along eta
-    const double b = 1 - p1 * p1;
-    *N = 0.25 * b * f0 * f2;
-    d[0] = 0.25 * b * r0 * f2;
-    d[1] = -0.5 * p1 * f0 * f2;
-    d[2] = 0.25 * b * f0 * r2;
-  } else {                                       // edge along zeta
-    const double b = 1 - p2 * p2;
-    *N = 0.25 * b * f0 * f1;
-    d[0] = 0.25 * b * r0 * f1;
-    d[1] = 0.25 * b * f0 * r1;
-    d[2] = -0.5 * p2 * f0 * f1;
-  }
-}
-
-__device__ inline void gauss3(int i, double* x, double* w) {
-  const double s = 0.7745966692414833770358531;  // sqrt(3/5)
-  *x = (i == 0) ? -s : ((i == 1) ? 0.0 : s);
-  *w = (i == 1) ? 8.0 / 9.0 : 5.0 / 9.0;
-}
 
 // ---------------------------------------------------------------------------------------
 // 1. node -> element incidence
@@ -606,7 +560,13 @@ gx_status gx_assemble(gx_ctx* c, const gx_mesh* m, const gx_plystack* ps, const 
   to_host(&herr, err.p, 1, s);
   GX_REQUIRE(!herr, "a block row has more than 128 blocks");
   // materials
-  DevBuf<double> eng(9 * ps->n_layers), ang(ps->n_layers), Cl(36 * ps->n_layers);
+  DevBuf<double> eng(9 * ps->n_layers);
+  DevBuf<double>& ang = c->ang;
+  DevBuf<double>& Cl = c->Cl;
+  ang.alloc(ps->n_layers);
+  Cl.alloc(36 * ps->n_layers);
+  c->n_layers = ps->n_layers;
+  c->eng.assign(ps->eng, ps->eng + 9 * ps->n_layers);
   to_dev(eng.p, ps->eng, 9 * ps->n_layers, s);
   to_dev(ang.p, ps->angle_deg, ps->n_layers, s);
   hipLaunchKernelGGL(k_layer_stiffness, dim3(nblocks(ps->n_layers, 64)), dim3(64), 0, s,
@@ -628,6 +588,7 @@ gx_status gx_assemble(gx_ctx* c, const gx_mesh* m, const gx_plystack* ps, const 
   GX_HIP(hipGetLastError());
   // loads
   GX_HIP(hipMemsetAsync(f_out, 0, 3 * N * sizeof(double), s));
+  c->n_faces = 0;
   if (ld->n_faces > 0) {
     GX_REQUIRE(ld->face_elem && ld->face_id, "null face list");
     std::vector<int32_t> he(ld->n_faces), hf(ld->n_faces);
@@ -636,7 +597,12 @@ gx_status gx_assemble(gx_ctx* c, const gx_mesh* m, const gx_plystack* ps, const 
     GX_HIP(hipStreamSynchronize(s));
     for (int64_t i = 0; i < ld->n_faces; ++i)
       GX_REQUIRE(he[i] >= 0 && he[i] < E && hf[i] >= 0 && hf[i] < 6, "bad load face");
-    DevBuf<int32_t> de(ld->n_faces), df(ld->n_faces);
+    DevBuf<int32_t>& de = c->face_e;
+    DevBuf<int32_t>& df = c->face_id;
+    de.alloc(ld->n_faces);
+    df.alloc(ld->n_faces);
+    c->n_faces = ld->n_faces;
+    c->traction = ld->traction;
     to_dev(de.p, he.data(), he.size(), s);
     to_dev(df.p, hf.data(), hf.size(), s);
     hipLaunchKernelGGL(k_face_loads, dim3(nblocks(ld->n_faces * 20, 64)), dim3(64), 0, s,

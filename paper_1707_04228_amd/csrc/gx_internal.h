@@ -194,6 +194,13 @@ struct gx_ctx {
   double mrhs_ms = 0.0, mrhs_bytes = 0.0;
   int64_t mrhs_calls = 0;
   int tune[4] = {0, 0, 0, 0};                  // see gx_tune
+  // materials and loads of the last assembly (kept for the sensitivities)
+  int32_t n_layers = 0;
+  std::vector<double> eng;                     // 9 engineering constants per layer
+  gx::DevBuf<double> Cl, ang;                  // layer stiffness (material axes), ply angle
+  int64_t n_faces = 0;
+  gx::DevBuf<int32_t> face_e, face_id;
+  gx_traction traction{};
 };
 
 namespace gx {
@@ -215,6 +222,9 @@ void band_solve_check(BandSet& bs, hipStream_t st);
 void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, int ncol = 1,
                 const int32_t* active = nullptr);
 double band_solve_bytes(const BandSet& bs, int ncol, const int32_t* active_host = nullptr);
+void laminate_velocity(const gx_laminate* lam, int param, double* xd, hipStream_t st);
+void laminate_region(const gx_laminate* lam, uint8_t* mask, hipStream_t st);
+void laminate_sizes(const gx_laminate* lam, int64_t* n_nodes, int64_t* n_elems);
 // HIP event pair on a stream (timing of single launches)
 struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;

@@ -147,9 +147,9 @@ __device__ inline void map_point(const LamDev& L, double s, double l, double zet
   }
 }
 
-__global__ void k_nodes(LamDev L, int64_t n_nodes, double* xyz) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= n_nodes) return;
+// lattice parameters (s, l, zeta) of node n
+__device__ inline void node_param(const LamDev& L, int64_t n, double* s, double* l,
+                                  double* z) {
   const int64_t re = 2 * (int64_t)L.nx + 1, ro = (int64_t)L.nx + 1;
   const int64_t pe = ((int64_t)L.ny + 1) * re + (int64_t)L.ny * ro;
   const int64_t po = ((int64_t)L.nx + 1) * ((int64_t)L.ny + 1);
@@ -168,15 +168,57 @@ __global__ void k_nodes(LamDev L, int64_t n_nodes, double* xyz) {
     j2 = (int)(2 * (rem / ro));
     i2 = (int)(2 * (rem % ro));
   }
-  const double s = lattice(s_bound(L, i2 >> 1), s_bound(L, (i2 >> 1) + (i2 & 1)), i2 & 1);
-  const double l = lattice(L.width * (j2 >> 1) / L.ny, L.width * ((j2 >> 1) + (j2 & 1)) / L.ny,
-                           j2 & 1);
-  const double z = lattice(z_bound(L, k2 >> 1), z_bound(L, (k2 >> 1) + (k2 & 1)), k2 & 1);
+  *s = lattice(s_bound(L, i2 >> 1), s_bound(L, (i2 >> 1) + (i2 & 1)), i2 & 1);
+  *l = lattice(L.width * (j2 >> 1) / L.ny, L.width * ((j2 >> 1) + (j2 & 1)) / L.ny, j2 & 1);
+  *z = lattice(z_bound(L, k2 >> 1), z_bound(L, (k2 >> 1) + (k2 & 1)), k2 & 1);
+}
+
+__global__ void k_nodes(LamDev L, int64_t n_nodes, double* xyz) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= n_nodes) return;
+  double s, l, z;
+  node_param(L, n, &s, &l, &z);
   double x[3];
   map_point(L, s, l, z, x);
   xyz[3 * n + 0] = x[0];
   xyz[3 * n + 1] = x[1];
   xyz[3 * n + 2] = x[2];
+}
+
+// dX/dp of every node for p = wrinkle amplitude (param 0) or wavelength (param 1): the
+// wrinkle shifts zeta_hat = zeta + w(s), so dX/dp = (dX/dzeta_hat) dw/dp, in closed form
+__global__ void k_node_velocity(LamDev L, int param, int64_t n_nodes, double* xd) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= n_nodes) return;
+  double s, l, z;
+  node_param(L, n, &s, &l, &z);
+  const double u = s - (L.geometry == GX_GEOM_FLAT ? 0.5 * L.length : 0.0);
+  const double q = u / L.wlen, ph = 2.0 * M_PI * u / L.wlen, g = exp(-q * q);
+  const double dw = param == 0 ? g * cos(ph)
+                               : L.amp * g * (2.0 * q * u / (L.wlen * L.wlen) * cos(ph) +
+                                              sin(ph) * 2.0 * M_PI * u / (L.wlen * L.wlen));
+  double d0 = 0.0, d2 = 1.0;                     // dX/dzeta_hat (the y component is 0)
+  if (L.geometry != GX_GEOM_FLAT) {
+    if (s > L.s_b) { d0 = 1.0; d2 = 0.0; }
+    else if (s >= L.s_a) {
+      const double th = (s - L.s_a) / L.r_ref;
+      d0 = sin(th);
+      d2 = cos(th);
+    }
+  }
+  xd[3 * n + 0] = d0 * dw;
+  xd[3 * n + 1] = 0.0;
+  xd[3 * n + 2] = d2 * dw;
+}
+
+// 1 for the elements of the objective region: every element of a flat laminate; the
+// elements of the arc (centre of the element's s-range in [s_a, s_b]) of an L-section
+__global__ void k_arc_mask(LamDev L, int64_t n_elems, uint8_t* mask) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_elems) return;
+  const int ex = (int)(e % L.nx);
+  const double sc = 0.5 * (s_bound(L, ex) + s_bound(L, ex + 1));
+  mask[e] = (L.geometry == GX_GEOM_FLAT || (sc >= L.s_a && sc <= L.s_b)) ? 1 : 0;
 }
 
 // lattice offsets (0..2 per axis) of the 20 element nodes in element-local order
@@ -227,6 +269,30 @@ __global__ void k_partition(LamDev L, int64_t n_elems, int px, int py, int32_t* 
   while (ix + 1 < px && (int64_t)(ix + 1) * L.nx / px <= ex) ++ix;
   while (iy + 1 < py && (int64_t)(iy + 1) * L.ny / py <= ey) ++iy;
   part[e] = iy * px + ix;
+}
+
+void laminate_velocity(const gx_laminate* lam, int param, double* xd, hipStream_t st) {
+  LamDev L = make_lam(lam);
+  GX_REQUIRE(lam->wrinkle_len > 0, "shape derivatives need a wrinkle wavelength > 0");
+  Counts k = counts(L.nx, L.ny, L.nz);
+  hipLaunchKernelGGL(k_node_velocity, dim3(nblocks(k.nodes, 256)), dim3(256), 0, st, L, param,
+                     k.nodes, xd);
+  GX_HIP(hipGetLastError());
+}
+
+void laminate_region(const gx_laminate* lam, uint8_t* mask, hipStream_t st) {
+  LamDev L = make_lam(lam);
+  Counts k = counts(L.nx, L.ny, L.nz);
+  hipLaunchKernelGGL(k_arc_mask, dim3(nblocks(k.elems, 256)), dim3(256), 0, st, L, k.elems,
+                     mask);
+  GX_HIP(hipGetLastError());
+}
+
+void laminate_sizes(const gx_laminate* lam, int64_t* n_nodes, int64_t* n_elems) {
+  LamDev L = make_lam(lam);
+  Counts k = counts(L.nx, L.ny, L.nz);
+  *n_nodes = k.nodes;
+  *n_elems = k.elems;
 }
 
 }  // namespace gx
