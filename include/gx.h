@@ -265,6 +265,18 @@ gx_status gx_band_factor_solve(gx_ctx* ctx, int32_t n_mat, const int64_t* n, con
                                const double* band, int32_t precision, int32_t nrhs,
                                int32_t groups, double* x);
 
+/* Batched PCG (extension: many laminates at once).  n contexts, each set up
+ * (gx_geneo_setup) for its own laminate and, for overlap, on its own HIP stream, solve
+ * K_i x_i = b_i in lockstep: every iteration enqueues the work of each unconverged system on
+ * its stream and then waits once for all of them; a system leaves the batch when it
+ * converges (the stopping test of gx_pcg_solve, per system).  b[i], x[i]: device vectors of
+ * context i (x[i] in: initial guess).  iters_out, relres_out, status_out: host [n] (may be
+ * NULL).  Returns GX_OK if every system converged, else the first non-OK status (each
+ * context's gx_last_error explains its own). */
+gx_status gx_pcg_solve_batch(int32_t n, gx_ctx* const* ctxs, const double* const* b,
+                             double* const* x, double rtol, int32_t maxit, int32_t* iters_out,
+                             double* relres_out, int32_t* status_out);
+
 /* Measurement of one library kernel with HIP events on the context's stream: the average
  * duration over `reps` launches (ms) and the algorithmic bytes one launch must move
  * (bytes, 0 when not defined).  which: 0 = block-CSR product y = K x; 1 = the batched

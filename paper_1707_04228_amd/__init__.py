@@ -101,6 +101,9 @@ for _name, _args in [("gx_geneo_setup", [vp, C.POINTER(GeneoOpts), i32p, i64p]),
                      ("gx_band_factor_solve", [vp, C.c_int32, i64p, i64p, vp, C.c_int32,
                                                C.c_int32, C.c_int32, vp]),
                      ("gx_objective", [vp, C.POINTER(Laminate), C.c_int32, vp, f64p]),
+                     ("gx_pcg_solve_batch", [C.c_int32, C.POINTER(vp), C.POINTER(vp),
+                                             C.POINTER(vp), C.c_double, C.c_int32, i32p, f64p,
+                                             i32p]),
                      ("gx_adjoint", [vp, C.POINTER(Laminate), C.c_int32, vp, C.c_double,
                                      C.c_int32, f64p, f64p, i32p])]:
     if hasattr(lib, _name):
@@ -111,7 +114,7 @@ EXPORTS = ["gx_create", "gx_destroy", "gx_last_error", "gx_version", "gx_laminat
            "gx_assemble", "gx_matrix_info", "gx_matrix_copy", "gx_spmv", "gx_geneo_setup",
            "gx_subdomain_info", "gx_geneo_eigenvalues", "gx_precond_apply", "gx_pcg_solve",
            "gx_phase_times", "gx_kernel_time", "gx_stats", "gx_tune", "gx_band_factor_solve",
-           "gx_objective", "gx_adjoint"]
+           "gx_objective", "gx_adjoint", "gx_pcg_solve_batch"]
 
 
 class GxError(RuntimeError):
@@ -161,6 +164,19 @@ def plystack_arrays(cfg):
     return np.array(eng, dtype=np.float64), np.array(ang, dtype=np.float64)
 
 
+def _on_stream(fn):
+    """Run a Solver method with the solver's stream current (torch work and allocations)."""
+    import functools
+
+    @functools.wraps(fn)
+    def wrapped(self, *a, **k):
+        if self.stream is None:
+            return fn(self, *a, **k)
+        with self.torch.cuda.stream(self.stream):
+            return fn(self, *a, **k)
+    return wrapped
+
+
 class Solver:
     """One gx context on a torch CUDA (HIP) device, holding mesh, K, P and work vectors."""
 
@@ -169,6 +185,13 @@ class Solver:
         self.torch = torch
         self.device = torch.device("cuda", device)
         torch.cuda.init()
+        # the library and the binding's own tensor work share one torch stream (the given
+        # one, else the current one unless that is the default stream, in which case the
+        # library runs on a stream of its own and every entry point synchronises it)
+        cur = torch.cuda.current_stream(self.device)
+        if stream is None and cur.cuda_stream != 0:
+            stream = cur
+        self.stream = stream
         h = vp()
         st = C.c_void_p(stream.cuda_stream) if stream is not None else None
         self._check_plain(lib.gx_create(C.byref(h), device, st), "gx_create")
@@ -192,6 +215,7 @@ class Solver:
         return code
 
     # ---- mesh --------------------------------------------------------------------
+    @_on_stream
     def laminate(self, cfg):
         """Build the laminate mesh and boundary lists of a workload descriptor."""
         torch = self.torch
@@ -228,6 +252,7 @@ class Solver:
         self.mesh = m
         return m
 
+    @_on_stream
     def partition(self, cfg, px, py):
         lam, keep = laminate_struct(cfg)
         part = self.torch.empty(self.mesh["n_elems"], dtype=self.torch.int32,
@@ -236,6 +261,7 @@ class Solver:
         return part
 
     # ---- assembly ------------------------------------------------------------------
+    @_on_stream
     def assemble(self, cfg=None, mesh=None):
         m = mesh or self.mesh
         cfg = cfg or m["cfg"]
@@ -251,6 +277,7 @@ class Solver:
         self.n_dofs = 3 * m["n_nodes"]
         return f
 
+    @_on_stream
     def matrix(self):
         """K as (row_ptr, col, val) torch tensors on the device."""
         torch = self.torch
@@ -262,12 +289,14 @@ class Solver:
         self._check(lib.gx_matrix_copy(self.h, _ptr(rp), _ptr(col), _ptr(val)))
         return rp, col, val
 
+    @_on_stream
     def spmv(self, x, y=None):
         y = self.torch.empty_like(x) if y is None else y
         self._check(lib.gx_spmv(self.h, _ptr(x), _ptr(y)))
         return y
 
     # ---- preconditioner and solve ----------------------------------------------------
+    @_on_stream
     def geneo_setup(self, part, n_sub, overlap=1, tau=0.1, nev=0, nev_max=32,
                     precision=GX_FP64, coarse=True, nev_per_sub=None, eig_tol=0.0,
                     eig_maxit=0):
@@ -299,11 +328,13 @@ class Solver:
         self._check(lib.gx_geneo_eigenvalues(self.h, j, lam.ctypes.data_as(f64p)))
         return lam[: int(self.nev[j])]
 
+    @_on_stream
     def precond(self, r, z=None):
         z = self.torch.empty_like(r) if z is None else z
         self._check(lib.gx_precond_apply(self.h, _ptr(r), _ptr(z)))
         return z
 
+    @_on_stream
     def pcg(self, b, x=None, rtol=1e-8, maxit=1000, history=False, allow_noconv=False):
         x = self.torch.zeros_like(b) if x is None else x
         it = C.c_int32()
@@ -318,6 +349,7 @@ class Solver:
             out["hist"] = hist[: it.value + 1]
         return out
 
+    @_on_stream
     def kernel_time(self, which, reps=5):
         """(average ms, algorithmic bytes per launch) of library kernel `which`."""
         ms, b = C.c_double(), C.c_double()
@@ -325,6 +357,7 @@ class Solver:
         return ms.value, b.value
 
     # ---- sensitivities ------------------------------------------------------------
+    @_on_stream
     def objective(self, u, cfg=None, region=1):
         """J = sum over the region of sigma_33^2 (region 1: the L-section arc; 0: all)."""
         lam, keep = laminate_struct(cfg or self.mesh["cfg"])
@@ -332,6 +365,7 @@ class Solver:
         self._check(lib.gx_objective(self.h, C.byref(lam), region, _ptr(u), C.byref(J)))
         return J.value
 
+    @_on_stream
     def adjoint(self, u, cfg=None, region=1, rtol=1e-12, maxit=2000, allow_noconv=False):
         """(J, dJ/dp, adjoint iterations); dJ/dp = [dA, dL_w, dE11 of every layer]."""
         cfg = cfg or self.mesh["cfg"]
@@ -347,6 +381,20 @@ class Solver:
     def tune(self, param, value):
         self._check(lib.gx_tune(self.h, param, value))
 
+    @_on_stream
+    def autotune(self, candidates=(1, 2, 3, 4), reps=3):
+        """Pick the work-groups per subdomain of the preconditioner's band solves by timing
+        them (gx_kernel_time 1) for each candidate; returns {candidate: ms} and keeps the
+        fastest."""
+        times = {}
+        for g in candidates:
+            self.tune(0, g)
+            times[g] = self.kernel_time(1, reps=reps)[0]
+        best = min(times, key=times.get)
+        self.tune(0, best)
+        return times
+
+    @_on_stream
     def band_factor_solve(self, n, bw, band, x, precision=GX_FP64, groups=0):
         """Factor the band matrices (row-major band storage, device FP64 tensor `band`) and
         solve in place for x (device FP64, n[j] x nrhs per matrix, concatenated)."""
@@ -438,3 +486,54 @@ def laminate_objective(p, cfg, region=1, rtol=1e-12, device=0):
 
 
 _LAMINATE_OBJECTIVE = None
+
+
+# ---- batches of laminates -------------------------------------------------------------
+class Batch:
+    """Many laminates solved together: one Solver per laminate, each on its own torch
+    stream (default priority) so that their kernels overlap, and one lockstep batched PCG
+    (gx_pcg_solve_batch) with a per-laminate convergence test."""
+
+    def __init__(self, cfgs, precision=GX_FP64, device=0):
+        import torch
+        self.torch = torch
+        self.cfgs = list(cfgs)
+        self.solvers, self.f = [], []
+        for cfg in self.cfgs:
+            s = Solver(device=device, stream=torch.cuda.Stream(device=device))
+            s.laminate(cfg)
+            self.f.append(s.assemble())
+            self.solvers.append(s)
+        self.precision = precision
+
+    def setup(self):
+        """Decomposition, GenEO coarse spaces and factors of every laminate."""
+        out = []
+        for cfg, s in zip(self.cfgs, self.solvers):
+            sv = cfg["solver"]
+            part = s.partition(cfg, sv["px"], sv["py"])
+            out.append(s.geneo_setup(part, sv["px"] * sv["py"], overlap=sv["overlap"],
+                                     tau=sv["tau"] or 0.1, nev=sv["nev"] or 0,
+                                     nev_max=sv["nev_max"], precision=self.precision))
+        return out
+
+    def solve(self, rtol=1e-8, maxit=2000):
+        """x_i for every laminate; (list of x, iterations, relative residuals, statuses)."""
+        n = len(self.solvers)
+        xs = []
+        for s, f in zip(self.solvers, self.f):
+            with self.torch.cuda.stream(s.stream):
+                xs.append(self.torch.zeros_like(f))
+        H = (vp * n)(*[s.h for s in self.solvers])
+        Bp = (vp * n)(*[f.data_ptr() for f in self.f])
+        Xp = (vp * n)(*[x.data_ptr() for x in xs])
+        it = np.zeros(n, dtype=np.int32)
+        rr = np.zeros(n)
+        st = np.zeros(n, dtype=np.int32)
+        lib.gx_pcg_solve_batch(n, H, Bp, Xp, rtol, maxit, it.ctypes.data_as(i32p),
+                               rr.ctypes.data_as(f64p), st.ctypes.data_as(i32p))
+        return xs, it, rr, st
+
+    def close(self):
+        for s in self.solvers:
+            s.close()

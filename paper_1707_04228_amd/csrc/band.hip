@@ -255,7 +255,7 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, int* err) {
   GX_HIP(hipStreamSynchronize(st));
 }
 
-void band_factor(BandSet& bs, hipStream_t st) {
+void band_factor(BandSet& bs, hipStream_t st, const char* what) {
   DevBuf<int> err(1);
   zero(err, st);
   if (bs.fp32)
@@ -264,7 +264,9 @@ void band_factor(BandSet& bs, hipStream_t st) {
     band_factor_t<double>(bs, bs.v64.p, bs.dinv64.p, st, err.p);
   int h = 0;
   to_host(&h, err.p, 1, st);
-  if (h) throw Error(GX_ENOTSPD, "non-positive pivot in a banded Cholesky factorisation");
+  if (h)
+    throw Error(GX_ENOTSPD, std::string("non-positive pivot in the banded Cholesky factorisation of ") +
+                                what);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -545,20 +547,21 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
 // inverse diagonal block against the block's right-hand side - are 64 x 64 x M and run on
 // FP64 matrix cores: v_mfma_f64_16x16x4, lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16] and holds D[4 r + l / 16][l % 16] in accumulator register r; wave w
-// of the 4 owns row tile w and all column tiles.  Chunks (64 x 64 of the band plus the
-// matching solution rows) are staged through LDS, the next chunk's loads in flight in
-// registers while the current one is multiplied; two work-groups share a compute unit.
+// of the 8 owns row tile w mod 4 and column tile w / 4.  Chunks (64 x 64 of the band plus
+// the matching solution rows) are staged through LDS; the loads of the next two chunks are
+// in flight in two register sets while the current one is multiplied (the chunk loop is
+// unrolled by two so that each set has a name of its own).
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int MC = 32;                            // right-hand sides per launch, at most
-constexpr int MT = 256;                           // threads per work-group
-constexpr int AL = SB * SB / MT;                  // band-chunk entries per thread (16)
+constexpr int MT = 512;                           // threads per work-group
+constexpr int AL = SB * SB / MT;                  // band-chunk entries per thread (8)
 
 template <class T, int M>
-__global__ void __launch_bounds__(MT, 2) k_band_solve_m(
+__global__ void __launch_bounds__(MT) k_band_solve_m(
     BandArgs a, const T* v, const T* dinv, const int64_t* boff, const int64_t* xoff,
     double* xall, int G, int n_pad, int n_mat, int* fflag, int* bflag, int64_t nblk_max,
     int epoch, const int32_t* active, int* err) {
-  constexpr int NCT = (M + 15) / 16;              // column tiles
+  constexpr int NCT = (M + 15) / 16;              // column tiles (1 or 2)
   constexpr int MP = 16 * NCT;                    // LDS row stride (zero columns past M)
   constexpr int YL = SB * M / MT;                 // solution-chunk entries per thread
   __shared__ double Ab[SB][SB + 1];               // band chunk; the inverse block later
@@ -574,19 +577,22 @@ __global__ void __launch_bounds__(MT, 2) k_band_solve_m(
   double* x = xall + xoff[j];
   int* ff = fflag + (int64_t)j * nblk_max;
   int* bf = bflag + (int64_t)j * nblk_max;
-  const int lane = threadIdx.x & 63, rt = threadIdx.x >> 6;   // wave = row tile
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rt = wave & 3, ct = wave >> 2;        // this wave's row and column tile
+  const bool tile = ct < NCT;                      // waves past the column tiles only stage
   const int li = lane & 15, lk = lane >> 4;
   const int64_t nblk = (n + SB - 1) / SB;
-  if (MP > M)
+  if constexpr (MP > M)
     for (int idx = threadIdx.x; idx < SB * (MP - M); idx += MT)
       Yc[(idx / (MP - M)) * MP + M + idx % (MP - M)] = 0.0;
   // forward chunk kk of block i0: band rows i0.., columns 64 kk..; backward chunk kk:
-  // band rows 64 kk.., columns i0..; both with solution rows 64 kk..
+  // band rows 64 kk.., columns i0..; both with solution rows 64 kk..  Thread t stages band
+  // rows t / 64 + 8 u at column t % 64.
   auto fetch = [&](bool bwd, int64_t i0, int64_t kk, T (&fa)[AL], double (&fy)[YL]) {
-    const int64_t r0 = (bwd ? kk * SB : i0) + rt;
+    const int64_t r0 = (bwd ? kk * SB : i0) + wave;
     const int64_t c = (bwd ? i0 : kk * SB) + lane;
 #pragma unroll
-    for (int u = 0; u < AL; ++u) fa[u] = cb[min<int64_t>(r0 + 4 * u, n - 1) * rs + c];
+    for (int u = 0; u < AL; ++u) fa[u] = cb[min<int64_t>(r0 + 8 * u, n - 1) * rs + c];
     const int64_t yend = min<int64_t>((int64_t)SB * M, (n - kk * SB) * M);   // rows < n
     const double* xs = x + kk * SB * M;
 #pragma unroll
@@ -594,13 +600,13 @@ __global__ void __launch_bounds__(MT, 2) k_band_solve_m(
   };
   auto stage = [&](bool bwd, int64_t i0, int nb, int64_t kk, const T (&fa)[AL],
                    const double (&fy)[YL]) {
-    const int64_t r0 = (bwd ? kk * SB : i0) + rt;
+    const int64_t r0 = (bwd ? kk * SB : i0) + wave;
     const int64_t c = (bwd ? i0 : kk * SB) + lane;
 #pragma unroll
     for (int u = 0; u < AL; ++u) {
-      const int64_t r = r0 + 4 * u;
+      const int64_t r = r0 + 8 * u;
       const bool in = r < n && c <= r && c >= r - B && (!bwd || lane < nb);
-      Ab[rt + 4 * u][lane] = in ? (double)fa[u] : 0.0;
+      Ab[wave + 8 * u][lane] = in ? (double)fa[u] : 0.0;
     }
     const int64_t yend = min<int64_t>((int64_t)SB * M, (n - kk * SB) * M);   // rows < n
 #pragma unroll
@@ -609,90 +615,92 @@ __global__ void __launch_bounds__(MT, 2) k_band_solve_m(
       Yc[(idx / M) * MP + idx % M] = idx < yend ? fy[u] : 0.0;
     }
   };
-  // acc[ct] += A Yc over the 64-deep chunk; A = Ab (forward) or Ab^T (backward)
-  constexpr int KU = NCT > 2 ? 2 : 4;              // k-steps unrolled (register budget)
-  auto mma = [&](bool trans, v4d (&acc)[NCT]) {
-#pragma unroll KU
+  // acc += A Yc over the 64-deep chunk for this wave's tile; A = Ab or Ab^T
+  auto mma = [&](bool trans, v4d& acc) {
+    if (!tile) return;
+#pragma unroll 4
     for (int ks = 0; ks < SB / 4; ++ks) {
       const int kq = 4 * ks + lk;
       const double av = trans ? Ab[kq][16 * rt + li] : Ab[16 * rt + li][kq];
-#pragma unroll
-      for (int ct = 0; ct < NCT; ++ct)
-        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Yc[kq * MP + 16 * ct + li], acc[ct],
-                                                        0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Yc[kq * MP + 16 * ct + li], acc, 0, 0, 0);
+    }
+  };
+  // the chunks kk = first, first + step, .., last (step +1 or -1), two loads ahead; `wait`
+  // is called (once, uniformly) before the first chunk whose loads need it
+  auto sweep = [&](bool bwd, int64_t i0, int nb, int64_t first, int64_t count, int step,
+                   auto&& need, auto&& wait, v4d& acc) {
+    T fa0[AL], fa1[AL];
+    double fy0[YL], fy1[YL];
+    auto get = [&](int64_t q, T (&fa)[AL], double (&fy)[YL]) {
+      const int64_t kk = first + step * q;
+      if (need(kk)) wait();
+      fetch(bwd, i0, kk, fa, fy);
+    };
+    if (count > 0) get(0, fa0, fy0);
+    if (count > 1) get(1, fa1, fy1);
+    for (int64_t q = 0; q < count; q += 2) {
+      __syncthreads();
+      stage(bwd, i0, nb, first + step * q, fa0, fy0);
+      __syncthreads();
+      if (q + 2 < count) get(q + 2, fa0, fy0);
+      mma(bwd, acc);
+      if (q + 1 >= count) break;
+      __syncthreads();
+      stage(bwd, i0, nb, first + step * (q + 1), fa1, fy1);
+      __syncthreads();
+      if (q + 3 < count) get(q + 3, fa1, fy1);
+      mma(bwd, acc);
     }
   };
   // Yc <- rhs - accumulated sums (rows >= nb zero), Ab <- inverse block; the product with
   // it is the block's solution, stored and published
-  auto finish = [&](bool bwd, int64_t i0, int nb, int64_t blk, const v4d (&acc)[NCT],
-                    int* flag) {
+  auto finish = [&](bool bwd, int64_t i0, int nb, int64_t blk, const v4d& acc, int* flag) {
     T dd[AL];
 #pragma unroll
     for (int u = 0; u < AL; ++u) dd[u] = dv[blk * SB * SB + threadIdx.x + MT * u];
-    double bb[NCT][4];
+    double bb[4];
 #pragma unroll
-    for (int ct = 0; ct < NCT; ++ct)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = min<int64_t>(i0 + 16 * rt + 4 * r + lk, n - 1);
-        bb[ct][r] = x[row * M + min(16 * ct + li, M - 1)];
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = min<int64_t>(i0 + 16 * rt + 4 * r + lk, n - 1);
+      bb[r] = x[row * M + min(16 * ct + li, M - 1)];
+    }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < AL; ++u) {
       const int idx = threadIdx.x + MT * u;
       Ab[idx >> 6][idx & 63] = (double)dd[u];
     }
-#pragma unroll
-    for (int ct = 0; ct < NCT; ++ct)
+    if (tile)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int ii = 16 * rt + 4 * r + lk, col = 16 * ct + li;
-        if (col < M) Yc[ii * MP + col] = ii < nb ? bb[ct][r] - acc[ct][r] : 0.0;
+        if (col < M) Yc[ii * MP + col] = ii < nb ? bb[r] - acc[r] : 0.0;
       }
     __syncthreads();
-    v4d y[NCT];
-#pragma unroll
-    for (int ct = 0; ct < NCT; ++ct) y[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+    v4d y = {0.0, 0.0, 0.0, 0.0};
     mma(bwd, y);
-#pragma unroll
-    for (int ct = 0; ct < NCT; ++ct)
+    if (tile)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int ii = 16 * rt + 4 * r + lk, col = 16 * ct + li;
-        if (ii < nb && col < M) x[(i0 + ii) * M + col] = y[ct][r];
+        if (ii < nb && col < M) x[(i0 + ii) * M + col] = y[r];
       }
     // every wave's stores complete before the block is published
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (G > 1 && threadIdx.x == 0) post_flag(flag, epoch);
   };
-  // ---- forward
+  // ---- forward: chunks in increasing order; those from kdone on are still in flight
   for (int64_t k = g; k < nblk; k += G) {
     const int64_t i0 = k * SB;
     const int nb = (int)min<int64_t>(SB, n - i0);
     const int64_t kfirst = max<int64_t>(i0 - B, 0) / SB;
-    const int64_t kdone = max<int64_t>(k - G + 1, 0);          // chunks < kdone complete
-    const bool need_wait = G > 1 && k > 0;
-    v4d acc[NCT];
-#pragma unroll
-    for (int ct = 0; ct < NCT; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
-    T fa[AL];
-    double fy[YL];
-    if (kfirst < k) {
-      if (need_wait && kfirst >= kdone) wait_flag(ff + k - 1, epoch, err);
-      fetch(false, i0, kfirst, fa, fy);
-    }
-    for (int64_t kk = kfirst; kk < k; ++kk) {
-      __syncthreads();
-      stage(false, i0, nb, kk, fa, fy);
-      __syncthreads();
-      if (kk + 1 < k) {
-        if (need_wait && kk + 1 == kdone) wait_flag(ff + k - 1, epoch, err);
-        fetch(false, i0, kk + 1, fa, fy);
-      }
-      mma(false, acc);
-    }
+    const int64_t kdone = max<int64_t>(k - G + 1, 0);
+    bool waited = !(G > 1 && k > 0);
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    sweep(false, i0, nb, kfirst, k - kfirst, 1,
+          [&](int64_t kk) { return !waited && kk >= kdone; },
+          [&]() { wait_flag(ff + k - 1, epoch, err); waited = true; }, acc);
     finish(false, i0, nb, k, acc, ff + k);
   }
   // ---- backward: chunks from the far end of the band inwards
@@ -704,31 +712,10 @@ __global__ void __launch_bounds__(MT, 2) k_band_solve_m(
     const int64_t kdone = kb + G;                  // row blocks >= kdone complete
     int* wflag = kb + 1 < nblk ? bf + kb + 1 : ff + kb;
     bool waited = G == 1;
-    v4d acc[NCT];
-#pragma unroll
-    for (int ct = 0; ct < NCT; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
-    T fa[AL];
-    double fy[YL];
-    if (klast > kb) {
-      if (!waited && klast < kdone) {
-        wait_flag(wflag, epoch, err);
-        waited = true;
-      }
-      fetch(true, i0, klast, fa, fy);
-    }
-    for (int64_t kk = klast; kk > kb; --kk) {
-      __syncthreads();
-      stage(true, i0, nb, kk, fa, fy);
-      __syncthreads();
-      if (kk - 1 > kb) {
-        if (!waited && kk - 1 < kdone) {
-          wait_flag(wflag, epoch, err);
-          waited = true;
-        }
-        fetch(true, i0, kk - 1, fa, fy);
-      }
-      mma(true, acc);
-    }
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    sweep(true, i0, nb, klast, klast - kb, -1,
+          [&](int64_t kk) { return !waited && kk < kdone; },
+          [&]() { wait_flag(wflag, epoch, err); waited = true; }, acc);
     if (!waited) wait_flag(wflag, epoch, err);
     finish(true, i0, nb, kb, acc, bf + kb);
   }
@@ -972,7 +959,7 @@ extern "C" gx_status gx_band_factor_solve(gx_ctx* c, int32_t n_mat, const int64_
                      off[n_mat], band, fp32 ? dsc.p : nullptr, d_off.p, bs.d_n.p, bs.d_B.p,
                      d_doff.p, n_mat, fp32 ? bs.v32.p : nullptr, fp32 ? nullptr : bs.v64.p);
   GX_HIP(hipGetLastError());
-  band_factor(bs, s);
+  band_factor(bs, s, "the given band matrices");
   if (fp32)
     hipLaunchKernelGGL(k_scale_rhs, dim3(nblocks(doff[n_mat] * nrhs, 256)), dim3(256), 0, s,
                        doff[n_mat], nrhs, dsc.p, x);

@@ -753,7 +753,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
     }
     GX_HIP(hipGetLastError());
     try {
-      band_factor(Mb, s);
+      band_factor(Mb, s, "the shifted Neumann matrices (GenEO eigensolver)");
     } catch (const Error& e) {
       if (!fp32 || e.code != GX_ENOTSPD) throw;
       // an FP32 factor broke down: this matrix set is refactored in FP64 (reported)
@@ -762,15 +762,16 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
       hipLaunchKernelGGL(k_neumann_fill<double>, dim3((unsigned)maxD, n_sub), dim3(64), lds,
                          s, g, sigma, bv, d_doff.p, (const double*)nullptr, Mb.v64.p);
       GX_HIP(hipGetLastError());
-      band_factor(Mb, s);
+      band_factor(Mb, s, "the shifted Neumann matrices (GenEO eigensolver)");
     }
   }
   const bool m32 = Mb.fp32;
-  // block size: fixed count + 8 guard vectors; with a threshold, start at 24 and double
-  // while some subdomain's selected modes reach into the guard
-  // block sizes are multiples of 8 (the multi-right-hand-side solves are built for them)
+  // block size: the wanted count + 8 guard vectors, rounded up to a multiple of 8 (the
+  // multi-right-hand-side solves are built for them), at most MAXM; with a threshold the
+  // wanted count is the cap nev_max, so the block starts full (the block solves cost about
+  // the same per iteration at any width, and a wider block converges faster)
   auto round8 = [](int v) { return std::min(MAXM, (v + 7) / 8 * 8); };
-  int m = fixed_count ? round8(mwant + 8) : round8(std::min(24, mwant + 8));
+  int m = round8(mwant + 8);
   std::vector<int64_t> voff;
   DevBuf<int64_t> d_voff;
   DevBuf<double> X;
@@ -878,8 +879,10 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
       if (fixed_count) {
         w = want[j];
       } else {
-        while (w < m - 2 && h_theta[j * MAXM + w] - sigma < 1.5 * tau) ++w;
-        w = std::min(w + 1, m - 2);               // one pair beyond the margin as well
+        // the pairs below tau, and the first one above it (Ritz values approach the
+        // eigenvalues from above, so the count below tau can only grow while iterating)
+        while (w < m - 2 && h_theta[j * MAXM + w] - sigma < tau) ++w;
+        w = std::min(w + 1, m - 2);
       }
       // backward-error test: ||M x - theta B x|| <= tol * S ||x||, S = max over the block of
       // ||M x|| / ||x|| (an estimate of ||M||).  Relative to ||M x|| alone the test cannot
@@ -975,7 +978,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   hipLaunchKernelGGL(k_coarse_fill, dim3(nblocks(n0 * n0, 256)), dim3(256), 0, s, n0, K0.p,
                      sw.C.v64.p);
   GX_HIP(hipGetLastError());
-  band_factor(sw.C, s);
+  band_factor(sw.C, s, "the coarse matrix K0 (near-dependent coarse vectors?)");
   const int64_t zero64 = 0;
   sw.d_c_xoff.alloc(1);
   to_dev(sw.d_c_xoff.p, &zero64, 1, s);
@@ -1027,6 +1030,10 @@ gx_status gx_tune(gx_ctx* c, int32_t param, int64_t value) {
   GX_REQUIRE(param >= 0 && param < 2, "unknown tuning parameter");
   GX_REQUIRE(value >= 0 && value <= 8, "value out of range");
   c->tune[param] = (int)value;
+  if (c->setup_done) {                             // takes effect at the next solve
+    c->sw.A.force_groups[param] = (int)value;
+    c->sw.A.solve_groups[param] = 0;
+  }
   GX_API_END(c)
 }
 

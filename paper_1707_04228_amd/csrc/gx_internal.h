@@ -69,6 +69,23 @@ struct DevBuf {
   operator T*() const { return p; }
 };
 
+// Pinned host buffer (device-to-host copies that the host reads after a stream sync)
+template <class T>
+struct HostBuf {
+  T* p = nullptr;
+  HostBuf() = default;
+  HostBuf(const HostBuf&) = delete;
+  HostBuf& operator=(const HostBuf&) = delete;
+  ~HostBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  void alloc(size_t count) {
+    if (p) return;
+    GX_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), count * sizeof(T), hipHostMallocDefault));
+  }
+};
+
+
 template <class T>
 inline void zero(DevBuf<T>& b, hipStream_t s) {
   if (b.n) GX_HIP(hipMemsetAsync(b.p, 0, b.bytes(), s));
@@ -185,6 +202,7 @@ struct gx_ctx {
   bool setup_done = false;
   // PCG work vectors
   gx::DevBuf<double> r, z, p, q, bm, red;
+  gx::HostBuf<double> hred;                    // the reduction scalars, read by the host
   int32_t pcg_iters = 0;
   int32_t eig_iters = 0;
   int64_t neumann_entries = 0;
@@ -217,7 +235,7 @@ std::vector<int64_t> list_bandwidth(gx_ctx* c, const int32_t* list, const int64_
                                     const std::vector<int64_t>& cnt);
 void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<int64_t>& B,
                  bool fp32, hipStream_t st);
-void band_factor(BandSet& bs, hipStream_t st);
+void band_factor(BandSet& bs, hipStream_t st, const char* what);
 void band_solve_check(BandSet& bs, hipStream_t st);
 void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, int ncol = 1,
                 const int32_t* active = nullptr);

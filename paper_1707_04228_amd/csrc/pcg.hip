@@ -102,6 +102,177 @@ static void dot(gx_ctx* c, const double* a, const double* b, int dst, int mode) 
 }
 
 
+// One PCG solve as a state machine: begin() enqueues the initial residual, advance() reads
+// the scalars copied to the host at the previous step and enqueues the next iteration (or
+// finishes).  Between the two the caller synchronises the context's stream, so that a
+// batch of solves on several streams waits once per iteration for all of them.
+struct PcgRun {
+  gx_ctx* c = nullptr;
+  const double* b = nullptr;
+  double* x = nullptr;
+  double rtol = 0.0;
+  int maxit = 0;
+  double* hist = nullptr;
+  double nb = 0.0, rel = 0.0;
+  int it = 0;
+  bool started = false, done = false, init_pending = true;
+  gx_status st = GX_OK;
+  std::string msg;
+  EventPair ev_spmv, ev_pre;
+  double t_spmv = 0.0, t_pre = 0.0;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  ~PcgRun() {
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+  }
+};
+
+static void pcg_copy_scalars(gx_ctx* c) {
+  GX_HIP(hipMemcpyAsync(c->hred.p, c->red.p, S_N * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+}
+
+// spmv, alpha, x and r updates, ||r||; then the scalars to the host
+static void pcg_body(PcgRun& R) {
+  gx_ctx* c = R.c;
+  hipStream_t s = c->stream;
+  const int64_t n = 3 * c->n_nodes;
+  GX_HIP(hipEventRecord(R.ev_spmv.a, s));
+  spmv(c, c->p.p, c->q.p);
+  GX_HIP(hipEventRecord(R.ev_spmv.b, s));
+  dot(c, c->p.p, c->q.p, S_PQ, 1);
+  hipLaunchKernelGGL(k_update, dim3(RG), dim3(RB), 0, s, n, c->red.p, c->p.p, c->q.p, R.x,
+                     c->r.p, c->red.p + S_N);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, s, c->red.p + S_N, c->red.p, S_RR, 0);
+  GX_HIP(hipGetLastError());
+  pcg_copy_scalars(c);
+}
+
+static void pcg_begin(PcgRun& R) {
+  gx_ctx* c = R.c;
+  if (!c->setup_done) throw Error(GX_ESTATE, "gx_geneo_setup has not been called");
+  GX_REQUIRE(R.b && R.x && R.rtol > 0 && R.maxit >= 0, "bad arguments");
+  hipStream_t s = c->stream;
+  const int64_t n = 3 * c->n_nodes;
+  if (c->r.n != (size_t)n) {
+    c->r.alloc(n);
+    c->z.alloc(n);
+    c->p.alloc(n);
+    c->q.alloc(n);
+    c->bm.alloc(n);
+    c->red.alloc(S_N + RG);
+  }
+  c->hred.alloc(S_N);
+  GX_HIP(hipEventCreate(&R.t0));
+  GX_HIP(hipEventCreate(&R.t1));
+  GX_HIP(hipEventRecord(R.t0, s));
+  const unsigned gb = nblocks(n, 256);
+  zero(c->red, s);
+  hipLaunchKernelGGL(k_zero_fixed, dim3(gb), dim3(256), 0, s, n, c->fixed.p, R.x);
+  spmv(c, R.x, c->q.p);
+  hipLaunchKernelGGL(k_residual0, dim3(gb), dim3(256), 0, s, n, c->fixed.p, R.b, c->q.p,
+                     c->r.p, c->bm.p, R.x);
+  dot(c, c->bm.p, c->bm.p, S_BB, 0);
+  dot(c, c->r.p, c->r.p, S_RR, 0);
+  pcg_copy_scalars(c);
+  R.started = true;
+}
+
+// precond, beta, new direction, then the next body
+static void pcg_next(PcgRun& R, bool first) {
+  gx_ctx* c = R.c;
+  hipStream_t s = c->stream;
+  const int64_t n = 3 * c->n_nodes;
+  GX_HIP(hipEventRecord(R.ev_pre.a, s));
+  precond_apply(c, c->r.p, c->z.p);
+  GX_HIP(hipEventRecord(R.ev_pre.b, s));
+  if (first) {
+    dot(c, c->r.p, c->z.p, S_RZ, 0);
+    GX_HIP(hipMemcpyAsync(c->p.p, c->z.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    dot(c, c->r.p, c->z.p, S_RZNEW, 2);
+    hipLaunchKernelGGL(k_newdir, dim3(nblocks(n, 256)), dim3(256), 0, s, n, c->red.p, c->z.p,
+                       c->p.p);
+  }
+  pcg_body(R);
+}
+
+// the scalars of the last step are on the host (the stream has been synchronised)
+static void pcg_advance(PcgRun& R) {
+  gx_ctx* c = R.c;
+  const double* h = c->hred.p;
+  if (R.init_pending) {
+    R.init_pending = false;
+    R.nb = std::sqrt(h[S_BB]);
+    if (!(R.nb > 0)) {                             // b = 0: x = 0
+      GX_HIP(hipMemsetAsync(R.x, 0, 3 * c->n_nodes * sizeof(double), c->stream));
+      R.rel = 0.0;
+      if (R.hist) R.hist[0] = 0.0;
+      R.done = true;
+      return;
+    }
+    R.rel = std::sqrt(h[S_RR]) / R.nb;
+    if (R.hist) R.hist[0] = R.rel;
+    if (R.rel <= R.rtol) {
+      R.done = true;
+      return;
+    }
+    R.st = GX_ENOCONV;
+    if (R.maxit == 0) {
+      R.msg = "maximum number of iterations reached";
+      R.done = true;
+      return;
+    }
+    pcg_next(R, true);
+    return;
+  }
+  R.t_pre += R.ev_pre.ms();
+  R.t_spmv += R.ev_spmv.ms();
+  ++R.it;
+  if (h[S_FLAG] != 0.0) {
+    R.st = GX_EBREAKDOWN;
+    R.msg = "CG breakdown: p^T K p <= 0 or not finite";
+    R.done = true;
+    return;
+  }
+  R.rel = std::sqrt(h[S_RR]) / R.nb;
+  if (R.hist) R.hist[R.it] = R.rel;
+  if (!std::isfinite(R.rel)) {
+    R.st = GX_EBREAKDOWN;
+    R.msg = "CG breakdown: residual not finite";
+    R.done = true;
+    return;
+  }
+  if (R.rel <= R.rtol) {
+    R.st = GX_OK;
+    R.done = true;
+    return;
+  }
+  if (R.it >= R.maxit) {
+    R.msg = "maximum number of iterations reached";
+    R.done = true;
+    return;
+  }
+  pcg_next(R, false);
+}
+
+static void pcg_end(PcgRun& R, int32_t* iters_out, double* relres_out) {
+  gx_ctx* c = R.c;
+  GX_HIP(hipEventRecord(R.t1, c->stream));
+  GX_HIP(hipStreamSynchronize(c->stream));
+  band_solve_check(c->sw.A, c->stream);
+  band_solve_check(c->sw.C, c->stream);
+  if (iters_out) *iters_out = R.it;
+  if (relres_out) *relres_out = R.rel;
+  float ms = 0.0f;
+  GX_HIP(hipEventElapsedTime(&ms, R.t0, R.t1));
+  c->phase_ms[5] = ms;
+  c->phase_ms[6] = R.t_pre;
+  c->phase_ms[7] = R.t_spmv;
+  c->pcg_iters = R.it;
+  if (R.st != GX_OK) c->err = R.msg;
+}
+
 }  // namespace gx
 
 using namespace gx;
@@ -122,101 +293,78 @@ gx_status gx_precond_apply(gx_ctx* c, const double* r, double* z) {
 gx_status gx_pcg_solve(gx_ctx* c, const double* b, double* x, double rtol, int32_t maxit,
                        int32_t* iters_out, double* relres_out, double* hist) {
   GX_API_BEGIN(c)
-  if (!c->setup_done) throw Error(GX_ESTATE, "gx_geneo_setup has not been called");
-  GX_REQUIRE(b && x && rtol > 0 && maxit >= 0, "bad arguments");
-  hipStream_t s = c->stream;
-  const int64_t n = 3 * c->n_nodes;
-  if (c->r.n != (size_t)n) {
-    c->r.alloc(n);
-    c->z.alloc(n);
-    c->p.alloc(n);
-    c->q.alloc(n);
-    c->bm.alloc(n);
-    c->red.alloc(S_N + RG);
+  PcgRun R;
+  R.c = c;
+  R.b = b;
+  R.x = x;
+  R.rtol = rtol;
+  R.maxit = maxit;
+  R.hist = hist;
+  pcg_begin(R);
+  while (!R.done) {
+    GX_HIP(hipStreamSynchronize(c->stream));
+    pcg_advance(R);
   }
-  Timer tm(s);
-  EventPair ev_spmv, ev_pre;
-  double t_spmv = 0, t_pre = 0;
-  const unsigned gb = nblocks(n, 256);
-  zero(c->red, s);
-  hipLaunchKernelGGL(k_zero_fixed, dim3(gb), dim3(256), 0, s, n, c->fixed.p, x);
-  spmv(c, x, c->q.p);
-  hipLaunchKernelGGL(k_residual0, dim3(gb), dim3(256), 0, s, n, c->fixed.p, b, c->q.p,
-                     c->r.p, c->bm.p, x);
-  dot(c, c->bm.p, c->bm.p, S_BB, 0);
-  dot(c, c->r.p, c->r.p, S_RR, 0);
-  double h[S_N];
-  to_host(h, c->red.p, S_N, s);
-  const double nb = std::sqrt(h[S_BB]);
-  if (!(nb > 0)) {
-    GX_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
-    GX_HIP(hipStreamSynchronize(s));
-    if (iters_out) *iters_out = 0;
-    if (relres_out) *relres_out = 0.0;
-    if (hist) hist[0] = 0.0;
-    c->phase_ms[5] = tm.ms();
-    return GX_OK;
-  }
-  double rel = std::sqrt(h[S_RR]) / nb;
-  if (hist) hist[0] = rel;
-  int it = 0;
-  gx_status st = GX_OK;
-  if (rel > rtol) {
-    GX_HIP(hipEventRecord(ev_pre.a, s));
-    precond_apply(c, c->r.p, c->z.p);
-    GX_HIP(hipEventRecord(ev_pre.b, s));
-    dot(c, c->r.p, c->z.p, S_RZ, 0);
-    GX_HIP(hipMemcpyAsync(c->p.p, c->z.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    st = GX_ENOCONV;
-    while (it < maxit) {
-      GX_HIP(hipEventRecord(ev_spmv.a, s));
-      spmv(c, c->p.p, c->q.p);
-      GX_HIP(hipEventRecord(ev_spmv.b, s));
-      dot(c, c->p.p, c->q.p, S_PQ, 1);
-      hipLaunchKernelGGL(k_update, dim3(RG), dim3(RB), 0, s, n, c->red.p, c->p.p, c->q.p, x,
-                         c->r.p, c->red.p + S_N);
-      hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, s, c->red.p + S_N, c->red.p, S_RR,
-                         0);
-      GX_HIP(hipGetLastError());
-      to_host(h, c->red.p, S_N, s);
-      t_pre += ev_pre.ms();
-      t_spmv += ev_spmv.ms();
-      ++it;
-      if (h[S_FLAG] != 0.0) {
-        st = GX_EBREAKDOWN;
-        c->err = "CG breakdown: p^T K p <= 0 or not finite";
-        break;
-      }
-      rel = std::sqrt(h[S_RR]) / nb;
-      if (hist) hist[it] = rel;
-      if (!std::isfinite(rel)) {
-        st = GX_EBREAKDOWN;
-        c->err = "CG breakdown: residual not finite";
-        break;
-      }
-      if (rel <= rtol) {
-        st = GX_OK;
-        break;
-      }
-      GX_HIP(hipEventRecord(ev_pre.a, s));
-      precond_apply(c, c->r.p, c->z.p);
-      GX_HIP(hipEventRecord(ev_pre.b, s));
-      dot(c, c->r.p, c->z.p, S_RZNEW, 2);
-      hipLaunchKernelGGL(k_newdir, dim3(gb), dim3(256), 0, s, n, c->red.p, c->z.p, c->p.p);
-    }
-    if (st == GX_ENOCONV) c->err = "maximum number of iterations reached";
-  }
-  GX_HIP(hipStreamSynchronize(s));
-  band_solve_check(c->sw.A, s);
-  band_solve_check(c->sw.C, s);
-  if (iters_out) *iters_out = it;
-  if (relres_out) *relres_out = rel;
-  c->phase_ms[5] = tm.ms();
-  c->phase_ms[6] = t_pre;
-  c->phase_ms[7] = t_spmv;
-  c->pcg_iters = it;
-  return st;
+  pcg_end(R, iters_out, relres_out);
+  return R.st;
   GX_API_END(c)
+}
+
+gx_status gx_pcg_solve_batch(int32_t n, gx_ctx* const* ctxs, const double* const* b,
+                             double* const* x, double rtol, int32_t maxit, int32_t* iters_out,
+                             double* relres_out, int32_t* status_out) {
+  if (n < 1 || !ctxs || !b || !x) return GX_EINVAL;
+  std::vector<PcgRun> runs(n);
+  std::vector<gx_status> st(n, GX_OK);
+  auto fail = [&](int i, gx_status code, const char* what) {
+    st[i] = code;
+    ctxs[i]->err = what;
+    runs[i].done = true;
+  };
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return GX_EINVAL;
+    runs[i].c = ctxs[i];
+    runs[i].b = b[i];
+    runs[i].x = x[i];
+    runs[i].rtol = rtol;
+    runs[i].maxit = maxit;
+    try {
+      ctxs[i]->err.clear();
+      GX_HIP(hipSetDevice(ctxs[i]->device));
+      pcg_begin(runs[i]);
+    } catch (const Error& e) {
+      fail(i, e.code, e.what());
+    }
+  }
+  // lockstep: one synchronisation of every active stream per iteration
+  for (;;) {
+    bool any = false;
+    for (int i = 0; i < n; ++i) {
+      if (runs[i].done) continue;
+      any = true;
+      try {
+        GX_HIP(hipSetDevice(ctxs[i]->device));
+        GX_HIP(hipStreamSynchronize(ctxs[i]->stream));
+        pcg_advance(runs[i]);
+      } catch (const Error& e) {
+        fail(i, e.code, e.what());
+      }
+    }
+    if (!any) break;
+  }
+  gx_status first = GX_OK;
+  for (int i = 0; i < n; ++i) {
+    try {
+      if (runs[i].started) pcg_end(runs[i], iters_out ? iters_out + i : nullptr,
+                                   relres_out ? relres_out + i : nullptr);
+    } catch (const Error& e) {
+      if (st[i] == GX_OK) fail(i, e.code, e.what());
+    }
+    if (st[i] == GX_OK) st[i] = runs[i].st;
+    if (status_out) status_out[i] = st[i];
+    if (first == GX_OK) first = st[i];
+  }
+  return first;
 }
 
 gx_status gx_kernel_time(gx_ctx* c, int32_t which, int32_t reps, double* avg_ms,

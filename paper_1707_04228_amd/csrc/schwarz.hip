@@ -310,7 +310,7 @@ void interior_factors(gx_ctx* c, int precision) {
                        sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, N, bv, sw.A.v64.p);
   GX_HIP(hipGetLastError());
   try {
-    band_factor(sw.A, s);
+    band_factor(sw.A, s, "the subdomain matrices");
   } catch (const Error& e) {
     if (!fp32 || e.code != GX_ENOTSPD) throw;
     // an FP32 factor broke down: the interior factors are rebuilt in FP64 (reported)
@@ -321,7 +321,7 @@ void interior_factors(gx_ctx* c, int precision) {
                        c->row_ptr.p, c->col.p, c->val.p, (const double*)nullptr, sw.I_nodes.p,
                        sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, N, bv64, sw.A.v64.p);
     GX_HIP(hipGetLastError());
-    band_factor(sw.A, s);
+    band_factor(sw.A, s, "the subdomain matrices");
     sw.precision = GX_FP64;
   }
   // solve work vectors, one segment of 3 nI_j per subdomain

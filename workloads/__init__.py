@@ -89,8 +89,11 @@ def cfg2(nx=240, ny=18, ply_nel=4, px=32, py=2, amp=0.3, wlen=4.0, limb=40.0):
                 solver=dict(px=px, py=py, overlap=2, nev=0, tau=0.1, nev_max=32, rtol=1e-8))
 
 
-def cfg3(nx=240, ny=4, px=8, py=2):
-    """Adjoint workload: cfg2 geometry with 2 elements per ply, 240x4x35 (490,377 DOFs)."""
+def cfg3(nx=240, ny=4, px=16, py=1):
+    """Adjoint workload: cfg2 geometry with 2 elements per ply, 240x4x35 (490,377 DOFs).
+
+    16 x 1 subdomains: across 4 elements of width, two subdomains grown by an overlap of 2
+    would each cover the full width and coincide."""
     return cfg2(nx=nx, ny=ny, ply_nel=2, px=px, py=py)
 
 
@@ -125,11 +128,14 @@ def cfg4(i, samples=None, nx_override=None):
     ny = int(min(16, max(2, round(smp["target"] / (12 * nx * nz)))))
     n_dofs_guess = 12 * nx * ny * nz
     nsub = max(2, int(round(n_dofs_guess / 4e4)))
+    # wide samples are split across the width as well (keeps the subdomain bandwidth small)
+    py = 2 if ny > 8 else 1
+    px = max(1, int(round(nsub / py)))
     return dict(name=f"cfg4_sample{i}", geometry="lsection", radius=radius, limb=limb,
                 width=10.0, nx=nx, ny=ny, nx_limb=_limb_elems(nx, limb, radius, layers),
                 layers=layers, wrinkle=(smp["amp"], smp["wlen"]),
                 load={"kind": "moment", "M": PAPER_MOMENT},
-                solver=dict(px=nsub, py=1, overlap=2, nev=0, tau=0.1, nev_max=32, rtol=1e-8))
+                solver=dict(px=px, py=py, overlap=2, nev=0, tau=0.1, nev_max=32, rtol=1e-8))
 
 
 def small_flat(nx=4, ny=3, layers=None, length=4.0, width=3.0):
