@@ -68,7 +68,8 @@ def batch_sweep(gx, torch, workloads, args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch = gx.Batch(cfgs, precision=prec)
-    batch.setup()
+    batch.setup(progress=lambda i, n: print(f"# set up {i + 1}/{n}", file=sys.stderr,
+                                            flush=True))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     xs, it, rr, st = batch.solve(rtol=1e-8, maxit=3000)

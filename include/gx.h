@@ -191,14 +191,13 @@ typedef struct {
   const int32_t* elem_part;  /* device [n_elems]: core subdomain of each element */
   int32_t overlap;           /* element layers of overlap (>= 1) */
   double tau;                /* eigenvalue threshold (used when nev <= 0) */
-  int32_t nev;               /* > 0: fixed number of modes per subdomain */
-  int32_t nev_max;           /* cap per subdomain (<= 32; at most 30 are kept: the
-                                eigensolver block of 32 holds 2 guard vectors) */
+  int32_t nev;               /* > 0: fixed number of modes per subdomain (<= 40) */
+  int32_t nev_max;           /* cap per subdomain (<= 32) */
   int32_t precision;         /* GX_FP64, or GX_MIXED: FP32 subdomain factors and solves */
   int32_t coarse;            /* 1: two-level (GenEO); 0: one-level Schwarz */
   const int32_t* nev_per_sub;/* optional host [n_sub]: modes per subdomain (overrides) */
   double eig_tol;            /* relative eigen-residual target (0: default 1e-10) */
-  int32_t eig_maxit;         /* eigensolver iteration cap (0: default 200) */
+  int32_t eig_maxit;         /* eigensolver iteration cap (0: default 1000) */
 } gx_geneo_opts;
 
 /* Build the decomposition, factor the subdomain matrices, solve the local eigenproblems
@@ -257,8 +256,9 @@ gx_status gx_adjoint(gx_ctx* ctx, const gx_laminate* lam, int32_t region, const 
  * off_j + r (bw[j] + 1) + (c - r + bw[j]), off_j = sum over i < j of n[i] (bw[i] + 1)
  * (device, FP64; copied, the input is not modified).  x (device) holds nrhs right-hand
  * sides per matrix, row-major n[j] x nrhs, matrices concatenated; overwritten with the
- * solutions.  nrhs is 1, 8, 16, 24 or 32.  precision GX_MIXED factors and solves with FP32
- * factors of diag(A)^-1/2 A diag(A)^-1/2 (x stays FP64).  groups > 0 forces the number of
+ * solutions.  nrhs is 1 or a multiple of 8 up to 64 (more than 32 are solved in panels of
+ * 32).  precision GX_MIXED factors and solves with FP32 factors of
+ * diag(A)^-1/2 A diag(A)^-1/2 (x stays FP64).  groups > 0 forces the number of
  * work-groups per matrix (bounded by what stays resident), 0 chooses it.  GX_ENOTSPD on a
  * non-positive pivot. */
 gx_status gx_band_factor_solve(gx_ctx* ctx, int32_t n_mat, const int64_t* n, const int64_t* bw,

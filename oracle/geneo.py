@@ -16,7 +16,13 @@ basis vectors are z = R_j^T (Xt_j p)|_{I_j}, and K_0 = Z^T K Z is Cholesky-facto
 
 Solver: ARPACK in shift-invert mode about -sigma (sigma = 1e-3 tau, or 1e-4 when nev is
 given), i.e. the largest mu of B p = mu (A^N + sigma B) p; A^N + sigma B is SPD because no
-rigid-body mode lies in the null space of B.
+rigid-body mode lies in the null space of B.  B itself is only semi-definite, and ARPACK
+(which uses B as its inner product here) can return vectors carrying null(B) components:
+for some start vectors such pairs had residuals of the order of ||A^N p||.  The returned
+block is therefore purified by one application of (A^N + sigma B)^-1 B, which removes those
+components, and a Rayleigh-Ritz step on the pencil (B, A^N + sigma B) over it gives the
+pairs.  ARPACK starts from a fixed vector (results do not depend on earlier calls), and
+every pair must have a residual below 1e-11 ||A^N||_1 ||p||, else the oracle raises.
 """
 from __future__ import annotations
 
@@ -62,9 +68,22 @@ def solve_local_eigen(AN, B, nev=0, tau=0.1, nev_max=32, tol=1e-13, dense=None):
         k = nev if nev > 0 else min(nev_max, int(np.sum(lam < tau)))
         return lam[:k], V[:, :k]
     k = nev if nev > 0 else min(8, nev_max)
+    v0 = np.random.default_rng(n).standard_normal(n)
+    Msh = (AN + shift * B).tocsc()
+    lu = spla.splu(Msh)
     while True:
         kk = min(k, n - 2)
-        lam, V = spla.eigsh(AN, k=kk, M=B, sigma=-shift, which="LM", tol=tol)
+        _, V = spla.eigsh(AN, k=kk, M=B, sigma=-shift, which="LM", tol=tol, v0=v0,
+                          ncv=min(n - 1, max(2 * kk + 1, kk + 40)))
+        V = lu.solve(B @ V)
+        mu, C = sla.eigh(V.T @ (B @ V), V.T @ (Msh @ V))
+        V = V @ C
+        lam = 1.0 / mu - shift
+        res = np.linalg.norm(AN @ V - (B @ V) * lam, axis=0) / (
+            abs(AN).sum(axis=0).max() * np.linalg.norm(V, axis=0))
+        if not np.all(res <= 1e-11):
+            raise RuntimeError(f"ARPACK returned an unconverged pair (backward error "
+                               f"{res.max():.1e})")
         order = np.argsort(lam)
         lam, V = lam[order], V[:, order]
         if nev > 0:

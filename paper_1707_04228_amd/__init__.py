@@ -506,15 +506,18 @@ class Batch:
             self.solvers.append(s)
         self.precision = precision
 
-    def setup(self):
-        """Decomposition, GenEO coarse spaces and factors of every laminate."""
+    def setup(self, progress=None):
+        """Decomposition, GenEO coarse spaces and factors of every laminate; progress(i, n)
+        is called after each."""
         out = []
-        for cfg, s in zip(self.cfgs, self.solvers):
+        for i, (cfg, s) in enumerate(zip(self.cfgs, self.solvers)):
             sv = cfg["solver"]
             part = s.partition(cfg, sv["px"], sv["py"])
             out.append(s.geneo_setup(part, sv["px"] * sv["py"], overlap=sv["overlap"],
                                      tau=sv["tau"] or 0.1, nev=sv["nev"] or 0,
                                      nev_max=sv["nev_max"], precision=self.precision))
+            if progress:
+                progress(i, len(self.solvers))
         return out
 
     def solve(self, rtol=1e-8, maxit=2000):

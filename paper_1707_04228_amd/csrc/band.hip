@@ -774,10 +774,49 @@ static void launch_m(BandSet& bs, const BandArgs& a, const int64_t* d_xoff, doub
                        fl + n_pad * nblk, nblk, bs.epoch, active, fl + 2 * n_pad * nblk);
 }
 
+// Columns c0 .. c0 + w of a row-major block of ncol columns to or from a contiguous panel
+// of w columns (panel of matrix j at poff[j]).
+__global__ void k_panel_copy(const int64_t* nrows, const int64_t* xoff, double* x, int ncol,
+                             int c0, int w, const int64_t* poff, double* panel,
+                             const int32_t* active, int to_panel) {
+  const int j = blockIdx.y;
+  if (active && !active[j]) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nrows[j] * w) return;
+  const int64_t r = e / w, c = e - r * w;
+  double* xe = x + xoff[j] + r * ncol + c0 + c;
+  double* pe = panel + poff[j] + e;
+  if (to_panel)
+    *pe = *xe;
+  else
+    *xe = *pe;
+}
+
 void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, int ncol,
                 const int32_t* active) {
-  GX_REQUIRE(ncol == 1 || (ncol % 8 == 0 && ncol <= MC),
-             "banded solve: right-hand sides must be 1, 8, 16, 24 or 32");
+  GX_REQUIRE(ncol == 1 || (ncol % 8 == 0 && ncol <= 2 * MC),
+             "banded solve: right-hand sides must be 1 or a multiple of 8 up to 64");
+  if (ncol > MC) {
+    // panels of at most MC columns through a scratch block; the factor is read once per panel
+    if (!bs.d_poff.n) {
+      std::vector<int64_t> po(bs.n_mat + 1, 0);
+      for (int j = 0; j < bs.n_mat; ++j) po[j + 1] = po[j] + bs.n[j] * MC;
+      bs.panel.alloc(po[bs.n_mat]);
+      bs.d_poff.alloc(bs.n_mat + 1);
+      to_dev(bs.d_poff.p, po.data(), bs.n_mat + 1, st);
+    }
+    for (int c0 = 0; c0 < ncol; c0 += MC) {
+      const int w = std::min(MC, ncol - c0);
+      const dim3 grid(nblocks((int64_t)bs.max_n * w, 256), bs.n_mat);
+      hipLaunchKernelGGL(k_panel_copy, grid, dim3(256), 0, st, bs.d_n.p, d_xoff, x, ncol, c0,
+                         w, bs.d_poff.p, bs.panel.p, active, 1);
+      band_solve(bs, bs.d_poff.p, bs.panel.p, st, w, active);
+      hipLaunchKernelGGL(k_panel_copy, grid, dim3(256), 0, st, bs.d_n.p, d_xoff, x, ncol, c0,
+                         w, bs.d_poff.p, bs.panel.p, active, 0);
+    }
+    GX_HIP(hipGetLastError());
+    return;
+  }
   BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p};
   int64_t nblk = 0;
   int n_pad = 0;
@@ -846,6 +885,8 @@ void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<i
   bs.fp32 = fp32;
   int64_t o = 0;
   bs.max_n = 0;
+  bs.panel.release();
+  bs.d_poff.release();
   bs.max_B = 0;
   for (size_t j = 0; j < n.size(); ++j) {
     bs.ld[j] = B[j] + 1;
@@ -931,7 +972,8 @@ extern "C" gx_status gx_band_factor_solve(gx_ctx* c, int32_t n_mat, const int64_
   GX_API_BEGIN(c)
   GX_REQUIRE(n_mat >= 1 && n && bw && band && x, "bad band matrices");
   GX_REQUIRE(precision == GX_FP64 || precision == GX_MIXED, "bad precision");
-  GX_REQUIRE(nrhs == 1 || (nrhs % 8 == 0 && nrhs <= MC), "nrhs must be 1, 8, 16, 24 or 32");
+  GX_REQUIRE(nrhs == 1 || (nrhs % 8 == 0 && nrhs <= 2 * MC),
+             "nrhs must be 1 or a multiple of 8 up to 64");
   std::vector<int64_t> nv(n, n + n_mat), bv(bw, bw + n_mat), off(n_mat + 1, 0),
       doff(n_mat + 1, 0), xoff(n_mat);
   for (int j = 0; j < n_mat; ++j) {

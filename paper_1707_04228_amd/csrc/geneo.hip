@@ -20,7 +20,8 @@
 
 namespace gx {
 
-constexpr int MAXM = 32;                       // eigensolver block size limit (multiple of 8)
+constexpr int MAXM = 48;                       // eigensolver block size limit (multiple of 8)
+constexpr int MSTART = 32;                     // threshold mode: first block (one solve panel)
 
 __device__ inline bool has_bit(const uint64_t* mask, int64_t item, int W, int j) {
   return (mask[item * W + j / 64] >> (j % 64)) & 1ull;
@@ -79,52 +80,63 @@ __global__ void k_neumann_diag(GeneoDev g, double sigma, const int64_t* doff, do
 }
 
 // M_j = A^N + sigma X A^o X in band storage over the Neumann DOFs; clamped DOFs -> identity.
-// The three band rows of a node are accumulated in LDS (element order, deterministic) and
-// written once, scaled symmetrically by diag(M)^-1/2 when dM is given (FP32 factors).
+// The three band rows of a node are accumulated in LDS (element order, deterministic), in
+// segments of at most NSEG band columns so any bandwidth fits; each segment is written once,
+// scaled symmetrically by diag(M)^-1/2 when dM is given (FP32 factors).
+constexpr int NSEG = 2048;                       // band-row columns per LDS segment
+
 template <class T>
 __global__ void __launch_bounds__(64) k_neumann_fill(GeneoDev g, double sigma, BandView bv,
                                                      const int64_t* doff, const double* dM,
                                                      T* v) {
-  extern __shared__ double rowbuf[];
+  extern __shared__ double rowbuf[];               // 3 rows x seg columns
   const int j = blockIdx.y;
   const int64_t ln = blockIdx.x;
   if (ln >= g.nD[j]) return;
   const int64_t n = g.D_nodes[g.offD[j] + ln];
   const int64_t B = bv.B[j], ld = bv.ld[j];
   T* base = v + bv.off[j];
-  for (int64_t i = threadIdx.x; i < 3 * ld; i += 64) rowbuf[i] = 0.0;
-  __syncthreads();
   const double xn = pou(g.I_loc, g.cnt, g.N, j, n);
-  for (int k = g.ne_ptr[n]; k < g.ne_ptr[n + 1]; ++k) {
-    const int64_t e = g.ne_idx[k];
-    if (!has_bit(g.emask, e, g.W, j)) continue;
-    const bool over = popc_mask(g.emask, e, g.W) >= 2;
-    int a = 0;
-    while (a < 19 && g.conn[20 * e + a] != n) ++a;
-    for (int t = threadIdx.x; t < 180; t += 64) {
-      const int b = t / 9, comp = t - 9 * (t / 9);
-      const int i = comp / 3, kk = comp - 3 * (comp / 3);
-      const int64_t m = g.conn[20 * e + b];
-      const int64_t lm = g.D_loc[(int64_t)j * g.N + m];
-      const int64_t row = 3 * ln + i, col = 3 * lm + kk;
-      if (col > row) continue;
-      const double w = over ? 1.0 + sigma * xn * pou(g.I_loc, g.cnt, g.N, j, m) : 1.0;
-      rowbuf[i * ld + (col - row + B)] += w * g.Ke[((e * 20 + a) * 20 + b) * 9 + comp];
+  const int64_t seg = min<int64_t>(ld, NSEG);
+  // the three band rows of the node, in segments of columns (band offsets o0 .. o0 + seg)
+  for (int64_t o0 = 0; o0 < ld; o0 += seg) {
+    for (int64_t i = threadIdx.x; i < 3 * seg; i += 64) rowbuf[i] = 0.0;
+    __syncthreads();
+    for (int k = g.ne_ptr[n]; k < g.ne_ptr[n + 1]; ++k) {
+      const int64_t e = g.ne_idx[k];
+      if (!has_bit(g.emask, e, g.W, j)) continue;
+      const bool over = popc_mask(g.emask, e, g.W) >= 2;
+      int a = 0;
+      while (a < 19 && g.conn[20 * e + a] != n) ++a;
+      for (int t = threadIdx.x; t < 180; t += 64) {
+        const int b = t / 9, comp = t - 9 * (t / 9);
+        const int i = comp / 3, kk = comp - 3 * (comp / 3);
+        const int64_t m = g.conn[20 * e + b];
+        const int64_t lm = g.D_loc[(int64_t)j * g.N + m];
+        const int64_t row = 3 * ln + i, col = 3 * lm + kk;
+        const int64_t o = col - row + B - o0;
+        if (col > row || o < 0 || o >= seg) continue;
+        const double w = over ? 1.0 + sigma * xn * pou(g.I_loc, g.cnt, g.N, j, m) : 1.0;
+        rowbuf[i * seg + o] += w * g.Ke[((e * 20 + a) * 20 + b) * 9 + comp];
+      }
+      __syncthreads();
+    }
+    const int64_t cnt = min<int64_t>(seg, ld - o0);
+    for (int64_t t = threadIdx.x; t < 3 * cnt; t += 64) {
+      const int64_t r3 = t / cnt, o = o0 + t % cnt;
+      const int64_t row = 3 * ln + r3, col = row - B + o;
+      double val = rowbuf[r3 * seg + (o - o0)];
+      if (col >= 0) {
+        const int64_t gr = 3 * n + row % 3;
+        const int64_t gc = 3 * (int64_t)g.D_nodes[g.offD[j] + col / 3] + col % 3;
+        if (g.fixed[gr] || g.fixed[gc]) val = (row == col) ? 1.0 : 0.0;
+        if (dM) val /= sqrt(dM[doff[j] + row] * dM[doff[j] + col]);
+      } else {
+        val = 0.0;
+      }
+      base[row * ld + o] = (T)val;
     }
     __syncthreads();
-  }
-  for (int64_t t = threadIdx.x; t < 3 * ld; t += 64) {
-    const int64_t row = 3 * ln + t / ld, col = row - B + t % ld;
-    double val = rowbuf[t];
-    if (col >= 0) {
-      const int64_t gr = 3 * n + row % 3;
-      const int64_t gc = 3 * (int64_t)g.D_nodes[g.offD[j] + col / 3] + col % 3;
-      if (g.fixed[gr] || g.fixed[gc]) val = (row == col) ? 1.0 : 0.0;
-      if (dM) val /= sqrt(dM[doff[j] + row] * dM[doff[j] + col]);
-    } else {
-      val = 0.0;
-    }
-    base[3 * ln * ld + t] = (T)val;
   }
 }
 
@@ -252,6 +264,16 @@ __global__ void k_rand_init(GeneoDev g, int m, const int64_t* voff, double* X) {
   z ^= z >> 31;
   const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
   X[voff[j] + r] = g.fixed[3 * n + row % 3] ? 0.0 : u;
+}
+
+// the m0 columns of a block into the first m0 columns of a block of m1 >= m0 columns
+__global__ void k_widen(const int64_t* nrows, int m0, const int64_t* voff0, const double* X0,
+                        int m1, const int64_t* voff1, double* X1) {
+  const int j = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * nrows[j] * m0) return;
+  const int64_t row = e / m0, c = e - row * m0;
+  X1[voff1[j] + row * m1 + c] = X0[voff0[j] + e];
 }
 
 __global__ void k_copy_active(int64_t n_rows_max, const int64_t* nrows, int m,
@@ -698,21 +720,21 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   const int n_sub = sw.n_sub;
   const int64_t N = c->n_nodes;
   const double tau = o->tau > 0 ? o->tau : 0.1;
-  // at most MAXM - 2 modes per subdomain fit the eigensolver block (two guard vectors)
-  const int nev_max = std::min(o->nev_max > 0 ? o->nev_max : 32, MAXM - 2);
+  // at most MAXM - 8 modes per subdomain fit the eigensolver block (eight guard vectors)
+  const int nev_max = std::min(o->nev_max > 0 ? o->nev_max : 32, MAXM - 8);
   std::vector<int> want(n_sub, o->nev > 0 ? o->nev : 0);
   if (o->nev_per_sub)
     for (int j = 0; j < n_sub; ++j) want[j] = o->nev_per_sub[j];
   const bool fixed_count = o->nev > 0 || o->nev_per_sub;
   int mwant = fixed_count ? 0 : nev_max;
   for (int j = 0; j < n_sub; ++j) mwant = std::max(mwant, want[j]);
-  GX_REQUIRE(mwant >= 1 && mwant + 2 <= MAXM, "requested modes exceed the eigensolver block");
+  GX_REQUIRE(mwant >= 1 && mwant + 8 <= MAXM, "requested modes exceed the eigensolver block");
   // shift of the pencil: tiny in FP64; in the mixed path 0.1 tau keeps A^N + sigma B well
   // enough conditioned for FP32 factors (convergence rate (lambda + s)/(lambda_m+1 + s))
   const double sigma = o->precision == GX_MIXED ? 0.1 * tau
                                                 : (fixed_count ? 1e-4 * tau : 1e-3 * tau);
   const double tol = o->eig_tol > 0 ? o->eig_tol : 1e-10;
-  const int maxit = o->eig_maxit > 0 ? o->eig_maxit : 200;
+  const int maxit = o->eig_maxit > 0 ? o->eig_maxit : 1000;
   for (int j = 0; j < n_sub; ++j)
     GX_REQUIRE(3 * sw.nD[j] >= mwant + 8, "subdomain too small for the eigensolver block");
   Timer te(s);
@@ -738,8 +760,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
     Mb.force_groups[0] = c->tune[0];
     Mb.force_groups[1] = c->tune[1];
     c->neumann_entries = Mb.total;
-    const size_t lds = 3 * (size_t)(Mb.max_B + 1) * sizeof(double);
-    GX_REQUIRE(lds <= 65536, "Neumann bandwidth too large for the band assembly");
+    const size_t lds = 3 * (size_t)std::min<int64_t>(Mb.max_B + 1, NSEG) * sizeof(double);
     BandView bv{Mb.d_B.p, Mb.d_ld.p, Mb.d_off.p};
     if (fp32) {
       dM.alloc(doff[n_sub]);
@@ -766,15 +787,21 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
     }
   }
   const bool m32 = Mb.fp32;
-  // block size: the wanted count + 8 guard vectors, rounded up to a multiple of 8 (the
-  // multi-right-hand-side solves are built for them), at most MAXM; with a threshold the
-  // wanted count is the cap nev_max, so the block starts full (the block solves cost about
-  // the same per iteration at any width, and a wider block converges faster)
+  // block size: a fixed count takes the wanted count + 8 guard vectors, rounded up to a
+  // multiple of 8 (the multi-right-hand-side solves are built for them).  A threshold starts
+  // with one full solve panel (MSTART columns: the solves cost about the same per iteration
+  // at any width up to it) and grows to nev_max + 16 as soon as more than m - 8 Ritz values
+  // lie below tau in some subdomain (Ritz values approach from above, so that count only
+  // grows); the grown block starts from the current one, padded with fresh random columns.
+  // A cluster of eigenvalues at the cut converges at the rate (lambda_w + s)/(lambda_m + s),
+  // so the guard vectors matter.
   auto round8 = [](int v) { return std::min(MAXM, (v + 7) / 8 * 8); };
-  int m = round8(mwant + 8);
+  const int mcap = fixed_count ? round8(mwant + 8) : round8(nev_max + 16);
+  int m = fixed_count ? mcap : std::min(mcap, MSTART);
   std::vector<int64_t> voff;
-  DevBuf<int64_t> d_voff;
-  DevBuf<double> X;
+  DevBuf<int64_t> d_voff, d_voff_prev;
+  DevBuf<double> X, X_prev;
+  int m_prev = 0;
   std::vector<double> lam_final;
   int it = 0;
   EventPair ev;
@@ -804,10 +831,16 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   const dim3 grows(nblocks(3 * maxD, 4), n_sub);
   const dim3 gch((unsigned)nch_max, n_sub);
   hipLaunchKernelGGL(k_rand_init, gvec, dim3(256), 0, s, g, m, d_voff.p, X.p);
+  if (m_prev)                                      // warm start: the previous block first
+    hipLaunchKernelGGL(k_widen, dim3(nblocks(3 * maxD * m_prev, 256), n_sub), dim3(256), 0, s,
+                       sw.d_nD.p, m_prev, d_voff_prev.p, X_prev.p, m, d_voff.p, X.p);
+  X_prev.release();
+  d_voff_prev.release();
   hipLaunchKernelGGL(k_bmul, growD, dim3(64), 0, s, g, m, d_voff.p, active.p, X.p, BX.p);
   std::vector<double> h_theta((size_t)n_sub * MAXM), h_res((size_t)n_sub * 3 * MAXM);
   lam_final.assign((size_t)n_sub * MAXM, 0.0);
   int n_active = n_sub;
+  bool grow = false;
   for (int itm = 0; itm < maxit && n_active > 0; ++itm, ++it) {
     if (m32) {
       // FP32 factor solves T ~ M^-1 (T = S Mt^-1 S): first step Y = T BX, then the
@@ -879,10 +912,12 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
       if (fixed_count) {
         w = want[j];
       } else {
-        // the pairs below tau, and the first one above it (Ritz values approach the
-        // eigenvalues from above, so the count below tau can only grow while iterating)
+        // the pairs below tau, and the first one above it unless the cap nev_max is
+        // reached (Ritz values approach the eigenvalues from above, so the count below tau
+        // can only grow while iterating)
         while (w < m - 2 && h_theta[j * MAXM + w] - sigma < tau) ++w;
-        w = std::min(w + 1, m - 2);
+        if (m < mcap && w > m - 8) grow = true;
+        w = std::min({w + 1, nev_max, m - 2});
       }
       // backward-error test: ||M x - theta B x|| <= tol * S ||x||, S = max over the block of
       // ||M x|| / ||x|| (an estimate of ||M||).  Relative to ||M x|| alone the test cannot
@@ -900,20 +935,20 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
         for (int a = 0; a < m; ++a) lam_final[j * MAXM + a] = h_theta[j * MAXM + a] - sigma;
       }
     }
+    if (grow) break;
     to_dev(active.p, act.data(), n_sub, s);
+  }
+  if (grow) {                                      // wider block, warm-started from this one
+    X_prev = std::move(X);
+    d_voff_prev = std::move(d_voff);
+    m_prev = m;
+    m = mcap;
+    continue;
   }
   if (n_active > 0)
     throw Error(GX_ENOCONV, "GenEO eigensolver did not converge in " + std::to_string(maxit) +
                                 " iterations");
-  bool grow = false;
-  if (!fixed_count && m < std::min(MAXM, nev_max + 8))
-    for (int j = 0; j < n_sub; ++j) {
-      int k = 0;
-      while (k < m && lam_final[j * MAXM + k] < tau) ++k;
-      if (k > m - 8) grow = true;
-    }
-  if (!grow) break;
-  m = round8(std::min(2 * m, nev_max + 8));
+  break;
   }
   // selection
   sw.nev.assign(n_sub, 0);

@@ -5,9 +5,11 @@
 
 #include <chrono>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/gx.h"
@@ -31,6 +33,17 @@ struct Error : std::runtime_error {
   do {                                                                                \
     if (!(cond)) throw ::gx::Error(GX_EINVAL, msg);                                   \
   } while (0)
+
+// Debugging aid: with GX_POISON_ALLOC=1 in the environment every new floating-point device
+// buffer is filled with a huge finite value (bytes 0x7F), so a kernel that uses memory
+// nobody wrote shows up as a wildly wrong result; reads masked by a zero factor stay exact.
+inline bool poison_alloc() {
+  static const bool on = [] {
+    const char* e = std::getenv("GX_POISON_ALLOC");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
 
 // Owning device buffer.
 template <class T>
@@ -57,6 +70,11 @@ struct DevBuf {
         n = 0;
         throw Error(GX_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) +
                                    " bytes failed: " + hipGetErrorString(e));
+      }
+      if (std::is_floating_point<T>::value && poison_alloc()) {
+        if (hipMemset(p, 0x7F, count * sizeof(T)) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess)
+          throw Error(GX_EHIP, "poisoning a new buffer failed");
       }
     }
   }
@@ -143,6 +161,9 @@ struct BandSet {
   DevBuf<int> flags;                           // block completion flags (+ error word)
   bool coarse = false;                         // the coarse matrix (own solve kernel name)
   int epoch = 0;
+  // column panels of solves with more right-hand sides than one launch takes
+  DevBuf<double> panel;
+  DevBuf<int64_t> d_poff;
 };
 
 struct Schwarz {

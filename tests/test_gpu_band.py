@@ -46,7 +46,7 @@ def _band_spd(n, B, rng):
     return band, lo
 
 
-@pytest.mark.parametrize("nrhs", [1, 8, 16, 24, 32])
+@pytest.mark.parametrize("nrhs", [1, 8, 16, 24, 32, 40, 48])
 @pytest.mark.parametrize("groups", [0, 1, 3])
 def test_band_factor_solve_fp64(solver, nrhs, groups):
     import torch
@@ -71,7 +71,7 @@ def test_band_factor_solve_fp64(solver, nrhs, groups):
         assert np.abs(g - ref).max() <= 1e-10 * np.abs(ref).max(), (n, B)
 
 
-@pytest.mark.parametrize("nrhs", [1, 16])
+@pytest.mark.parametrize("nrhs", [1, 16, 48])
 def test_band_factor_solve_mixed(solver, nrhs):
     import torch
     gx, s = solver
@@ -101,6 +101,9 @@ def test_band_rejects_bad_input(solver):
     band = torch.zeros(10, dtype=torch.float64, device="cuda")
     x = torch.zeros(5 * 3, dtype=torch.float64, device="cuda")
     with pytest.raises(gx.GxError):                # 3 right-hand sides: not supported
+        s.band_factor_solve([5], [1], band, x)
+    x = torch.zeros(5 * 72, dtype=torch.float64, device="cuda")
+    with pytest.raises(gx.GxError):                # 72: more than 64 not supported
         s.band_factor_solve([5], [1], band, x)
     x = torch.zeros(5, dtype=torch.float64, device="cuda")
     with pytest.raises(gx.GxError):                # zero matrix: not positive definite

@@ -7,7 +7,9 @@ each, per-laminate convergence).
 * laminates of different size converge after different iteration counts and leave the
   batch independently;
 * the work-group autotuner times its candidates and keeps the fastest; the solve after
-  tuning still matches.
+  tuning still matches (to 1e-9 relative: a different work-group count splits the band
+  solves differently, so the preconditioner changes by rounding and the two PCG runs to
+  rtol 1e-10 drift apart by a few 1e-12; the iteration count stays within one).
 """
 import numpy as np
 import pytest
@@ -47,9 +49,12 @@ def test_autotune_keeps_the_fastest_and_the_solution():
     batch = gx.Batch([cfg])
     batch.setup()
     s = batch.solvers[0]
-    ref = s.pcg(batch.f[0], rtol=1e-10, maxit=500)["x"].cpu().numpy()
+    o1 = s.pcg(batch.f[0], rtol=1e-10, maxit=500)
+    ref = o1["x"].cpu().numpy()
     times = s.autotune(candidates=(1, 2, 3))
     assert set(times) == {1, 2, 3} and all(t > 0 for t in times.values())
-    x = s.pcg(batch.f[0], rtol=1e-10, maxit=500)["x"].cpu().numpy()
-    assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
+    o2 = s.pcg(batch.f[0], rtol=1e-10, maxit=500)
+    x = o2["x"].cpu().numpy()
+    assert abs(o2["iters"] - o1["iters"]) <= 1
+    assert np.abs(x - ref).max() <= 1e-9 * np.abs(ref).max()
     batch.close()

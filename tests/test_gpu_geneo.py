@@ -57,3 +57,69 @@ def test_geneo_two_level(gx, cfg):
     out = s.pcg(f, rtol=1e-8, maxit=500, history=True)
     assert abs(out["iters"] - R["iters"]) <= 1
     check_solution(s, f, prob, out, R["hist"])
+
+
+def _wide():
+    """Nodes are numbered with the thickness index slowest, so the Neumann band of a
+    subdomain 16 x 13 elements in plan has rows of about 2600 columns: more than one LDS
+    segment of the band assembly, so each row is built in two segments."""
+    cfg = workloads.small_flat(nx=28, ny=13, length=28.0, width=13.0)
+    cfg["name"] = "wide_28x13x4"
+    cfg["solver"].update(px=2, py=1, overlap=1, nev=6)
+    return cfg
+
+
+@pytest.fixture(scope="module")
+def wide_oracle():
+    from oracle import pcg
+    return pcg.solve(_wide(), rtol=1e-8, maxit=1)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_geneo_wide_neumann_band(gx, wide_oracle, precision):
+    import torch
+    R = wide_oracle
+    prob, co = R["prob"], R["coarse"]
+    s, f, part = _setup(gx, _wide(), coarse=True, precision=precision, eig_tol=1e-12)
+    _, nn, _ = s.subdomain_info()
+    mean_ld = s.stats()["neumann_band_entries"] / nn.sum()
+    assert mean_ld > 2049, mean_ld
+    assert list(s.nev) == co.nev and s.n0 == co.n0
+    for j in range(len(co.nev)):
+        lg, lo = s.eigenvalues(j), co.lams[j]
+        # subdomain 1 floats: its six rigid-body eigenvalues are rounding noise (about
+        # 1e-10 on both sides at this size), hence the wider absolute term
+        assert np.all(np.abs(lg - lo) <= 1e-8 * np.abs(lo) + 1e-9), (j, lg, lo)
+    if precision:                                  # FP32 factors: eigenvalues only
+        assert s.stats()["fp64_fallbacks"] == 0
+        return
+    rng = np.random.default_rng(13)
+    r = rng.standard_normal(prob.n)
+    z = s.precond(torch.tensor(prob.to_full(r), device="cuda")).cpu().numpy()
+    # larger subdomains than above: the coarse span carries more eigensolver rounding into
+    # K_0^-1 (3.6e-8 measured), so 1e-7 here
+    assert rel_err(z[prob.free], R["P"].apply(r)) <= 1e-7
+
+
+def test_geneo_block_growth_and_cap(gx):
+    """tau = 1.2 puts about 30 eigenvalues of two subdomains below the threshold and more
+    than nev_max = 32 in the third: the eigensolver starts with a block of 32, must widen
+    it (warm-started) to 48, and keeps only the 32 smallest where the cap binds.  Counts,
+    eigenvalues and P r against the oracle, as above."""
+    import torch
+    from oracle import pcg
+    cfg = workloads.small_lsection(nx=12, ny=2)
+    cfg["name"] = "lsec_12x2_tau1.2"
+    cfg["solver"].update(nev=0, tau=1.2, nev_max=32)
+    R = pcg.solve(cfg, rtol=1e-8, maxit=1)
+    prob, co = R["prob"], R["coarse"]
+    assert max(co.nev) == 32 and min(co.nev) > 24   # the case this test is for
+    s, f, part = _setup(gx, cfg, coarse=True, eig_tol=1e-12)
+    assert list(s.nev) == co.nev and s.n0 == co.n0
+    for j in range(len(co.nev)):
+        lg, lo = s.eigenvalues(j), co.lams[j]
+        assert np.all(np.abs(lg - lo) <= 1e-8 * np.abs(lo) + 1e-10), (j, lg, lo)
+    rng = np.random.default_rng(14)
+    r = rng.standard_normal(prob.n)
+    z = s.precond(torch.tensor(prob.to_full(r), device="cuda")).cpu().numpy()
+    assert rel_err(z[prob.free], R["P"].apply(r)) <= 1e-7

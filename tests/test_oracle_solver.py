@@ -135,3 +135,31 @@ def test_threshold_selection():
     for lam in R["coarse"].lams:
         assert np.all(lam < 0.1)
     assert R["iters"] < 60
+
+
+def test_arpack_clustered_spectrum_and_cap():
+    """tau = 1.2 on the small L-section: about 30 eigenvalues per subdomain below the
+    threshold, clustered near 1, and the cap nev_max = 32 binding in the middle subdomain.
+    The sparse path equals the dense generalised eigensolver (eigenvalues, and the span of
+    the selected vectors), also after unrelated ARPACK calls: the start vector is fixed and
+    the returned block is purified."""
+    cfg = workloads.small_lsection(nx=12, ny=2)
+    prob = fem.Problem(cfg)
+    sv = cfg["solver"]
+    dec = dd.Decomposition(prob, dd.box_partition(prob.mesh, sv["px"], sv["py"]),
+                           sv["overlap"])
+    counts = []
+    for j in range(dec.n_sub):
+        AN, B, xt, pos = geneo.local_matrices(dec, j)
+        l2, V2 = geneo.solve_local_eigen(AN, B, tau=1.2, nev_max=32, dense=True)
+        for _ in range(2):                         # the second run follows other calls
+            spla.eigsh(AN, k=3, which="LM", return_eigenvectors=False)
+            l1, V1 = geneo.solve_local_eigen(AN, B, tau=1.2, nev_max=32, dense=False)
+            assert len(l1) == len(l2)
+            assert np.all(np.abs(l1 - l2) <= 1e-10 * np.abs(l2) + 1e-10)   # zero modes: noise
+            Q1, _ = np.linalg.qr(V1)
+            Q2, _ = np.linalg.qr(V2)
+            s = np.linalg.svd(Q1.T @ Q2, compute_uv=False)
+            assert s.min() >= 1 - 1e-12                # principal angles below ~1.4e-6
+        counts.append(len(l1))
+    assert max(counts) == 32 and min(counts) > 24
