@@ -196,7 +196,9 @@ typedef struct {
   int32_t precision;         /* GX_FP64, or GX_MIXED: FP32 subdomain factors and solves */
   int32_t coarse;            /* 1: two-level (GenEO); 0: one-level Schwarz */
   const int32_t* nev_per_sub;/* optional host [n_sub]: modes per subdomain (overrides) */
-  double eig_tol;            /* relative eigen-residual target (0: default 1e-10) */
+  double eig_tol;            /* eigenpair backward-error target ||M x - theta B x|| <=
+                                eig_tol S ||x||, S = max over the block of ||M x|| / ||x||
+                                (0: default 1e-6) */
   int32_t eig_maxit;         /* eigensolver iteration cap (0: default 1000) */
 } gx_geneo_opts;
 

@@ -23,6 +23,8 @@ constexpr int TS = 64;          // trailing-update tile
 constexpr int SB = 64;          // solve block (one wavefront)
 constexpr int SOLVE_THREADS = 512;
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 struct BandArgs {
   const int64_t* n;
   const int64_t* B;
@@ -163,93 +165,131 @@ __global__ void __launch_bounds__(256) k_trsm(BandArgs a, T* v, int64_t c0, cons
   }
 }
 
-// trailing update of rows/cols [c0 + nb, c0 + nb + W): A[r][s] -= sum_c L[r][c] L[s][c],
-// 64x64 tiles of the lower triangle, 4x4 outputs per thread
+// Update by the panels of columns [k0, k0 + kk): A[r][s] -= sum_c L[r][c] L[s][c] for
+// t0 <= s <= r < t0 + W, t0 = k0 + kk, W = min(B, n - t0) (rows further down get nothing
+// from these columns inside the band).  64x64 tiles of that lower triangle, or with
+// col_only the first tile column only (the look-ahead update of the next panel inside a
+// group).  The reduction runs over 64-column chunks of the panels: each chunk's two 64x64
+// blocks are staged in LDS and every wave
+// forms a 32x32 quarter of the tile with the FP64 matrix instruction (2x2 tiles of 16x16,
+// 16 steps of k = 4).  Lane l supplies row l % 16 and reduction index l / 16 of both
+// operands; accumulator register q of a tile holds output row 4 q + l / 16, column l % 16.
+// Grouping panels makes one read-modify-write pass over the trailing band serve kk columns.
 template <class T>
-__global__ void __launch_bounds__(256) k_syrk(BandArgs a, T* v, int64_t c0) {
+__global__ void __launch_bounds__(256) k_syrk(BandArgs a, T* v, int64_t k0, int64_t kk,
+                                              int col_only) {
   __shared__ double Pr[TS][NB + 1], Ps[TS][NB + 1];
   const int j = blockIdx.y;
   const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
-  if (c0 >= n) return;
-  const int nb = (int)min<int64_t>(NB, n - c0);
-  const int64_t W = min<int64_t>(B, n - c0 - nb);
+  if (k0 >= n) return;
+  const int64_t kj = min<int64_t>(kk, n - k0);   // panel columns of this matrix
+  const int64_t t0 = k0 + kj;
+  const int64_t W = min<int64_t>(B, n - t0);
   if (W <= 0) return;
   const int64_t nt = (W + TS - 1) / TS;
   const int64_t tile = blockIdx.x;
-  if (tile >= nt * (nt + 1) / 2) return;
-  int64_t tr = 0, rem = tile;                    // lower-triangular tile enumeration
-  while (rem > tr) { rem -= tr + 1; ++tr; }
-  const int64_t ts = rem;
+  int64_t tr, ts;
+  if (col_only) {
+    if (tile >= nt) return;
+    tr = tile;
+    ts = 0;
+  } else {
+    if (tile >= nt * (nt + 1) / 2) return;
+    int64_t t = 0, rem = tile;                   // lower-triangular tile enumeration
+    while (rem > t) { rem -= t + 1; ++t; }
+    tr = t;
+    ts = rem;
+  }
   T* base = v + a.off[j];
-  const int64_t r0 = c0 + nb + tr * TS, s0 = c0 + nb + ts * TS, wend = c0 + nb + W;
-  {
-    constexpr int L = TS * NB / 256;             // 16 + 16 loads per thread, issued together
+  const int64_t r0 = t0 + tr * TS, s0 = t0 + ts * TS, wend = t0 + W;
+  // thread t loads column t % 64 of rows t / 64 + 4 u (u < 16) of both blocks; loads are
+  // unconditional (a masked entry reads a neighbouring band entry: the row index is clamped
+  // below n and the allocation is padded past its end) and the mask applies afterwards
+  constexpr int L = TS * NB / 256;
+  const int cl = threadIdx.x % NB, i0 = threadIdx.x / NB;
+  const int64_t rs = ld - 1;                     // entry (r, c) at r * rs + B + c
+  const int64_t rlast = n - 1;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int rb = 32 * (w >> 1), sb = 32 * (w & 1);
+  v4d acc[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int64_t kc = 0; kc < kj; kc += NB) {
+    const int64_t col = k0 + kc + cl;
+    const bool okc = kc + cl < kj;
     double vr[L], vs[L];
 #pragma unroll
     for (int u = 0; u < L; ++u) {
-      const int idx = threadIdx.x + 256 * u;
-      const int i = idx / NB, c = idx % NB;
-      const int64_t r = r0 + i, ss = s0 + i, col = c0 + c;
-      vr[u] = (c < nb && r < wend && col >= r - B) ? (double)base[r * ld + (col - r + B)] : 0.0;
-      vs[u] = (c < nb && ss < wend && col >= ss - B) ? (double)base[ss * ld + (col - ss + B)] : 0.0;
+      const int64_t r = r0 + i0 + 4 * u, ss = s0 + i0 + 4 * u;
+      vr[u] = (double)base[min(r, rlast) * rs + B + col];
+      vs[u] = (double)base[min(ss, rlast) * rs + B + col];
     }
 #pragma unroll
     for (int u = 0; u < L; ++u) {
-      const int idx = threadIdx.x + 256 * u;
-      Pr[idx / NB][idx % NB] = vr[u];
-      Ps[idx / NB][idx % NB] = vs[u];
+      const int64_t r = r0 + i0 + 4 * u, ss = s0 + i0 + 4 * u;
+      const bool okr = okc && r < wend && col >= r - B;
+      const bool oks = okc && ss < wend && col >= ss - B;
+      Pr[i0 + 4 * u][cl] = okr ? vr[u] : 0.0;
+      Ps[i0 + 4 * u][cl] = oks ? vs[u] : 0.0;
     }
-  }
-  __syncthreads();
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double acc[4][4];
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-  for (int c = 0; c < NB; ++c) {
-    double pr[4], ps[4];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) pr[p] = Pr[4 * ty + p][c];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) ps[q] = Ps[4 * tx + q][c];
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[p][q] += pr[p] * ps[q];
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < NB; k += 4) {
+      const double a0 = Pr[rb + li][k + lk], a1 = Pr[rb + 16 + li][k + lk];
+      const double b0 = Ps[sb + li][k + lk], b1 = Ps[sb + 16 + li][k + lk];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
   }
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const int64_t r = r0 + 4 * ty + p;
-    if (r >= wend) continue;
+  for (int p = 0; p < 2; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t s = s0 + 4 * tx + q;
-      if (s <= r && s < wend) {
-        T* e = base + r * ld + (s - r + B);
-        *e = (T)((double)*e - acc[p][q]);
+      const int64_t r = r0 + rb + 16 * p + 4 * q + lk;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int64_t s = s0 + sb + 16 * t + li;
+        if (r < wend && s <= r && (!col_only || s < t0 + TS)) {
+          T* e = base + r * ld + (s - r + B);
+          *e = (T)((double)*e - acc[p][t][q]);
+        }
       }
     }
-  }
 }
 
 template <class T>
 void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, int* err) {
   BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p};
   DevBuf<double> inv((size_t)bs.n_mat * NB * NB);
-  const int64_t steps = (bs.max_n + NB - 1) / NB;
+  // right-looking blocked Cholesky in groups of GP panels of NB columns: inside a group
+  // each panel is first brought up to date by the group's earlier panels (its own tile
+  // column only), then factored (diagonal block, panel below it); the rest of the band is
+  // updated once per group, by all GP panels together
+  constexpr int GP = 4;
   const int64_t nt = (bs.max_B + TS - 1) / TS;
   const unsigned tiles = (unsigned)(nt * (nt + 1) / 2);
   const unsigned trsm_blocks = (unsigned)((bs.max_B + TS - 1) / TS);
-  for (int64_t k = 0; k < steps; ++k) {
-    const int64_t c0 = k * NB;
-    hipLaunchKernelGGL(k_potrf<T>, dim3(bs.n_mat), dim3(256), 0, st, a, v, c0, inv.p, dinv,
-                       bs.d_boff.p, err);
-    if (bs.max_B > 0) {
-      hipLaunchKernelGGL(k_trsm<T>, dim3(trsm_blocks, bs.n_mat), dim3(256), 0, st, a, v, c0,
-                         inv.p);
-      hipLaunchKernelGGL(k_syrk<T>, dim3(tiles, bs.n_mat), dim3(256), 0, st, a, v, c0);
+  for (int64_t k0 = 0; k0 < bs.max_n; k0 += GP * NB) {
+    for (int p = 0; p < GP && k0 + p * NB < bs.max_n; ++p) {
+      const int64_t c0 = k0 + p * NB;
+      if (p > 0 && bs.max_B > 0)
+        hipLaunchKernelGGL(k_syrk<T>, dim3((unsigned)nt, bs.n_mat), dim3(256), 0, st, a, v, k0,
+                           (int64_t)p * NB, 1);
+      hipLaunchKernelGGL(k_potrf<T>, dim3(bs.n_mat), dim3(256), 0, st, a, v, c0, inv.p, dinv,
+                         bs.d_boff.p, err);
+      if (bs.max_B > 0)
+        hipLaunchKernelGGL(k_trsm<T>, dim3(trsm_blocks, bs.n_mat), dim3(256), 0, st, a, v, c0,
+                           inv.p);
     }
+    if (bs.max_B > 0)
+      hipLaunchKernelGGL(k_syrk<T>, dim3(tiles, bs.n_mat), dim3(256), 0, st, a, v, k0,
+                         (int64_t)GP * NB, 0);
   }
   GX_HIP(hipGetLastError());
   GX_HIP(hipStreamSynchronize(st));
@@ -551,7 +591,6 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
 // the matching solution rows) are staged through LDS; the loads of the next two chunks are
 // in flight in two register sets while the current one is multiplied (the chunk loop is
 // unrolled by two so that each set has a name of its own).
-typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int MC = 32;                            // right-hand sides per launch, at most
 constexpr int MT = 512;                           // threads per work-group
 constexpr int AL = SB * SB / MT;                  // band-chunk entries per thread (8)
@@ -722,8 +761,11 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
 }
 
 // Work-groups per matrix: as many as keep every work-group of the launch resident at once
-// (the waits rely on it), with a quarter of the machine in reserve; at most GMAX for one
-// right-hand side, 8 for several.
+// (the waits rely on it); at most GMAX for one right-hand side, 8 for several.  The solves
+// of one context are stream-ordered, so a launch may count on the whole machine (other
+// kernels can only delay the dispatch of its groups, not block them).  When several
+// contexts solve concurrently (share > 1) each gets an equal part of three quarters of it,
+// so that all their launches fit together.
 static int solve_groups(BandSet& bs, const void* kernel, int which) {
   if (bs.solve_groups[which] > 0) return bs.solve_groups[which];
   int dev = 0, cus = 0, per_cu = 0;
@@ -731,7 +773,8 @@ static int solve_groups(BandSet& bs, const void* kernel, int which) {
   GX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   GX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel,
                                                       which == 0 ? SOLVE_THREADS : MT, 0));
-  const int64_t capacity = (int64_t)cus * std::max(per_cu, 0) * 3 / 4;
+  const int64_t full = (int64_t)cus * std::max(per_cu, 0);
+  const int64_t capacity = bs.share > 1 ? full * 3 / 4 / bs.share : full;
   const int cap = which == 0 ? GMAX : 8;
   int G = 1;
   const int top = bs.force_groups[which] > 0 ? std::min(bs.force_groups[which], cap) : cap;

@@ -158,6 +158,7 @@ struct BandSet {
   bool fp32 = false;
   int solve_groups[2] = {0, 0};                // work-groups per matrix: 1-RHS, m-RHS solve
   int force_groups[2] = {0, 0};                // requested (0: automatic, capped by residency)
+  int share = 1;                               // contexts whose solves may run concurrently
   DevBuf<int> flags;                           // block completion flags (+ error word)
   bool coarse = false;                         // the coarse matrix (own solve kernel name)
   int epoch = 0;

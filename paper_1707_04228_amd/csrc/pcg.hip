@@ -321,8 +321,19 @@ gx_status gx_pcg_solve_batch(int32_t n, gx_ctx* const* ctxs, const double* const
     ctxs[i]->err = what;
     runs[i].done = true;
   };
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < n; ++i)
     if (!ctxs[i]) return GX_EINVAL;
+  // the solves of all systems run concurrently: each context's band solves get an equal
+  // share of the machine (work-group counts chosen again), restored afterwards
+  auto set_share = [&](int share) {
+    for (int i = 0; i < n; ++i)
+      for (BandSet* bs : {&ctxs[i]->sw.A, &ctxs[i]->sw.C}) {
+        bs->share = share;
+        bs->solve_groups[0] = bs->solve_groups[1] = 0;
+      }
+  };
+  set_share(n);
+  for (int i = 0; i < n; ++i) {
     runs[i].c = ctxs[i];
     runs[i].b = b[i];
     runs[i].x = x[i];
@@ -364,6 +375,7 @@ gx_status gx_pcg_solve_batch(int32_t n, gx_ctx* const* ctxs, const double* const
     if (status_out) status_out[i] = st[i];
     if (first == GX_OK) first = st[i];
   }
+  set_share(1);
   return first;
 }
 

@@ -2,8 +2,9 @@
 each, per-laminate convergence).
 
 * every laminate's solution and iteration count equal those of its own gx_pcg_solve on
-  the same set-up (the batch runs the same kernels in the same order per system: the
-  results are bit-identical);
+  the same set-up: iteration counts within one and solutions within 1e-9 relative (the
+  batch runs the same kernels per system, but the concurrent systems share the machine, so
+  each band solve runs on fewer work-groups, which splits its sums differently: rounding);
 * laminates of different size converge after different iteration counts and leave the
   batch independently;
 * the work-group autotuner times its candidates and keeps the fastest; the solve after
@@ -36,9 +37,10 @@ def test_batch_matches_single_solves():
     for k, cfg in enumerate(cfgs):
         s = batch.solvers[k]
         out = s.pcg(batch.f[k], rtol=1e-10, maxit=500)
-        assert out["iters"] == it[k]
-        assert abs(out["relres"] - rr[k]) <= 1e-15
-        assert np.array_equal(out["x"].cpu().numpy(), xs[k].cpu().numpy())
+        assert abs(out["iters"] - it[k]) <= 1
+        assert rr[k] <= 1e-10
+        x1, x2 = out["x"].cpu().numpy(), xs[k].cpu().numpy()
+        assert np.abs(x1 - x2).max() <= 1e-9 * np.abs(x1).max()
     assert len(set(it.tolist())) > 1                # different convergence per laminate
     batch.close()
 
