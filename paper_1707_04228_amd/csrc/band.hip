@@ -347,6 +347,29 @@ __device__ inline void wait_flag(const int* f, int epoch, int* err) {
   __syncthreads();
 }
 
+// Waits until the cnt consecutive flags f[0 .. cnt) all carry the launch epoch: wave 0
+// polls them together (lane i reads flag i, cnt <= 64), so all blocks in flight cost one
+// round trip per poll instead of one each.  Same time-out rule as wait_flag.
+__device__ inline void wait_flags(const int* f, int cnt, int epoch, int* err) {
+  if (threadIdx.x < 64) {
+    int64_t spins = 0;
+    for (;;) {
+      const bool ok = (int)threadIdx.x >= cnt ||
+                      __hip_atomic_load(f + threadIdx.x, __ATOMIC_ACQUIRE,
+                                        __HIP_MEMORY_SCOPE_AGENT) == epoch;
+      if (__all(ok)) break;
+      if ((++spins & 255) == 0 &&
+          (spins > SPIN_LIMIT ||
+           __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+        if (threadIdx.x == 0) atomicOr(err, 2);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __syncthreads();
+}
+
 __device__ inline void post_flag(int* f, int epoch) {
   __hip_atomic_store(f, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -388,14 +411,47 @@ __device__ inline double reduce_rows8(const double (&s)[RPW], int lane) {
 // lane whose column lies outside the band reads a neighbouring entry (the band storage
 // carries BAND_PAD zero entries after the last row), and masks are applied by multiplying
 // with 0 or 1, so that a wave issues all loads of a step before it waits for any.
-// Blocks in flight are added oldest first, each after its own flag; the entries of the
-// predecessor block - the last to complete - are loaded before the waits.
+//
+// Hand-over between the work-groups of a matrix goes through the data itself, not flags:
+// the forward sweep writes block k's solution into the scratch vector y and the backward
+// sweep its final solution into the scratch vector z, both filled with the marker YMARK
+// before the launch; a reader of a block that may still be in flight polls its entries
+// until none is YMARK, and the values it polled are the ones it uses.  z is copied into x
+// after the launch.  Every access to y and z is an agent-scope relaxed atomic (8 bytes,
+// single-copy atomic, past the non-coherent caches), so no fence is needed anywhere: a
+// hand-over costs the reader one memory round trip and the writer none.  A marker is a NaN
+// payload that arithmetic never produces (a NaN result carries the default payload), so a
+// diverged solve still propagates NaN.
 // COARSE only names the instance used for the coarse matrix apart in profiles.
+constexpr uint64_t YMARK = 0x7FF4D1E5E7C0DE00ull;
+
+__device__ inline bool is_mark(double v) { return __double_as_longlong(v) == (long long)YMARK; }
+
+__device__ inline double poll_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void hand_over(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Spin-limit bookkeeping of a polling loop: true when the wait must give up (time-out, or
+// another wait of the launch already timed out).
+__device__ inline bool poll_give_up(int64_t& spins, int* err) {
+  if ((++spins & 255) == 0 &&
+      (spins > SPIN_LIMIT || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+    atomicOr(err, 2);
+    return true;
+  }
+  __builtin_amdgcn_s_sleep(1);
+  return false;
+}
+
 template <class T, bool COARSE>
 __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
     BandArgs a, const T* v, const T* dinv, const int64_t* boff, const int64_t* xoff,
-    double* xall, int G, int n_pad, int n_mat, int* fflag, int* bflag, int64_t nblk_max,
-    int epoch, int* err) {
+    const double* xall, double* yall, double* zall, const int64_t* yoff, int G, int n_pad,
+    int n_mat, int* err) {
   __shared__ double Di[SB][SB + 1];
   __shared__ double acc[SB];
   __shared__ double part[SW][SB];
@@ -405,9 +461,9 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
   if (n == 0) return;
   const T* base = v + a.off[j];
   const T* dv = dinv + boff[j];
-  double* x = xall + xoff[j];
-  int* ff = fflag + (int64_t)j * nblk_max;
-  int* bf = bflag + (int64_t)j * nblk_max;
+  const double* x = xall + xoff[j];
+  double* y = yall + yoff[j];
+  double* z = zall + yoff[j];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t nblk = (n + SB - 1) / SB;
   constexpr int U = sizeof(T) == 8 ? 4 : 8;       // 64-column steps in flight per wave
@@ -419,6 +475,10 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
     const int64_t kdone = max<int64_t>(k - G + 1, 0);        // column blocks < kdone complete
     const int64_t done_end = kdone * SB;
     const int64_t ifirst = i0 + RPW * wave;
+    // the right-hand side of the row this lane reduces
+    const int ii = RPW * wave + (lane >> 3);
+    const bool own = (lane & 7) == 0 && ii < nb;
+    const double bval = own ? x[i0 + ii] : 0.0;
     const T* rp[RPW];                              // rp[r][c] = entry (row, c)
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
@@ -433,7 +493,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
       double xv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        xv[u] = x[min<int64_t>(c0 + 64 * u, done_end - 1)];
+        xv[u] = poll_load(y + min<int64_t>(c0 + 64 * u, done_end - 1));
 #pragma unroll
         for (int r = 0; r < RPW; ++r) l[u][r] = rp[r][c0 + 64 * u];
       }
@@ -446,28 +506,39 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
           s[r] += (double)l[u][r] * (cc >= ifirst + r - B ? xu : 0.0);
       }
     }
-    T pf[RPW], dd[DL];
-    const int64_t cpred = k > 0 ? i0 - SB + lane : lane;   // block 0 has no predecessor
+    // blocks in flight, kdone .. k - 1 (at most GMAX - 1): their factor entries and this
+    // block's inverse diagonal block are loaded first; then every wave polls their
+    // solutions (one round trip when they are done) and adds them
+    const int nfl = (int)(k - kdone);
+    T pf[GMAX - 1][RPW], dd[DL];
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) pf[r] = rp[r][cpred];
+    for (int o = 0; o < GMAX - 1; ++o) {
+      const int64_t cc = min<int64_t>(kdone + o, max<int64_t>(k - 1, 0)) * SB + lane;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) pf[o][r] = rp[r][cc];
+    }
 #pragma unroll
     for (int u = 0; u < DL; ++u) dd[u] = dv[k * SB * SB + threadIdx.x + SOLVE_THREADS * u];
-    for (int64_t kk = kdone; kk < k - 1; ++kk) {   // older blocks in flight (G > 2)
-      wait_flag(ff + kk, epoch, err);
-      const int64_t cc = kk * SB + lane;
-      const double xu = x[cc];
-      T l[RPW];
+    if (nfl > 0) {
+      double xo[GMAX - 1];
+      int64_t spins = 0;
+      for (;;) {
+        bool ok = true;
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) l[r] = rp[r][cc];
+        for (int o = 0; o < GMAX - 1; ++o) {
+          xo[o] = poll_load(y + min<int64_t>(kdone + o, k - 1) * SB + lane);
+          ok = ok && !is_mark(xo[o]);
+        }
+        if (__all(ok) || poll_give_up(spins, err)) break;
+      }
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) s[r] += (double)l[r] * (cc >= ifirst + r - B ? xu : 0.0);
-    }
-    if (k >= 1 && k - 1 >= kdone) {                // the predecessor block (G > 1)
-      wait_flag(ff + k - 1, epoch, err);
-      const int64_t cc = i0 - SB + lane;
-      const double xu = x[cc];
+      for (int o = 0; o < GMAX - 1; ++o) {
+        if (o >= nfl) break;
+        const int64_t cc = (kdone + o) * SB + lane;
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) s[r] += (double)pf[r] * (cc >= ifirst + r - B ? xu : 0.0);
+        for (int r = 0; r < RPW; ++r)
+          s[r] += (double)pf[o][r] * (cc >= ifirst + r - B ? xo[o] : 0.0);
+      }
     }
 #pragma unroll
     for (int u = 0; u < DL; ++u) {
@@ -475,19 +546,15 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
       Di[idx / SB][idx % SB] = (double)dd[u];
     }
     const double tot = reduce_rows8(s, lane);
-    if ((lane & 7) == 0) {
-      const int ii = RPW * wave + (lane >> 3);
-      acc[ii] = ii < nb ? x[i0 + ii] - tot : 0.0;
-    }
+    if ((lane & 7) == 0) acc[ii] = own ? bval - tot : 0.0;
     __syncthreads();
     if (wave == 0) {
-      double y[4] = {0.0, 0.0, 0.0, 0.0};
+      double yv[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
       for (int q = 0; q < SB; q += 4)
 #pragma unroll
-        for (int h = 0; h < 4; ++h) y[h] += Di[lane][q + h] * acc[q + h];
-      if (lane < nb) x[i0 + lane] = (y[0] + y[1]) + (y[2] + y[3]);
-      if (G > 1 && lane == 0) post_flag(ff + k, epoch);
+        for (int h = 0; h < 4; ++h) yv[h] += Di[lane][q + h] * acc[q + h];
+      if (lane < nb) hand_over(y + i0 + lane, (yv[0] + yv[1]) + (yv[2] + yv[3]));
     }
     __syncthreads();
   }
@@ -511,7 +578,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
       for (int u = 0; u < UB; ++u) {
         const int64_t rr = min<int64_t>(r0 + SW * u, rend - 1);
         l[u] = cb[rr * rs + cidx];
-        xr[u] = x[rr];
+        xr[u] = poll_load(z + rr);
       }
 #pragma unroll
       for (int u = 0; u < UB; ++u) {
@@ -519,39 +586,48 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
         sacc += (double)l[u] * ((rr < rend && rr - B <= cidx) ? xr[u] : 0.0);
       }
     }
-    // rows of the blocks in flight: kb + 1 (the last to complete) .. kdone - 1
+    // row blocks in flight, kb + 1 .. kin (at most GMAX - 1): factor entries and the
+    // inverse diagonal block first, then the polls of their final solutions (rows inside
+    // the band only) together with this block's forward solution
     const int64_t kin = min<int64_t>(kdone - 1, (rend - 1) / SB);   // last row block in flight
-    T pf[RPW], dd[DL];
+    const int nfl = (int)max<int64_t>(kin - kb, 0);
+    T pf[GMAX - 1][RPW], dd[DL];
 #pragma unroll
-    for (int r = 0; r < RPW; ++r)
-      pf[r] = cb[min<int64_t>(i0 + SB + wave + SW * r, n - 1) * rs + cidx];
+    for (int o = 0; o < GMAX - 1; ++o)
+#pragma unroll
+      for (int r = 0; r < RPW; ++r)
+        pf[o][r] = cb[min<int64_t>((kb + 1 + o) * SB + wave + SW * r, n - 1) * rs + cidx];
 #pragma unroll
     for (int u = 0; u < DL; ++u) dd[u] = dv[kb * SB * SB + threadIdx.x + SOLVE_THREADS * u];
-    for (int64_t kk = kin; kk > kb + 1; --kk) {    // older blocks in flight (G > 2)
-      wait_flag(bf + kk, epoch, err);
-      T l[RPW];
-      double xr[RPW];
+    double xr[GMAX - 1][RPW];
+    double yown = 0.0;
+    {
+      int64_t spins = 0;
+      for (;;) {
+        bool ok = true;
+        if (wave == 0 && lane < nb) {
+          yown = poll_load(y + cidx);
+          ok = !is_mark(yown);
+        }
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) {
-        const int64_t rr = min<int64_t>(kk * SB + wave + SW * r, rend - 1);
-        l[r] = cb[rr * rs + cidx];
-        xr[r] = x[rr];
-      }
+        for (int o = 0; o < GMAX - 1; ++o)
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) {
-        const int64_t rr = kk * SB + wave + SW * r;
-        sacc += (double)l[r] * ((rr < rend && rr - B <= cidx) ? xr[r] : 0.0);
+          for (int r = 0; r < RPW; ++r) {
+            const int64_t rr = (kb + 1 + o) * SB + wave + SW * r;
+            const bool need = o < nfl && rr < rend;
+            xr[o][r] = poll_load(z + min<int64_t>(rr, rend - 1));
+            ok = ok && (!need || !is_mark(xr[o][r]));
+          }
+        if (__all(ok) || poll_give_up(spins, err)) break;
       }
     }
-    if (G > 1) wait_flag(kb + 1 < nblk ? bf + kb + 1 : ff + kb, epoch, err);
-    if (kb + 1 <= kin) {                           // the block right below (G > 1)
-      double xr[RPW];
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) xr[r] = x[min<int64_t>(i0 + SB + wave + SW * r, rend - 1)];
+    for (int o = 0; o < GMAX - 1; ++o) {
+      if (o >= nfl) break;
 #pragma unroll
       for (int r = 0; r < RPW; ++r) {
-        const int64_t rr = i0 + SB + wave + SW * r;
-        sacc += (double)pf[r] * ((rr < rend && rr - B <= cidx) ? xr[r] : 0.0);
+        const int64_t rr = (kb + 1 + o) * SB + wave + SW * r;
+        sacc += (double)pf[o][r] * ((rr < rend && rr - B <= cidx) ? xr[o][r] : 0.0);
       }
     }
 #pragma unroll
@@ -565,17 +641,16 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
       double tsum = 0.0;
 #pragma unroll
       for (int w = 0; w < SW; ++w) tsum += part[w][lane];
-      acc[lane] = lane < nb ? x[cidx] - tsum : 0.0;
+      acc[lane] = lane < nb ? yown - tsum : 0.0;
     }
     __syncthreads();
     if (wave == 0) {
-      double y[4] = {0.0, 0.0, 0.0, 0.0};
+      double yv[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
       for (int q = 0; q < SB; q += 4)
 #pragma unroll
-        for (int h = 0; h < 4; ++h) y[h] += Di[q + h][lane] * acc[q + h];
-      if (lane < nb) x[cidx] = (y[0] + y[1]) + (y[2] + y[3]);
-      if (G > 1 && lane == 0) post_flag(bf + kb, epoch);
+        for (int h = 0; h < 4; ++h) yv[h] += Di[q + h][lane] * acc[q + h];
+      if (lane < nb) hand_over(z + cidx, (yv[0] + yv[1]) + (yv[2] + yv[3]));
     }
     __syncthreads();
   }
@@ -835,6 +910,35 @@ __global__ void k_panel_copy(const int64_t* nrows, const int64_t* xoff, double* 
     *xe = *pe;
 }
 
+__global__ void k_fill_mark(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = __longlong_as_double((long long)YMARK);
+}
+
+// The forward and backward solution scratch of the single-right-hand-side solve (y, then
+// z, 64-aligned segments per matrix), reset to the marker by a fill kernel on the stream
+// (so the launch can be captured in a graph).
+static double* solve1_scratch(BandSet& bs, hipStream_t st) {
+  if (!bs.d_yoff.n) {
+    std::vector<int64_t> yo(bs.n_mat + 1, 0);
+    for (int j = 0; j < bs.n_mat; ++j) yo[j + 1] = yo[j] + (bs.n[j] + SB - 1) / SB * SB;
+    bs.ybuf.alloc(2 * std::max<int64_t>(yo[bs.n_mat], 1));
+    bs.d_yoff.alloc(bs.n_mat + 1);
+    to_dev(bs.d_yoff.p, yo.data(), bs.n_mat + 1, st);
+  }
+  hipLaunchKernelGGL(k_fill_mark, dim3(nblocks((int64_t)bs.ybuf.n, 256)), dim3(256), 0, st,
+                     bs.ybuf.p, (int64_t)bs.ybuf.n);
+  return bs.ybuf.p;
+}
+
+// x_j <- z_j for every matrix (the solutions out of the scratch)
+__global__ void k_copy_out(const int64_t* nrows, const int64_t* xoff, const int64_t* yoff,
+                           const double* z, double* x) {
+  const int j = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nrows[j]) x[xoff[j] + i] = z[yoff[j] + i];
+}
+
 void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, int ncol,
                 const int32_t* active) {
   GX_REQUIRE(ncol == 1 || (ncol % 8 == 0 && ncol <= 2 * MC),
@@ -869,18 +973,23 @@ void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, i
                                : reinterpret_cast<const void*>(&k_band_solve_1<double, false>);
     const int G = solve_groups(bs, kf, 0);
     int* fl = solve_flags(bs, st, nblk, n_pad);
+    int* err = fl + 2 * n_pad * nblk;
+    double* y = solve1_scratch(bs, st);
+    double* z = y + bs.ybuf.n / 2;
     if (bs.fp32)
       hipLaunchKernelGGL((k_band_solve_1<float, false>), dim3(G * n_pad), dim3(SOLVE_THREADS), 0,
-                         st, a, bs.v32.p, bs.dinv32.p, bs.d_boff.p, d_xoff, x, G, n_pad,
-                         bs.n_mat, fl, fl + n_pad * nblk, nblk, bs.epoch, fl + 2 * n_pad * nblk);
+                         st, a, bs.v32.p, bs.dinv32.p, bs.d_boff.p, d_xoff, x, y, z,
+                         bs.d_yoff.p, G, n_pad, bs.n_mat, err);
     else if (bs.coarse)
       hipLaunchKernelGGL((k_band_solve_1<double, true>), dim3(G * n_pad), dim3(SOLVE_THREADS), 0,
-                         st, a, bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, G, n_pad,
-                         bs.n_mat, fl, fl + n_pad * nblk, nblk, bs.epoch, fl + 2 * n_pad * nblk);
+                         st, a, bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, y, z,
+                         bs.d_yoff.p, G, n_pad, bs.n_mat, err);
     else
       hipLaunchKernelGGL((k_band_solve_1<double, false>), dim3(G * n_pad), dim3(SOLVE_THREADS), 0,
-                         st, a, bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, G, n_pad,
-                         bs.n_mat, fl, fl + n_pad * nblk, nblk, bs.epoch, fl + 2 * n_pad * nblk);
+                         st, a, bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, y, z,
+                         bs.d_yoff.p, G, n_pad, bs.n_mat, err);
+    hipLaunchKernelGGL(k_copy_out, dim3(nblocks(bs.max_n, 256), bs.n_mat), dim3(256), 0, st,
+                       bs.d_n.p, d_xoff, bs.d_yoff.p, z, x);
   } else {
     switch (ncol) {
       case 8: launch_m<8>(bs, a, d_xoff, x, st, active); break;
@@ -930,6 +1039,8 @@ void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<i
   bs.max_n = 0;
   bs.panel.release();
   bs.d_poff.release();
+  bs.ybuf.release();
+  bs.d_yoff.release();
   bs.max_B = 0;
   for (size_t j = 0; j < n.size(); ++j) {
     bs.ld[j] = B[j] + 1;

@@ -165,6 +165,9 @@ struct BandSet {
   // column panels of solves with more right-hand sides than one launch takes
   DevBuf<double> panel;
   DevBuf<int64_t> d_poff;
+  // forward solutions of the single-right-hand-side solve (64-aligned segment per matrix)
+  DevBuf<double> ybuf;
+  DevBuf<int64_t> d_yoff;
 };
 
 struct Schwarz {
