@@ -327,6 +327,7 @@ constexpr int SW = SOLVE_THREADS / 64;           // waves per work-group (8)
 constexpr int RPW = SB / SW;                      // forward rows per wave (8)
 constexpr int GMAX = 4;                           // work-groups per matrix, 1-RHS solve
 constexpr int DL = SB * SB / SOLVE_THREADS;       // inverse-block entries per thread (8)
+static_assert(DL == RPW, "the inverse-block products reuse the 8-row lane reduction");
 constexpr int64_t SPIN_LIMIT = (int64_t)1 << 22;
 constexpr int64_t BAND_PAD = 1024;               // trailing entries of a band allocation
 
@@ -452,9 +453,9 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
     BandArgs a, const T* v, const T* dinv, const int64_t* boff, const int64_t* xoff,
     const double* xall, double* yall, double* zall, const int64_t* yoff, int G, int n_pad,
     int n_mat, int* err) {
-  __shared__ double Di[SB][SB + 1];
   __shared__ double acc[SB];
   __shared__ double part[SW][SB];
+  __shared__ double xs[GMAX - 1][SB];               // polled solutions of blocks in flight
   const int g = blockIdx.x / n_pad, j = blockIdx.x % n_pad;
   if (j >= n_mat || g >= G) return;
   const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
@@ -507,8 +508,8 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
       }
     }
     // blocks in flight, kdone .. k - 1 (at most GMAX - 1): their factor entries and this
-    // block's inverse diagonal block are loaded first; then every wave polls their
-    // solutions (one round trip when they are done) and adds them
+    // block's inverse diagonal block are loaded first; then wave 0 polls their solutions
+    // (one round trip when they are done) and passes them on through LDS
     const int nfl = (int)(k - kdone);
     T pf[GMAX - 1][RPW], dd[DL];
 #pragma unroll
@@ -520,17 +521,25 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
 #pragma unroll
     for (int u = 0; u < DL; ++u) dd[u] = dv[k * SB * SB + threadIdx.x + SOLVE_THREADS * u];
     if (nfl > 0) {
-      double xo[GMAX - 1];
-      int64_t spins = 0;
-      for (;;) {
-        bool ok = true;
+      if (wave == 0) {
+        double xo[GMAX - 1];
+        int64_t spins = 0;
+        for (;;) {
+          bool ok = true;
 #pragma unroll
-        for (int o = 0; o < GMAX - 1; ++o) {
-          xo[o] = poll_load(y + min<int64_t>(kdone + o, k - 1) * SB + lane);
-          ok = ok && !is_mark(xo[o]);
+          for (int o = 0; o < GMAX - 1; ++o) {
+            xo[o] = poll_load(y + min<int64_t>(kdone + o, k - 1) * SB + lane);
+            ok = ok && !is_mark(xo[o]);
+          }
+          if (__all(ok) || poll_give_up(spins, err)) break;
         }
-        if (__all(ok) || poll_give_up(spins, err)) break;
+#pragma unroll
+        for (int o = 0; o < GMAX - 1; ++o) xs[o][lane] = xo[o];
       }
+      __syncthreads();
+      double xo[GMAX - 1];
+#pragma unroll
+      for (int o = 0; o < GMAX - 1; ++o) xo[o] = xs[o][lane];
 #pragma unroll
       for (int o = 0; o < GMAX - 1; ++o) {
         if (o >= nfl) break;
@@ -540,21 +549,19 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
           s[r] += (double)pf[o][r] * (cc >= ifirst + r - B ? xo[o] : 0.0);
       }
     }
-#pragma unroll
-    for (int u = 0; u < DL; ++u) {
-      const int idx = threadIdx.x + SOLVE_THREADS * u;
-      Di[idx / SB][idx % SB] = (double)dd[u];
-    }
     const double tot = reduce_rows8(s, lane);
     if ((lane & 7) == 0) acc[ii] = own ? bval - tot : 0.0;
     __syncthreads();
-    if (wave == 0) {
-      double yv[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-      for (int q = 0; q < SB; q += 4)
+    // y = Di acc: thread (wave, lane) holds Di[wave + 8 u][lane] (u < 8) from the prefetch,
+    // so each wave forms rows wave + 8 u with one lane-wide reduction
+    {
+      const double av = acc[lane];
+      double pr[RPW];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) yv[h] += Di[lane][q + h] * acc[q + h];
-      if (lane < nb) hand_over(y + i0 + lane, (yv[0] + yv[1]) + (yv[2] + yv[3]));
+      for (int u = 0; u < DL; ++u) pr[u] = (double)dd[u] * av;
+      const double yr = reduce_rows8(pr, lane);
+      const int row = wave + SW * (lane >> 3);
+      if ((lane & 7) == 0 && row < nb) hand_over(y + i0 + row, yr);
     }
     __syncthreads();
   }
@@ -599,28 +606,36 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
         pf[o][r] = cb[min<int64_t>((kb + 1 + o) * SB + wave + SW * r, n - 1) * rs + cidx];
 #pragma unroll
     for (int u = 0; u < DL; ++u) dd[u] = dv[kb * SB * SB + threadIdx.x + SOLVE_THREADS * u];
-    double xr[GMAX - 1][RPW];
+    // wave 0 polls this block's forward solution and the final solutions of the rows in
+    // flight (lane l: row l of each block), and passes them on through LDS
     double yown = 0.0;
-    {
+    if (wave == 0) {
+      double xo[GMAX - 1];
       int64_t spins = 0;
       for (;;) {
         bool ok = true;
-        if (wave == 0 && lane < nb) {
+        if (lane < nb) {
           yown = poll_load(y + cidx);
           ok = !is_mark(yown);
         }
 #pragma unroll
-        for (int o = 0; o < GMAX - 1; ++o)
-#pragma unroll
-          for (int r = 0; r < RPW; ++r) {
-            const int64_t rr = (kb + 1 + o) * SB + wave + SW * r;
-            const bool need = o < nfl && rr < rend;
-            xr[o][r] = poll_load(z + min<int64_t>(rr, rend - 1));
-            ok = ok && (!need || !is_mark(xr[o][r]));
-          }
+        for (int o = 0; o < GMAX - 1; ++o) {
+          const int64_t rr = (kb + 1 + o) * SB + lane;
+          const bool need = o < nfl && rr < rend;
+          xo[o] = poll_load(z + min<int64_t>(rr, rend - 1));
+          ok = ok && (!need || !is_mark(xo[o]));
+        }
         if (__all(ok) || poll_give_up(spins, err)) break;
       }
+#pragma unroll
+      for (int o = 0; o < GMAX - 1; ++o) xs[o][lane] = xo[o];
     }
+    __syncthreads();
+    double xr[GMAX - 1][RPW];
+#pragma unroll
+    for (int o = 0; o < GMAX - 1; ++o)
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) xr[o][r] = xs[o][wave + SW * r];
 #pragma unroll
     for (int o = 0; o < GMAX - 1; ++o) {
       if (o >= nfl) break;
@@ -630,27 +645,30 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
         sacc += (double)pf[o][r] * ((rr < rend && rr - B <= cidx) ? xr[o][r] : 0.0);
       }
     }
-#pragma unroll
-    for (int u = 0; u < DL; ++u) {
-      const int idx = threadIdx.x + SOLVE_THREADS * u;
-      Di[idx / SB][idx % SB] = (double)dd[u];
-    }
     part[wave][lane] = sacc;
+    if (wave == 0) acc[lane] = lane < nb ? yown : 0.0;
     __syncthreads();
-    if (wave == 0) {
-      double tsum = 0.0;
+    // z = Di^T (yown - sums): thread (wave, lane) holds Di[wave + 8 u][lane]; each wave
+    // forms its rows' right-hand sides (broadcast reads), then its share of every column
+    {
+      double pc = 0.0;
 #pragma unroll
-      for (int w = 0; w < SW; ++w) tsum += part[w][lane];
-      acc[lane] = lane < nb ? yown - tsum : 0.0;
+      for (int u = 0; u < DL; ++u) {
+        const int r = wave + SW * u;
+        double t = acc[r];
+#pragma unroll
+        for (int w = 0; w < SW; ++w) t -= part[w][r];
+        pc += (double)dd[u] * (r < nb ? t : 0.0);
+      }
+      __syncthreads();
+      part[wave][lane] = pc;
     }
     __syncthreads();
     if (wave == 0) {
-      double yv[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-      for (int q = 0; q < SB; q += 4)
+      double zs = 0.0;
 #pragma unroll
-        for (int h = 0; h < 4; ++h) yv[h] += Di[q + h][lane] * acc[q + h];
-      if (lane < nb) hand_over(z + cidx, (yv[0] + yv[1]) + (yv[2] + yv[3]));
+      for (int w = 0; w < SW; ++w) zs += part[w][lane];
+      if (lane < nb) hand_over(z + cidx, zs);
     }
     __syncthreads();
   }
