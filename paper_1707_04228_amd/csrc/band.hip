@@ -467,8 +467,8 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
   double* z = zall + yoff[j];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t nblk = (n + SB - 1) / SB;
-  constexpr int U = sizeof(T) == 8 ? 4 : 8;       // 64-column steps in flight per wave
-  constexpr int UB = 16;                           // band rows in flight per wave (backward)
+  constexpr int U = 8;                             // 64-column steps in flight per wave
+  constexpr int UB = 32;                           // band rows in flight per wave (backward)
   // ---- forward: wave w owns rows 8w..8w+7 of the block, lanes run along the columns
   for (int64_t k = g; k < nblk; k += G) {
     const int64_t i0 = k * SB;
@@ -579,18 +579,19 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
     const int64_t cidx = i0 + lane;
     double sacc = 0.0;
     for (int64_t r0 = done_beg + wave; r0 < rend; r0 += SW * UB) {
+      // lane u < UB loads the solution of row r0 + 8 u, handed to all lanes by a lane read
       T l[UB];
-      double xr[UB];
+      const double xz = poll_load(z + min<int64_t>(r0 + SW * (lane % UB), rend - 1));
 #pragma unroll
       for (int u = 0; u < UB; ++u) {
         const int64_t rr = min<int64_t>(r0 + SW * u, rend - 1);
         l[u] = cb[rr * rs + cidx];
-        xr[u] = poll_load(z + rr);
       }
 #pragma unroll
       for (int u = 0; u < UB; ++u) {
         const int64_t rr = r0 + SW * u;
-        sacc += (double)l[u] * ((rr < rend && rr - B <= cidx) ? xr[u] : 0.0);
+        const double xu = __shfl(xz, u);
+        sacc += (double)l[u] * ((rr < rend && rr - B <= cidx) ? xu : 0.0);
       }
     }
     // row blocks in flight, kb + 1 .. kin (at most GMAX - 1): factor entries and the
