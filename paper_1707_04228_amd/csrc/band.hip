@@ -684,7 +684,11 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
 // of the 8 owns row tile w mod 4 and column tile w / 4.  Chunks (64 x 64 of the band plus
 // the matching solution rows) are staged through LDS; the loads of the next two chunks are
 // in flight in two register sets while the current one is multiplied (the chunk loop is
-// unrolled by two so that each set has a name of its own).
+// unrolled by two so that each set has a name of its own).  Hand-over between work-groups
+// goes through marker-filled scratch solutions as in the single-right-hand-side solve
+// (forward into y, backward into z, z copied into x afterwards): solution entries are
+// loaded with agent-scope relaxed atomics, and a chunk is staged only once none of the
+// entries it needs is a marker (a chunk still in flight is polled again until then).
 constexpr int MC = 32;                            // right-hand sides per launch, at most
 constexpr int MT = 512;                           // threads per work-group
 constexpr int AL = SB * SB / MT;                  // band-chunk entries per thread (8)
@@ -692,8 +696,8 @@ constexpr int AL = SB * SB / MT;                  // band-chunk entries per thre
 template <class T, int M>
 __global__ void __launch_bounds__(MT) k_band_solve_m(
     BandArgs a, const T* v, const T* dinv, const int64_t* boff, const int64_t* xoff,
-    double* xall, int G, int n_pad, int n_mat, int* fflag, int* bflag, int64_t nblk_max,
-    int epoch, const int32_t* active, int* err) {
+    const double* xall, double* yall, double* zall, const int64_t* yoff, int G, int n_pad,
+    int n_mat, const int32_t* active, int* err) {
   constexpr int NCT = (M + 15) / 16;              // column tiles (1 or 2)
   constexpr int MP = 16 * NCT;                    // LDS row stride (zero columns past M)
   constexpr int YL = SB * M / MT;                 // solution-chunk entries per thread
@@ -707,9 +711,9 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
   const T* cb = v + a.off[j] + B;                 // entry (r, c) = cb[r * rs + c]
   const int64_t rs = ld - 1;
   const T* dv = dinv + boff[j];
-  double* x = xall + xoff[j];
-  int* ff = fflag + (int64_t)j * nblk_max;
-  int* bf = bflag + (int64_t)j * nblk_max;
+  const double* x = xall + xoff[j];
+  double* y = yall + yoff[j] * M;
+  double* z = zall + yoff[j] * M;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rt = wave & 3, ct = wave >> 2;        // this wave's row and column tile
   const bool tile = ct < NCT;                      // waves past the column tiles only stage
@@ -727,12 +731,27 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
 #pragma unroll
     for (int u = 0; u < AL; ++u) fa[u] = cb[min<int64_t>(r0 + 8 * u, n - 1) * rs + c];
     const int64_t yend = min<int64_t>((int64_t)SB * M, (n - kk * SB) * M);   // rows < n
-    const double* xs = x + kk * SB * M;
+    const double* xs = (bwd ? z : y) + kk * SB * M;
 #pragma unroll
-    for (int u = 0; u < YL; ++u) fy[u] = xs[min<int64_t>(threadIdx.x + MT * u, yend - 1)];
+    for (int u = 0; u < YL; ++u) fy[u] = poll_load(xs + min<int64_t>(threadIdx.x + MT * u, yend - 1));
   };
   auto stage = [&](bool bwd, int64_t i0, int nb, int64_t kk, const T (&fa)[AL],
-                   const double (&fy)[YL]) {
+                   double (&fy)[YL]) {
+    {                                              // until every needed entry is handed over
+      const int64_t yend = min<int64_t>((int64_t)SB * M, (n - kk * SB) * M);
+      const double* xs = (bwd ? z : y) + kk * SB * M;
+      int64_t spins = 0;
+      for (;;) {
+        bool ok = true;
+#pragma unroll
+        for (int u = 0; u < YL; ++u)
+          ok = ok && (threadIdx.x + MT * u >= yend || !is_mark(fy[u]));
+        if (__all(ok) || poll_give_up(spins, err)) break;
+#pragma unroll
+        for (int u = 0; u < YL; ++u)
+          fy[u] = poll_load(xs + min<int64_t>(threadIdx.x + MT * u, yend - 1));
+      }
+    }
     const int64_t r0 = (bwd ? kk * SB : i0) + wave;
     const int64_t c = (bwd ? i0 : kk * SB) + lane;
 #pragma unroll
@@ -758,16 +777,13 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Yc[kq * MP + 16 * ct + li], acc, 0, 0, 0);
     }
   };
-  // the chunks kk = first, first + step, .., last (step +1 or -1), two loads ahead; `wait`
-  // is called (once, uniformly) before the first chunk whose loads need it
+  // the chunks kk = first, first + step, .., last (step +1 or -1), two loads ahead
   auto sweep = [&](bool bwd, int64_t i0, int nb, int64_t first, int64_t count, int step,
-                   auto&& need, auto&& wait, v4d& acc) {
+                   v4d& acc) {
     T fa0[AL], fa1[AL];
     double fy0[YL], fy1[YL];
     auto get = [&](int64_t q, T (&fa)[AL], double (&fy)[YL]) {
-      const int64_t kk = first + step * q;
-      if (need(kk)) wait();
-      fetch(bwd, i0, kk, fa, fy);
+      fetch(bwd, i0, first + step * q, fa, fy);
     };
     if (count > 0) get(0, fa0, fy0);
     if (count > 1) get(1, fa1, fy1);
@@ -786,16 +802,32 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
     }
   };
   // Yc <- rhs - accumulated sums (rows >= nb zero), Ab <- inverse block; the product with
-  // it is the block's solution, stored and published
-  auto finish = [&](bool bwd, int64_t i0, int nb, int64_t blk, const v4d& acc, int* flag) {
+  // it is the block's solution, handed over.  The right-hand side is x forward and the
+  // block's forward solution (polled) backward.
+  auto finish = [&](bool bwd, int64_t i0, int nb, int64_t blk, const v4d& acc) {
     T dd[AL];
 #pragma unroll
     for (int u = 0; u < AL; ++u) dd[u] = dv[blk * SB * SB + threadIdx.x + MT * u];
     double bb[4];
+    const int cc = min(16 * ct + li, M - 1);
+    if (!bwd) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = min<int64_t>(i0 + 16 * rt + 4 * r + lk, n - 1);
-      bb[r] = x[row * M + min(16 * ct + li, M - 1)];
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = min<int64_t>(i0 + 16 * rt + 4 * r + lk, n - 1);
+        bb[r] = x[row * M + cc];
+      }
+    } else {
+      int64_t spins = 0;
+      for (;;) {
+        bool ok = true;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ii = 16 * rt + 4 * r + lk;
+          bb[r] = poll_load(y + (i0 + min(ii, nb - 1)) * M + cc);
+          ok = ok && (!tile || ii >= nb || !is_mark(bb[r]));
+        }
+        if (__all(ok) || poll_give_up(spins, err)) break;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -810,31 +842,25 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
         if (col < M) Yc[ii * MP + col] = ii < nb ? bb[r] - acc[r] : 0.0;
       }
     __syncthreads();
-    v4d y = {0.0, 0.0, 0.0, 0.0};
-    mma(bwd, y);
+    v4d yv = {0.0, 0.0, 0.0, 0.0};
+    mma(bwd, yv);
+    double* dst = bwd ? z : y;
     if (tile)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int ii = 16 * rt + 4 * r + lk, col = 16 * ct + li;
-        if (ii < nb && col < M) x[(i0 + ii) * M + col] = y[r];
+        if (ii < nb && col < M) hand_over(dst + (i0 + ii) * M + col, yv[r]);
       }
-    // every wave's stores complete before the block is published
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (G > 1 && threadIdx.x == 0) post_flag(flag, epoch);
   };
   // ---- forward: chunks in increasing order; those from kdone on are still in flight
   for (int64_t k = g; k < nblk; k += G) {
     const int64_t i0 = k * SB;
     const int nb = (int)min<int64_t>(SB, n - i0);
     const int64_t kfirst = max<int64_t>(i0 - B, 0) / SB;
-    const int64_t kdone = max<int64_t>(k - G + 1, 0);
-    bool waited = !(G > 1 && k > 0);
     v4d acc = {0.0, 0.0, 0.0, 0.0};
-    sweep(false, i0, nb, kfirst, k - kfirst, 1,
-          [&](int64_t kk) { return !waited && kk >= kdone; },
-          [&]() { wait_flag(ff + k - 1, epoch, err); waited = true; }, acc);
-    finish(false, i0, nb, k, acc, ff + k);
+    sweep(false, i0, nb, kfirst, k - kfirst, 1, acc);
+    finish(false, i0, nb, k, acc);
   }
   // ---- backward: chunks from the far end of the band inwards
   for (int64_t t = g; t < nblk; t += G) {
@@ -842,15 +868,9 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
     const int64_t i0 = kb * SB;
     const int nb = (int)min<int64_t>(SB, n - i0);
     const int64_t klast = (min<int64_t>(n, i0 + nb + B) - 1) / SB;   // last row block
-    const int64_t kdone = kb + G;                  // row blocks >= kdone complete
-    int* wflag = kb + 1 < nblk ? bf + kb + 1 : ff + kb;
-    bool waited = G == 1;
     v4d acc = {0.0, 0.0, 0.0, 0.0};
-    sweep(true, i0, nb, klast, klast - kb, -1,
-          [&](int64_t kk) { return !waited && kk < kdone; },
-          [&]() { wait_flag(wflag, epoch, err); waited = true; }, acc);
-    if (!waited) wait_flag(wflag, epoch, err);
-    finish(true, i0, nb, kb, acc, bf + kb);
+    sweep(true, i0, nb, klast, klast - kb, -1, acc);
+    finish(true, i0, nb, kb, acc);
   }
 }
 
@@ -893,42 +913,6 @@ static int* solve_flags(BandSet& bs, hipStream_t st, int64_t& nblk, int& n_pad) 
   return bs.flags.p;
 }
 
-template <int M>
-static void launch_m(BandSet& bs, const BandArgs& a, const int64_t* d_xoff, double* x,
-                     hipStream_t st, const int32_t* active) {
-  const int G = bs.fp32 ? solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_m<float, M>), 1)
-                        : solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_m<double, M>), 1);
-  int64_t nblk = 0;
-  int n_pad = 0;
-  int* fl = solve_flags(bs, st, nblk, n_pad);
-  if (bs.fp32)
-    hipLaunchKernelGGL((k_band_solve_m<float, M>), dim3(G * n_pad), dim3(MT), 0, st, a, bs.v32.p,
-                       bs.dinv32.p, bs.d_boff.p, d_xoff, x, G, n_pad, bs.n_mat, fl,
-                       fl + n_pad * nblk, nblk, bs.epoch, active, fl + 2 * n_pad * nblk);
-  else
-    hipLaunchKernelGGL((k_band_solve_m<double, M>), dim3(G * n_pad), dim3(MT), 0, st, a,
-                       bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, G, n_pad, bs.n_mat, fl,
-                       fl + n_pad * nblk, nblk, bs.epoch, active, fl + 2 * n_pad * nblk);
-}
-
-// Columns c0 .. c0 + w of a row-major block of ncol columns to or from a contiguous panel
-// of w columns (panel of matrix j at poff[j]).
-__global__ void k_panel_copy(const int64_t* nrows, const int64_t* xoff, double* x, int ncol,
-                             int c0, int w, const int64_t* poff, double* panel,
-                             const int32_t* active, int to_panel) {
-  const int j = blockIdx.y;
-  if (active && !active[j]) return;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nrows[j] * w) return;
-  const int64_t r = e / w, c = e - r * w;
-  double* xe = x + xoff[j] + r * ncol + c0 + c;
-  double* pe = panel + poff[j] + e;
-  if (to_panel)
-    *pe = *xe;
-  else
-    *xe = *pe;
-}
-
 __global__ void k_fill_mark(double* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = __longlong_as_double((long long)YMARK);
@@ -956,6 +940,62 @@ __global__ void k_copy_out(const int64_t* nrows, const int64_t* xoff, const int6
   const int j = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nrows[j]) x[xoff[j] + i] = z[yoff[j] + i];
+}
+
+// z_j -> x_j for the active matrices (n_j rows of w columns)
+__global__ void k_copy_out_m(const int64_t* nrows, const int64_t* xoff, const int64_t* yoff,
+                             int w, const double* z, double* x, const int32_t* active) {
+  const int j = blockIdx.y;
+  if (active && !active[j]) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nrows[j] * w) x[xoff[j] + i] = z[yoff[j] * w + i];
+}
+
+template <int M>
+static void launch_m(BandSet& bs, const BandArgs& a, const int64_t* d_xoff, double* x,
+                     hipStream_t st, const int32_t* active) {
+  const int G = bs.fp32 ? solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_m<float, M>), 1)
+                        : solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_m<double, M>), 1);
+  int64_t nblk = 0;
+  int n_pad = 0;
+  int* fl = solve_flags(bs, st, nblk, n_pad);
+  int* err = fl + 2 * n_pad * nblk;
+  // y and z scratch of M columns: segments at yoff[j] * M rows (64-aligned row offsets)
+  if (!bs.d_yoff.n) (void)solve1_scratch(bs, st);
+  const int64_t rows = (int64_t)bs.ybuf.n / 2;     // padded rows of all matrices
+  if (bs.mbuf.n < (size_t)(2 * rows * MC)) bs.mbuf.alloc(2 * rows * MC);
+  hipLaunchKernelGGL(k_fill_mark, dim3(nblocks(2 * rows * M, 256)), dim3(256), 0, st, bs.mbuf.p,
+                     2 * rows * M);
+  double* y = bs.mbuf.p;
+  double* z = bs.mbuf.p + rows * M;
+  if (bs.fp32)
+    hipLaunchKernelGGL((k_band_solve_m<float, M>), dim3(G * n_pad), dim3(MT), 0, st, a, bs.v32.p,
+                       bs.dinv32.p, bs.d_boff.p, d_xoff, x, y, z, bs.d_yoff.p, G, n_pad,
+                       bs.n_mat, active, err);
+  else
+    hipLaunchKernelGGL((k_band_solve_m<double, M>), dim3(G * n_pad), dim3(MT), 0, st, a,
+                       bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, y, z, bs.d_yoff.p, G,
+                       n_pad, bs.n_mat, active, err);
+  hipLaunchKernelGGL(k_copy_out_m, dim3(nblocks(bs.max_n * M, 256), bs.n_mat), dim3(256), 0, st,
+                     bs.d_n.p, d_xoff, bs.d_yoff.p, M, z, x, active);
+}
+
+// Columns c0 .. c0 + w of a row-major block of ncol columns to or from a contiguous panel
+// of w columns (panel of matrix j at poff[j]).
+__global__ void k_panel_copy(const int64_t* nrows, const int64_t* xoff, double* x, int ncol,
+                             int c0, int w, const int64_t* poff, double* panel,
+                             const int32_t* active, int to_panel) {
+  const int j = blockIdx.y;
+  if (active && !active[j]) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nrows[j] * w) return;
+  const int64_t r = e / w, c = e - r * w;
+  double* xe = x + xoff[j] + r * ncol + c0 + c;
+  double* pe = panel + poff[j] + e;
+  if (to_panel)
+    *pe = *xe;
+  else
+    *xe = *pe;
 }
 
 void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, int ncol,
@@ -1060,6 +1100,7 @@ void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<i
   bs.d_poff.release();
   bs.ybuf.release();
   bs.d_yoff.release();
+  bs.mbuf.release();
   bs.max_B = 0;
   for (size_t j = 0; j < n.size(); ++j) {
     bs.ld[j] = B[j] + 1;

@@ -168,6 +168,7 @@ struct BandSet {
   // forward solutions of the single-right-hand-side solve (64-aligned segment per matrix)
   DevBuf<double> ybuf;
   DevBuf<int64_t> d_yoff;
+  DevBuf<double> mbuf;                         // the same for up to 32 right-hand sides
 };
 
 struct Schwarz {
