@@ -61,33 +61,56 @@ __global__ void __launch_bounds__(256) k_potrf(BandArgs a, T* v, int64_t c0, dou
     }
   }
   __syncthreads();
-  for (int i = 0; i < nb; ++i) {
-    if (threadIdx.x == 0) {
+  // right-looking elimination on the unscaled columns (one barrier per column): step i
+  // subtracts D[r][i] D[s][i] / D[i][i] from the trailing triangle, thread (r, q) owning
+  // row r = t / 4 and the columns s = q mod 4; the columns are scaled by 1/sqrt(pivot) at
+  // the end.  A non-positive pivot is reported and replaced by 1.
+  __shared__ double piv[NB];
+  {
+    const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
+    for (int i = 0; i < nb; ++i) {
       double d = D[i][i];
-      if (!(d > 0.0)) {
-        atomicOr(err, 1);
-        d = 1.0;
+      if (!(d > 0.0)) d = 1.0;
+      if (r > i && r < nb) {
+        const double f = D[r][i] / d;
+        for (int s2 = i + 1 + ((q - (i + 1)) & 3); s2 <= r; s2 += 4) D[r][s2] -= f * D[s2][i];
       }
-      D[i][i] = sqrt(d);
+      if (threadIdx.x == 0) {
+        if (!(D[i][i] > 0.0)) atomicOr(err, 1);
+        piv[i] = d;
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    for (int r = i + 1 + threadIdx.x; r < nb; r += blockDim.x) D[r][i] /= D[i][i];
-    __syncthreads();
-    const int m = nb - i - 1;
-    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-      const int r = i + 1 + idx / m, s = i + 1 + idx % m;
-      if (s <= r) D[r][s] -= D[r][i] * D[s][i];
+    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+      const int rr = idx / NB, c = idx % NB;
+      if (c < nb && rr < nb && c <= rr) D[rr][c] = (rr == c) ? sqrt(piv[c]) : D[rr][c] / sqrt(piv[c]);
     }
     __syncthreads();
   }
-  // inverse of the lower triangle, one column per thread (padding rows are identity)
-  if (threadIdx.x < NB) {
-    const int c = threadIdx.x;
+  // inverse of the lower triangle (padding rows are identity): column c by forward
+  // substitution, four threads per column (thread t: column t / 4, rows q = t mod 4 of
+  // every four, kept in registers); each row's sum is combined across the four by two lane
+  // exchanges
+  if (threadIdx.x < NB) piv[threadIdx.x] = 1.0 / D[threadIdx.x][threadIdx.x];
+  __syncthreads();
+  {
+    const int c = threadIdx.x >> 2, q = threadIdx.x & 3;
+    double xr[NB / 4];
+#pragma unroll
+    for (int m = 0; m < NB / 4; ++m) xr[m] = 0.0;
+#pragma unroll
     for (int i = 0; i < NB; ++i) {
-      double sum = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) sum -= D[i][k] * Li[k][c];
-      Li[i][c] = (i < c) ? 0.0 : sum / D[i][i];
+      double part = 0.0;
+#pragma unroll
+      for (int m = 0; m < (i + 3) / 4; ++m)
+        if (4 * m + q < i) part += D[i][4 * m + q] * xr[m];
+      part += __shfl_xor(part, 1);
+      part += __shfl_xor(part, 2);
+      const double xi = ((i == c ? 1.0 : 0.0) - part) * piv[i];
+      if (q == (i & 3)) xr[i >> 2] = xi;
     }
+#pragma unroll
+    for (int m = 0; m < NB / 4; ++m) Li[4 * m + q][c] = xr[m];
   }
   __syncthreads();
   double* ij = inv + (int64_t)j * NB * NB;
