@@ -193,14 +193,16 @@ __global__ void __launch_bounds__(256) k_trsm(BandArgs a, T* v, int64_t c0, cons
 // from these columns inside the band).  64x64 tiles of that lower triangle, or with
 // col_only the first tile column only (the look-ahead update of the next panel inside a
 // group).  The reduction runs over 64-column chunks of the panels: each chunk's two 64x64
-// blocks are staged in LDS and every wave
-// forms a 32x32 quarter of the tile with the FP64 matrix instruction (2x2 tiles of 16x16,
-// 16 steps of k = 4).  Lane l supplies row l % 16 and reduction index l / 16 of both
+// blocks are staged in LDS and each of the
+// eight waves forms a 16x32 eighth of the tile with the FP64 matrix instruction (1x2 tiles
+// of 16x16, 16 steps of k = 4); two work-groups fit a compute unit.  Lane l supplies row l % 16 and reduction index l / 16 of both
 // operands; accumulator register q of a tile holds output row 4 q + l / 16, column l % 16.
 // Grouping panels makes one read-modify-write pass over the trailing band serve kk columns.
+constexpr int ST = 512;                           // threads of the trailing update
+
 template <class T>
-__global__ void __launch_bounds__(256) k_syrk(BandArgs a, T* v, int64_t k0, int64_t kk,
-                                              int col_only) {
+__global__ void __launch_bounds__(ST) k_syrk(BandArgs a, T* v, int64_t k0, int64_t kk,
+                                             int col_only) {
   __shared__ double Pr[TS][NB + 1], Ps[TS][NB + 1];
   const int j = blockIdx.y;
   const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
@@ -228,62 +230,57 @@ __global__ void __launch_bounds__(256) k_syrk(BandArgs a, T* v, int64_t k0, int6
   // thread t loads column t % 64 of rows t / 64 + 4 u (u < 16) of both blocks; loads are
   // unconditional (a masked entry reads a neighbouring band entry: the row index is clamped
   // below n and the allocation is padded past its end) and the mask applies afterwards
-  constexpr int L = TS * NB / 256;
+  constexpr int L = TS * NB / ST;
+  constexpr int RS = ST / NB;                    // rows staged per pass
   const int cl = threadIdx.x % NB, i0 = threadIdx.x / NB;
   const int64_t rs = ld - 1;                     // entry (r, c) at r * rs + B + c
   const int64_t rlast = n - 1;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int rb = 32 * (w >> 1), sb = 32 * (w & 1);
-  v4d acc[2][2];
+  const int rb = 16 * (w & 3), sb = 32 * (w >> 2);
+  v4d acc[2];
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int q = 0; q < 2; ++q) acc[p][q] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < 2; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
   for (int64_t kc = 0; kc < kj; kc += NB) {
     const int64_t col = k0 + kc + cl;
     const bool okc = kc + cl < kj;
     double vr[L], vs[L];
 #pragma unroll
     for (int u = 0; u < L; ++u) {
-      const int64_t r = r0 + i0 + 4 * u, ss = s0 + i0 + 4 * u;
+      const int64_t r = r0 + i0 + RS * u, ss = s0 + i0 + RS * u;
       vr[u] = (double)base[min(r, rlast) * rs + B + col];
       vs[u] = (double)base[min(ss, rlast) * rs + B + col];
     }
 #pragma unroll
     for (int u = 0; u < L; ++u) {
-      const int64_t r = r0 + i0 + 4 * u, ss = s0 + i0 + 4 * u;
+      const int64_t r = r0 + i0 + RS * u, ss = s0 + i0 + RS * u;
       const bool okr = okc && r < wend && col >= r - B;
       const bool oks = okc && ss < wend && col >= ss - B;
-      Pr[i0 + 4 * u][cl] = okr ? vr[u] : 0.0;
-      Ps[i0 + 4 * u][cl] = oks ? vs[u] : 0.0;
+      Pr[i0 + RS * u][cl] = okr ? vr[u] : 0.0;
+      Ps[i0 + RS * u][cl] = oks ? vs[u] : 0.0;
     }
     __syncthreads();
 #pragma unroll 4
     for (int k = 0; k < NB; k += 4) {
-      const double a0 = Pr[rb + li][k + lk], a1 = Pr[rb + 16 + li][k + lk];
+      const double a0 = Pr[rb + li][k + lk];
       const double b0 = Ps[sb + li][k + lk], b1 = Ps[sb + 16 + li][k + lk];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[1], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
+  for (int q = 0; q < 4; ++q) {
+    const int64_t r = r0 + rb + 4 * q + lk;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t r = r0 + rb + 16 * p + 4 * q + lk;
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int64_t s = s0 + sb + 16 * t + li;
-        if (r < wend && s <= r && (!col_only || s < t0 + TS)) {
-          T* e = base + r * ld + (s - r + B);
-          *e = (T)((double)*e - acc[p][t][q]);
-        }
+    for (int t = 0; t < 2; ++t) {
+      const int64_t s = s0 + sb + 16 * t + li;
+      if (r < wend && s <= r && (!col_only || s < t0 + TS)) {
+        T* e = base + r * ld + (s - r + B);
+        *e = (T)((double)*e - acc[t][q]);
       }
     }
+  }
 }
 
 template <class T>
@@ -302,7 +299,7 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, int* err) {
     for (int p = 0; p < GP && k0 + p * NB < bs.max_n; ++p) {
       const int64_t c0 = k0 + p * NB;
       if (p > 0 && bs.max_B > 0)
-        hipLaunchKernelGGL(k_syrk<T>, dim3((unsigned)nt, bs.n_mat), dim3(256), 0, st, a, v, k0,
+        hipLaunchKernelGGL(k_syrk<T>, dim3((unsigned)nt, bs.n_mat), dim3(ST), 0, st, a, v, k0,
                            (int64_t)p * NB, 1);
       hipLaunchKernelGGL(k_potrf<T>, dim3(bs.n_mat), dim3(256), 0, st, a, v, c0, inv.p, dinv,
                          bs.d_boff.p, err);
@@ -311,7 +308,7 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, int* err) {
                            inv.p);
     }
     if (bs.max_B > 0)
-      hipLaunchKernelGGL(k_syrk<T>, dim3(tiles, bs.n_mat), dim3(256), 0, st, a, v, k0,
+      hipLaunchKernelGGL(k_syrk<T>, dim3(tiles, bs.n_mat), dim3(ST), 0, st, a, v, k0,
                          (int64_t)GP * NB, 0);
   }
   GX_HIP(hipGetLastError());

@@ -80,63 +80,67 @@ __global__ void k_neumann_diag(GeneoDev g, double sigma, const int64_t* doff, do
 }
 
 // M_j = A^N + sigma X A^o X in band storage over the Neumann DOFs; clamped DOFs -> identity.
-// The three band rows of a node are accumulated in LDS (element order, deterministic), in
-// segments of at most NSEG band columns so any bandwidth fits; each segment is written once,
-// scaled symmetrically by diag(M)^-1/2 when dM is given (FP32 factors).
-constexpr int NSEG = 2048;                       // band-row columns per LDS segment
+// The band is zero-filled first; one 64-thread work-group per (node, subdomain) then sums
+// the node's three rows over its elements in the subdomain (element order, deterministic)
+// into the node's block row of K's pattern in LDS, and writes the blocks whose column node
+// is in the subdomain and lies on or below the diagonal, scaled symmetrically by
+// diag(M)^-1/2 when dM is given (FP32 factors).  Only the nonzero blocks are written.
+constexpr int NROW = 128;                        // blocks in one block row of K, at most
 
 template <class T>
-__global__ void __launch_bounds__(64) k_neumann_fill(GeneoDev g, double sigma, BandView bv,
-                                                     const int64_t* doff, const double* dM,
-                                                     T* v) {
-  extern __shared__ double rowbuf[];               // 3 rows x seg columns
+__global__ void __launch_bounds__(64) k_neumann_fill(GeneoDev g, const int32_t* rp,
+                                                     const int32_t* colk, double sigma,
+                                                     BandView bv, const int64_t* doff,
+                                                     const double* dM, T* v, int* err) {
+  __shared__ double rv[NROW * 9];
+  __shared__ int32_t rc[NROW];
   const int j = blockIdx.y;
   const int64_t ln = blockIdx.x;
   if (ln >= g.nD[j]) return;
   const int64_t n = g.D_nodes[g.offD[j] + ln];
   const int64_t B = bv.B[j], ld = bv.ld[j];
   T* base = v + bv.off[j];
+  const int rb = rp[n], len = rp[n + 1] - rb;
+  if (len > NROW) {
+    if (threadIdx.x == 0) atomicOr(err, 1);
+    return;
+  }
+  for (int i = threadIdx.x; i < len; i += 64) rc[i] = colk[rb + i];
+  for (int i = threadIdx.x; i < len * 9; i += 64) rv[i] = 0.0;
+  __syncthreads();
   const double xn = pou(g.I_loc, g.cnt, g.N, j, n);
-  const int64_t seg = min<int64_t>(ld, NSEG);
-  // the three band rows of the node, in segments of columns (band offsets o0 .. o0 + seg)
-  for (int64_t o0 = 0; o0 < ld; o0 += seg) {
-    for (int64_t i = threadIdx.x; i < 3 * seg; i += 64) rowbuf[i] = 0.0;
-    __syncthreads();
-    for (int k = g.ne_ptr[n]; k < g.ne_ptr[n + 1]; ++k) {
-      const int64_t e = g.ne_idx[k];
-      if (!has_bit(g.emask, e, g.W, j)) continue;
-      const bool over = popc_mask(g.emask, e, g.W) >= 2;
-      int a = 0;
-      while (a < 19 && g.conn[20 * e + a] != n) ++a;
-      for (int t = threadIdx.x; t < 180; t += 64) {
-        const int b = t / 9, comp = t - 9 * (t / 9);
-        const int i = comp / 3, kk = comp - 3 * (comp / 3);
-        const int64_t m = g.conn[20 * e + b];
-        const int64_t lm = g.D_loc[(int64_t)j * g.N + m];
-        const int64_t row = 3 * ln + i, col = 3 * lm + kk;
-        const int64_t o = col - row + B - o0;
-        if (col > row || o < 0 || o >= seg) continue;
-        const double w = over ? 1.0 + sigma * xn * pou(g.I_loc, g.cnt, g.N, j, m) : 1.0;
-        rowbuf[i * seg + o] += w * g.Ke[((e * 20 + a) * 20 + b) * 9 + comp];
+  for (int k = g.ne_ptr[n]; k < g.ne_ptr[n + 1]; ++k) {
+    const int64_t e = g.ne_idx[k];
+    if (!has_bit(g.emask, e, g.W, j)) continue;
+    const bool over = popc_mask(g.emask, e, g.W) >= 2;
+    int a = 0;
+    while (a < 19 && g.conn[20 * e + a] != n) ++a;
+    for (int t = threadIdx.x; t < 180; t += 64) {
+      const int b = t / 9, comp = t - 9 * (t / 9);
+      const int m = g.conn[20 * e + b];
+      int lo = 0, hi = len - 1;                    // m's block in the row (sorted columns)
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (rc[mid] < m) lo = mid + 1; else hi = mid;
       }
-      __syncthreads();
-    }
-    const int64_t cnt = min<int64_t>(seg, ld - o0);
-    for (int64_t t = threadIdx.x; t < 3 * cnt; t += 64) {
-      const int64_t r3 = t / cnt, o = o0 + t % cnt;
-      const int64_t row = 3 * ln + r3, col = row - B + o;
-      double val = rowbuf[r3 * seg + (o - o0)];
-      if (col >= 0) {
-        const int64_t gr = 3 * n + row % 3;
-        const int64_t gc = 3 * (int64_t)g.D_nodes[g.offD[j] + col / 3] + col % 3;
-        if (g.fixed[gr] || g.fixed[gc]) val = (row == col) ? 1.0 : 0.0;
-        if (dM) val /= sqrt(dM[doff[j] + row] * dM[doff[j] + col]);
-      } else {
-        val = 0.0;
-      }
-      base[row * ld + o] = (T)val;
+      const double w = over ? 1.0 + sigma * xn * pou(g.I_loc, g.cnt, g.N, j, m) : 1.0;
+      rv[9 * lo + comp] += w * g.Ke[((e * 20 + a) * 20 + b) * 9 + comp];
     }
     __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < len * 9; idx += 64) {
+    const int sl = idx / 9, comp = idx - 9 * (idx / 9);
+    const int i = comp / 3, kk = comp - 3 * (comp / 3);
+    const int64_t m = rc[sl];
+    const int64_t lm = g.D_loc[(int64_t)j * g.N + m];
+    if (lm < 0) continue;
+    const int64_t row = 3 * ln + i, col = 3 * lm + kk;
+    const int64_t o = col - row + B;
+    if (col > row || o < 0) continue;
+    double val = rv[idx];
+    if (g.fixed[3 * n + i] || g.fixed[3 * m + kk]) val = (row == col) ? 1.0 : 0.0;
+    if (dM) val /= sqrt(dM[doff[j] + row] * dM[doff[j] + col]);
+    base[row * ld + o] = (T)val;
   }
 }
 
@@ -211,45 +215,96 @@ __global__ void k_scale_rows(const int64_t* nrows, int m, const int64_t* voff,
 }
 
 // Y = X_j A^o X_j X for the m columns of subdomain j (row-major, lane = column)
-__global__ void __launch_bounds__(64) k_bmul(GeneoDev g, int m, const int64_t* voff,
-                                             const int32_t* active, const double* X,
-                                             double* Y) {
+// B = X A^o X on the Neumann DOFs of each subdomain, stored once as node block rows over
+// K's pattern (the blocks of row (j, node) at brow[offD[j] + ln], 9 values each, zero where
+// no overlap element of j connects the two nodes or a DOF is clamped), so that each B
+// product reads every block once instead of re-reading element matrices and solution rows
+// per element
+__global__ void k_brow_len(GeneoDev g, const int32_t* rp, int64_t* len) {
+  const int j = blockIdx.y;
+  const int64_t ln = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ln >= g.nD[j]) return;
+  const int64_t n = g.D_nodes[g.offD[j] + ln];
+  len[g.offD[j] + ln] = rp[n + 1] - rp[n];
+}
+
+__global__ void __launch_bounds__(64) k_b_fill(GeneoDev g, const int32_t* rp,
+                                               const int32_t* colk, const int64_t* brow,
+                                               double* bv) {
+  __shared__ double rv[NROW * 9];
+  __shared__ int32_t rc[NROW];
   const int j = blockIdx.y;
   const int64_t ln = blockIdx.x;
-  if (ln >= g.nD[j] || !active[j]) return;
-  const int lane = threadIdx.x;
+  if (ln >= g.nD[j]) return;
   const int64_t n = g.D_nodes[g.offD[j] + ln];
-  const double* Xj = X + voff[j];
-  double y0 = 0, y1 = 0, y2 = 0;
+  const int rb = rp[n], len = rp[n + 1] - rb;      // <= NROW (checked by the Neumann fill)
+  for (int i = threadIdx.x; i < len; i += 64) rc[i] = colk[rb + i];
+  for (int i = threadIdx.x; i < len * 9; i += 64) rv[i] = 0.0;
+  __syncthreads();
   const double xn = pou(g.I_loc, g.cnt, g.N, j, n);
-  if (xn != 0.0 && lane < m) {
+  if (xn != 0.0)
     for (int k = g.ne_ptr[n]; k < g.ne_ptr[n + 1]; ++k) {
       const int64_t e = g.ne_idx[k];
       if (!has_bit(g.emask, e, g.W, j) || popc_mask(g.emask, e, g.W) < 2) continue;
       int a = 0;
       while (a < 19 && g.conn[20 * e + a] != n) ++a;
-      for (int b = 0; b < 20; ++b) {
-        const int64_t mm = g.conn[20 * e + b];
-        const double w = xn * pou(g.I_loc, g.cnt, g.N, j, mm);
-        if (w == 0.0) continue;
-        const int64_t lm = g.D_loc[(int64_t)j * g.N + mm];
-        const double* kb = g.Ke + ((e * 20 + a) * 20 + b) * 9;
-        const double x0 = g.fixed[3 * mm] ? 0.0 : Xj[(3 * lm) * m + lane];
-        const double x1 = g.fixed[3 * mm + 1] ? 0.0 : Xj[(3 * lm + 1) * m + lane];
-        const double x2 = g.fixed[3 * mm + 2] ? 0.0 : Xj[(3 * lm + 2) * m + lane];
-        y0 += w * (kb[0] * x0 + kb[1] * x1 + kb[2] * x2);
-        y1 += w * (kb[3] * x0 + kb[4] * x1 + kb[5] * x2);
-        y2 += w * (kb[6] * x0 + kb[7] * x1 + kb[8] * x2);
+      for (int t = threadIdx.x; t < 180; t += 64) {
+        const int b = t / 9, comp = t - 9 * (t / 9);
+        const int m = g.conn[20 * e + b];
+        int lo = 0, hi = len - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (rc[mid] < m) lo = mid + 1; else hi = mid;
+        }
+        rv[9 * lo + comp] += xn * pou(g.I_loc, g.cnt, g.N, j, m) *
+                             g.Ke[((e * 20 + a) * 20 + b) * 9 + comp];
       }
+      __syncthreads();
     }
-  }
-  if (lane < m) {
-    double* Yj = Y + voff[j];
-    Yj[(3 * ln) * m + lane] = g.fixed[3 * n] ? 0.0 : y0;
-    Yj[(3 * ln + 1) * m + lane] = g.fixed[3 * n + 1] ? 0.0 : y1;
-    Yj[(3 * ln + 2) * m + lane] = g.fixed[3 * n + 2] ? 0.0 : y2;
+  double* out = bv + 9 * brow[g.offD[j] + ln];
+  for (int idx = threadIdx.x; idx < len * 9; idx += 64) {
+    const int sl = idx / 9, comp = idx - 9 * (idx / 9);
+    const int64_t m = rc[sl];
+    const bool fx = g.fixed[3 * n + comp / 3] || g.fixed[3 * m + comp % 3];
+    out[idx] = fx ? 0.0 : rv[idx];
   }
 }
+
+// Y = B X for the m columns of the active subdomains (lane = column), from the stored rows
+__global__ void __launch_bounds__(64) k_bmul_rows(GeneoDev g, const int32_t* rp,
+                                                  const int32_t* colk, const int64_t* brow,
+                                                  const double* bv, int m, const int64_t* voff,
+                                                  const int32_t* active, const double* X,
+                                                  double* Y) {
+  const int j = blockIdx.y;
+  const int64_t ln = blockIdx.x;
+  if (ln >= g.nD[j] || !active[j]) return;
+  const int lane = threadIdx.x;
+  const int64_t n = g.D_nodes[g.offD[j] + ln];
+  const int rb = rp[n], len = rp[n + 1] - rb;
+  const double* Xj = X + voff[j];
+  const double* blk = bv + 9 * brow[g.offD[j] + ln];
+  double y0 = 0, y1 = 0, y2 = 0;
+  if (lane < m && pou(g.I_loc, g.cnt, g.N, j, n) != 0.0)
+    for (int sl = 0; sl < len; ++sl) {
+      const int64_t lm = g.D_loc[(int64_t)j * g.N + colk[rb + sl]];
+      if (lm < 0) continue;
+      const double* kb = blk + 9 * sl;
+      const double x0 = Xj[(3 * lm) * m + lane];
+      const double x1 = Xj[(3 * lm + 1) * m + lane];
+      const double x2 = Xj[(3 * lm + 2) * m + lane];
+      y0 += kb[0] * x0 + kb[1] * x1 + kb[2] * x2;
+      y1 += kb[3] * x0 + kb[4] * x1 + kb[5] * x2;
+      y2 += kb[6] * x0 + kb[7] * x1 + kb[8] * x2;
+    }
+  if (lane < m) {
+    double* Yj = Y + voff[j];
+    Yj[(3 * ln) * m + lane] = y0;
+    Yj[(3 * ln + 1) * m + lane] = y1;
+    Yj[(3 * ln + 2) * m + lane] = y2;
+  }
+}
+
 
 // deterministic pseudo-random start block (splitmix64 of the entry index), zero on clamps
 __global__ void k_rand_init(GeneoDev g, int m, const int64_t* voff, double* X) {
@@ -764,19 +819,27 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
     Mb.force_groups[0] = c->tune[0];
     Mb.force_groups[1] = c->tune[1];
     c->neumann_entries = Mb.total;
-    const size_t lds = 3 * (size_t)std::min<int64_t>(Mb.max_B + 1, NSEG) * sizeof(double);
     BandView bv{Mb.d_B.p, Mb.d_ld.p, Mb.d_off.p};
+    DevBuf<int> ferr(1);
+    zero(ferr, s);
     if (fp32) {
       dM.alloc(doff[n_sub]);
       hipLaunchKernelGGL(k_neumann_diag, dim3(nblocks(maxD, 256), n_sub), dim3(256), 0, s, g,
                          sigma, d_doff.p, dM.p);
-      hipLaunchKernelGGL(k_neumann_fill<float>, dim3((unsigned)maxD, n_sub), dim3(64), lds, s,
-                         g, sigma, bv, d_doff.p, (const double*)dM.p, Mb.v32.p);
+      GX_HIP(hipMemsetAsync(Mb.v32.p, 0, Mb.total * sizeof(float), s));
+      hipLaunchKernelGGL(k_neumann_fill<float>, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g,
+                         c->row_ptr.p, c->col.p, sigma, bv, d_doff.p, (const double*)dM.p,
+                         Mb.v32.p, ferr.p);
     } else {
-      hipLaunchKernelGGL(k_neumann_fill<double>, dim3((unsigned)maxD, n_sub), dim3(64), lds, s,
-                         g, sigma, bv, d_doff.p, (const double*)nullptr, Mb.v64.p);
+      GX_HIP(hipMemsetAsync(Mb.v64.p, 0, Mb.total * sizeof(double), s));
+      hipLaunchKernelGGL(k_neumann_fill<double>, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g,
+                         c->row_ptr.p, c->col.p, sigma, bv, d_doff.p, (const double*)nullptr,
+                         Mb.v64.p, ferr.p);
     }
     GX_HIP(hipGetLastError());
+    int hferr = 0;
+    to_host(&hferr, ferr.p, 1, s);
+    GX_REQUIRE(!hferr, "a block row of K is longer than the Neumann assembly takes");
     try {
       band_factor(Mb, s, "the shifted Neumann matrices (GenEO eigensolver)");
     } catch (const Error& e) {
@@ -784,13 +847,32 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
       // an FP32 factor broke down: this matrix set is refactored in FP64 (reported)
       c->fp64_fallbacks |= 2;
       band_layout(Mb, n3, B, false, s);
-      hipLaunchKernelGGL(k_neumann_fill<double>, dim3((unsigned)maxD, n_sub), dim3(64), lds,
-                         s, g, sigma, bv, d_doff.p, (const double*)nullptr, Mb.v64.p);
+      bv = BandView{Mb.d_B.p, Mb.d_ld.p, Mb.d_off.p};
+      GX_HIP(hipMemsetAsync(Mb.v64.p, 0, Mb.total * sizeof(double), s));
+      hipLaunchKernelGGL(k_neumann_fill<double>, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g,
+                         c->row_ptr.p, c->col.p, sigma, bv, d_doff.p, (const double*)nullptr,
+                         Mb.v64.p, ferr.p);
       GX_HIP(hipGetLastError());
       band_factor(Mb, s, "the shifted Neumann matrices (GenEO eigensolver)");
     }
   }
   const bool m32 = Mb.fp32;
+  // B as stored node block rows (see k_b_fill)
+  int64_t sumD = 0;
+  for (int j = 0; j < n_sub; ++j) sumD += sw.nD[j];
+  DevBuf<int64_t> brow(sumD + 1);
+  DevBuf<double> Bv;
+  {
+    zero(brow, s);
+    hipLaunchKernelGGL(k_brow_len, dim3(nblocks(maxD, 256), n_sub), dim3(256), 0, s, g,
+                       c->row_ptr.p, brow.p);
+    DevBuf<int64_t> stmp(scan_tmp_size(sumD + 1));
+    const int64_t nbl = exclusive_scan(brow.p, sumD + 1, stmp.p, s);
+    Bv.alloc(std::max<int64_t>(9 * nbl, 1));
+    hipLaunchKernelGGL(k_b_fill, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g, c->row_ptr.p,
+                       c->col.p, brow.p, Bv.p);
+    GX_HIP(hipGetLastError());
+  }
   // block size: a fixed count takes the wanted count + 8 guard vectors, rounded up to a
   // multiple of 8 (the multi-right-hand-side solves are built for them).  A threshold starts
   // with one full solve panel (MSTART columns: the solves cost about the same per iteration
@@ -840,7 +922,8 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
                        sw.d_nD.p, m_prev, d_voff_prev.p, X_prev.p, m, d_voff.p, X.p);
   X_prev.release();
   d_voff_prev.release();
-  hipLaunchKernelGGL(k_bmul, growD, dim3(64), 0, s, g, m, d_voff.p, active.p, X.p, BX.p);
+  hipLaunchKernelGGL(k_bmul_rows, growD, dim3(64), 0, s, g, c->row_ptr.p, c->col.p, brow.p,
+                     Bv.p, m, d_voff.p, active.p, X.p, BX.p);
   std::vector<double> h_theta((size_t)n_sub * MAXM), h_res((size_t)n_sub * 3 * MAXM);
   lam_final.assign((size_t)n_sub * MAXM, 0.0);
   int n_active = n_sub;
@@ -876,7 +959,8 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
       band_solve(Mb, d_voff.p, Y.p, s, m, active.p);
       GX_HIP(hipEventRecord(ev.b, s));
     }
-    hipLaunchKernelGGL(k_bmul, growD, dim3(64), 0, s, g, m, d_voff.p, active.p, Y.p, BY.p);
+    hipLaunchKernelGGL(k_bmul_rows, growD, dim3(64), 0, s, g, c->row_ptr.p, c->col.p, brow.p,
+                       Bv.p, m, d_voff.p, active.p, Y.p, BY.p);
     if (m32)
       hipLaunchKernelGGL(k_amul, growD, dim3(64), 0, s, g, m, d_voff.p, active.p, Y.p, BY.p,
                          sigma, MY);

@@ -61,8 +61,8 @@ def test_geneo_two_level(gx, cfg):
 
 def _wide():
     """Nodes are numbered with the thickness index slowest, so the Neumann band of a
-    subdomain 16 x 13 elements in plan has rows of about 2600 columns: more than one LDS
-    segment of the band assembly, so each row is built in two segments."""
+    subdomain 16 x 13 elements in plan has rows of about 2600 columns (wider than any other
+    parity case here, and wider than an LDS row buffer of the band assembly could hold)."""
     cfg = workloads.small_flat(nx=28, ny=13, length=28.0, width=13.0)
     cfg["name"] = "wide_28x13x4"
     cfg["solver"].update(px=2, py=1, overlap=1, nev=6)
