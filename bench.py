@@ -24,6 +24,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Solve time per 1M DOFs at rtol 1e-8 (FP64 vs mixed); CG iters; SpMV GB/s"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes of one PCG subdomain band solve on this workload (FP64 factors), from the
+# FETCH_SIZE / WRITE_SIZE counters of `bench.py --traffic-probe` scaled by a 4 GiB copy;
+# None for the FP32 factors, whose counters were not taken.  Valid for the solve kernel as
+# it stands: retake the counters when it changes.
+SOLVE_TRAFFIC_BYTES = {"fp64": 159.6e9, "mixed": None}
 
 
 def run_step(gx, torch, cfg, precision):
@@ -87,6 +92,26 @@ def batch_sweep(gx, torch, workloads, args):
     print(json.dumps(line), flush=True)
 
 
+COPY_BYTES = 4 << 30      # calibration copy of the traffic probe (read and written once)
+
+
+def traffic_probe(gx, torch, workloads, args):
+    """The dispatches whose FETCH_SIZE / WRITE_SIZE counters give the subdomain solve's HBM
+    traffic: one device-to-device copy of COPY_BYTES (known traffic, the calibration) and
+    one launch of the PCG subdomain band solve on the bench workload."""
+    cfg = workloads.cfg1()
+    prec = gx.GX_MIXED if args.precision == "mixed" else gx.GX_FP64
+    s, _, _, _ = run_step(gx, torch, cfg, prec)
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ms, nbytes = s.kernel_time(1, reps=1)
+    print(json.dumps({"copy_bytes": COPY_BYTES, "solve_ms": ms, "solve_algorithmic_bytes": nbytes}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +122,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead: the seeded sweep of wrinkled L-sections, this many samples")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="instead: set up the workload, then launch one plain copy of "
+                         "COPY_BYTES and one subdomain band solve (for hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -106,6 +134,8 @@ def main():
     import workloads
     if args.batch:
         return batch_sweep(gx, torch, workloads, args)
+    if args.traffic_probe:
+        return traffic_probe(gx, torch, workloads, args)
 
     cfg = workloads.cfg1(nx=24, ny=24, px=3, py=3) if args.small else workloads.cfg1()
     prec = gx.GX_MIXED if args.precision == "mixed" else gx.GX_FP64
@@ -166,7 +196,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_band_solve_1 (PCG subdomain solves, "
                                                "forward+backward)",
                      "achieved": solve_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": solve_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": solve_gbs / HBM_PEAK_GBS,
+                     "traffic": SOLVE_TRAFFIC_BYTES[args.precision],
                      "bytes_per_launch": solve_bytes, "ms_per_launch": solve_ms},
         "eigensolve_roofline": {"bound": "hbm", "kernel": "k_band_solve_m (GenEO block solves)",
                                 "achieved": eig_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
