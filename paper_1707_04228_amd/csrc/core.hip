@@ -3,6 +3,99 @@
 
 namespace gx {
 
+namespace {
+constexpr size_t CACHE_MIN = (size_t)64 << 20;   // blocks this large are cached
+
+struct CachedBlock {
+  int dev;
+  size_t bytes;
+  void* p;
+};
+
+std::mutex cache_mu;
+std::vector<CachedBlock> cache_blocks;
+std::vector<size_t> cache_bytes, cache_cap;          // per device
+
+size_t& cached_on(int dev) {
+  if ((int)cache_bytes.size() <= dev) {
+    cache_bytes.resize(dev + 1, 0);
+    cache_cap.resize(dev + 1, 0);
+  }
+  if (!cache_cap[dev]) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) cache_cap[dev] = tot / 2;
+  }
+  return cache_bytes[dev];
+}
+
+void trim_cache(int dev) {                          // caller holds cache_mu
+  (void)hipDeviceSynchronize();
+  for (size_t i = 0; i < cache_blocks.size();) {
+    if (cache_blocks[i].dev == dev) {
+      (void)hipFree(cache_blocks[i].p);
+      cached_on(dev) -= cache_blocks[i].bytes;
+      cache_blocks[i] = cache_blocks.back();
+      cache_blocks.pop_back();
+    } else {
+      ++i;
+    }
+  }
+}
+}  // namespace
+
+void* dev_alloc(size_t bytes, int* dev, hipError_t* err) {
+  int d = 0;
+  (void)hipGetDevice(&d);
+  *dev = d;
+  if (bytes >= CACHE_MIN) {
+    std::unique_lock<std::mutex> lk(cache_mu);
+    int best = -1;
+    for (int i = 0; i < (int)cache_blocks.size(); ++i) {
+      const CachedBlock& c = cache_blocks[i];
+      if (c.dev == d && c.bytes >= bytes && c.bytes <= bytes + bytes / 8 + CACHE_MIN &&
+          (best < 0 || c.bytes < cache_blocks[best].bytes))
+        best = i;
+    }
+    if (best >= 0) {
+      void* p = cache_blocks[best].p;
+      cached_on(d) -= cache_blocks[best].bytes;
+      cache_blocks[best] = cache_blocks.back();
+      cache_blocks.pop_back();
+      lk.unlock();
+      // the block is ours; its previous user's kernels must be done with it
+      *err = hipDeviceSynchronize();
+      if (*err != hipSuccess) return nullptr;
+      // (released again, it is filed under the requested size, never more than it has)
+      return p;
+    }
+  }
+  void* p = nullptr;
+  *err = hipMalloc(&p, bytes);
+  if (*err == hipErrorOutOfMemory) {
+    {
+      std::lock_guard<std::mutex> lk(cache_mu);
+      trim_cache(d);
+    }
+    (void)hipGetLastError();
+    *err = hipMalloc(&p, bytes);
+  }
+  return *err == hipSuccess ? p : nullptr;
+}
+
+void dev_free(void* p, size_t bytes, int dev) {
+  if (!p) return;
+  if (bytes >= CACHE_MIN && dev >= 0) {
+    std::lock_guard<std::mutex> lk(cache_mu);
+    size_t& c = cached_on(dev);
+    if (c + bytes <= cache_cap[dev]) {
+      cache_blocks.push_back({dev, bytes, p});
+      c += bytes;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+
 constexpr int SCAN_BS = 256;
 constexpr int SCAN_PT = 8;                       // items per thread
 constexpr int SCAN_TILE = SCAN_BS * SCAN_PT;

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <type_traits>
@@ -45,18 +46,34 @@ inline bool poison_alloc() {
   return on;
 }
 
+// Device memory for DevBuf.  Blocks of 64 MiB and more are kept after release in a
+// per-device cache (up to half the device's memory) and handed out again to a request of
+// the same size or slightly smaller, after a device synchronisation (so no kernel still
+// uses the block): the large band storages of repeated set-ups then cost no hipMalloc /
+// hipFree cycle.  A failed hipMalloc empties the cache of that device and retries.
+void* dev_alloc(size_t bytes, int* dev, hipError_t* err);
+void dev_free(void* p, size_t bytes, int dev);
+
 // Owning device buffer.
 template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  int dev = -1;
   DevBuf() = default;
   explicit DevBuf(size_t count) { alloc(count); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), dev(o.dev) { o.p = nullptr; o.n = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      dev = o.dev;
+      o.p = nullptr;
+      o.n = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
@@ -64,9 +81,9 @@ struct DevBuf {
     release();
     n = count;
     if (count) {
-      hipError_t e = hipMalloc(&p, count * sizeof(T));
-      if (e != hipSuccess) {
-        p = nullptr;
+      hipError_t e = hipSuccess;
+      p = static_cast<T*>(dev_alloc(count * sizeof(T), &dev, &e));
+      if (!p) {
         n = 0;
         throw Error(GX_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) +
                                    " bytes failed: " + hipGetErrorString(e));
@@ -79,7 +96,7 @@ struct DevBuf {
     }
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p, n * sizeof(T), dev);
     p = nullptr;
     n = 0;
   }
