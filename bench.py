@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE counters of `bench.py --traffic-probe` scaled by a 4 GiB copy;
 # None for the FP32 factors, whose counters were not taken.  Valid for the solve kernel as
 # it stands: retake the counters when it changes.
-SOLVE_TRAFFIC_BYTES = {"fp64": 159.6e9, "mixed": None}
+SOLVE_TRAFFIC_BYTES = {"fp64": 158.5e9, "mixed": None}
 
 
 def run_step(gx, torch, cfg, precision):

@@ -270,11 +270,14 @@ gx_status gx_band_factor_solve(gx_ctx* ctx, int32_t n_mat, const int64_t* n, con
 /* Batched PCG (extension: many laminates at once).  n contexts, each set up
  * (gx_geneo_setup) for its own laminate and, for overlap, on its own HIP stream, solve
  * K_i x_i = b_i in lockstep: every iteration enqueues the work of each unconverged system on
- * its stream and then waits once for all of them; a system leaves the batch when it
- * converges (the stopping test of gx_pcg_solve, per system).  b[i], x[i]: device vectors of
- * context i (x[i] in: initial guess).  iters_out, relres_out, status_out: host [n] (may be
- * NULL).  Returns GX_OK if every system converged, else the first non-OK status (each
- * context's gx_last_error explains its own). */
+ * its stream, the subdomain solves of all of them as one launch per device and factor
+ * precision (on a stream of the batch's own that waits for the systems' streams and that
+ * they wait for), and then waits once for all of them; a system leaves the batch when it
+ * converges (the stopping test of gx_pcg_solve, per system).  Each context appears once
+ * (GX_EINVAL otherwise).  b[i], x[i]: device vectors of context i (x[i] in: initial
+ * guess).  iters_out, relres_out, status_out: host [n] (may be NULL).  Returns GX_OK if
+ * every system converged, else the first non-OK status (each context's gx_last_error
+ * explains its own). */
 gx_status gx_pcg_solve_batch(int32_t n, gx_ctx* const* ctxs, const double* const* b,
                              double* const* x, double rtol, int32_t maxit, int32_t* iters_out,
                              double* relres_out, int32_t* status_out);

@@ -468,23 +468,15 @@ __device__ inline bool poll_give_up(int64_t& spins, int* err) {
   return false;
 }
 
-template <class T, bool COARSE>
-__global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
-    BandArgs a, const T* v, const T* dinv, const int64_t* boff, const int64_t* xoff,
-    const double* xall, double* yall, double* zall, const int64_t* yoff, int G, int n_pad,
-    int n_mat, int* err) {
+// Work-group g of the G that solve one matrix of n rows, half-bandwidth B and row stride
+// ld: factor from base, inverse diagonal blocks from dv, right-hand side x, scratch y, z.
+template <class T>
+__device__ __forceinline__ void band_solve_1_mat(int64_t n, int64_t B, int64_t ld,
+                                                 const T* base, const T* dv, const double* x,
+                                                 double* y, double* z, int g, int G, int* err) {
   __shared__ double acc[SB];
   __shared__ double part[SW][SB];
   __shared__ double xs[GMAX - 1][SB];               // polled solutions of blocks in flight
-  const int g = blockIdx.x / n_pad, j = blockIdx.x % n_pad;
-  if (j >= n_mat || g >= G) return;
-  const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
-  if (n == 0) return;
-  const T* base = v + a.off[j];
-  const T* dv = dinv + boff[j];
-  const double* x = xall + xoff[j];
-  double* y = yall + yoff[j];
-  double* z = zall + yoff[j];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t nblk = (n + SB - 1) / SB;
   constexpr int U = 8;                             // 64-column steps in flight per wave
@@ -693,6 +685,51 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
     }
     __syncthreads();
   }
+}
+
+// Matrices j of one band set: work-group (g, j) at blockIdx.x = g * n_pad + j.
+template <class T, bool COARSE>
+__global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
+    BandArgs a, const T* v, const T* dinv, const int64_t* boff, const int64_t* xoff,
+    const double* xall, double* yall, double* zall, const int64_t* yoff, int G, int n_pad,
+    int n_mat, int* err) {
+  const int g = blockIdx.x / n_pad, j = blockIdx.x % n_pad;
+  if (j >= n_mat || g >= G) return;
+  const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
+  if (n == 0) return;
+  band_solve_1_mat<T>(n, B, ld, v + a.off[j], dinv + boff[j], xall + xoff[j], yall + yoff[j],
+                      zall + yoff[j], g, G, err);
+}
+
+// The matrices of several band sets in one launch (all of one precision): matrix j's rows,
+// bandwidth, factor, inverse diagonal blocks, right-hand side and scratch from tab[j].
+template <class T>
+__global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1_multi(const BandPtrs* tab,
+                                                                       int G, int n_pad,
+                                                                       int n_mat, int* err) {
+  const int g = blockIdx.x / n_pad, j = blockIdx.x % n_pad;
+  if (j >= n_mat || g >= G) return;
+  const BandPtrs t = tab[j];
+  if (t.n == 0) return;
+  band_solve_1_mat<T>(t.n, t.B, t.B + 1, static_cast<const T*>(t.v),
+                      static_cast<const T*>(t.dinv), t.x, t.y, t.z, g, G, err);
+}
+
+// y and z scratch of every matrix of a multi-set solve back to the marker
+__global__ void k_fill_mark_multi(const BandPtrs* tab) {
+  const BandPtrs t = tab[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (t.n + SB - 1) / SB * SB) {
+    t.y[i] = __longlong_as_double((long long)YMARK);
+    t.z[i] = __longlong_as_double((long long)YMARK);
+  }
+}
+
+// x_j <- z_j for every matrix of a multi-set solve
+__global__ void k_copy_out_multi(const BandPtrs* tab) {
+  const BandPtrs t = tab[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < t.n) t.x[i] = t.z[i];
 }
 
 // ---- M right-hand sides per matrix (M a multiple of 8, at most MC; row-major, row
@@ -941,14 +978,18 @@ __global__ void k_fill_mark(double* p, int64_t n) {
 // The forward and backward solution scratch of the single-right-hand-side solve (y, then
 // z, 64-aligned segments per matrix), reset to the marker by a fill kernel on the stream
 // (so the launch can be captured in a graph).
+static void alloc_solve1_scratch(BandSet& bs, hipStream_t st) {
+  if (bs.d_yoff.n) return;
+  std::vector<int64_t> yo(bs.n_mat + 1, 0);
+  for (int j = 0; j < bs.n_mat; ++j) yo[j + 1] = yo[j] + (bs.n[j] + SB - 1) / SB * SB;
+  bs.ybuf.alloc(2 * std::max<int64_t>(yo[bs.n_mat], 1));
+  bs.d_yoff.alloc(bs.n_mat + 1);
+  to_dev(bs.d_yoff.p, yo.data(), bs.n_mat + 1, st);
+  GX_HIP(hipStreamSynchronize(st));                // yo is a local host vector
+}
+
 static double* solve1_scratch(BandSet& bs, hipStream_t st) {
-  if (!bs.d_yoff.n) {
-    std::vector<int64_t> yo(bs.n_mat + 1, 0);
-    for (int j = 0; j < bs.n_mat; ++j) yo[j + 1] = yo[j] + (bs.n[j] + SB - 1) / SB * SB;
-    bs.ybuf.alloc(2 * std::max<int64_t>(yo[bs.n_mat], 1));
-    bs.d_yoff.alloc(bs.n_mat + 1);
-    to_dev(bs.d_yoff.p, yo.data(), bs.n_mat + 1, st);
-  }
+  alloc_solve1_scratch(bs, st);
   hipLaunchKernelGGL(k_fill_mark, dim3(nblocks((int64_t)bs.ybuf.n, 256)), dim3(256), 0, st,
                      bs.ybuf.p, (int64_t)bs.ybuf.n);
   return bs.ybuf.p;
@@ -1092,6 +1133,96 @@ double band_solve_bytes(const BandSet& bs, int ncol, const int32_t* active_host)
          4.0 * 8.0 * (double)bs.n[j] * ncol;
   }
   return b;
+}
+
+// The table of a multi-set solve: matrix j of set k solves in place on x[k] + xoff[k][j]
+// (xoff[k]: host offsets of set k's right-hand-side segments).  Synchronises st.
+void multi_solve_plan(MultiSolve& m, const std::vector<BandSet*>& sets,
+                      const std::vector<double*>& x, const std::vector<const int64_t*>& xoff,
+                      hipStream_t st) {
+  GX_REQUIRE(!sets.empty() && x.size() == sets.size() && xoff.size() == sets.size(),
+             "multi-set solve: one right-hand side and offset list per band set");
+  GX_HIP(hipStreamSynchronize(st));                // earlier launches may still read the table
+  m.sets = sets;
+  m.fp32 = sets[0]->fp32;
+  m.host.clear();
+  m.max_n = 0;
+  for (size_t k = 0; k < sets.size(); ++k) {
+    BandSet& bs = *sets[k];
+    GX_REQUIRE(bs.fp32 == m.fp32 && !bs.coarse && x[k] && xoff[k],
+               "multi-set solve: band sets of one precision with right-hand sides");
+    alloc_solve1_scratch(bs, st);
+    const int64_t half = (int64_t)bs.ybuf.n / 2;
+    int64_t yo = 0;
+    for (int j = 0; j < bs.n_mat; ++j) {
+      BandPtrs t;
+      t.v = m.fp32 ? static_cast<const void*>(bs.v32.p + bs.off[j])
+                   : static_cast<const void*>(bs.v64.p + bs.off[j]);
+      t.dinv = m.fp32 ? static_cast<const void*>(bs.dinv32.p + bs.boff[j])
+                      : static_cast<const void*>(bs.dinv64.p + bs.boff[j]);
+      t.x = x[k] + xoff[k][j];
+      t.y = bs.ybuf.p + yo;
+      t.z = bs.ybuf.p + half + yo;
+      t.n = bs.n[j];
+      t.B = bs.B[j];
+      yo += (bs.n[j] + SB - 1) / SB * SB;
+      m.max_n = std::max(m.max_n, bs.n[j]);
+      m.host.push_back(t);
+    }
+  }
+  m.n_mat = (int)m.host.size();
+  GX_REQUIRE(m.n_mat > 0 && m.n_mat <= 65535, "multi-set solve: 1 to 65535 matrices");
+  if (m.tab.n < m.host.size()) m.tab.alloc(m.host.size());
+  to_dev(m.tab.p, m.host.data(), m.host.size(), st);
+  if (!m.err.n) {
+    m.err.alloc(1);
+    zero(m.err, st);
+  }
+  GX_HIP(hipStreamSynchronize(st));
+  // work-groups per matrix: all of them resident at once (the waits between the groups of a
+  // matrix need that), at most GMAX, and at least two blocks of rows per group
+  int dev = 0, cus = 0, per_cu = 0;
+  GX_HIP(hipGetDevice(&dev));
+  GX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const void* kf = m.fp32 ? reinterpret_cast<const void*>(&k_band_solve_1_multi<float>)
+                          : reinterpret_cast<const void*>(&k_band_solve_1_multi<double>);
+  GX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf, SOLVE_THREADS, 0));
+  const int64_t full = (int64_t)cus * std::max(per_cu, 0);
+  m.G = 1;
+  for (int c = GMAX; c >= 2; --c)
+    if ((int64_t)m.n_mat * c <= full && m.max_n >= (int64_t)2 * SB * c) {
+      m.G = c;
+      break;
+    }
+}
+
+// Solves every matrix of the table in place (marker fill, solve, copy-out on st).
+void multi_solve(MultiSolve& m, hipStream_t st) {
+  GX_REQUIRE(m.n_mat > 0, "multi-set solve: no table");
+  const unsigned nm = (unsigned)m.n_mat;
+  const int n_pad = (m.n_mat + 7) / 8 * 8;         // all groups of a matrix on one XCD
+  hipLaunchKernelGGL(k_fill_mark_multi, dim3(nblocks((m.max_n + SB - 1) / SB * SB, 256), nm),
+                     dim3(256), 0, st, m.tab.p);
+  if (m.fp32)
+    hipLaunchKernelGGL(k_band_solve_1_multi<float>, dim3(m.G * n_pad), dim3(SOLVE_THREADS), 0,
+                       st, m.tab.p, m.G, n_pad, m.n_mat, m.err.p);
+  else
+    hipLaunchKernelGGL(k_band_solve_1_multi<double>, dim3(m.G * n_pad), dim3(SOLVE_THREADS), 0,
+                       st, m.tab.p, m.G, n_pad, m.n_mat, m.err.p);
+  hipLaunchKernelGGL(k_copy_out_multi, dim3(nblocks(m.max_n, 256), nm), dim3(256), 0, st,
+                     m.tab.p);
+  GX_HIP(hipGetLastError());
+}
+
+// Raises if a multi-set solve since the last check timed out waiting for a block.
+void multi_solve_check(MultiSolve& m, hipStream_t st) {
+  if (!m.err.n) return;
+  int h = 0;
+  to_host(&h, m.err.p, 1, st);
+  if (h) {
+    zero(m.err, st);
+    throw Error(GX_EHIP, "banded solve: a work-group timed out waiting for a block");
+  }
 }
 
 // Raises if a multi-work-group solve since the last check timed out waiting for a block.

@@ -188,6 +188,28 @@ struct BandSet {
   DevBuf<double> mbuf;                         // the same for up to 32 right-hand sides
 };
 
+// Addresses of one matrix in a solve over the factors of several band sets in one launch
+struct BandPtrs {
+  const void* v;                               // factor (precision of the launch)
+  const void* dinv;                            // inverse 64x64 diagonal blocks
+  double* x;                                   // right-hand side in, solution out
+  double* y;                                   // forward-solution scratch (64-aligned length)
+  double* z;                                   // backward-solution scratch
+  int64_t n, B;                                // rows, half-bandwidth
+};
+
+// The single-right-hand-side solves of several band sets of one precision on one device in
+// one launch (the subdomain solves of many independent systems advanced in lockstep)
+struct MultiSolve {
+  std::vector<BandSet*> sets;                  // in table order
+  std::vector<BandPtrs> host;
+  DevBuf<BandPtrs> tab;
+  DevBuf<int> err;                             // time-out word of the launches
+  int n_mat = 0, G = 1;
+  int64_t max_n = 0;
+  bool fp32 = false;
+};
+
 struct Schwarz {
   int n_sub = 0, W = 0;                        // subdomains, 64-bit mask words
   DevBuf<uint64_t> elem_mask, node_or, node_and;
@@ -283,6 +305,13 @@ void band_solve_check(BandSet& bs, hipStream_t st);
 void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, int ncol = 1,
                 const int32_t* active = nullptr);
 double band_solve_bytes(const BandSet& bs, int ncol, const int32_t* active_host = nullptr);
+void multi_solve_plan(MultiSolve& m, const std::vector<BandSet*>& sets,
+                      const std::vector<double*>& x, const std::vector<const int64_t*>& xoff,
+                      hipStream_t st);
+void multi_solve(MultiSolve& m, hipStream_t st);
+void multi_solve_check(MultiSolve& m, hipStream_t st);
+void precond_local(gx_ctx* c, const double* r);
+void precond_finish(gx_ctx* c, const double* r, double* z);
 void laminate_velocity(const gx_laminate* lam, int param, double* xd, hipStream_t st);
 void laminate_region(const gx_laminate* lam, uint8_t* mask, hipStream_t st);
 void laminate_sizes(const gx_laminate* lam, int64_t* n_nodes, int64_t* n_elems);

@@ -5,6 +5,7 @@
 // them in a fixed order); alpha and beta are formed on the device, so the host reads one
 // scalar pair per iteration for the stopping test ||r|| <= rtol ||b||.
 #include <cmath>
+#include <memory>
 
 #include "gx_internal.h"
 
@@ -116,14 +117,19 @@ struct PcgRun {
   double nb = 0.0, rel = 0.0;
   int it = 0;
   bool started = false, done = false, init_pending = true;
+  // split: the subdomain solves are left to the caller (a multi-set launch), which then
+  // calls pcg_next_post; post_pending / post_first record that such a step is open
+  bool split = false, post_pending = false, post_first = false;
   gx_status st = GX_OK;
   std::string msg;
   EventPair ev_spmv, ev_pre;
   double t_spmv = 0.0, t_pre = 0.0;
   hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipEvent_t ready = nullptr;                      // local right-hand sides formed (split)
   ~PcgRun() {
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
+    if (ready) (void)hipEventDestroy(ready);
   }
 };
 
@@ -178,13 +184,14 @@ static void pcg_begin(PcgRun& R) {
   R.started = true;
 }
 
-// precond, beta, new direction, then the next body
-static void pcg_next(PcgRun& R, bool first) {
+// after the subdomain solves: the rest of the preconditioner, beta, new direction, then
+// the next body
+static void pcg_next_post(PcgRun& R, bool first) {
   gx_ctx* c = R.c;
   hipStream_t s = c->stream;
   const int64_t n = 3 * c->n_nodes;
-  GX_HIP(hipEventRecord(R.ev_pre.a, s));
-  precond_apply(c, c->r.p, c->z.p);
+  R.post_pending = false;
+  precond_finish(c, c->r.p, c->z.p);
   GX_HIP(hipEventRecord(R.ev_pre.b, s));
   if (first) {
     dot(c, c->r.p, c->z.p, S_RZ, 0);
@@ -195,6 +202,20 @@ static void pcg_next(PcgRun& R, bool first) {
                        c->p.p);
   }
   pcg_body(R);
+}
+
+// precond (local right-hand sides, subdomain solves unless split), then pcg_next_post
+static void pcg_next(PcgRun& R, bool first) {
+  gx_ctx* c = R.c;
+  GX_HIP(hipEventRecord(R.ev_pre.a, c->stream));
+  precond_local(c, c->r.p);
+  if (R.split) {
+    R.post_pending = true;
+    R.post_first = first;
+    return;
+  }
+  band_solve(c->sw.A, c->sw.d_xoff.p, c->sw.wr64.p, c->stream);
+  pcg_next_post(R, first);
 }
 
 // the scalars of the last step are on the host (the stream has been synchronised)
@@ -314,23 +335,27 @@ gx_status gx_pcg_solve_batch(int32_t n, gx_ctx* const* ctxs, const double* const
                              double* const* x, double rtol, int32_t maxit, int32_t* iters_out,
                              double* relres_out, int32_t* status_out) {
   if (n < 1 || !ctxs || !b || !x) return GX_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return GX_EINVAL;
+    for (int k = 0; k < i; ++k)
+      if (ctxs[k] == ctxs[i]) return GX_EINVAL;    // one system per context
+  }
   std::vector<PcgRun> runs(n);
   std::vector<gx_status> st(n, GX_OK);
   auto fail = [&](int i, gx_status code, const char* what) {
-    st[i] = code;
+    if (st[i] == GX_OK) st[i] = code;
     ctxs[i]->err = what;
     runs[i].done = true;
+    runs[i].post_pending = false;
   };
-  for (int i = 0; i < n; ++i)
-    if (!ctxs[i]) return GX_EINVAL;
-  // the solves of all systems run concurrently: each context's band solves get an equal
-  // share of the machine (work-group counts chosen again), restored afterwards
+  // the coarse solves of all systems run concurrently: each context's gets an equal share of
+  // the machine (work-group counts chosen again), restored afterwards
   auto set_share = [&](int share) {
-    for (int i = 0; i < n; ++i)
-      for (BandSet* bs : {&ctxs[i]->sw.A, &ctxs[i]->sw.C}) {
-        bs->share = share;
-        bs->solve_groups[0] = bs->solve_groups[1] = 0;
-      }
+    for (int i = 0; i < n; ++i) {
+      BandSet& bs = ctxs[i]->sw.C;
+      bs.share = share;
+      bs.solve_groups[0] = bs.solve_groups[1] = 0;
+    }
   };
   set_share(n);
   for (int i = 0; i < n; ++i) {
@@ -339,17 +364,114 @@ gx_status gx_pcg_solve_batch(int32_t n, gx_ctx* const* ctxs, const double* const
     runs[i].x = x[i];
     runs[i].rtol = rtol;
     runs[i].maxit = maxit;
+    runs[i].split = true;
     try {
       ctxs[i]->err.clear();
       GX_HIP(hipSetDevice(ctxs[i]->device));
+      GX_HIP(hipEventCreateWithFlags(&runs[i].ready, hipEventDisableTiming));
       pcg_begin(runs[i]);
     } catch (const Error& e) {
       fail(i, e.code, e.what());
     }
   }
+  // The subdomain solves of every system that goes on, one launch per device and factor
+  // precision.  The launches of a device go one after another on a stream of their own,
+  // which waits for the systems' local right-hand sides; every system's stream then waits
+  // for all of them, so each launch has the device to itself (the waits between its
+  // work-groups need them all resident).  A table is planned again when its set of systems
+  // changes.
+  struct Lane {
+    int dev = 0;
+    hipStream_t st = nullptr;
+    hipEvent_t done = nullptr;
+  };
+  struct Joint {
+    int dev = 0;
+    bool fp32 = false;
+    std::vector<int> members;
+    MultiSolve ms;
+  };
+  std::vector<Lane> lanes;
+  std::vector<std::unique_ptr<Joint>> joints;
+  std::vector<char> joined(n, 0);
+  auto lane_of = [&](int dev) -> Lane& {
+    for (Lane& l : lanes)
+      if (l.dev == dev) return l;
+    Lane l;
+    l.dev = dev;
+    GX_HIP(hipSetDevice(dev));
+    GX_HIP(hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking));
+    if (hipEventCreateWithFlags(&l.done, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(l.st);
+      throw Error(GX_EHIP, "hipEventCreateWithFlags failed");
+    }
+    lanes.push_back(l);
+    return lanes.back();
+  };
+  auto joint_solves = [&](const std::vector<int>& cont) {
+    for (auto& j : joints) j->members.clear();
+    std::vector<Joint*> used;
+    for (int i : cont) {
+      const int dev = ctxs[i]->device;
+      const bool f32 = ctxs[i]->sw.A.fp32;
+      Joint* J = nullptr;
+      for (auto& j : joints)
+        if (j->dev == dev && j->fp32 == f32) J = j.get();
+      if (!J) {
+        joints.push_back(std::make_unique<Joint>());
+        J = joints.back().get();
+        J->dev = dev;
+        J->fp32 = f32;
+      }
+      if (J->members.empty()) used.push_back(J);
+      J->members.push_back(i);
+    }
+    for (Joint* J : used) {
+      try {
+        GX_HIP(hipSetDevice(J->dev));
+        hipStream_t ls = lane_of(J->dev).st;
+        bool same = J->ms.sets.size() == J->members.size();
+        for (size_t k = 0; same && k < J->members.size(); ++k)
+          same = J->ms.sets[k] == &ctxs[J->members[k]]->sw.A;
+        if (!same) {
+          std::vector<BandSet*> sets;
+          std::vector<double*> xs;
+          std::vector<const int64_t*> xo;
+          for (int i : J->members) {
+            Schwarz& sw = ctxs[i]->sw;
+            sets.push_back(&sw.A);
+            xs.push_back(sw.wr64.p);
+            xo.push_back(sw.xoff.data());
+          }
+          multi_solve_plan(J->ms, sets, xs, xo, ls);
+        }
+        for (int i : J->members) {
+          GX_HIP(hipEventRecord(runs[i].ready, ctxs[i]->stream));
+          GX_HIP(hipStreamWaitEvent(ls, runs[i].ready, 0));
+          joined[i] = 1;
+        }
+        multi_solve(J->ms, ls);
+      } catch (const Error& e) {
+        for (int i : J->members) fail(i, e.code, e.what());
+      }
+    }
+    for (Lane& l : lanes) {
+      try {
+        GX_HIP(hipSetDevice(l.dev));
+        GX_HIP(hipEventRecord(l.done, l.st));
+        for (int i : cont)
+          if (!runs[i].done && ctxs[i]->device == l.dev)
+            GX_HIP(hipStreamWaitEvent(ctxs[i]->stream, l.done, 0));
+      } catch (const Error& e) {
+        for (int i : cont)
+          if (ctxs[i]->device == l.dev) fail(i, e.code, e.what());
+      }
+    }
+  };
   // lockstep: one synchronisation of every active stream per iteration
   for (;;) {
     bool any = false;
+    std::vector<int> cont;
     for (int i = 0; i < n; ++i) {
       if (runs[i].done) continue;
       any = true;
@@ -357,11 +479,41 @@ gx_status gx_pcg_solve_batch(int32_t n, gx_ctx* const* ctxs, const double* const
         GX_HIP(hipSetDevice(ctxs[i]->device));
         GX_HIP(hipStreamSynchronize(ctxs[i]->stream));
         pcg_advance(runs[i]);
+        if (runs[i].post_pending) cont.push_back(i);
       } catch (const Error& e) {
         fail(i, e.code, e.what());
       }
     }
     if (!any) break;
+    if (cont.empty()) continue;
+    joint_solves(cont);
+    for (int i : cont) {
+      if (runs[i].done) continue;
+      try {
+        GX_HIP(hipSetDevice(ctxs[i]->device));
+        pcg_next_post(runs[i], runs[i].post_first);
+      } catch (const Error& e) {
+        fail(i, e.code, e.what());
+      }
+    }
+  }
+  for (auto& J : joints) {
+    try {
+      GX_HIP(hipSetDevice(J->dev));
+      hipStream_t ls = lane_of(J->dev).st;
+      GX_HIP(hipStreamSynchronize(ls));
+      multi_solve_check(J->ms, ls);
+    } catch (const Error& e) {
+      for (int i = 0; i < n; ++i)
+        if (joined[i] && ctxs[i]->device == J->dev && ctxs[i]->sw.A.fp32 == J->fp32)
+          fail(i, e.code, e.what());
+    }
+  }
+  joints.clear();                                  // tables freed before their streams go
+  for (Lane& l : lanes) {
+    (void)hipSetDevice(l.dev);
+    (void)hipEventDestroy(l.done);
+    (void)hipStreamDestroy(l.st);
   }
   gx_status first = GX_OK;
   for (int i = 0; i < n; ++i) {
@@ -369,7 +521,7 @@ gx_status gx_pcg_solve_batch(int32_t n, gx_ctx* const* ctxs, const double* const
       if (runs[i].started) pcg_end(runs[i], iters_out ? iters_out + i : nullptr,
                                    relres_out ? relres_out + i : nullptr);
     } catch (const Error& e) {
-      if (st[i] == GX_OK) fail(i, e.code, e.what());
+      fail(i, e.code, e.what());
     }
     if (st[i] == GX_OK) st[i] = runs[i].st;
     if (status_out) status_out[i] = st[i];

@@ -417,18 +417,30 @@ __global__ void k_combine(const uint64_t* nand, int W, int64_t N, const int32_t*
   z[d] = fixed[d] ? 0.0 : acc + crs;
 }
 
-void precond_apply(gx_ctx* c, const double* r, double* z) {
+static int64_t max_interior(const Schwarz& sw) {
+  int64_t maxI = 0;
+  for (int j = 0; j < sw.n_sub; ++j) maxI = std::max(maxI, sw.nI[j]);
+  return maxI;
+}
+
+// The local right-hand sides R_j r (scaled by the diagonal for FP32 factors).
+void precond_local(gx_ctx* c, const double* r) {
+  Schwarz& sw = c->sw;
+  const int64_t maxI = max_interior(sw);
+  const double* dg = sw.precision == GX_MIXED ? sw.dg.p : nullptr;
+  hipLaunchKernelGGL(k_gather_local<double>, dim3(nblocks(3 * maxI, 256), sw.n_sub),
+                     dim3(256), 0, c->stream, r, dg, sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p,
+                     sw.d_xoff.p, sw.wr64.p);
+}
+
+// After the local solves: the coarse correction and z = sum_j R_j^T D_j (local solution)
+// plus the coarse part.
+void precond_finish(gx_ctx* c, const double* r, double* z) {
   Schwarz& sw = c->sw;
   hipStream_t s = c->stream;
   const int64_t N = c->n_nodes;
-  int64_t maxI = 0;
-  for (int j = 0; j < sw.n_sub; ++j) maxI = std::max(maxI, sw.nI[j]);
-  const bool fp32 = sw.precision == GX_MIXED;
-  const double* dg = fp32 ? sw.dg.p : nullptr;
-  hipLaunchKernelGGL(k_gather_local<double>, dim3(nblocks(3 * maxI, 256), sw.n_sub),
-                     dim3(256), 0, s, r, dg, sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p,
-                     sw.d_xoff.p, sw.wr64.p);
-  band_solve(sw.A, sw.d_xoff.p, sw.wr64.p, s);
+  const int64_t maxI = max_interior(sw);
+  const double* dg = sw.precision == GX_MIXED ? sw.dg.p : nullptr;
   const bool two = sw.two_level && sw.n0 > 0;
   if (two) {
     const int64_t nch = (3 * maxI + RCH - 1) / RCH;
@@ -444,6 +456,12 @@ void precond_apply(gx_ctx* c, const double* r, double* z) {
                      sw.d_z_off.p, sw.d_nev.p, sw.d_c_off.p, sw.d_nI.p,
                      two ? sw.Z.p : nullptr, sw.y0.p, c->fixed.p, z);
   GX_HIP(hipGetLastError());
+}
+
+void precond_apply(gx_ctx* c, const double* r, double* z) {
+  precond_local(c, r);
+  band_solve(c->sw.A, c->sw.d_xoff.p, c->sw.wr64.p, c->stream);
+  precond_finish(c, r, z);
 }
 
 }  // namespace gx
