@@ -24,11 +24,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Solve time per 1M DOFs at rtol 1e-8 (FP64 vs mixed); CG iters; SpMV GB/s"
 HBM_PEAK_GBS = 8000.0
-# HBM bytes of one PCG subdomain band solve on this workload (FP64 factors), from the
-# FETCH_SIZE / WRITE_SIZE counters of `bench.py --traffic-probe` scaled by a 4 GiB copy;
-# None for the FP32 factors, whose counters were not taken.  Valid for the solve kernel as
-# it stands: retake the counters when it changes.
-SOLVE_TRAFFIC_BYTES = {"fp64": 158.5e9, "mixed": None}
+# HBM bytes of one PCG subdomain band solve on this workload (FP64 or FP32 factors), from
+# the FETCH_SIZE / WRITE_SIZE counters of `bench.py --traffic-probe [--precision mixed]`
+# scaled by a 4 GiB copy.  Valid for the solve kernel as it stands: retake the counters
+# when it changes.
+SOLVE_TRAFFIC_BYTES = {"fp64": 158.5e9, "mixed": 83.0e9}
 
 
 def run_step(gx, torch, cfg, precision):
@@ -73,7 +73,10 @@ def batch_sweep(gx, torch, workloads, args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch = gx.Batch(cfgs, precision=prec)
-    batch.setup(progress=lambda i, n: print(f"# set up {i + 1}/{n}", file=sys.stderr,
+    print(f"# {len(cfgs)} samples meshed and assembled; set-up, {args.concurrent} at a time",
+          file=sys.stderr, flush=True)
+    batch.setup(concurrent=args.concurrent,
+                progress=lambda i, n: print(f"# set up {i + 1}/{n}", file=sys.stderr,
                                             flush=True))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -81,12 +84,17 @@ def batch_sweep(gx, torch, workloads, args):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ndof = [3 * s.mesh["n_nodes"] for s in batch.solvers]
+    entries = sum(s.stats()["interior_band_entries"] for s in batch.solvers)
+    w = 8 if args.precision == "fp64" else 4
     line = {"metric": "batched sweep: samples per second (mesh, assembly, set-up and PCG)",
             "value": len(cfgs) / (t2 - t0), "unit": "samples/s", "n_gpus": 1,
             "higher_is_better": True, "data": "synthetic", "dtype": args.precision,
             "config": {"workload": f"{len(cfgs)} seeded wrinkled L-section samples",
                        "dofs_min": min(ndof), "dofs_max": max(ndof), "dofs_total": sum(ndof)},
             "setup_s": t1 - t0, "solve_s": t2 - t1, "pcg_solves_per_s": len(cfgs) / (t2 - t1),
+            "concurrent_setups": args.concurrent, "interior_band_entries": entries,
+            # factor read once per sweep by the joint subdomain solve, all samples active
+            "joint_solve_factor_bytes": 2 * w * entries,
             "iters": it.tolist(), "all_converged": bool(np.all(st == 0))}
     batch.close()
     print(json.dumps(line), flush=True)
@@ -122,6 +130,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead: the seeded sweep of wrinkled L-sections, this many samples")
+    ap.add_argument("--concurrent", type=int, default=4,
+                    help="with --batch: set-ups run at a time")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="instead: set up the workload, then launch one plain copy of "
                          "COPY_BYTES and one subdomain band solve (for hardware counters)")

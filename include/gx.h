@@ -208,6 +208,20 @@ typedef struct {
 gx_status gx_geneo_setup(gx_ctx* ctx, const gx_geneo_opts* opts, int32_t* nev_out,
                          int64_t* n0_out);
 
+/* Set-up of many contexts (extension: many laminates at once): gx_geneo_setup(ctxs[i],
+ * opts[i], nev_out[i], n0_out + i) for every i, up to `concurrent` of them at a time on
+ * host threads of the library, each context on its own stream.  While they run, each
+ * context's multi-work-group launches take 3/4 of the device's resident capacity divided
+ * by min(concurrent, n), so that concurrent launches stay resident together.  Each
+ * context appears once and its stream is not used by the caller meanwhile.  nev_out
+ * (host array of n host pointers, each NULL or [opts[i]->n_sub]), n0_out and status_out
+ * (host [n]) may be NULL.  Returns GX_EINVAL for bad arguments (nothing run), else GX_OK
+ * if every set-up succeeded, else the first non-OK status (each context's gx_last_error
+ * explains its own). */
+gx_status gx_geneo_setup_batch(int32_t n, gx_ctx* const* ctxs, const gx_geneo_opts* const* opts,
+                               int32_t concurrent, int32_t* const* nev_out, int64_t* n0_out,
+                               int32_t* status_out);
+
 /* Per-subdomain sizes: interior DOFs, Neumann DOFs, half bandwidth of the interior factor
  * (host arrays [n_sub], any may be NULL). */
 gx_status gx_subdomain_info(gx_ctx* ctx, int64_t* n_interior, int64_t* n_neumann,

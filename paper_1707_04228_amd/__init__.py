@@ -104,6 +104,9 @@ for _name, _args in [("gx_geneo_setup", [vp, C.POINTER(GeneoOpts), i32p, i64p]),
                      ("gx_pcg_solve_batch", [C.c_int32, C.POINTER(vp), C.POINTER(vp),
                                              C.POINTER(vp), C.c_double, C.c_int32, i32p, f64p,
                                              i32p]),
+                     ("gx_geneo_setup_batch", [C.c_int32, C.POINTER(vp),
+                                               C.POINTER(C.POINTER(GeneoOpts)), C.c_int32,
+                                               C.POINTER(i32p), i64p, i32p]),
                      ("gx_adjoint", [vp, C.POINTER(Laminate), C.c_int32, vp, C.c_double,
                                      C.c_int32, f64p, f64p, i32p])]:
     if hasattr(lib, _name):
@@ -114,7 +117,7 @@ EXPORTS = ["gx_create", "gx_destroy", "gx_last_error", "gx_version", "gx_laminat
            "gx_assemble", "gx_matrix_info", "gx_matrix_copy", "gx_spmv", "gx_geneo_setup",
            "gx_subdomain_info", "gx_geneo_eigenvalues", "gx_precond_apply", "gx_pcg_solve",
            "gx_phase_times", "gx_kernel_time", "gx_stats", "gx_tune", "gx_band_factor_solve",
-           "gx_objective", "gx_adjoint", "gx_pcg_solve_batch"]
+           "gx_objective", "gx_adjoint", "gx_pcg_solve_batch", "gx_geneo_setup_batch"]
 
 
 class GxError(RuntimeError):
@@ -506,19 +509,37 @@ class Batch:
             self.solvers.append(s)
         self.precision = precision
 
-    def setup(self, progress=None):
-        """Decomposition, GenEO coarse spaces and factors of every laminate; progress(i, n)
-        is called after each."""
-        out = []
-        for i, (cfg, s) in enumerate(zip(self.cfgs, self.solvers)):
+    def setup(self, progress=None, concurrent=4):
+        """Decomposition, GenEO coarse spaces and factors of every laminate, up to
+        `concurrent` set-ups at a time (gx_geneo_setup_batch); progress(n - 1, n) is called
+        when all are done.  Returns [(nev per subdomain, n0)] per laminate."""
+        n = len(self.solvers)
+        parts, opts = [], []
+        for cfg, s in zip(self.cfgs, self.solvers):
             sv = cfg["solver"]
-            part = s.partition(cfg, sv["px"], sv["py"])
-            out.append(s.geneo_setup(part, sv["px"] * sv["py"], overlap=sv["overlap"],
-                                     tau=sv["tau"] or 0.1, nev=sv["nev"] or 0,
-                                     nev_max=sv["nev_max"], precision=self.precision))
-            if progress:
-                progress(i, len(self.solvers))
-        return out
+            with self.torch.cuda.stream(s.stream):
+                part = s.partition(cfg, sv["px"], sv["py"])
+            parts.append(part)
+            opts.append(GeneoOpts(sv["px"] * sv["py"], _ptr(part), sv["overlap"],
+                                  sv["tau"] or 0.1, sv["nev"] or 0, sv["nev_max"],
+                                  self.precision, 1, None, 0.0, 0))
+        nevs = [np.zeros(o.n_sub, dtype=np.int32) for o in opts]
+        n0 = np.zeros(n, dtype=np.int64)
+        st = np.zeros(n, dtype=np.int32)
+        H = (vp * n)(*[s.h for s in self.solvers])
+        O = (C.POINTER(GeneoOpts) * n)(*[C.pointer(o) for o in opts])
+        NV = (i32p * n)(*[a.ctypes.data_as(i32p) for a in nevs])
+        code = lib.gx_geneo_setup_batch(n, H, O, int(concurrent), NV, n0.ctypes.data_as(i64p),
+                                        st.ctypes.data_as(i32p))
+        if code == GX_EINVAL and not st.any():
+            raise GxError(code, "gx_geneo_setup_batch: bad arguments")
+        for k, s in enumerate(self.solvers):
+            if st[k] != GX_OK:
+                raise GxError(int(st[k]), f"laminate {k}: " + lib.gx_last_error(s.h).decode())
+            s.nev, s.n0, s.n_sub = nevs[k], int(n0[k]), opts[k].n_sub
+        if progress:
+            progress(n - 1, n)
+        return [(nevs[k], int(n0[k])) for k in range(n)]
 
     def solve(self, rtol=1e-8, maxit=2000):
         """x_i for every laminate; (list of x, iterations, relative residuals, statuses)."""

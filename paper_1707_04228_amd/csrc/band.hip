@@ -338,11 +338,10 @@ void band_factor(BandSet& bs, hipStream_t st, const char* what) {
 // G work-groups share a matrix: block k belongs to work-group k mod G in the forward sweep
 // and to (nblk - 1 - k) mod G in the backward sweep.  A work-group first adds the
 // contributions of the blocks that are complete by construction (its own previous block
-// and everything before it), then waits - bounded spin, acquire - for the predecessor
-// block (which waited for its own predecessor, so all earlier blocks are complete), adds
-// the at most G - 1 blocks that were in flight, applies the inverse diagonal block and
-// publishes the block with a release store of the launch epoch.  A timed-out wait raises
-// err and proceeds, so every wave always reaches the end of the kernel.
+// and everything before it), then takes the at most G - 1 blocks still in flight from the
+// other work-groups (bounded polls of their solutions, below), applies the inverse
+// diagonal block and hands its block on.  A timed-out poll raises the launch's error word
+// and proceeds, so every wave always reaches the end of the kernel.
 constexpr int SW = SOLVE_THREADS / 64;           // waves per work-group (8)
 constexpr int RPW = SB / SW;                      // forward rows per wave (8)
 constexpr int GMAX = 4;                           // work-groups per matrix, 1-RHS solve
@@ -350,50 +349,6 @@ constexpr int DL = SB * SB / SOLVE_THREADS;       // inverse-block entries per t
 static_assert(DL == RPW, "the inverse-block products reuse the 8-row lane reduction");
 constexpr int64_t SPIN_LIMIT = (int64_t)1 << 22;
 constexpr int64_t BAND_PAD = 1024;               // trailing entries of a band allocation
-
-// Once any wait of the launch has timed out, every later wait gives up at once, so a
-// broken pipeline costs one time-out, not one per block.
-__device__ inline void wait_flag(const int* f, int epoch, int* err) {
-  if (threadIdx.x == 0) {
-    int64_t spins = 0;
-    while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-      if ((++spins & 255) == 0 &&
-          (spins > SPIN_LIMIT || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-        atomicOr(err, 2);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(2);
-    }
-  }
-  __syncthreads();
-}
-
-// Waits until the cnt consecutive flags f[0 .. cnt) all carry the launch epoch: wave 0
-// polls them together (lane i reads flag i, cnt <= 64), so all blocks in flight cost one
-// round trip per poll instead of one each.  Same time-out rule as wait_flag.
-__device__ inline void wait_flags(const int* f, int cnt, int epoch, int* err) {
-  if (threadIdx.x < 64) {
-    int64_t spins = 0;
-    for (;;) {
-      const bool ok = (int)threadIdx.x >= cnt ||
-                      __hip_atomic_load(f + threadIdx.x, __ATOMIC_ACQUIRE,
-                                        __HIP_MEMORY_SCOPE_AGENT) == epoch;
-      if (__all(ok)) break;
-      if ((++spins & 255) == 0 &&
-          (spins > SPIN_LIMIT ||
-           __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-        if (threadIdx.x == 0) atomicOr(err, 2);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(2);
-    }
-  }
-  __syncthreads();
-}
-
-__device__ inline void post_flag(int* f, int epoch) {
-  __hip_atomic_store(f, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Band entry (r, c) loaded from a clamped, always valid address; the caller masks entries
 // outside the band.  The loads are unconditional so that a wave issues all of them before
@@ -958,16 +913,14 @@ static int solve_groups(BandSet& bs, const void* kernel, int which) {
   return G;
 }
 
-static int* solve_flags(BandSet& bs, hipStream_t st, int64_t& nblk, int& n_pad) {
-  nblk = (bs.max_n + SB - 1) / SB;
+// The launch's error word (raised by a poll that timed out), zero until a check clears it
+static int* solve_err(BandSet& bs, hipStream_t st, int& n_pad) {
   n_pad = (bs.n_mat + 7) / 8 * 8;                  // all groups of a matrix on one XCD
-  if (bs.flags.n != (size_t)(2 * n_pad * nblk + 1)) {
-    bs.flags.alloc(2 * n_pad * nblk + 1);
-    zero(bs.flags, st);
-    bs.epoch = 0;
+  if (!bs.err.n) {
+    bs.err.alloc(1);
+    zero(bs.err, st);
   }
-  ++bs.epoch;
-  return bs.flags.p;
+  return bs.err.p;
 }
 
 __global__ void k_fill_mark(double* p, int64_t n) {
@@ -1017,10 +970,8 @@ static void launch_m(BandSet& bs, const BandArgs& a, const int64_t* d_xoff, doub
                      hipStream_t st, const int32_t* active) {
   const int G = bs.fp32 ? solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_m<float, M>), 1)
                         : solve_groups(bs, reinterpret_cast<const void*>(&k_band_solve_m<double, M>), 1);
-  int64_t nblk = 0;
   int n_pad = 0;
-  int* fl = solve_flags(bs, st, nblk, n_pad);
-  int* err = fl + 2 * n_pad * nblk;
+  int* err = solve_err(bs, st, n_pad);
   // y and z scratch of M columns: segments at yoff[j] * M rows (64-aligned row offsets)
   if (!bs.d_yoff.n) (void)solve1_scratch(bs, st);
   const int64_t rows = (int64_t)bs.ybuf.n / 2;     // padded rows of all matrices
@@ -1085,15 +1036,13 @@ void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, i
     return;
   }
   BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p};
-  int64_t nblk = 0;
   int n_pad = 0;
   if (ncol == 1 && !active) {
     const void* kf = bs.fp32 ? reinterpret_cast<const void*>(&k_band_solve_1<float, false>)
                    : bs.coarse ? reinterpret_cast<const void*>(&k_band_solve_1<double, true>)
                                : reinterpret_cast<const void*>(&k_band_solve_1<double, false>);
     const int G = solve_groups(bs, kf, 0);
-    int* fl = solve_flags(bs, st, nblk, n_pad);
-    int* err = fl + 2 * n_pad * nblk;
+    int* err = solve_err(bs, st, n_pad);
     double* y = solve1_scratch(bs, st);
     double* z = y + bs.ybuf.n / 2;
     if (bs.fp32)
@@ -1227,12 +1176,11 @@ void multi_solve_check(MultiSolve& m, hipStream_t st) {
 
 // Raises if a multi-work-group solve since the last check timed out waiting for a block.
 void band_solve_check(BandSet& bs, hipStream_t st) {
-  if (!bs.flags.n) return;
+  if (!bs.err.n) return;
   int h = 0;
-  to_host(&h, bs.flags.p + bs.flags.n - 1, 1, st);
+  to_host(&h, bs.err.p, 1, st);
   if (h) {
-    zero(bs.flags, st);
-    bs.epoch = 0;
+    zero(bs.err, st);
     throw Error(GX_EHIP, "banded solve: a work-group timed out waiting for a block");
   }
 }

@@ -14,6 +14,8 @@
 // With Y = M^-1 B X the M-products come for free (M Y = B X), so each iteration needs one
 // multi-column band solve, one B product, two Gram matrices and a small dense eigenproblem
 // (parallel cyclic Jacobi in LDS).  Eigen-residuals and the threshold test are FP64.
+#include <atomic>
+#include <thread>
 #include <cmath>
 
 #include "gx_internal.h"
@@ -806,6 +808,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   // residuals and threshold test stay FP64 (M Y is then formed explicitly)
   const bool fp32 = o->precision == GX_MIXED;
   BandSet Mb;
+  Mb.share = c->share;
   std::vector<int64_t> doff(n_sub + 1, 0);
   for (int j = 0; j < n_sub; ++j) doff[j + 1] = doff[j] + 3 * sw.nD[j];
   DevBuf<int64_t> d_doff(n_sub + 1);
@@ -1180,6 +1183,46 @@ gx_status gx_subdomain_info(gx_ctx* c, int64_t* ni, int64_t* nn, int64_t* hb) {
     if (hb) hb[j] = c->sw.A.B[j];
   }
   GX_API_END(c)
+}
+
+gx_status gx_geneo_setup_batch(int32_t n, gx_ctx* const* ctxs, const gx_geneo_opts* const* opts,
+                               int32_t concurrent, int32_t* const* nev_out, int64_t* n0_out,
+                               int32_t* status_out) {
+  if (n < 1 || !ctxs || !opts || concurrent < 1) return GX_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i] || !opts[i]) return GX_EINVAL;
+    for (int k = 0; k < i; ++k)
+      if (ctxs[k] == ctxs[i]) return GX_EINVAL;    // one set-up per context
+  }
+  const int T = std::min<int>(concurrent, n);
+  for (int i = 0; i < n; ++i) ctxs[i]->share = T;
+  std::vector<gx_status> st(n, GX_OK);
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= n) return;
+      st[i] = gx_geneo_setup(ctxs[i], opts[i], nev_out ? nev_out[i] : nullptr,
+                             n0_out ? n0_out + i : nullptr);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < T; ++t) {
+    try {
+      pool.emplace_back(work);
+    } catch (const std::exception&) {
+      break;                                       // fewer threads: the rest run below
+    }
+  }
+  work();
+  for (std::thread& th : pool) th.join();
+  gx_status first = GX_OK;
+  for (int i = 0; i < n; ++i) {
+    ctxs[i]->share = 1;
+    if (status_out) status_out[i] = st[i];
+    if (first == GX_OK) first = st[i];
+  }
+  return first;
 }
 
 gx_status gx_geneo_eigenvalues(gx_ctx* c, int32_t j, double* lam) {

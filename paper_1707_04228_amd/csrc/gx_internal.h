@@ -176,9 +176,8 @@ struct BandSet {
   int solve_groups[2] = {0, 0};                // work-groups per matrix: 1-RHS, m-RHS solve
   int force_groups[2] = {0, 0};                // requested (0: automatic, capped by residency)
   int share = 1;                               // contexts whose solves may run concurrently
-  DevBuf<int> flags;                           // block completion flags (+ error word)
+  DevBuf<int> err;                             // error word of the solves (poll time-out)
   bool coarse = false;                         // the coarse matrix (own solve kernel name)
-  int epoch = 0;
   // column panels of solves with more right-hand sides than one launch takes
   DevBuf<double> panel;
   DevBuf<int64_t> d_poff;
@@ -277,6 +276,9 @@ struct gx_ctx {
   double mrhs_ms = 0.0, mrhs_bytes = 0.0;
   int64_t mrhs_calls = 0;
   int tune[4] = {0, 0, 0, 0};                  // see gx_tune
+  // contexts set up at once on the device (gx_geneo_setup_batch): the set-up's
+  // multi-work-group launches take this share of the machine's resident capacity
+  int share = 1;
   // materials and loads of the last assembly (kept for the sensitivities)
   int32_t n_layers = 0;
   std::vector<double> eng;                     // 9 engineering constants per layer

@@ -7,6 +7,11 @@ each, per-laminate convergence).
   whose work-group count per matrix differs from the lone solve's, so the band sums are
   split differently: rounding);
 * a context listed twice is refused (GX_EINVAL);
+* set-ups run concurrently (gx_geneo_setup_batch, three at a time) keep the modes and
+  eigenvalues of one-at-a-time set-ups (eigenvalues within 1e-8 relative: the concurrent
+  eigensolver block solves run on fewer work-groups, which changes rounding only), and
+  the PCG on them takes the same iterations (within one) to the same solution; a set-up
+  that fails is reported for its own laminate while the others complete;
 * laminates of different size converge after different iteration counts and leave the
   batch independently;
 * the work-group autotuner times its candidates and keeps the fastest; the solve after
@@ -83,6 +88,56 @@ def test_batch_refuses_a_context_twice():
                                      rr.ctypes.data_as(C.POINTER(C.c_double)),
                                      st.ctypes.data_as(C.POINTER(C.c_int32)))
     assert code == gx.GX_EINVAL
+    batch.close()
+
+
+def test_concurrent_setup_matches_one_at_a_time():
+    import paper_1707_04228_amd as gx
+    cfgs = _cfgs()
+    b1 = gx.Batch(cfgs)
+    r1 = b1.setup(concurrent=1)
+    b3 = gx.Batch(cfgs)
+    r3 = b3.setup(concurrent=3)
+    for k in range(len(cfgs)):
+        assert np.array_equal(r1[k][0], r3[k][0]) and r1[k][1] == r3[k][1]
+        for j in range(len(r1[k][0])):
+            l1 = b1.solvers[k].eigenvalues(j)
+            l3 = b3.solvers[k].eigenvalues(j)
+            assert np.abs(l1 - l3).max() <= 1e-8 * np.abs(l1).max()
+    x1, i1, _, s1 = b1.solve(rtol=1e-10, maxit=500)
+    x3, i3, _, s3 = b3.solve(rtol=1e-10, maxit=500)
+    assert np.all(s1 == gx.GX_OK) and np.all(s3 == gx.GX_OK)
+    assert np.all(np.abs(i1 - i3) <= 1)
+    for a, b in zip(x1, x3):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-9 * np.abs(a).max()
+    b1.close()
+    b3.close()
+
+
+def test_concurrent_setup_reports_a_failure_per_laminate():
+    import ctypes as C
+    import paper_1707_04228_amd as gx
+    cfgs = _cfgs()[:2]
+    batch = gx.Batch(cfgs)
+    parts, opts = [], []
+    for cfg, s in zip(cfgs, batch.solvers):
+        sv = cfg["solver"]
+        part = s.partition(cfg, sv["px"], sv["py"])
+        parts.append(part)
+        opts.append(gx.GeneoOpts(sv["px"] * sv["py"], part.data_ptr(), sv["overlap"], 0.1, 0,
+                                 32, gx.GX_FP64, 1, None, 0.0, 0))
+    opts[1].overlap = 0                             # invalid: refused by that set-up alone
+    vp = C.c_void_p
+    H = (vp * 2)(*[s.h for s in batch.solvers])
+    O = (C.POINTER(gx.GeneoOpts) * 2)(*[C.pointer(o) for o in opts])
+    st = np.full(2, -1, dtype=np.int32)
+    n0 = np.zeros(2, dtype=np.int64)
+    code = gx.lib.gx_geneo_setup_batch(2, H, O, 2, None, n0.ctypes.data_as(C.POINTER(C.c_int64)),
+                                       st.ctypes.data_as(C.POINTER(C.c_int32)))
+    assert code == gx.GX_EINVAL
+    assert st[0] == gx.GX_OK and st[1] == gx.GX_EINVAL and n0[0] > 0
+    assert "overlap" in gx.lib.gx_last_error(batch.solvers[1].h).decode()
     batch.close()
 
 
