@@ -3,29 +3,46 @@
 
 namespace gx {
 
+thread_local gx_ctx* tls_ctx = nullptr;
+
+CtxScope::CtxScope(gx_ctx* c) : prev(tls_ctx) { tls_ctx = c; }
+CtxScope::~CtxScope() { tls_ctx = prev; }
+
 namespace {
-constexpr size_t CACHE_MIN = (size_t)64 << 20;   // blocks this large are cached
+constexpr size_t CACHE_MIN = (size_t)64 << 20;   // large blocks: cached whoever frees them
+constexpr size_t SMALL_CAP = (size_t)1 << 30;    // small tagged blocks kept per device
 
 struct CachedBlock {
   int dev;
   size_t bytes;
   void* p;
+  const gx_ctx* owner;                           // context whose call released it, or null
 };
 
 std::mutex cache_mu;
 std::vector<CachedBlock> cache_blocks;
-std::vector<size_t> cache_bytes, cache_cap;          // per device
+std::vector<size_t> cache_bytes, cache_cap, small_bytes;   // per device
 
-size_t& cached_on(int dev) {
+void ensure_dev(int dev) {                         // caller holds cache_mu
   if ((int)cache_bytes.size() <= dev) {
     cache_bytes.resize(dev + 1, 0);
     cache_cap.resize(dev + 1, 0);
+    small_bytes.resize(dev + 1, 0);
   }
   if (!cache_cap[dev]) {
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess) cache_cap[dev] = tot / 2;
   }
-  return cache_bytes[dev];
+}
+
+void drop_block(size_t i) {                        // caller holds cache_mu; counters only
+  const CachedBlock& c = cache_blocks[i];
+  if (c.bytes >= CACHE_MIN)
+    cache_bytes[c.dev] -= c.bytes;
+  else
+    small_bytes[c.dev] -= c.bytes;
+  cache_blocks[i] = cache_blocks.back();
+  cache_blocks.pop_back();
 }
 
 void trim_cache(int dev) {                          // caller holds cache_mu
@@ -33,9 +50,7 @@ void trim_cache(int dev) {                          // caller holds cache_mu
   for (size_t i = 0; i < cache_blocks.size();) {
     if (cache_blocks[i].dev == dev) {
       (void)hipFree(cache_blocks[i].p);
-      cached_on(dev) -= cache_blocks[i].bytes;
-      cache_blocks[i] = cache_blocks.back();
-      cache_blocks.pop_back();
+      drop_block(i);
     } else {
       ++i;
     }
@@ -47,24 +62,34 @@ void* dev_alloc(size_t bytes, int* dev, hipError_t* err) {
   int d = 0;
   (void)hipGetDevice(&d);
   *dev = d;
-  if (bytes >= CACHE_MIN) {
+  const gx_ctx* me = tls_ctx && tls_ctx->device == d ? tls_ctx : nullptr;
+  const bool large = bytes >= CACHE_MIN;
+  if (large || me) {
     std::unique_lock<std::mutex> lk(cache_mu);
+    ensure_dev(d);
     int best = -1;
+    bool best_mine = false;
     for (int i = 0; i < (int)cache_blocks.size(); ++i) {
       const CachedBlock& c = cache_blocks[i];
-      if (c.dev == d && c.bytes >= bytes && c.bytes <= bytes + bytes / 8 + CACHE_MIN &&
-          (best < 0 || c.bytes < cache_blocks[best].bytes))
+      if (c.dev != d || c.bytes < bytes || (c.bytes >= CACHE_MIN) != large) continue;
+      if (large ? c.bytes > bytes + bytes / 8 + CACHE_MIN : c.bytes > 2 * bytes + 4096) continue;
+      const bool mine = me && c.owner == me;
+      if (!large && !mine) continue;               // small blocks: their own context only
+      if (best < 0 || (mine && !best_mine) ||
+          (mine == best_mine && c.bytes < cache_blocks[best].bytes)) {
         best = i;
+        best_mine = mine;
+      }
     }
     if (best >= 0) {
       void* p = cache_blocks[best].p;
-      cached_on(d) -= cache_blocks[best].bytes;
-      cache_blocks[best] = cache_blocks.back();
-      cache_blocks.pop_back();
+      drop_block(best);
       lk.unlock();
-      // the block is ours; its previous user's kernels must be done with it
-      *err = hipDeviceSynchronize();
-      if (*err != hipSuccess) return nullptr;
+      // a block of another context (or untagged) may still be in use by its kernels
+      if (!best_mine) {
+        *err = hipDeviceSynchronize();
+        if (*err != hipSuccess) return nullptr;
+      }
       // (released again, it is filed under the requested size, never more than it has)
       return p;
     }
@@ -84,16 +109,39 @@ void* dev_alloc(size_t bytes, int* dev, hipError_t* err) {
 
 void dev_free(void* p, size_t bytes, int dev) {
   if (!p) return;
-  if (bytes >= CACHE_MIN && dev >= 0) {
+  const gx_ctx* me = tls_ctx && tls_ctx->device == dev ? tls_ctx : nullptr;
+  if (dev >= 0) {
     std::lock_guard<std::mutex> lk(cache_mu);
-    size_t& c = cached_on(dev);
-    if (c + bytes <= cache_cap[dev]) {
-      cache_blocks.push_back({dev, bytes, p});
-      c += bytes;
+    ensure_dev(dev);
+    if (bytes >= CACHE_MIN) {
+      if (cache_bytes[dev] + bytes <= cache_cap[dev]) {
+        cache_blocks.push_back({dev, bytes, p, me});
+        cache_bytes[dev] += bytes;
+        return;
+      }
+    } else if (me && small_bytes[dev] + bytes <= SMALL_CAP) {
+      cache_blocks.push_back({dev, bytes, p, me});
+      small_bytes[dev] += bytes;
       return;
     }
   }
   (void)hipFree(p);
+}
+
+void dev_forget(const gx_ctx* c) {
+  std::lock_guard<std::mutex> lk(cache_mu);
+  for (size_t i = 0; i < cache_blocks.size();) {
+    CachedBlock& b = cache_blocks[i];
+    if (b.owner != c) {
+      ++i;
+    } else if (b.bytes >= CACHE_MIN) {
+      b.owner = nullptr;                           // stays cached, untagged
+      ++i;
+    } else {
+      (void)hipFree(b.p);
+      drop_block(i);
+    }
+  }
 }
 
 constexpr int SCAN_BS = 256;
@@ -217,6 +265,7 @@ void gx_destroy(gx_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  gx::dev_forget(c);                               // before the address can be reused
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

@@ -15,6 +15,8 @@
 
 #include "../../include/gx.h"
 
+struct gx_ctx;
+
 namespace gx {
 
 struct Error : std::runtime_error {
@@ -46,13 +48,29 @@ inline bool poison_alloc() {
   return on;
 }
 
-// Device memory for DevBuf.  Blocks of 64 MiB and more are kept after release in a
-// per-device cache (up to half the device's memory) and handed out again to a request of
-// the same size or slightly smaller, after a device synchronisation (so no kernel still
-// uses the block): the large band storages of repeated set-ups then cost no hipMalloc /
-// hipFree cycle.  A failed hipMalloc empties the cache of that device and retries.
+// Device memory for DevBuf, with a per-device cache of released blocks.  A block released
+// during an API call on a context is tagged with that context: all of a context's kernels
+// run on its one stream, so a later request of the same context takes the block back with
+// no synchronisation (stream order makes the reuse safe).  Blocks of 64 MiB and more are
+// cached whoever releases them (up to half the device's memory); another context (or an
+// untagged request) takes one only after a device synchronisation, so that no kernel still
+// uses it.  Smaller blocks are cached only with a tag (up to 1 GiB per device) and reused
+// only by their context: hipFree synchronises the whole device, which would serialise
+// contexts set up concurrently.  A failed hipMalloc empties the cache of that device and
+// retries.  dev_forget(ctx) drops a context's tags (its stream must be idle).
 void* dev_alloc(size_t bytes, int* dev, hipError_t* err);
 void dev_free(void* p, size_t bytes, int dev);
+void dev_forget(const gx_ctx* c);
+
+// The context of the API call running on this thread (tags released device blocks); set
+// for the duration of a call by GX_API_BEGIN.
+struct CtxScope {
+  gx_ctx* prev;
+  explicit CtxScope(gx_ctx* c);
+  ~CtxScope();
+  CtxScope(const CtxScope&) = delete;
+  CtxScope& operator=(const CtxScope&) = delete;
+};
 
 // Owning device buffer.
 template <class T>
@@ -89,7 +107,8 @@ struct DevBuf {
                                    " bytes failed: " + hipGetErrorString(e));
       }
       if (std::is_floating_point<T>::value && poison_alloc()) {
-        if (hipMemset(p, 0x7F, count * sizeof(T)) != hipSuccess ||
+        if (hipDeviceSynchronize() != hipSuccess ||
+            hipMemset(p, 0x7F, count * sizeof(T)) != hipSuccess ||
             hipDeviceSynchronize() != hipSuccess)
           throw Error(GX_EHIP, "poisoning a new buffer failed");
       }
@@ -353,6 +372,7 @@ struct Timer {
 #define GX_API_BEGIN(ctx)                                                             \
   if (!(ctx)) return GX_EINVAL;                                                       \
   try {                                                                               \
+    ::gx::CtxScope gx_scope_(ctx);                                                    \
     (ctx)->err.clear();                                                               \
     GX_HIP(hipSetDevice((ctx)->device));
 
