@@ -4,19 +4,25 @@
 namespace gx {
 
 thread_local gx_ctx* tls_ctx = nullptr;
+thread_local bool tls_idle = false;                // releases happen on an idle device
 
 CtxScope::CtxScope(gx_ctx* c) : prev(tls_ctx) { tls_ctx = c; }
 CtxScope::~CtxScope() { tls_ctx = prev; }
 
 namespace {
 constexpr size_t CACHE_MIN = (size_t)64 << 20;   // large blocks: cached whoever frees them
-constexpr size_t SMALL_CAP = (size_t)1 << 30;    // small tagged blocks kept per device
+constexpr size_t SMALL_CAP = (size_t)1 << 30;    // small blocks kept per device
 
+// What a cached block may still be used by: nothing (idle), the work its owner's stream
+// had queued when it was released (owner, ev), or unknown work (neither: a device
+// synchronisation before reuse).
 struct CachedBlock {
   int dev;
   size_t bytes;
   void* p;
-  const gx_ctx* owner;                           // context whose call released it, or null
+  const gx_ctx* owner;
+  hipEvent_t ev;                                 // recorded on owner's stream at release
+  bool idle;
 };
 
 std::mutex cache_mu;
@@ -49,12 +55,20 @@ void trim_cache(int dev) {                          // caller holds cache_mu
   (void)hipDeviceSynchronize();
   for (size_t i = 0; i < cache_blocks.size();) {
     if (cache_blocks[i].dev == dev) {
+      if (cache_blocks[i].ev) (void)hipEventDestroy(cache_blocks[i].ev);
       (void)hipFree(cache_blocks[i].p);
       drop_block(i);
     } else {
       ++i;
     }
   }
+}
+
+// preference among reusable blocks: 0 no wait (own stream, or idle), 1 a host wait for the
+// owner's event, 2 a device synchronisation
+int wait_class(const CachedBlock& c, const gx_ctx* me) {
+  if (c.idle || (me && c.owner == me)) return 0;
+  return c.ev ? 1 : 2;
 }
 }  // namespace
 
@@ -64,34 +78,39 @@ void* dev_alloc(size_t bytes, int* dev, hipError_t* err) {
   *dev = d;
   const gx_ctx* me = tls_ctx && tls_ctx->device == d ? tls_ctx : nullptr;
   const bool large = bytes >= CACHE_MIN;
-  if (large || me) {
+  {
     std::unique_lock<std::mutex> lk(cache_mu);
     ensure_dev(d);
-    int best = -1;
-    bool best_mine = false;
+    int best = -1, best_w = 3;
     for (int i = 0; i < (int)cache_blocks.size(); ++i) {
       const CachedBlock& c = cache_blocks[i];
       if (c.dev != d || c.bytes < bytes || (c.bytes >= CACHE_MIN) != large) continue;
       if (large ? c.bytes > bytes + bytes / 8 + CACHE_MIN : c.bytes > 2 * bytes + 4096) continue;
-      const bool mine = me && c.owner == me;
-      if (!large && !mine) continue;               // small blocks: their own context only
-      if (best < 0 || (mine && !best_mine) ||
-          (mine == best_mine && c.bytes < cache_blocks[best].bytes)) {
+      const int w = wait_class(c, me);
+      if (!large && w == 2) continue;              // small blocks: never a device sync
+      if (best < 0 || w < best_w || (w == best_w && c.bytes < cache_blocks[best].bytes)) {
         best = i;
-        best_mine = mine;
+        best_w = w;
       }
     }
     if (best >= 0) {
-      void* p = cache_blocks[best].p;
+      const CachedBlock c = cache_blocks[best];
       drop_block(best);
       lk.unlock();
-      // a block of another context (or untagged) may still be in use by its kernels
-      if (!best_mine) {
+      // the block's earlier users must be done with it before anything of ours runs
+      *err = hipSuccess;
+      if (best_w == 1)
+        *err = hipEventSynchronize(c.ev);          // the owner's work up to the release
+      else if (best_w == 2)
         *err = hipDeviceSynchronize();
-        if (*err != hipSuccess) return nullptr;
+      if (c.ev) (void)hipEventDestroy(c.ev);
+      if (*err != hipSuccess) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(c.p);
+        return nullptr;
       }
       // (released again, it is filed under the requested size, never more than it has)
-      return p;
+      return c.p;
     }
   }
   void* p = nullptr;
@@ -113,16 +132,28 @@ void dev_free(void* p, size_t bytes, int dev) {
   if (dev >= 0) {
     std::lock_guard<std::mutex> lk(cache_mu);
     ensure_dev(dev);
-    if (bytes >= CACHE_MIN) {
-      if (cache_bytes[dev] + bytes <= cache_cap[dev]) {
-        cache_blocks.push_back({dev, bytes, p, me});
-        cache_bytes[dev] += bytes;
+    const bool large = bytes >= CACHE_MIN;
+    const bool room = large ? cache_bytes[dev] + bytes <= cache_cap[dev]
+                            : (me || tls_idle) && small_bytes[dev] + bytes <= SMALL_CAP;
+    if (room) {
+      CachedBlock c{dev, bytes, p, nullptr, nullptr, tls_idle};
+      if (!tls_idle && me) {
+        // tag with the owner's stream position; without an event the block stays untagged
+        hipEvent_t ev = nullptr;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+          if (hipEventRecord(ev, me->stream) == hipSuccess) {
+            c.owner = me;
+            c.ev = ev;
+          } else {
+            (void)hipEventDestroy(ev);
+          }
+        }
+      }
+      if (large || c.owner || c.idle) {
+        cache_blocks.push_back(c);
+        (large ? cache_bytes : small_bytes)[dev] += bytes;
         return;
       }
-    } else if (me && small_bytes[dev] + bytes <= SMALL_CAP) {
-      cache_blocks.push_back({dev, bytes, p, me});
-      small_bytes[dev] += bytes;
-      return;
     }
   }
   (void)hipFree(p);
@@ -130,19 +161,17 @@ void dev_free(void* p, size_t bytes, int dev) {
 
 void dev_forget(const gx_ctx* c) {
   std::lock_guard<std::mutex> lk(cache_mu);
-  for (size_t i = 0; i < cache_blocks.size();) {
-    CachedBlock& b = cache_blocks[i];
-    if (b.owner != c) {
-      ++i;
-    } else if (b.bytes >= CACHE_MIN) {
-      b.owner = nullptr;                           // stays cached, untagged
-      ++i;
-    } else {
-      (void)hipFree(b.p);
-      drop_block(i);
+  for (CachedBlock& b : cache_blocks)
+    if (b.owner == c) {                            // its stream is idle: nothing pending
+      if (b.ev) (void)hipEventDestroy(b.ev);
+      b.ev = nullptr;
+      b.owner = nullptr;
+      b.idle = true;
     }
-  }
 }
+
+IdleScope::IdleScope() : prev(tls_idle) { tls_idle = true; }
+IdleScope::~IdleScope() { tls_idle = prev; }
 
 constexpr int SCAN_BS = 256;
 constexpr int SCAN_PT = 8;                       // items per thread
@@ -267,6 +296,7 @@ void gx_destroy(gx_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   gx::dev_forget(c);                               // before the address can be reused
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  gx::IdleScope idle;                              // its buffers are released unused
   delete c;
 }
 

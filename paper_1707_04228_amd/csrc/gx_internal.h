@@ -48,19 +48,29 @@ inline bool poison_alloc() {
   return on;
 }
 
-// Device memory for DevBuf, with a per-device cache of released blocks.  A block released
-// during an API call on a context is tagged with that context: all of a context's kernels
-// run on its one stream, so a later request of the same context takes the block back with
-// no synchronisation (stream order makes the reuse safe).  Blocks of 64 MiB and more are
-// cached whoever releases them (up to half the device's memory); another context (or an
-// untagged request) takes one only after a device synchronisation, so that no kernel still
-// uses it.  Smaller blocks are cached only with a tag (up to 1 GiB per device) and reused
-// only by their context: hipFree synchronises the whole device, which would serialise
-// contexts set up concurrently.  A failed hipMalloc empties the cache of that device and
-// retries.  dev_forget(ctx) drops a context's tags (its stream must be idle).
+// Device memory for DevBuf, with a per-device cache of released blocks (hipFree
+// synchronises the whole device, which would serialise contexts set up concurrently).  A
+// block released during an API call on a context is tagged with that context and an event
+// recorded on its stream: all of a context's kernels run on that one stream, so the same
+// context takes the block back with no wait, and any other request waits on the host for
+// the event (the owner's work up to the release, not the whole device).  Blocks released on an
+// idle device (IdleScope, a destroyed context) need no wait; blocks released outside any
+// context are reused after a device synchronisation.  Blocks of 64 MiB and more are cached
+// up to half the device's memory, smaller tagged or idle blocks up to 1 GiB per device.  A
+// failed hipMalloc empties the cache of that device and retries.  dev_forget(ctx) marks a
+// context's blocks idle (its stream must have been synchronised).
 void* dev_alloc(size_t bytes, int* dev, hipError_t* err);
 void dev_free(void* p, size_t bytes, int dev);
 void dev_forget(const gx_ctx* c);
+
+// While one exists on a thread, the blocks that thread releases are marked idle.
+struct IdleScope {
+  bool prev;
+  IdleScope();
+  ~IdleScope();
+  IdleScope(const IdleScope&) = delete;
+  IdleScope& operator=(const IdleScope&) = delete;
+};
 
 // The context of the API call running on this thread (tags released device blocks); set
 // for the duration of a call by GX_API_BEGIN.
