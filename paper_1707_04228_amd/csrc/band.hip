@@ -779,15 +779,22 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
       Yc[(idx / M) * MP + idx % M] = idx < yend ? fy[u] : 0.0;
     }
   };
-  // acc += A Yc over the 64-deep chunk for this wave's tile; A = Ab or Ab^T
+  // acc += A Yc over the 64-deep chunk for this wave's tile; A = Ab or Ab^T.  Even and odd
+  // 4-deep steps go to two accumulators, so consecutive matrix instructions do not wait
+  // for each other's result.
   auto mma = [&](bool trans, v4d& acc) {
     if (!tile) return;
-#pragma unroll 4
-    for (int ks = 0; ks < SB / 4; ++ks) {
-      const int kq = 4 * ks + lk;
-      const double av = trans ? Ab[kq][16 * rt + li] : Ab[16 * rt + li][kq];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Yc[kq * MP + 16 * ct + li], acc, 0, 0, 0);
+    v4d acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < SB / 4; ks += 2) {
+      const int kq0 = 4 * ks + lk, kq1 = kq0 + 4;
+      const double a0 = trans ? Ab[kq0][16 * rt + li] : Ab[16 * rt + li][kq0];
+      const double a1 = trans ? Ab[kq1][16 * rt + li] : Ab[16 * rt + li][kq1];
+      const double b0 = Yc[kq0 * MP + 16 * ct + li], b1 = Yc[kq1 * MP + 16 * ct + li];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
     }
+    acc += acc1;
   };
   // the chunks kk = first, first + step, .., last (step +1 or -1), two loads ahead
   auto sweep = [&](bool bwd, int64_t i0, int nb, int64_t first, int64_t count, int step,
@@ -816,10 +823,9 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
   // Yc <- rhs - accumulated sums (rows >= nb zero), Ab <- inverse block; the product with
   // it is the block's solution, handed over.  The right-hand side is x forward and the
   // block's forward solution (polled) backward.
-  auto finish = [&](bool bwd, int64_t i0, int nb, int64_t blk, const v4d& acc) {
-    T dd[AL];
-#pragma unroll
-    for (int u = 0; u < AL; ++u) dd[u] = dv[blk * SB * SB + threadIdx.x + MT * u];
+  // (dd: the block's inverse diagonal block, loaded before the sweep so that its latency
+  // stays off the chain of hand-overs)
+  auto finish = [&](bool bwd, int64_t i0, int nb, const T (&dd)[AL], const v4d& acc) {
     double bb[4];
     const int cc = min(16 * ct + li, M - 1);
     if (!bwd) {
@@ -870,9 +876,12 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
     const int64_t i0 = k * SB;
     const int nb = (int)min<int64_t>(SB, n - i0);
     const int64_t kfirst = max<int64_t>(i0 - B, 0) / SB;
+    T dd[AL];
+#pragma unroll
+    for (int u = 0; u < AL; ++u) dd[u] = dv[k * SB * SB + threadIdx.x + MT * u];
     v4d acc = {0.0, 0.0, 0.0, 0.0};
     sweep(false, i0, nb, kfirst, k - kfirst, 1, acc);
-    finish(false, i0, nb, k, acc);
+    finish(false, i0, nb, dd, acc);
   }
   // ---- backward: chunks from the far end of the band inwards
   for (int64_t t = g; t < nblk; t += G) {
@@ -880,9 +889,12 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
     const int64_t i0 = kb * SB;
     const int nb = (int)min<int64_t>(SB, n - i0);
     const int64_t klast = (min<int64_t>(n, i0 + nb + B) - 1) / SB;   // last row block
+    T dd[AL];
+#pragma unroll
+    for (int u = 0; u < AL; ++u) dd[u] = dv[kb * SB * SB + threadIdx.x + MT * u];
     v4d acc = {0.0, 0.0, 0.0, 0.0};
     sweep(true, i0, nb, klast, klast - kb, -1, acc);
-    finish(true, i0, nb, kb, acc);
+    finish(true, i0, nb, dd, acc);
   }
 }
 
