@@ -694,9 +694,10 @@ __global__ void k_copy_out_multi(const BandPtrs* tab) {
 // FP64 matrix cores: v_mfma_f64_16x16x4, lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16] and holds D[4 r + l / 16][l % 16] in accumulator register r; wave w
 // of the 8 owns row tile w mod 4 and column tile w / 4.  Chunks (64 x 64 of the band plus
-// the matching solution rows) are staged through LDS; the loads of the next two chunks are
-// in flight in two register sets while the current one is multiplied (the chunk loop is
-// unrolled by two so that each set has a name of its own).  Hand-over between work-groups
+// the matching solution rows) are staged through two LDS buffers in turn; the loads of the
+// next two chunks are in flight in two register sets while the current one is multiplied
+// (the chunk loop is unrolled by two so that each set and buffer has a name of its own).
+// Hand-over between work-groups
 // goes through marker-filled scratch solutions as in the single-right-hand-side solve
 // (forward into y, backward into z, z copied into x afterwards): solution entries are
 // loaded with agent-scope relaxed atomics, and a chunk is staged only once none of the
@@ -713,8 +714,8 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
   constexpr int NCT = (M + 15) / 16;              // column tiles (1 or 2)
   constexpr int MP = 16 * NCT;                    // LDS row stride (zero columns past M)
   constexpr int YL = SB * M / MT;                 // solution-chunk entries per thread
-  __shared__ double Ab[SB][SB + 1];               // band chunk; the inverse block later
-  __shared__ double Yc[SB * MP];                  // solution chunk
+  __shared__ double Ab[2][SB][SB + 1];            // band chunks (double buffer); buffer 0
+  __shared__ double Yc[2][SB * MP];               // holds the inverse block in finish
   const int g = blockIdx.x / n_pad, j = blockIdx.x % n_pad;
   if (j >= n_mat || g >= G) return;
   if (active && !active[j]) return;
@@ -732,8 +733,10 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
   const int li = lane & 15, lk = lane >> 4;
   const int64_t nblk = (n + SB - 1) / SB;
   if constexpr (MP > M)
-    for (int idx = threadIdx.x; idx < SB * (MP - M); idx += MT)
-      Yc[(idx / (MP - M)) * MP + M + idx % (MP - M)] = 0.0;
+    for (int idx = threadIdx.x; idx < 2 * SB * (MP - M); idx += MT) {
+      const int e = idx % (SB * (MP - M));
+      Yc[idx / (SB * (MP - M))][(e / (MP - M)) * MP + M + e % (MP - M)] = 0.0;
+    }
   // forward chunk kk of block i0: band rows i0.., columns 64 kk..; backward chunk kk:
   // band rows 64 kk.., columns i0..; both with solution rows 64 kk..  Thread t stages band
   // rows t / 64 + 8 u at column t % 64.
@@ -747,21 +750,30 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
 #pragma unroll
     for (int u = 0; u < YL; ++u) fy[u] = poll_load(xs + min<int64_t>(threadIdx.x + MT * u, yend - 1));
   };
-  auto stage = [&](bool bwd, int64_t i0, int nb, int64_t kk, const T (&fa)[AL],
+  auto stage = [&](int buf, bool bwd, int64_t i0, int nb, int64_t kk, const T (&fa)[AL],
                    double (&fy)[YL]) {
     {                                              // until every needed entry is handed over
       const int64_t yend = min<int64_t>((int64_t)SB * M, (n - kk * SB) * M);
       const double* xs = (bwd ? z : y) + kk * SB * M;
-      int64_t spins = 0;
-      for (;;) {
-        bool ok = true;
+      // the first test on the values already loaded is straight-line code, so the wait
+      // before it covers only this chunk's loads, not the prefetch of the next one; the
+      // polling loop is the slow path of a chunk still in flight
+      bool ok = true;
 #pragma unroll
-        for (int u = 0; u < YL; ++u)
-          ok = ok && (threadIdx.x + MT * u >= yend || !is_mark(fy[u]));
-        if (__all(ok) || poll_give_up(spins, err)) break;
+      for (int u = 0; u < YL; ++u) ok = ok && (threadIdx.x + MT * u >= yend || !is_mark(fy[u]));
+      if (!__all(ok)) {
+        int64_t spins = 0;
+        for (;;) {
+          if (poll_give_up(spins, err)) break;
 #pragma unroll
-        for (int u = 0; u < YL; ++u)
-          fy[u] = poll_load(xs + min<int64_t>(threadIdx.x + MT * u, yend - 1));
+          for (int u = 0; u < YL; ++u)
+            fy[u] = poll_load(xs + min<int64_t>(threadIdx.x + MT * u, yend - 1));
+          bool again = false;
+#pragma unroll
+          for (int u = 0; u < YL; ++u)
+            again = again || (threadIdx.x + MT * u < yend && is_mark(fy[u]));
+          if (!__any(again)) break;
+        }
       }
     }
     const int64_t r0 = (bwd ? kk * SB : i0) + wave;
@@ -770,54 +782,62 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
     for (int u = 0; u < AL; ++u) {
       const int64_t r = r0 + 8 * u;
       const bool in = r < n && c <= r && c >= r - B && (!bwd || lane < nb);
-      Ab[wave + 8 * u][lane] = in ? (double)fa[u] : 0.0;
+      Ab[buf][wave + 8 * u][lane] = in ? (double)fa[u] : 0.0;
     }
     const int64_t yend = min<int64_t>((int64_t)SB * M, (n - kk * SB) * M);   // rows < n
 #pragma unroll
     for (int u = 0; u < YL; ++u) {
       const int idx = threadIdx.x + MT * u;
-      Yc[(idx / M) * MP + idx % M] = idx < yend ? fy[u] : 0.0;
+      Yc[buf][(idx / M) * MP + idx % M] = idx < yend ? fy[u] : 0.0;
     }
   };
   // acc += A Yc over the 64-deep chunk for this wave's tile; A = Ab or Ab^T.  Even and odd
   // 4-deep steps go to two accumulators, so consecutive matrix instructions do not wait
   // for each other's result.
-  auto mma = [&](bool trans, v4d& acc) {
+  auto mma = [&](int buf, bool trans, v4d& acc) {
     if (!tile) return;
     v4d acc1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ks = 0; ks < SB / 4; ks += 2) {
       const int kq0 = 4 * ks + lk, kq1 = kq0 + 4;
-      const double a0 = trans ? Ab[kq0][16 * rt + li] : Ab[16 * rt + li][kq0];
-      const double a1 = trans ? Ab[kq1][16 * rt + li] : Ab[16 * rt + li][kq1];
-      const double b0 = Yc[kq0 * MP + 16 * ct + li], b1 = Yc[kq1 * MP + 16 * ct + li];
+      const double a0 = trans ? Ab[buf][kq0][16 * rt + li] : Ab[buf][16 * rt + li][kq0];
+      const double a1 = trans ? Ab[buf][kq1][16 * rt + li] : Ab[buf][16 * rt + li][kq1];
+      const double b0 = Yc[buf][kq0 * MP + 16 * ct + li];
+      const double b1 = Yc[buf][kq1 * MP + 16 * ct + li];
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
       acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
     }
     acc += acc1;
   };
-  // the chunks kk = first, first + step, .., last (step +1 or -1), two loads ahead
+  // the chunks kk = first, first + step, .., last (step +1 or -1): chunk q is multiplied
+  // from LDS buffer q % 2 while its loads were issued two chunks earlier; each wave stages
+  // chunk q + 1 into the other buffer right after its product of chunk q, so one barrier
+  // per chunk separates the staging of a buffer from its readers (the product two chunks
+  // back, and the next product)
   auto sweep = [&](bool bwd, int64_t i0, int nb, int64_t first, int64_t count, int step,
                    v4d& acc) {
+    if (count <= 0) return;
     T fa0[AL], fa1[AL];
     double fy0[YL], fy1[YL];
-    auto get = [&](int64_t q, T (&fa)[AL], double (&fy)[YL]) {
-      fetch(bwd, i0, first + step * q, fa, fy);
-    };
-    if (count > 0) get(0, fa0, fy0);
-    if (count > 1) get(1, fa1, fy1);
+    // chunk q, clamped to the last one: every prefetch is issued unconditionally (a chunk
+    // past the end repeats the last, never used), which keeps the loads in flight the same
+    // on every path and lets each wait count only the chunk it needs
+    const int64_t qmax = count - 1;
+    auto kk_of = [&](int64_t q) { return first + step * min(q, qmax); };
+    fetch(bwd, i0, kk_of(0), fa0, fy0);
+    fetch(bwd, i0, kk_of(1), fa1, fy1);
+    __syncthreads();                               // finish of the last block read buffer 0
+    stage(0, bwd, i0, nb, kk_of(0), fa0, fy0);
     for (int64_t q = 0; q < count; q += 2) {
       __syncthreads();
-      stage(bwd, i0, nb, first + step * q, fa0, fy0);
-      __syncthreads();
-      if (q + 2 < count) get(q + 2, fa0, fy0);
-      mma(bwd, acc);
+      fetch(bwd, i0, kk_of(q + 2), fa0, fy0);
+      mma(0, bwd, acc);
       if (q + 1 >= count) break;
+      stage(1, bwd, i0, nb, kk_of(q + 1), fa1, fy1);
       __syncthreads();
-      stage(bwd, i0, nb, first + step * (q + 1), fa1, fy1);
-      __syncthreads();
-      if (q + 3 < count) get(q + 3, fa1, fy1);
-      mma(bwd, acc);
+      fetch(bwd, i0, kk_of(q + 3), fa1, fy1);
+      mma(1, bwd, acc);
+      stage(0, bwd, i0, nb, kk_of(q + 2), fa0, fy0);
     }
   };
   // Yc <- rhs - accumulated sums (rows >= nb zero), Ab <- inverse block; the product with
@@ -851,17 +871,17 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
 #pragma unroll
     for (int u = 0; u < AL; ++u) {
       const int idx = threadIdx.x + MT * u;
-      Ab[idx >> 6][idx & 63] = (double)dd[u];
+      Ab[0][idx >> 6][idx & 63] = (double)dd[u];
     }
     if (tile)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int ii = 16 * rt + 4 * r + lk, col = 16 * ct + li;
-        if (col < M) Yc[ii * MP + col] = ii < nb ? bb[r] - acc[r] : 0.0;
+        if (col < M) Yc[0][ii * MP + col] = ii < nb ? bb[r] - acc[r] : 0.0;
       }
     __syncthreads();
     v4d yv = {0.0, 0.0, 0.0, 0.0};
-    mma(bwd, yv);
+    mma(0, bwd, yv);
     double* dst = bwd ? z : y;
     if (tile)
 #pragma unroll
