@@ -202,7 +202,7 @@ constexpr int ST = 512;                           // threads of the trailing upd
 
 template <class T>
 __global__ void __launch_bounds__(ST) k_syrk(BandArgs a, T* v, int64_t k0, int64_t kk,
-                                             int col_only) {
+                                             int col_only, int64_t ts_lo, int64_t ts_hi) {
   __shared__ double Pr[TS][NB + 1], Ps[TS][NB + 1];
   const int j = blockIdx.y;
   const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
@@ -219,11 +219,12 @@ __global__ void __launch_bounds__(ST) k_syrk(BandArgs a, T* v, int64_t k0, int64
     tr = tile;
     ts = 0;
   } else {
-    if (tile >= nt * (nt + 1) / 2) return;
-    int64_t t = 0, rem = tile;                   // lower-triangular tile enumeration
-    while (rem > t) { rem -= t + 1; ++t; }
-    tr = t;
-    ts = rem;
+    // tile columns ts_lo <= ts < ts_hi, each with its rows ts <= tr < nt, column by column
+    const int64_t te = min(ts_hi, nt);
+    int64_t rem = tile;
+    for (ts = ts_lo; ts < te && rem >= nt - ts; ++ts) rem -= nt - ts;
+    if (ts >= te) return;
+    tr = ts + rem;
   }
   T* base = v + a.off[j];
   const int64_t r0 = t0 + tr * TS, s0 = t0 + ts * TS, wend = t0 + W;
@@ -283,6 +284,33 @@ __global__ void __launch_bounds__(ST) k_syrk(BandArgs a, T* v, int64_t k0, int64
   }
 }
 
+// Second stream and events of the factorisation's look-ahead (default priority); the
+// stream is drained before it goes.
+struct LookAhead {
+  hipStream_t st = nullptr;
+  hipEvent_t panels = nullptr, rest = nullptr;
+  LookAhead() {
+    GX_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    GX_HIP(hipEventCreateWithFlags(&panels, hipEventDisableTiming));
+    GX_HIP(hipEventCreateWithFlags(&rest, hipEventDisableTiming));
+  }
+  ~LookAhead() {
+    if (st) (void)hipStreamSynchronize(st);
+    if (panels) (void)hipEventDestroy(panels);
+    if (rest) (void)hipEventDestroy(rest);
+    if (st) (void)hipStreamDestroy(st);
+  }
+  LookAhead(const LookAhead&) = delete;
+  LookAhead& operator=(const LookAhead&) = delete;
+};
+
+// Number of tiles k_syrk enumerates for tile columns [lo, hi) of an nt x nt lower triangle.
+static unsigned syrk_tiles(int64_t nt, int64_t lo, int64_t hi) {
+  int64_t c = 0;
+  for (int64_t ts = lo; ts < std::min(hi, nt); ++ts) c += nt - ts;
+  return (unsigned)c;
+}
+
 template <class T>
 void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, int* err) {
   BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p};
@@ -290,27 +318,46 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, int* err) {
   // right-looking blocked Cholesky in groups of GP panels of NB columns: inside a group
   // each panel is first brought up to date by the group's earlier panels (its own tile
   // column only), then factored (diagonal block, panel below it); the rest of the band is
-  // updated once per group, by all GP panels together
+  // updated once per group, by all GP panels together.  That update is split with
+  // look-ahead: the next group's GP tile columns on st, which then goes on to factor that
+  // group's panels, and all further tile columns on a second stream at the same time.
+  // The next group's own update of the columns after it waits for that second part (the
+  // two touch the same tiles); everything else they do touches disjoint tiles.
   constexpr int GP = 4;
   const int64_t nt = (bs.max_B + TS - 1) / TS;
-  const unsigned tiles = (unsigned)(nt * (nt + 1) / 2);
+  const unsigned tiles_next = syrk_tiles(nt, 0, GP), tiles_rest = syrk_tiles(nt, GP, nt);
   const unsigned trsm_blocks = (unsigned)((bs.max_B + TS - 1) / TS);
+  LookAhead la;
+  bool rest_pending = false;
   for (int64_t k0 = 0; k0 < bs.max_n; k0 += GP * NB) {
     for (int p = 0; p < GP && k0 + p * NB < bs.max_n; ++p) {
       const int64_t c0 = k0 + p * NB;
       if (p > 0 && bs.max_B > 0)
         hipLaunchKernelGGL(k_syrk<T>, dim3((unsigned)nt, bs.n_mat), dim3(ST), 0, st, a, v, k0,
-                           (int64_t)p * NB, 1);
+                           (int64_t)p * NB, 1, (int64_t)0, (int64_t)0);
       hipLaunchKernelGGL(k_potrf<T>, dim3(bs.n_mat), dim3(256), 0, st, a, v, c0, inv.p, dinv,
                          bs.d_boff.p, err);
       if (bs.max_B > 0)
         hipLaunchKernelGGL(k_trsm<T>, dim3(trsm_blocks, bs.n_mat), dim3(256), 0, st, a, v, c0,
                            inv.p);
     }
-    if (bs.max_B > 0)
-      hipLaunchKernelGGL(k_syrk<T>, dim3(tiles, bs.n_mat), dim3(ST), 0, st, a, v, k0,
-                         (int64_t)GP * NB, 0);
+    if (bs.max_B > 0) {
+      GX_HIP(hipEventRecord(la.panels, st));
+      if (tiles_rest) {
+        GX_HIP(hipStreamWaitEvent(la.st, la.panels, 0));
+        hipLaunchKernelGGL(k_syrk<T>, dim3(tiles_rest, bs.n_mat), dim3(ST), 0, la.st, a, v, k0,
+                           (int64_t)GP * NB, 0, (int64_t)GP, nt);
+      }
+      if (rest_pending) GX_HIP(hipStreamWaitEvent(st, la.rest, 0));
+      hipLaunchKernelGGL(k_syrk<T>, dim3(tiles_next, bs.n_mat), dim3(ST), 0, st, a, v, k0,
+                         (int64_t)GP * NB, 0, (int64_t)0, (int64_t)GP);
+      if (tiles_rest) {
+        GX_HIP(hipEventRecord(la.rest, la.st));
+        rest_pending = true;
+      }
+    }
   }
+  if (rest_pending) GX_HIP(hipStreamWaitEvent(st, la.rest, 0));
   GX_HIP(hipGetLastError());
   GX_HIP(hipStreamSynchronize(st));
 }
