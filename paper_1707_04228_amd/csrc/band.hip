@@ -14,6 +14,8 @@
 // bandwidth run in the same launches.
 //
 // Solves: see the comment above the solve kernels.
+#include <algorithm>
+
 #include "gx_internal.h"
 
 namespace gx {
@@ -703,18 +705,20 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
                       zall + yoff[j], g, G, err);
 }
 
-// The matrices of several band sets in one launch (all of one precision): matrix j's rows,
-// bandwidth, factor, inverse diagonal blocks, right-hand side and scratch from tab[j].
+// The matrices of several band sets in one launch (all of one precision): work-group i
+// takes group work[2 i + 1] of matrix work[2 i] (none if negative); matrix j's rows,
+// bandwidth, group count, factor, inverse diagonal blocks, right-hand side and scratch
+// come from tab[j].
 template <class T>
 __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1_multi(const BandPtrs* tab,
-                                                                       int G, int n_pad,
-                                                                       int n_mat, int* err) {
-  const int g = blockIdx.x / n_pad, j = blockIdx.x % n_pad;
-  if (j >= n_mat || g >= G) return;
+                                                                       const int32_t* work,
+                                                                       int* err) {
+  const int j = work[2 * blockIdx.x], g = work[2 * blockIdx.x + 1];
+  if (j < 0) return;
   const BandPtrs t = tab[j];
   if (t.n == 0) return;
   band_solve_1_mat<T>(t.n, t.B, t.B + 1, static_cast<const T*>(t.v),
-                      static_cast<const T*>(t.dinv), t.x, t.y, t.z, g, G, err);
+                      static_cast<const T*>(t.dinv), t.x, t.y, t.z, g, (int)t.G, err);
 }
 
 // y and z scratch of every matrix of a multi-set solve back to the marker
@@ -1200,43 +1204,92 @@ void multi_solve_plan(MultiSolve& m, const std::vector<BandSet*>& sets,
   }
   m.n_mat = (int)m.host.size();
   GX_REQUIRE(m.n_mat > 0 && m.n_mat <= 65535, "multi-set solve: 1 to 65535 matrices");
-  if (m.tab.n < m.host.size()) m.tab.alloc(m.host.size());
-  to_dev(m.tab.p, m.host.data(), m.host.size(), st);
-  if (!m.err.n) {
-    m.err.alloc(1);
-    zero(m.err, st);
-  }
-  GX_HIP(hipStreamSynchronize(st));
-  // work-groups per matrix: all of them resident at once (the waits between the groups of a
-  // matrix need that), at most GMAX, and at least two blocks of rows per group
+  // Work-groups per matrix.  The waits between the groups of a matrix need them all
+  // resident, and work-group i runs on XCD i mod NX (each with its share of the resident
+  // capacity).  Matrices go to XCDs largest first, each to the least loaded one with a
+  // free slot; the spare slots of an XCD then go one at a time to its matrix with the most
+  // factor entries per group (at most GMAX, at least two blocks of rows per group).  If
+  // there are more matrices than slots every matrix gets one group (no waits at all).
   int dev = 0, cus = 0, per_cu = 0;
   GX_HIP(hipGetDevice(&dev));
   GX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   const void* kf = m.fp32 ? reinterpret_cast<const void*>(&k_band_solve_1_multi<float>)
                           : reinterpret_cast<const void*>(&k_band_solve_1_multi<double>);
   GX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf, SOLVE_THREADS, 0));
-  const int64_t full = (int64_t)cus * std::max(per_cu, 0);
-  m.G = 1;
-  for (int c = GMAX; c >= 2; --c)
-    if ((int64_t)m.n_mat * c <= full && m.max_n >= (int64_t)2 * SB * c) {
-      m.G = c;
-      break;
+  const int NX = cus % 8 == 0 ? 8 : 1;             // XCDs (MI355X: 8 of 32 CUs)
+  const int64_t per_x = (int64_t)cus / NX * std::max(per_cu, 1);
+  const int nm = m.n_mat;
+  std::vector<int> xcd(nm, 0);
+  std::vector<double> wk(nm);
+  for (int j = 0; j < nm; ++j) {
+    wk[j] = (double)m.host[j].n * (double)(m.host[j].B + 1);
+    m.host[j].G = 1;
+  }
+  std::vector<int> order(nm);
+  for (int j = 0; j < nm; ++j) order[j] = j;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return wk[a] > wk[b]; });
+  std::vector<double> load(NX, 0.0);
+  std::vector<int64_t> used(NX, 0);
+  const bool fits = nm <= per_x * NX;
+  for (int r = 0; r < nm; ++r) {
+    const int j = order[r];
+    int best = -1;
+    for (int x = 0; x < NX; ++x)
+      if ((!fits || used[x] < per_x) && (best < 0 || load[x] < load[best])) best = x;
+    xcd[j] = best;
+    load[best] += wk[j];
+    ++used[best];
+  }
+  if (fits)
+    for (int x = 0; x < NX; ++x)
+      for (; used[x] < per_x; ++used[x]) {
+        int pick = -1;
+        for (int j = 0; j < nm; ++j) {
+          const BandPtrs& t = m.host[j];
+          if (xcd[j] != x || t.G >= GMAX || t.n < (int64_t)2 * SB * (t.G + 1)) continue;
+          if (pick < 0 || wk[j] / (double)t.G > wk[pick] / (double)m.host[pick].G) pick = j;
+        }
+        if (pick < 0) break;
+        ++m.host[pick].G;
+      }
+  std::vector<std::vector<int32_t>> lists(NX);
+  for (int j = 0; j < nm; ++j)
+    for (int g = 0; g < (int)m.host[j].G; ++g) {
+      lists[xcd[j]].push_back(j);
+      lists[xcd[j]].push_back(g);
     }
+  size_t slots = 0;
+  for (auto& l : lists) slots = std::max(slots, l.size() / 2);
+  std::vector<int32_t> wl(2 * slots * NX, -1);
+  for (int x = 0; x < NX; ++x)
+    for (size_t q = 0; q < lists[x].size() / 2; ++q) {
+      wl[2 * (q * NX + x)] = lists[x][2 * q];
+      wl[2 * (q * NX + x) + 1] = lists[x][2 * q + 1];
+    }
+  m.n_wg = (int)(slots * NX);
+  if (m.tab.n < m.host.size()) m.tab.alloc(m.host.size());
+  to_dev(m.tab.p, m.host.data(), m.host.size(), st);
+  if (m.work.n < wl.size()) m.work.alloc(wl.size());
+  to_dev(m.work.p, wl.data(), wl.size(), st);
+  if (!m.err.n) {
+    m.err.alloc(1);
+    zero(m.err, st);
+  }
+  GX_HIP(hipStreamSynchronize(st));                // wl and host are read by the copies
 }
 
 // Solves every matrix of the table in place (marker fill, solve, copy-out on st).
 void multi_solve(MultiSolve& m, hipStream_t st) {
   GX_REQUIRE(m.n_mat > 0, "multi-set solve: no table");
   const unsigned nm = (unsigned)m.n_mat;
-  const int n_pad = (m.n_mat + 7) / 8 * 8;         // all groups of a matrix on one XCD
   hipLaunchKernelGGL(k_fill_mark_multi, dim3(nblocks((m.max_n + SB - 1) / SB * SB, 256), nm),
                      dim3(256), 0, st, m.tab.p);
   if (m.fp32)
-    hipLaunchKernelGGL(k_band_solve_1_multi<float>, dim3(m.G * n_pad), dim3(SOLVE_THREADS), 0,
-                       st, m.tab.p, m.G, n_pad, m.n_mat, m.err.p);
+    hipLaunchKernelGGL(k_band_solve_1_multi<float>, dim3((unsigned)m.n_wg), dim3(SOLVE_THREADS),
+                       0, st, m.tab.p, m.work.p, m.err.p);
   else
-    hipLaunchKernelGGL(k_band_solve_1_multi<double>, dim3(m.G * n_pad), dim3(SOLVE_THREADS), 0,
-                       st, m.tab.p, m.G, n_pad, m.n_mat, m.err.p);
+    hipLaunchKernelGGL(k_band_solve_1_multi<double>, dim3((unsigned)m.n_wg), dim3(SOLVE_THREADS),
+                       0, st, m.tab.p, m.work.p, m.err.p);
   hipLaunchKernelGGL(k_copy_out_multi, dim3(nblocks(m.max_n, 256), nm), dim3(256), 0, st,
                      m.tab.p);
   GX_HIP(hipGetLastError());

@@ -224,6 +224,7 @@ struct BandPtrs {
   double* y;                                   // forward-solution scratch (64-aligned length)
   double* z;                                   // backward-solution scratch
   int64_t n, B;                                // rows, half-bandwidth
+  int64_t G;                                   // work-groups sharing the matrix
 };
 
 // The single-right-hand-side solves of several band sets of one precision on one device in
@@ -232,8 +233,9 @@ struct MultiSolve {
   std::vector<BandSet*> sets;                  // in table order
   std::vector<BandPtrs> host;
   DevBuf<BandPtrs> tab;
+  DevBuf<int32_t> work;                        // (matrix, group) per work-group, -1: none
   DevBuf<int> err;                             // time-out word of the launches
-  int n_mat = 0, G = 1;
+  int n_mat = 0, n_wg = 0;
   int64_t max_n = 0;
   bool fp32 = false;
 };
