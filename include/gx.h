@@ -19,7 +19,10 @@
  *   - All work is queued on the context's HIP stream; calls return after that work has
  *     completed (results are ready for any stream).
  *   - No exception crosses this interface.  Every call returns a gx_status; on failure a
- *     message is available from gx_last_error().  One context per host thread.
+ *     message is available from gx_last_error().
+ *   - A context is used by one host thread at a time; different contexts may be used from
+ *     different threads at once (the library's shared state, a cache of released device
+ *     blocks, is locked).
  *   - Library-owned state (mesh copy, element matrices, K, decomposition, factors, coarse
  *     space) lives in the context and is released by gx_destroy().
  */
