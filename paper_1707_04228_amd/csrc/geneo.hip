@@ -272,33 +272,108 @@ __global__ void __launch_bounds__(64) k_b_fill(GeneoDev g, const int32_t* rp,
   }
 }
 
-// Y = B X for the m columns of the active subdomains (lane = column), from the stored rows
-__global__ void __launch_bounds__(64) k_bmul_rows(GeneoDev g, const int32_t* rp,
-                                                  const int32_t* colk, const int64_t* brow,
-                                                  const double* bv, int m, const int64_t* voff,
+// The blocks of each stored row of B that can contribute: nonzero, with a column node
+// among the subdomain's Neumann nodes.  One 64-lane work-group per row, lanes over the
+// row's slots (at most NROW = 128); k_bcount writes each row's count, k_bcompact (after an
+// exclusive scan of the counts) copies those blocks in slot order with the column node's
+// local index.
+__device__ inline bool b_keep(const GeneoDev& g, const int32_t* colk, const double* bv,
+                              int j, int rb, int64_t b0, int sl, int len, int32_t* lm_out) {
+  if (sl >= len) return false;
+  const int32_t lm = g.D_loc[(int64_t)j * g.N + colk[rb + sl]];
+  *lm_out = lm;
+  if (lm < 0) return false;
+  const double* kb = bv + 9 * (b0 + sl);
+  bool nz = false;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) nz = nz || kb[c] != 0.0;
+  return nz;
+}
+
+__global__ void __launch_bounds__(64) k_bcount(GeneoDev g, const int32_t* rp,
+                                               const int32_t* colk, const int64_t* brow,
+                                               const double* bv, int64_t* cnt) {
+  const int j = blockIdx.y;
+  const int64_t ln = blockIdx.x;
+  if (ln >= g.nD[j]) return;
+  const int64_t n = g.D_nodes[g.offD[j] + ln];
+  const int rb = rp[n], len = rp[n + 1] - rb;
+  const int64_t b0 = brow[g.offD[j] + ln];
+  int c = 0;
+  for (int base = 0; base < len; base += 64) {
+    int32_t lm = -1;
+    c += __popcll(__ballot(b_keep(g, colk, bv, j, rb, b0, base + (int)threadIdx.x, len, &lm)));
+  }
+  if (threadIdx.x == 0) cnt[g.offD[j] + ln] = c;
+}
+
+__global__ void __launch_bounds__(64) k_bcompact(GeneoDev g, const int32_t* rp,
+                                                 const int32_t* colk, const int64_t* brow,
+                                                 const double* bv, const int64_t* crow,
+                                                 int32_t* cloc, double* cbv) {
+  const int j = blockIdx.y;
+  const int64_t ln = blockIdx.x;
+  if (ln >= g.nD[j]) return;
+  const int64_t n = g.D_nodes[g.offD[j] + ln];
+  const int rb = rp[n], len = rp[n + 1] - rb;
+  const int64_t b0 = brow[g.offD[j] + ln];
+  int64_t o = crow[g.offD[j] + ln];
+  const int lane = threadIdx.x;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;   // lanes < this one
+  for (int base = 0; base < len; base += 64) {
+    int32_t lm = -1;
+    const bool keep = b_keep(g, colk, bv, j, rb, b0, base + lane, len, &lm);
+    const uint64_t mask = __ballot(keep);
+    if (keep) {
+      const int64_t d = o + __popcll(mask & below);
+      cloc[d] = lm;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) cbv[9 * d + c] = bv[9 * (b0 + base + lane) + c];
+    }
+    o += __popcll(mask);
+  }
+}
+
+// Y = B X for the m columns of the active subdomains (lane = column), from the compact
+// rows: each lane holds two of the row's local column indices, handed to all lanes by a
+// lane read, and the X rows of 8 blocks are loaded before any is used.  Blocks are summed
+// in slot order.
+__global__ void __launch_bounds__(64) k_bmul_rows(GeneoDev g, const int64_t* crow,
+                                                  const int32_t* cloc, const double* cbv,
+                                                  int m, const int64_t* voff,
                                                   const int32_t* active, const double* X,
                                                   double* Y) {
   const int j = blockIdx.y;
   const int64_t ln = blockIdx.x;
   if (ln >= g.nD[j] || !active[j]) return;
   const int lane = threadIdx.x;
-  const int64_t n = g.D_nodes[g.offD[j] + ln];
-  const int rb = rp[n], len = rp[n + 1] - rb;
+  const int64_t r = g.offD[j] + ln;
+  const int64_t c0 = crow[r];
+  const int cnt = (int)(crow[r + 1] - c0);         // <= NROW
+  const int32_t la = lane < cnt ? cloc[c0 + lane] : 0;
+  const int32_t lb = lane + 64 < cnt ? cloc[c0 + 64 + lane] : 0;
   const double* Xj = X + voff[j];
-  const double* blk = bv + 9 * brow[g.offD[j] + ln];
+  const double* kb0 = cbv + 9 * c0;
+  const int col = min(lane, m - 1);                // lanes past m repeat a column, unstored
   double y0 = 0, y1 = 0, y2 = 0;
-  if (lane < m && pou(g.I_loc, g.cnt, g.N, j, n) != 0.0)
-    for (int sl = 0; sl < len; ++sl) {
-      const int64_t lm = g.D_loc[(int64_t)j * g.N + colk[rb + sl]];
-      if (lm < 0) continue;
-      const double* kb = blk + 9 * sl;
-      const double x0 = Xj[(3 * lm) * m + lane];
-      const double x1 = Xj[(3 * lm + 1) * m + lane];
-      const double x2 = Xj[(3 * lm + 2) * m + lane];
-      y0 += kb[0] * x0 + kb[1] * x1 + kb[2] * x2;
-      y1 += kb[3] * x0 + kb[4] * x1 + kb[5] * x2;
-      y2 += kb[6] * x0 + kb[7] * x1 + kb[8] * x2;
+  for (int s0 = 0; s0 < cnt; s0 += 8) {
+    double xv[8][3];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int sl = min(s0 + q, cnt - 1);
+      const int64_t lm = sl < 64 ? __shfl(la, sl) : __shfl(lb, sl - 64);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xv[q][c] = Xj[(3 * lm + c) * m + col];
     }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (s0 + q >= cnt) break;
+      const double* kb = kb0 + 9 * (s0 + q);
+      y0 += kb[0] * xv[q][0] + kb[1] * xv[q][1] + kb[2] * xv[q][2];
+      y1 += kb[3] * xv[q][0] + kb[4] * xv[q][1] + kb[5] * xv[q][2];
+      y2 += kb[6] * xv[q][0] + kb[7] * xv[q][1] + kb[8] * xv[q][2];
+    }
+  }
   if (lane < m) {
     double* Yj = Y + voff[j];
     Yj[(3 * ln) * m + lane] = y0;
@@ -306,7 +381,6 @@ __global__ void __launch_bounds__(64) k_bmul_rows(GeneoDev g, const int32_t* rp,
     Yj[(3 * ln + 2) * m + lane] = y2;
   }
 }
-
 
 // deterministic pseudo-random start block (splitmix64 of the entry index), zero on clamps
 __global__ void k_rand_init(GeneoDev g, int m, const int64_t* voff, double* X) {
@@ -863,8 +937,9 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   // B as stored node block rows (see k_b_fill)
   int64_t sumD = 0;
   for (int j = 0; j < n_sub; ++j) sumD += sw.nD[j];
-  DevBuf<int64_t> brow(sumD + 1);
-  DevBuf<double> Bv;
+  DevBuf<int64_t> brow(sumD + 1), crow(sumD + 1);
+  DevBuf<double> Bv, cbv;
+  DevBuf<int32_t> cloc;
   {
     zero(brow, s);
     hipLaunchKernelGGL(k_brow_len, dim3(nblocks(maxD, 256), n_sub), dim3(256), 0, s, g,
@@ -874,7 +949,19 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
     Bv.alloc(std::max<int64_t>(9 * nbl, 1));
     hipLaunchKernelGGL(k_b_fill, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g, c->row_ptr.p,
                        c->col.p, brow.p, Bv.p);
+    // compact rows: the blocks that can contribute, with their local column indices
+    zero(crow, s);
+    hipLaunchKernelGGL(k_bcount, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g, c->row_ptr.p,
+                       c->col.p, brow.p, Bv.p, crow.p);
+    const int64_t nbc = exclusive_scan(crow.p, sumD + 1, stmp.p, s);
+    cloc.alloc(std::max<int64_t>(nbc, 1));
+    cbv.alloc(std::max<int64_t>(9 * nbc, 1));
+    hipLaunchKernelGGL(k_bcompact, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g,
+                       c->row_ptr.p, c->col.p, brow.p, Bv.p, crow.p, cloc.p, cbv.p);
     GX_HIP(hipGetLastError());
+    GX_HIP(hipStreamSynchronize(s));
+    Bv.release();
+    brow.release();
   }
   // block size: a fixed count takes the wanted count + 8 guard vectors, rounded up to a
   // multiple of 8 (the multi-right-hand-side solves are built for them).  A threshold starts
@@ -925,8 +1012,8 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
                        sw.d_nD.p, m_prev, d_voff_prev.p, X_prev.p, m, d_voff.p, X.p);
   X_prev.release();
   d_voff_prev.release();
-  hipLaunchKernelGGL(k_bmul_rows, growD, dim3(64), 0, s, g, c->row_ptr.p, c->col.p, brow.p,
-                     Bv.p, m, d_voff.p, active.p, X.p, BX.p);
+  hipLaunchKernelGGL(k_bmul_rows, growD, dim3(64), 0, s, g, crow.p, cloc.p, cbv.p, m,
+                     d_voff.p, active.p, X.p, BX.p);
   std::vector<double> h_theta((size_t)n_sub * MAXM), h_res((size_t)n_sub * 3 * MAXM);
   lam_final.assign((size_t)n_sub * MAXM, 0.0);
   int n_active = n_sub;
@@ -962,8 +1049,8 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
       band_solve(Mb, d_voff.p, Y.p, s, m, active.p);
       GX_HIP(hipEventRecord(ev.b, s));
     }
-    hipLaunchKernelGGL(k_bmul_rows, growD, dim3(64), 0, s, g, c->row_ptr.p, c->col.p, brow.p,
-                       Bv.p, m, d_voff.p, active.p, Y.p, BY.p);
+    hipLaunchKernelGGL(k_bmul_rows, growD, dim3(64), 0, s, g, crow.p, cloc.p, cbv.p, m,
+                       d_voff.p, active.p, Y.p, BY.p);
     if (m32)
       hipLaunchKernelGGL(k_amul, growD, dim3(64), 0, s, g, m, d_voff.p, active.p, Y.p, BY.p,
                          sigma, MY);
