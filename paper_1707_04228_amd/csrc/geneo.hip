@@ -652,7 +652,18 @@ __global__ void __launch_bounds__(256) k_rayleigh_ritz(int m, const int32_t* act
   }
 }
 
-// out[i][b] = sum_a in[i][a] c[a][b] (row-major blocks of m columns)
+// v of lane l (l wave-uniform), through the scalar unit
+__device__ inline double lane_value(double v, int l) {
+  const long long bits = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(bits & 0xffffffffll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// out[i][b] = sum_a in[i][a] c[a][b] (row-major blocks of m columns).  A work-group takes
+// ROT_ROWS rows, so that the m x m matrix it stages in LDS serves many of them; each wave
+// forms four rows at a time (lane = column).
+constexpr int ROT_ROWS = 64;
 __global__ void __launch_bounds__(256) k_rotate(const int64_t* nrows, int m,
                                                 const int64_t* voff, const int32_t* active,
                                                 const double* Cm, const double* in,
@@ -660,15 +671,32 @@ __global__ void __launch_bounds__(256) k_rotate(const int64_t* nrows, int m,
   __shared__ double c[MAXM][MAXM];
   const int j = blockIdx.y;
   if (!active[j]) return;
+  const int64_t n3 = 3 * nrows[j];
+  const int64_t r0 = (int64_t)blockIdx.x * ROT_ROWS;
+  if (r0 >= n3) return;
   for (int e = threadIdx.x; e < m * m; e += 256) c[e / m][e % m] = Cm[(int64_t)j * MAXM * MAXM + e];
   __syncthreads();
-  const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  const int b = threadIdx.x % 64;
-  if (row >= 3 * nrows[j] || b >= m) return;
-  const double* ir = in + voff[j] + row * m;
-  double s = 0.0;
-  for (int a = 0; a < m; ++a) s += ir[a] * c[a][b];
-  out[voff[j] + row * m + b] = s;
+  const int b = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int bb = min(b, m - 1);
+  const int64_t rend = min(n3, r0 + ROT_ROWS);
+  const double* base = in + voff[j];
+  for (int64_t row = r0 + w; row < rend; row += 16) {   // rows row + 4 q, q < 4
+    // lane a loads entry a of each row (one coalesced load per row); the products take
+    // entry a from lane a (a wave-uniform lane read into a scalar operand)
+    double xv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xv[q] = base[min(row + 4 * q, rend - 1) * m + bb];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int a = 0; a < m; ++a) {
+      const double ca = c[a][bb];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] += lane_value(xv[q], a) * ca;
+    }
+    if (b < m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (row + 4 * q < rend) out[voff[j] + (row + 4 * q) * m + b] = acc[q];
+  }
 }
 
 // per column: ||MX - theta BX||^2, ||MX||^2 and ||X||^2 (chunk partials, then fixed-order
@@ -1004,7 +1032,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   zero(err, s);
   const dim3 growD((unsigned)maxD, n_sub);
   const dim3 gvec(nblocks(3 * maxD * m, 256), n_sub);
-  const dim3 grows(nblocks(3 * maxD, 4), n_sub);
+  const dim3 grows(nblocks(3 * maxD, ROT_ROWS), n_sub);
   const dim3 gch((unsigned)nch_max, n_sub);
   hipLaunchKernelGGL(k_rand_init, gvec, dim3(256), 0, s, g, m, d_voff.p, X.p);
   if (m_prev)                                      // warm start: the previous block first
