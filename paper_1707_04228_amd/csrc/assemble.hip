@@ -450,7 +450,8 @@ __global__ void k_fixed(int64_t n, const int32_t* nodes, uint8_t* fixed) {
 
 // ---------------------------------------------------------------------------------------
 // y = K x, one 64-lane wavefront per block row; lane v of the row reads value v (values of
-// a row are contiguous, so every load instruction is a coalesced 512-byte segment)
+// a row are contiguous, so every load instruction is a coalesced 512-byte segment), and
+// all loads of a row are in flight before the first product
 __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, const int32_t* __restrict__ rp,
                                               const int32_t* __restrict__ col,
                                               const double* __restrict__ val,
@@ -460,15 +461,36 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, const int32_t* __r
   const int lane = threadIdx.x & 63;
   if (row >= n_rows) return;
   const int b0 = rp[row], b1 = rp[row + 1];
-  const int64_t v0 = (int64_t)b0 * 9, nv = (int64_t)(b1 - b0) * 9;
+  const int64_t v0 = (int64_t)b0 * 9;
+  const int nv = (b1 - b0) * 9;
   double a0 = 0, a1 = 0, a2 = 0;
-  for (int v = lane; v < nv; v += 64) {
-    const int blk = v / 9, c9 = v - 9 * blk;
-    const int r = c9 / 3, cc = c9 - 3 * r;
-    const double p = val[v0 + v] * x[3 * (int64_t)col[b0 + blk] + cc];
-    a0 += r == 0 ? p : 0.0;
-    a1 += r == 1 ? p : 0.0;
-    a2 += r == 2 ? p : 0.0;
+  // VU passes of 64 values at a time: every value and column load of the passes is issued,
+  // then every gather of x, before the products (a row has at most 128 blocks, so one or
+  // two rounds); each lane still sums its values in order
+  constexpr int VU = 12;
+  for (int vb = 0; vb < nv; vb += 64 * VU) {
+    double pv[VU], xv[VU];
+    int cc[VU];
+    int64_t xi[VU];
+#pragma unroll
+    for (int u = 0; u < VU; ++u) {
+      const int v = min(vb + 64 * u + lane, nv - 1);
+      const int blk = v / 9, c9 = v - 9 * blk;
+      cc[u] = c9;
+      pv[u] = val[v0 + v];
+      xi[u] = 3 * (int64_t)col[b0 + blk] + (c9 - 3 * (c9 / 3));
+    }
+#pragma unroll
+    for (int u = 0; u < VU; ++u) xv[u] = x[xi[u]];
+#pragma unroll
+    for (int u = 0; u < VU; ++u) {
+      const bool ok = vb + 64 * u + lane < nv;     // masked, not branched: loads stay hoisted
+      const double p = pv[u] * xv[u];
+      const int r = ok ? cc[u] / 3 : 3;
+      a0 += r == 0 ? p : 0.0;
+      a1 += r == 1 ? p : 0.0;
+      a2 += r == 2 ? p : 0.0;
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     a0 += __shfl_xor(a0, off);
