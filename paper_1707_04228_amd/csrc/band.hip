@@ -286,26 +286,6 @@ __global__ void __launch_bounds__(ST) k_syrk(BandArgs a, T* v, int64_t k0, int64
   }
 }
 
-// Second stream and events of the factorisation's look-ahead (default priority); the
-// stream is drained before it goes.
-struct LookAhead {
-  hipStream_t st = nullptr;
-  hipEvent_t panels = nullptr, rest = nullptr;
-  LookAhead() {
-    GX_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    GX_HIP(hipEventCreateWithFlags(&panels, hipEventDisableTiming));
-    GX_HIP(hipEventCreateWithFlags(&rest, hipEventDisableTiming));
-  }
-  ~LookAhead() {
-    if (st) (void)hipStreamSynchronize(st);
-    if (panels) (void)hipEventDestroy(panels);
-    if (rest) (void)hipEventDestroy(rest);
-    if (st) (void)hipStreamDestroy(st);
-  }
-  LookAhead(const LookAhead&) = delete;
-  LookAhead& operator=(const LookAhead&) = delete;
-};
-
 // Number of tiles k_syrk enumerates for tile columns [lo, hi) of an nt x nt lower triangle.
 static unsigned syrk_tiles(int64_t nt, int64_t lo, int64_t hi) {
   int64_t c = 0;
@@ -314,9 +294,11 @@ static unsigned syrk_tiles(int64_t nt, int64_t lo, int64_t hi) {
 }
 
 template <class T>
-void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, int* err) {
+void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job) {
   BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p};
-  DevBuf<double> inv((size_t)bs.n_mat * NB * NB);
+  job.inv.alloc((size_t)bs.n_mat * NB * NB);
+  double* inv = job.inv.p;
+  int* err = job.err.p;
   // right-looking blocked Cholesky in groups of GP panels of NB columns: inside a group
   // each panel is first brought up to date by the group's earlier panels (its own tile
   // column only), then factored (diagonal block, panel below it); the rest of the band is
@@ -329,7 +311,9 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, int* err) {
   const int64_t nt = (bs.max_B + TS - 1) / TS;
   const unsigned tiles_next = syrk_tiles(nt, 0, GP), tiles_rest = syrk_tiles(nt, GP, nt);
   const unsigned trsm_blocks = (unsigned)((bs.max_B + TS - 1) / TS);
-  LookAhead la;
+  GX_HIP(hipStreamCreateWithFlags(&job.la, hipStreamNonBlocking));
+  GX_HIP(hipEventCreateWithFlags(&job.panels, hipEventDisableTiming));
+  GX_HIP(hipEventCreateWithFlags(&job.rest, hipEventDisableTiming));
   bool rest_pending = false;
   for (int64_t k0 = 0; k0 < bs.max_n; k0 += GP * NB) {
     for (int p = 0; p < GP && k0 + p * NB < bs.max_n; ++p) {
@@ -337,45 +321,65 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, int* err) {
       if (p > 0 && bs.max_B > 0)
         hipLaunchKernelGGL(k_syrk<T>, dim3((unsigned)nt, bs.n_mat), dim3(ST), 0, st, a, v, k0,
                            (int64_t)p * NB, 1, (int64_t)0, (int64_t)0);
-      hipLaunchKernelGGL(k_potrf<T>, dim3(bs.n_mat), dim3(256), 0, st, a, v, c0, inv.p, dinv,
+      hipLaunchKernelGGL(k_potrf<T>, dim3(bs.n_mat), dim3(256), 0, st, a, v, c0, inv, dinv,
                          bs.d_boff.p, err);
       if (bs.max_B > 0)
         hipLaunchKernelGGL(k_trsm<T>, dim3(trsm_blocks, bs.n_mat), dim3(256), 0, st, a, v, c0,
-                           inv.p);
+                           inv);
     }
     if (bs.max_B > 0) {
-      GX_HIP(hipEventRecord(la.panels, st));
+      GX_HIP(hipEventRecord(job.panels, st));
       if (tiles_rest) {
-        GX_HIP(hipStreamWaitEvent(la.st, la.panels, 0));
-        hipLaunchKernelGGL(k_syrk<T>, dim3(tiles_rest, bs.n_mat), dim3(ST), 0, la.st, a, v, k0,
+        GX_HIP(hipStreamWaitEvent(job.la, job.panels, 0));
+        hipLaunchKernelGGL(k_syrk<T>, dim3(tiles_rest, bs.n_mat), dim3(ST), 0, job.la, a, v, k0,
                            (int64_t)GP * NB, 0, (int64_t)GP, nt);
       }
-      if (rest_pending) GX_HIP(hipStreamWaitEvent(st, la.rest, 0));
+      if (rest_pending) GX_HIP(hipStreamWaitEvent(st, job.rest, 0));
       hipLaunchKernelGGL(k_syrk<T>, dim3(tiles_next, bs.n_mat), dim3(ST), 0, st, a, v, k0,
                          (int64_t)GP * NB, 0, (int64_t)0, (int64_t)GP);
       if (tiles_rest) {
-        GX_HIP(hipEventRecord(la.rest, la.st));
+        GX_HIP(hipEventRecord(job.rest, job.la));
         rest_pending = true;
       }
     }
   }
-  if (rest_pending) GX_HIP(hipStreamWaitEvent(st, la.rest, 0));
+  if (rest_pending) GX_HIP(hipStreamWaitEvent(st, job.rest, 0));
   GX_HIP(hipGetLastError());
-  GX_HIP(hipStreamSynchronize(st));
+}
+
+FactorJob::~FactorJob() {
+  if (st) (void)hipStreamSynchronize(st);         // nothing of the job may still run when
+  if (la) (void)hipStreamSynchronize(la);         // its buffers are released
+  if (panels) (void)hipEventDestroy(panels);
+  if (rest) (void)hipEventDestroy(rest);
+  if (la) (void)hipStreamDestroy(la);
+}
+
+void band_factor_start(BandSet& bs, hipStream_t st, FactorJob& job, const char* what) {
+  GX_REQUIRE(!job.st, "factorisation job already started");
+  job.st = st;
+  job.what = what;
+  job.err.alloc(1);
+  zero(job.err, st);
+  if (bs.fp32)
+    band_factor_t<float>(bs, bs.v32.p, bs.dinv32.p, st, job);
+  else
+    band_factor_t<double>(bs, bs.v64.p, bs.dinv64.p, st, job);
+}
+
+void band_factor_finish(FactorJob& job) {
+  GX_REQUIRE(job.st, "factorisation job not started");
+  int h = 0;
+  to_host(&h, job.err.p, 1, job.st);               // waits for all of the job
+  if (h)
+    throw Error(GX_ENOTSPD,
+                "non-positive pivot in the banded Cholesky factorisation of " + job.what);
 }
 
 void band_factor(BandSet& bs, hipStream_t st, const char* what) {
-  DevBuf<int> err(1);
-  zero(err, st);
-  if (bs.fp32)
-    band_factor_t<float>(bs, bs.v32.p, bs.dinv32.p, st, err.p);
-  else
-    band_factor_t<double>(bs, bs.v64.p, bs.dinv64.p, st, err.p);
-  int h = 0;
-  to_host(&h, err.p, 1, st);
-  if (h)
-    throw Error(GX_ENOTSPD, std::string("non-positive pivot in the banded Cholesky factorisation of ") +
-                                what);
+  FactorJob job;
+  band_factor_start(bs, st, job, what);
+  band_factor_finish(job);
 }
 
 // ---------------------------------------------------------------------------------------

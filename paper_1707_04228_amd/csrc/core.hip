@@ -4,10 +4,19 @@
 namespace gx {
 
 thread_local gx_ctx* tls_ctx = nullptr;
+thread_local hipStream_t tls_stream = nullptr;     // overrides the context's stream if set
 thread_local bool tls_idle = false;                // releases happen on an idle device
 
-CtxScope::CtxScope(gx_ctx* c) : prev(tls_ctx) { tls_ctx = c; }
-CtxScope::~CtxScope() { tls_ctx = prev; }
+CtxScope::CtxScope(gx_ctx* c) : prev(tls_ctx), prev_stream(tls_stream) {
+  tls_ctx = c;
+  tls_stream = nullptr;
+}
+CtxScope::~CtxScope() {
+  tls_ctx = prev;
+  tls_stream = prev_stream;
+}
+StreamScope::StreamScope(hipStream_t s) : prev(tls_stream) { tls_stream = s; }
+StreamScope::~StreamScope() { tls_stream = prev; }
 
 namespace {
 constexpr size_t CACHE_MIN = (size_t)64 << 20;   // large blocks: cached whoever frees them
@@ -21,9 +30,13 @@ struct CachedBlock {
   size_t bytes;
   void* p;
   const gx_ctx* owner;
-  hipEvent_t ev;                                 // recorded on owner's stream at release
+  hipStream_t st;                                // the stream its last kernels ran on
+  hipEvent_t ev;                                 // recorded on st at release
   bool idle;
 };
+
+// The stream a context's work on this thread goes to (null outside any context).
+hipStream_t cur_stream(const gx_ctx* me) { return tls_stream ? tls_stream : me ? me->stream : nullptr; }
 
 std::mutex cache_mu;
 std::vector<CachedBlock> cache_blocks;
@@ -67,7 +80,7 @@ void trim_cache(int dev) {                          // caller holds cache_mu
 // preference among reusable blocks: 0 no wait (own stream, or idle), 1 a host wait for the
 // owner's event, 2 a device synchronisation
 int wait_class(const CachedBlock& c, const gx_ctx* me) {
-  if (c.idle || (me && c.owner == me)) return 0;
+  if (c.idle || (me && c.owner == me && c.st == cur_stream(me))) return 0;
   return c.ev ? 1 : 2;
 }
 }  // namespace
@@ -136,13 +149,15 @@ void dev_free(void* p, size_t bytes, int dev) {
     const bool room = large ? cache_bytes[dev] + bytes <= cache_cap[dev]
                             : (me || tls_idle) && small_bytes[dev] + bytes <= SMALL_CAP;
     if (room) {
-      CachedBlock c{dev, bytes, p, nullptr, nullptr, tls_idle};
+      CachedBlock c{dev, bytes, p, nullptr, nullptr, nullptr, tls_idle};
       if (!tls_idle && me) {
         // tag with the owner's stream position; without an event the block stays untagged
         hipEvent_t ev = nullptr;
+        const hipStream_t st = cur_stream(me);
         if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
-          if (hipEventRecord(ev, me->stream) == hipSuccess) {
+          if (hipEventRecord(ev, st) == hipSuccess) {
             c.owner = me;
+            c.st = st;
             c.ev = ev;
           } else {
             (void)hipEventDestroy(ev);

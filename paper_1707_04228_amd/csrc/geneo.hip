@@ -1236,6 +1236,20 @@ using namespace gx;
 
 extern "C" {
 
+// A stream of the set-up's own (default priority), drained before it goes.
+struct SideStream {
+  hipStream_t st = nullptr;
+  SideStream() { GX_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking)); }
+  ~SideStream() {
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+  }
+  SideStream(const SideStream&) = delete;
+  SideStream& operator=(const SideStream&) = delete;
+};
+
 gx_status gx_geneo_setup(gx_ctx* c, const gx_geneo_opts* o, int32_t* nev_out,
                          int64_t* n0_out) {
   GX_API_BEGIN(c)
@@ -1252,13 +1266,29 @@ gx_status gx_geneo_setup(gx_ctx* c, const gx_geneo_opts* o, int32_t* nev_out,
   dd_build(c, o->elem_part, o->n_sub, o->overlap);
   c->phase_ms[1] = t1.ms();
   c->phase_ms[3] = c->phase_ms[4] = 0;
-  // the Neumann factors of the eigensolver are released before the interior factors are
-  // built, so the two never occupy device memory together
   c->sw.two_level = o->coarse != 0;
-  if (c->sw.two_level) geneo_coarse(c, o);
-  Timer t2(c->stream);
-  interior_factors(c, o->precision);
-  c->phase_ms[2] = t2.ms();
+  if (c->sw.two_level) {
+    // The interior factorisation shares nothing with the eigensolves: it runs on a side
+    // stream while they run on the context's stream (the two sets of factors are then
+    // resident together).  The side stream is declared first, so the job (which waits for
+    // its streams when it goes) is destroyed before it.
+    SideStream side;
+    InteriorJob job;
+    EventPair ev;
+    {
+      StreamScope scope(side.st);
+      GX_HIP(hipEventRecord(ev.a, side.st));
+      interior_factors_start(c, o->precision, side.st, job);
+      GX_HIP(hipEventRecord(ev.b, side.st));
+    }
+    geneo_coarse(c, o);
+    interior_factors_finish(c, job);
+    c->phase_ms[2] = ev.ms();
+  } else {
+    Timer t2(c->stream);
+    interior_factors(c, o->precision);
+    c->phase_ms[2] = t2.ms();
+  }
   if (nev_out)
     for (int j = 0; j < o->n_sub; ++j) nev_out[j] = c->sw.two_level ? c->sw.nev[j] : 0;
   if (n0_out) *n0_out = c->sw.two_level ? c->sw.n0 : 0;

@@ -50,10 +50,11 @@ inline bool poison_alloc() {
 
 // Device memory for DevBuf, with a per-device cache of released blocks (hipFree
 // synchronises the whole device, which would serialise contexts set up concurrently).  A
-// block released during an API call on a context is tagged with that context and an event
-// recorded on its stream: all of a context's kernels run on that one stream, so the same
-// context takes the block back with no wait, and any other request waits on the host for
-// the event (the owner's work up to the release, not the whole device).  Blocks released on an
+// block released during an API call on a context is tagged with that context, the stream
+// its work went to (the context's, or a side stream, StreamScope) and an event recorded
+// there: a request of the same context for the same stream takes the block back with no
+// wait (stream order), and any other request waits on the host for the event (that
+// stream's work up to the release, not the whole device).  Blocks released on an
 // idle device (IdleScope, a destroyed context) need no wait; blocks released outside any
 // context are reused after a device synchronisation.  Blocks of 64 MiB and more are cached
 // up to half the device's memory, smaller tagged or idle blocks up to 1 GiB per device.  A
@@ -76,10 +77,21 @@ struct IdleScope {
 // for the duration of a call by GX_API_BEGIN.
 struct CtxScope {
   gx_ctx* prev;
+  hipStream_t prev_stream;
   explicit CtxScope(gx_ctx* c);
   ~CtxScope();
   CtxScope(const CtxScope&) = delete;
   CtxScope& operator=(const CtxScope&) = delete;
+};
+
+// While one exists on a thread, the context's work that the thread enqueues, and the blocks
+// it releases, belong to stream s instead of the context's own stream (a side stream).
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s);
+  ~StreamScope();
+  StreamScope(const StreamScope&) = delete;
+  StreamScope& operator=(const StreamScope&) = delete;
 };
 
 // Owning device buffer.
@@ -334,6 +346,33 @@ std::vector<int64_t> list_bandwidth(gx_ctx* c, const int32_t* list, const int64_
 void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<int64_t>& B,
                  bool fp32, hipStream_t st);
 void band_factor(BandSet& bs, hipStream_t st, const char* what);
+// A banded factorisation in flight (band_factor_start enqueues it on st, band_factor_finish
+// waits for it and raises GX_ENOTSPD on a non-positive pivot).  It owns the look-ahead
+// stream, the diagonal-block scratch and the pivot-error word; its destructor waits for
+// both streams first, so none of them is released while a kernel of the job may run.
+struct FactorJob {
+  hipStream_t st = nullptr;
+  std::string what;
+  DevBuf<int> err;
+  DevBuf<double> inv;
+  hipStream_t la = nullptr;                    // look-ahead stream (default priority)
+  hipEvent_t panels = nullptr, rest = nullptr;
+  FactorJob() = default;
+  ~FactorJob();
+  FactorJob(const FactorJob&) = delete;
+  FactorJob& operator=(const FactorJob&) = delete;
+};
+void band_factor_start(BandSet& bs, hipStream_t st, FactorJob& job, const char* what);
+void band_factor_finish(FactorJob& job);
+// The interior factorisation as a job that can run on a side stream (see schwarz.hip).
+struct InteriorJob {
+  std::vector<int64_t> n, B;
+  int64_t maxI = 0;
+  bool fp32 = false;
+  FactorJob factor;
+};
+void interior_factors_start(gx_ctx* c, int precision, hipStream_t s, InteriorJob& job);
+void interior_factors_finish(gx_ctx* c, InteriorJob& job);
 void band_solve_check(BandSet& bs, hipStream_t st);
 void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, int ncol = 1,
                 const int32_t* active = nullptr);

@@ -279,59 +279,74 @@ std::vector<int64_t> list_bandwidth(gx_ctx* c, const int32_t* list, const int64_
   return B;
 }
 
-void interior_factors(gx_ctx* c, int precision) {
+// Fills the interior band matrices and enqueues their factorisation on s (which may be a
+// side stream: nothing here waits for it); interior_factors_finish completes the job.
+void interior_factors_start(gx_ctx* c, int precision, hipStream_t s, InteriorJob& job) {
   Schwarz& sw = c->sw;
-  hipStream_t s = c->stream;
   const int64_t N = c->n_nodes;
   const int n_sub = sw.n_sub;
-  int64_t maxI = 0;
-  for (int j = 0; j < n_sub; ++j) maxI = std::max(maxI, sw.nI[j]);
-  std::vector<int64_t> n(n_sub), B =
-      list_bandwidth(c, sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, sw.nI);
-  for (int j = 0; j < n_sub; ++j) n[j] = 3 * sw.nI[j];
+  job.maxI = 0;
+  for (int j = 0; j < n_sub; ++j) job.maxI = std::max(job.maxI, sw.nI[j]);
+  job.B = list_bandwidth(c, sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, sw.nI);
+  job.n.assign(n_sub, 0);
+  for (int j = 0; j < n_sub; ++j) job.n[j] = 3 * sw.nI[j];
   sw.precision = precision;
-  const bool fp32 = precision == GX_MIXED;
-  band_layout(sw.A, n, B, fp32, s);
+  job.fp32 = precision == GX_MIXED;
+  band_layout(sw.A, job.n, job.B, job.fp32, s);
   sw.A.force_groups[0] = c->tune[0];
   sw.A.force_groups[1] = c->tune[1];
-  if (fp32) {
+  if (job.fp32) {
     sw.dg.alloc(3 * N);
     hipLaunchKernelGGL(k_diag, dim3(nblocks(N, 256)), dim3(256), 0, s, c->row_ptr.p,
                        c->col.p, c->val.p, N, sw.dg.p);
   }
   BandView bv{sw.A.d_B.p, sw.A.d_ld.p, sw.A.d_off.p};
-  if (fp32)
-    hipLaunchKernelGGL(k_band_fill<float>, dim3((unsigned)maxI, n_sub), dim3(64), 0, s,
+  if (job.fp32)
+    hipLaunchKernelGGL(k_band_fill<float>, dim3((unsigned)job.maxI, n_sub), dim3(64), 0, s,
                        c->row_ptr.p, c->col.p, c->val.p, sw.dg.p, sw.I_nodes.p, sw.d_offI.p,
                        sw.d_nI.p, sw.I_loc.p, N, bv, sw.A.v32.p);
   else
-    hipLaunchKernelGGL(k_band_fill<double>, dim3((unsigned)maxI, n_sub), dim3(64), 0, s,
+    hipLaunchKernelGGL(k_band_fill<double>, dim3((unsigned)job.maxI, n_sub), dim3(64), 0, s,
                        c->row_ptr.p, c->col.p, c->val.p, (const double*)nullptr, sw.I_nodes.p,
                        sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, N, bv, sw.A.v64.p);
   GX_HIP(hipGetLastError());
+  band_factor_start(sw.A, s, job.factor, "the subdomain matrices");
+}
+
+// Waits for the factorisation (an FP32 breakdown is redone in FP64 on the context's
+// stream, reported), then the solve work vectors, one segment of 3 nI_j per subdomain.
+void interior_factors_finish(gx_ctx* c, InteriorJob& job) {
+  Schwarz& sw = c->sw;
+  hipStream_t s = c->stream;
+  const int64_t N = c->n_nodes;
+  const int n_sub = sw.n_sub;
   try {
-    band_factor(sw.A, s, "the subdomain matrices");
+    band_factor_finish(job.factor);
   } catch (const Error& e) {
-    if (!fp32 || e.code != GX_ENOTSPD) throw;
-    // an FP32 factor broke down: the interior factors are rebuilt in FP64 (reported)
+    if (!job.fp32 || e.code != GX_ENOTSPD) throw;
     c->fp64_fallbacks |= 1;
-    band_layout(sw.A, n, B, false, s);
+    band_layout(sw.A, job.n, job.B, false, s);
     BandView bv64{sw.A.d_B.p, sw.A.d_ld.p, sw.A.d_off.p};
-    hipLaunchKernelGGL(k_band_fill<double>, dim3((unsigned)maxI, n_sub), dim3(64), 0, s,
+    hipLaunchKernelGGL(k_band_fill<double>, dim3((unsigned)job.maxI, n_sub), dim3(64), 0, s,
                        c->row_ptr.p, c->col.p, c->val.p, (const double*)nullptr, sw.I_nodes.p,
                        sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, N, bv64, sw.A.v64.p);
     GX_HIP(hipGetLastError());
     band_factor(sw.A, s, "the subdomain matrices");
     sw.precision = GX_FP64;
   }
-  // solve work vectors, one segment of 3 nI_j per subdomain
   std::vector<int64_t> xo(n_sub + 1, 0);
-  for (int j = 0; j < n_sub; ++j) xo[j + 1] = xo[j] + n[j];
+  for (int j = 0; j < n_sub; ++j) xo[j + 1] = xo[j] + job.n[j];
   sw.xoff = xo;
   sw.d_xoff.alloc(n_sub + 1);
   to_dev(sw.d_xoff.p, xo.data(), n_sub + 1, s);
   sw.wr64.alloc(xo[n_sub]);                      // FP64 local vectors in both precisions
   GX_HIP(hipStreamSynchronize(s));
+}
+
+void interior_factors(gx_ctx* c, int precision) {
+  InteriorJob job;
+  interior_factors_start(c, precision, c->stream, job);
+  interior_factors_finish(c, job);
 }
 
 // ---------------------------------------------------------------------------------------
