@@ -74,8 +74,21 @@ __global__ void __launch_bounds__(256) k_potrf(BandArgs a, T* v, int64_t c0, dou
       double d = D[i][i];
       if (!(d > 0.0)) d = 1.0;
       if (r > i && r < nb) {
+        // this thread's columns s2 = s0 + 4 u <= r: all reads first, then the writes
+        // (column i is not written in step i, and no other thread writes this row's
+        // columns of residue q), so the LDS round trips overlap
         const double f = D[r][i] / d;
-        for (int s2 = i + 1 + ((q - (i + 1)) & 3); s2 <= r; s2 += 4) D[r][s2] -= f * D[s2][i];
+        const int s0 = i + 1 + ((q - (i + 1)) & 3);
+        double col[NB / 4], row[NB / 4];
+#pragma unroll
+        for (int u = 0; u < NB / 4; ++u) {         // slots past r read column i (unwritten)
+          const bool in = s0 + 4 * u <= r;
+          col[u] = D[in ? s0 + 4 * u : i][i];
+          row[u] = D[r][in ? s0 + 4 * u : i];
+        }
+#pragma unroll
+        for (int u = 0; u < NB / 4; ++u)
+          if (s0 + 4 * u <= r) D[r][s0 + 4 * u] = row[u] - f * col[u];
       }
       if (threadIdx.x == 0) {
         if (!(D[i][i] > 0.0)) atomicOr(err, 1);
