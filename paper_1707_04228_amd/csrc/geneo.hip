@@ -146,45 +146,6 @@ __global__ void __launch_bounds__(64) k_neumann_fill(GeneoDev g, const int32_t* 
   }
 }
 
-// Y = (A^N X) + sigma BX for the m columns of subdomain j (FP64; lane = column)
-__global__ void __launch_bounds__(64) k_amul(GeneoDev g, int m, const int64_t* voff,
-                                             const int32_t* active, const double* X,
-                                             const double* BX, double sigma, double* Y) {
-  const int j = blockIdx.y;
-  const int64_t ln = blockIdx.x;
-  if (ln >= g.nD[j] || !active[j]) return;
-  const int lane = threadIdx.x;
-  if (lane >= m) return;
-  const int64_t n = g.D_nodes[g.offD[j] + ln];
-  const double* Xj = X + voff[j];
-  double y0 = 0, y1 = 0, y2 = 0;
-  for (int k = g.ne_ptr[n]; k < g.ne_ptr[n + 1]; ++k) {
-    const int64_t e = g.ne_idx[k];
-    if (!has_bit(g.emask, e, g.W, j)) continue;
-    int a = 0;
-    while (a < 19 && g.conn[20 * e + a] != n) ++a;
-    for (int b = 0; b < 20; ++b) {
-      const int64_t mm = g.conn[20 * e + b];
-      const int64_t lm = g.D_loc[(int64_t)j * g.N + mm];
-      const double* kb = g.Ke + ((e * 20 + a) * 20 + b) * 9;
-      const double x0 = g.fixed[3 * mm] ? 0.0 : Xj[(3 * lm) * m + lane];
-      const double x1 = g.fixed[3 * mm + 1] ? 0.0 : Xj[(3 * lm + 1) * m + lane];
-      const double x2 = g.fixed[3 * mm + 2] ? 0.0 : Xj[(3 * lm + 2) * m + lane];
-      y0 += kb[0] * x0 + kb[1] * x1 + kb[2] * x2;
-      y1 += kb[3] * x0 + kb[4] * x1 + kb[5] * x2;
-      y2 += kb[6] * x0 + kb[7] * x1 + kb[8] * x2;
-    }
-  }
-  const double* BXj = BX + voff[j];
-  double* Yj = Y + voff[j];
-  const int64_t r = 3 * ln;
-  Yj[r * m + lane] = g.fixed[3 * n] ? Xj[r * m + lane] : y0 + sigma * BXj[r * m + lane];
-  Yj[(r + 1) * m + lane] =
-      g.fixed[3 * n + 1] ? Xj[(r + 1) * m + lane] : y1 + sigma * BXj[(r + 1) * m + lane];
-  Yj[(r + 2) * m + lane] =
-      g.fixed[3 * n + 2] ? Xj[(r + 2) * m + lane] : y2 + sigma * BXj[(r + 2) * m + lane];
-}
-
 // T = MX - theta BX (per-column Ritz values), active subdomains only
 __global__ void k_res_block(const int64_t* nrows, int m, const int64_t* voff,
                             const int32_t* active, const double* theta, const double* MX,
@@ -272,6 +233,49 @@ __global__ void __launch_bounds__(64) k_b_fill(GeneoDev g, const int32_t* rp,
   }
 }
 
+// A^N of each subdomain as node block rows over K's pattern, laid out like B: the sum of
+// the element matrices of the subdomain's elements, with the rows and columns of clamped
+// DOFs zero (the product puts X back on clamped rows).  Used by the mixed path, which
+// forms M X explicitly.
+__global__ void __launch_bounds__(64) k_a_fill(GeneoDev g, const int32_t* rp,
+                                               const int32_t* colk, const int64_t* brow,
+                                               double* av) {
+  __shared__ double rv[NROW * 9];
+  __shared__ int32_t rc[NROW];
+  const int j = blockIdx.y;
+  const int64_t ln = blockIdx.x;
+  if (ln >= g.nD[j]) return;
+  const int64_t n = g.D_nodes[g.offD[j] + ln];
+  const int rb = rp[n], len = rp[n + 1] - rb;      // <= NROW (checked by the Neumann fill)
+  for (int i = threadIdx.x; i < len; i += 64) rc[i] = colk[rb + i];
+  for (int i = threadIdx.x; i < len * 9; i += 64) rv[i] = 0.0;
+  __syncthreads();
+  for (int k = g.ne_ptr[n]; k < g.ne_ptr[n + 1]; ++k) {
+    const int64_t e = g.ne_idx[k];
+    if (!has_bit(g.emask, e, g.W, j)) continue;
+    int a = 0;
+    while (a < 19 && g.conn[20 * e + a] != n) ++a;
+    for (int t = threadIdx.x; t < 180; t += 64) {  // distinct nodes b: distinct slots
+      const int b = t / 9, comp = t - 9 * (t / 9);
+      const int mnode = g.conn[20 * e + b];
+      int lo = 0, hi = len - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (rc[mid] < mnode) lo = mid + 1; else hi = mid;
+      }
+      rv[9 * lo + comp] += g.Ke[((e * 20 + a) * 20 + b) * 9 + comp];
+    }
+    __syncthreads();
+  }
+  double* out = av + 9 * brow[g.offD[j] + ln];
+  for (int idx = threadIdx.x; idx < len * 9; idx += 64) {
+    const int sl = idx / 9, comp = idx - 9 * (idx / 9);
+    const int64_t mnode = rc[sl];
+    const bool fx = g.fixed[3 * n + comp / 3] || g.fixed[3 * mnode + comp % 3];
+    out[idx] = fx ? 0.0 : rv[idx];
+  }
+}
+
 // The blocks of each stored row of B that can contribute: nonzero, with a column node
 // among the subdomain's Neumann nodes.  One 64-lane work-group per row, lanes over the
 // row's slots (at most NROW = 128); k_bcount writes each row's count, k_bcompact (after an
@@ -334,28 +338,20 @@ __global__ void __launch_bounds__(64) k_bcompact(GeneoDev g, const int32_t* rp,
   }
 }
 
-// Y = B X for the m columns of the active subdomains (lane = column), from the compact
-// rows: each lane holds two of the row's local column indices, handed to all lanes by a
-// lane read, and the X rows of 8 blocks are loaded before any is used.  Blocks are summed
-// in slot order.
-__global__ void __launch_bounds__(64) k_bmul_rows(GeneoDev g, const int64_t* crow,
-                                                  const int32_t* cloc, const double* cbv,
-                                                  int m, const int64_t* voff,
-                                                  const int32_t* active, const double* X,
-                                                  double* Y) {
-  const int j = blockIdx.y;
-  const int64_t ln = blockIdx.x;
-  if (ln >= g.nD[j] || !active[j]) return;
-  const int lane = threadIdx.x;
-  const int64_t r = g.offD[j] + ln;
+// (y0, y1, y2) = row ln of S X for a compact block-row operator S (lane = column): each
+// lane holds two of the row's local column indices, handed to all lanes by a lane read,
+// and the X rows of 8 blocks are loaded before any is used.  Blocks are summed in slot
+// order.
+__device__ inline void rows_product(const int64_t* crow, const int32_t* cloc, const double* cbv,
+                                    int64_t r, int m, const double* Xj, int lane, double& y0,
+                                    double& y1, double& y2) {
   const int64_t c0 = crow[r];
   const int cnt = (int)(crow[r + 1] - c0);         // <= NROW
   const int32_t la = lane < cnt ? cloc[c0 + lane] : 0;
   const int32_t lb = lane + 64 < cnt ? cloc[c0 + 64 + lane] : 0;
-  const double* Xj = X + voff[j];
   const double* kb0 = cbv + 9 * c0;
   const int col = min(lane, m - 1);                // lanes past m repeat a column, unstored
-  double y0 = 0, y1 = 0, y2 = 0;
+  y0 = y1 = y2 = 0.0;
   for (int s0 = 0; s0 < cnt; s0 += 8) {
     double xv[8][3];
 #pragma unroll
@@ -374,11 +370,51 @@ __global__ void __launch_bounds__(64) k_bmul_rows(GeneoDev g, const int64_t* cro
       y2 += kb[6] * xv[q][0] + kb[7] * xv[q][1] + kb[8] * xv[q][2];
     }
   }
+}
+
+// Y = B X for the m columns of the active subdomains, from the compact rows of B
+__global__ void __launch_bounds__(64) k_bmul_rows(GeneoDev g, const int64_t* crow,
+                                                  const int32_t* cloc, const double* cbv,
+                                                  int m, const int64_t* voff,
+                                                  const int32_t* active, const double* X,
+                                                  double* Y) {
+  const int j = blockIdx.y;
+  const int64_t ln = blockIdx.x;
+  if (ln >= g.nD[j] || !active[j]) return;
+  const int lane = threadIdx.x;
+  double y0, y1, y2;
+  rows_product(crow, cloc, cbv, g.offD[j] + ln, m, X + voff[j], lane, y0, y1, y2);
   if (lane < m) {
     double* Yj = Y + voff[j];
     Yj[(3 * ln) * m + lane] = y0;
     Yj[(3 * ln + 1) * m + lane] = y1;
     Yj[(3 * ln + 2) * m + lane] = y2;
+  }
+}
+
+// Y = A^N X + sigma BX for the m columns of the active subdomains, from the compact rows of
+// A^N; clamped rows take X (the pencil carries identity rows there)
+__global__ void __launch_bounds__(64) k_amul_rows(GeneoDev g, const int64_t* crow,
+                                                  const int32_t* cloc, const double* cbv,
+                                                  int m, const int64_t* voff,
+                                                  const int32_t* active, const double* X,
+                                                  const double* BX, double sigma, double* Y) {
+  const int j = blockIdx.y;
+  const int64_t ln = blockIdx.x;
+  if (ln >= g.nD[j] || !active[j]) return;
+  const int lane = threadIdx.x;
+  const double* Xj = X + voff[j];
+  double y[3];
+  rows_product(crow, cloc, cbv, g.offD[j] + ln, m, Xj, lane, y[0], y[1], y[2]);
+  if (lane < m) {
+    const int64_t n = g.D_nodes[g.offD[j] + ln];
+    const double* BXj = BX + voff[j];
+    double* Yj = Y + voff[j];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t e = (3 * ln + c) * m + lane;
+      Yj[e] = g.fixed[3 * n + c] ? Xj[e] : y[c] + sigma * BXj[e];
+    }
   }
 }
 
@@ -965,9 +1001,9 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   // B as stored node block rows (see k_b_fill)
   int64_t sumD = 0;
   for (int j = 0; j < n_sub; ++j) sumD += sw.nD[j];
-  DevBuf<int64_t> brow(sumD + 1), crow(sumD + 1);
-  DevBuf<double> Bv, cbv;
-  DevBuf<int32_t> cloc;
+  DevBuf<int64_t> brow(sumD + 1), crow(sumD + 1), crowA(m32 ? sumD + 1 : 0);
+  DevBuf<double> Bv, cbv, cbvA;                    // cbvA, clocA: compact A^N rows (mixed)
+  DevBuf<int32_t> cloc, clocA;
   {
     zero(brow, s);
     hipLaunchKernelGGL(k_brow_len, dim3(nblocks(maxD, 256), n_sub), dim3(256), 0, s, g,
@@ -987,6 +1023,21 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
     hipLaunchKernelGGL(k_bcompact, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g,
                        c->row_ptr.p, c->col.p, brow.p, Bv.p, crow.p, cloc.p, cbv.p);
     GX_HIP(hipGetLastError());
+    if (m32) {                                     // A^N rows, the same way (mixed path)
+      Bv.release();
+      Bv.alloc(std::max<int64_t>(9 * nbl, 1));
+      hipLaunchKernelGGL(k_a_fill, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g,
+                         c->row_ptr.p, c->col.p, brow.p, Bv.p);
+      zero(crowA, s);
+      hipLaunchKernelGGL(k_bcount, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g,
+                         c->row_ptr.p, c->col.p, brow.p, Bv.p, crowA.p);
+      const int64_t nac = exclusive_scan(crowA.p, sumD + 1, stmp.p, s);
+      clocA.alloc(std::max<int64_t>(nac, 1));
+      cbvA.alloc(std::max<int64_t>(9 * nac, 1));
+      hipLaunchKernelGGL(k_bcompact, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g,
+                         c->row_ptr.p, c->col.p, brow.p, Bv.p, crowA.p, clocA.p, cbvA.p);
+      GX_HIP(hipGetLastError());
+    }
     GX_HIP(hipStreamSynchronize(s));
     Bv.release();
     brow.release();
@@ -1080,8 +1131,8 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
     hipLaunchKernelGGL(k_bmul_rows, growD, dim3(64), 0, s, g, crow.p, cloc.p, cbv.p, m,
                        d_voff.p, active.p, Y.p, BY.p);
     if (m32)
-      hipLaunchKernelGGL(k_amul, growD, dim3(64), 0, s, g, m, d_voff.p, active.p, Y.p, BY.p,
-                         sigma, MY);
+      hipLaunchKernelGGL(k_amul_rows, growD, dim3(64), 0, s, g, crowA.p, clocA.p, cbvA.p, m,
+                         d_voff.p, active.p, Y.p, BY.p, sigma, MY);
     hipLaunchKernelGGL(k_gram, gch, dim3(256), 0, s, sw.d_nD.p, m, d_voff.p, active.p, Y.p,
                        MY, BY.p, nch_max, gpart.p);
     hipLaunchKernelGGL(k_gram_sum, dim3(nblocks(2 * MAXM * MAXM, 256), n_sub), dim3(256), 0,
