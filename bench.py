@@ -19,6 +19,21 @@ import os
 import sys
 import time
 
+HW_QUEUES_SWEEP = 16
+if any(a.startswith("--batch") for a in sys.argv[1:]):
+    # The sweep's concurrent set-ups are chains of small launches on several streams each,
+    # which HIP's default of 4 hardware queues serialises.  The runtime reads the count once,
+    # when it starts, so it is set here, before anything can start it (--hw-queues N).
+    _q = HW_QUEUES_SWEEP
+    for _i, _a in enumerate(sys.argv[1:]):
+        if _a == "--hw-queues" and _i + 2 < len(sys.argv):
+            _q = int(sys.argv[_i + 2])
+        elif _a.startswith("--hw-queues="):
+            _q = int(_a.split("=", 1)[1])
+    if not 1 <= _q <= 32:
+        sys.exit("--hw-queues must be 1 to 32")
+    os.environ["GPU_MAX_HW_QUEUES"] = str(_q)
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -92,7 +107,8 @@ def batch_sweep(gx, torch, workloads, args):
             "config": {"workload": f"{len(cfgs)} seeded wrinkled L-section samples",
                        "dofs_min": min(ndof), "dofs_max": max(ndof), "dofs_total": sum(ndof)},
             "setup_s": t1 - t0, "solve_s": t2 - t1, "pcg_solves_per_s": len(cfgs) / (t2 - t1),
-            "concurrent_setups": args.concurrent, "interior_band_entries": entries,
+            "concurrent_setups": args.concurrent,
+            "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"), "interior_band_entries": entries,
             # factor read once per sweep by the joint subdomain solve, all samples active
             "joint_solve_factor_bytes": 2 * w * entries,
             "iters": it.tolist(), "all_converged": bool(np.all(st == 0))}
@@ -130,8 +146,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead: the seeded sweep of wrinkled L-sections, this many samples")
-    ap.add_argument("--concurrent", type=int, default=4,
+    ap.add_argument("--concurrent", type=int, default=6,
                     help="with --batch: set-ups run at a time")
+    ap.add_argument("--hw-queues", type=int, default=HW_QUEUES_SWEEP,
+                    help="with --batch: HIP hardware queues of the process (1 to 32)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="instead: set up the workload, then launch one plain copy of "
                          "COPY_BYTES and one subdomain band solve (for hardware counters)")

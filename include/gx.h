@@ -215,7 +215,10 @@ gx_status gx_geneo_setup(gx_ctx* ctx, const gx_geneo_opts* opts, int32_t* nev_ou
  * opts[i], nev_out[i], n0_out + i) for every i, up to `concurrent` of them at a time on
  * host threads of the library, each context on its own stream.  While they run, each
  * context's multi-work-group launches take 3/4 of the device's resident capacity divided
- * by min(concurrent, n), so that concurrent launches stay resident together.  Each
+ * by min(concurrent, n), so that concurrent launches stay resident together.  Set-ups are
+ * chains of small launches on a few streams each, so they overlap only as far as the
+ * process has hardware queues (GPU_MAX_HW_QUEUES, read when the HIP runtime starts;
+ * HIP's default is 4).  Each
  * context appears once and its stream is not used by the caller meanwhile.  nev_out
  * (host array of n host pointers, each NULL or [opts[i]->n_sub]), n0_out and status_out
  * (host [n]) may be NULL.  Returns GX_EINVAL for bad arguments (nothing run), else GX_OK

@@ -512,7 +512,9 @@ class Batch:
     def setup(self, progress=None, concurrent=4):
         """Decomposition, GenEO coarse spaces and factors of every laminate, up to
         `concurrent` set-ups at a time (gx_geneo_setup_batch); progress(n - 1, n) is called
-        when all are done.  Returns [(nev per subdomain, n0)] per laminate."""
+        when all are done.  Returns [(nev per subdomain, n0)] per laminate.  More than four
+        at a time pays off only with more hardware queues than HIP's default of 4
+        (GPU_MAX_HW_QUEUES in the environment before the HIP runtime starts)."""
         n = len(self.solvers)
         parts, opts = [], []
         for cfg, s in zip(self.cfgs, self.solvers):
