@@ -63,36 +63,79 @@ __global__ void __launch_bounds__(256) k_potrf(BandArgs a, T* v, int64_t c0, dou
     }
   }
   __syncthreads();
-  // right-looking elimination on the unscaled columns (one barrier per column): step i
-  // subtracts D[r][i] D[s][i] / D[i][i] from the trailing triangle, thread (r, q) owning
-  // row r = t / 4 and the columns s = q mod 4; the columns are scaled by 1/sqrt(pivot) at
-  // the end.  A non-positive pivot is reported and replaced by 1.
+  // right-looking elimination on the unscaled columns: step i subtracts
+  // D[r][i] D[s][i] / D[i][i] from the trailing lower triangle (s <= r); the columns are
+  // scaled by 1/sqrt(pivot) at the end.  A non-positive pivot is reported and replaced by 1.
+  // The steps go in blocks of BK columns, with the same operations in the same order per
+  // entry: (1) wave 0 eliminates the BK x BK diagonal block in registers (lane r: row r,
+  // pivots and column entries from wave-uniform lane reads), (2) one thread per row below
+  // it applies the block's steps to its BK panel entries in registers and keeps the
+  // multipliers f = D[r][i] / D[i][i], (3) all threads apply the block's steps to the
+  // trailing lower triangle.  Three barriers per block instead of one per column.
+  constexpr int BK = 16;
   __shared__ double piv[NB];
+  __shared__ double F[NB][BK + 1];                 // multipliers of the current block
   {
-    const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
-    for (int i = 0; i < nb; ++i) {
-      double d = D[i][i];
-      if (!(d > 0.0)) d = 1.0;
-      if (r > i && r < nb) {
-        // this thread's columns s2 = s0 + 4 u <= r: all reads first, then the writes
-        // (column i is not written in step i, and no other thread writes this row's
-        // columns of residue q), so the LDS round trips overlap
-        const double f = D[r][i] / d;
-        const int s0 = i + 1 + ((q - (i + 1)) & 3);
-        double col[NB / 4], row[NB / 4];
+    for (int k0 = 0; k0 < nb; k0 += BK) {
+      const int kn = min(BK, nb - k0);             // steps of this block
+      if (threadIdx.x < 64) {                      // (1) diagonal block
+        const int lane = threadIdx.x;
+        const int rr = min(lane, BK - 1);
+        double a[BK];
 #pragma unroll
-        for (int u = 0; u < NB / 4; ++u) {         // slots past r read column i (unwritten)
-          const bool in = s0 + 4 * u <= r;
-          col[u] = D[in ? s0 + 4 * u : i][i];
-          row[u] = D[r][in ? s0 + 4 * u : i];
+        for (int c = 0; c < BK; ++c) a[c] = D[k0 + rr][k0 + c];
+#pragma unroll
+        for (int i = 0; i < BK; ++i) {
+          if (i < kn) {
+            const double dii = lane_value(a[i], i);
+            const double d = dii > 0.0 ? dii : 1.0;
+            const double f = a[i] / d;
+#pragma unroll
+            for (int s2 = i + 1; s2 < BK; ++s2) {
+              const double dsi = lane_value(a[i], s2);      // D[k0 + s2][k0 + i]
+              if (lane > i && lane < BK && s2 <= lane) a[s2] -= f * dsi;
+            }
+            if (lane == 0) {
+              if (!(dii > 0.0)) atomicOr(err, 1);
+              piv[k0 + i] = d;
+            }
+          }
+        }
+        if (lane < BK)
+#pragma unroll
+          for (int c = 0; c < BK; ++c)
+            if (c <= lane) D[k0 + lane][k0 + c] = a[c];
+      }
+      __syncthreads();
+      const int r0 = k0 + BK;                      // first row below the block
+      if (r0 + (int)threadIdx.x < NB) {            // (2) panel rows
+        const int r = r0 + threadIdx.x;
+        double p[BK];
+#pragma unroll
+        for (int c = 0; c < BK; ++c) p[c] = D[r][k0 + c];
+#pragma unroll
+        for (int i = 0; i < BK; ++i) {
+          if (i < kn) {
+            const double f = p[i] / piv[k0 + i];
+            F[r][i] = f;
+#pragma unroll
+            for (int s2 = i + 1; s2 < BK; ++s2) p[s2] -= f * D[k0 + s2][k0 + i];
+          }
         }
 #pragma unroll
-        for (int u = 0; u < NB / 4; ++u)
-          if (s0 + 4 * u <= r) D[r][s0 + 4 * u] = row[u] - f * col[u];
+        for (int c = 0; c < BK; ++c) D[r][k0 + c] = p[c];
       }
-      if (threadIdx.x == 0) {
-        if (!(D[i][i] > 0.0)) atomicOr(err, 1);
-        piv[i] = d;
+      __syncthreads();
+      // (3) trailing lower triangle rows and columns r0 .. NB - 1, entry e -> (r, s)
+      const int nt = NB - r0;
+      for (int e = threadIdx.x; e < nt * (nt + 1) / 2; e += blockDim.x) {
+        int r = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while ((r + 1) * (r + 2) / 2 <= e) ++r;
+        while (r * (r + 1) / 2 > e) --r;
+        const int s2 = e - r * (r + 1) / 2;
+        double x = D[r0 + r][r0 + s2];
+        for (int i = 0; i < kn; ++i) x -= F[r0 + r][i] * D[r0 + s2][k0 + i];
+        D[r0 + r][r0 + s2] = x;
       }
       __syncthreads();
     }

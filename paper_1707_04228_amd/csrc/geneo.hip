@@ -688,14 +688,6 @@ __global__ void __launch_bounds__(256) k_rayleigh_ritz(int m, const int32_t* act
   }
 }
 
-// v of lane l (l wave-uniform), through the scalar unit
-__device__ inline double lane_value(double v, int l) {
-  const long long bits = __double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(bits & 0xffffffffll), l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(bits >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 // out[i][b] = sum_a in[i][a] c[a][b] (row-major blocks of m columns).  A work-group takes
 // ROT_ROWS rows, so that the m x m matrix it stages in LDS serves many of them; each wave
 // forms four rows at a time (lane = column).

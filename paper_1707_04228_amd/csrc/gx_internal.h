@@ -178,6 +178,14 @@ inline void to_host(T* dst, const T* src, size_t n, hipStream_t s) {
 
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// v of lane l (l wave-uniform), through the scalar unit
+__device__ inline double lane_value(double v, int l) {
+  const long long bits = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(bits & 0xffffffffll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Exclusive prefix sum of n int64 values in place; returns the total.  tmp must hold
 // scan_tmp_size(n) elements.
 size_t scan_tmp_size(int64_t n);
