@@ -316,7 +316,8 @@ gx_status gx_kernel_time(gx_ctx* ctx, int32_t which, int32_t reps, double* avg_m
  * param 0: work-groups per subdomain for the single right-hand-side band solves (PCG);
  * param 1: work-groups per subdomain for the multi-column band solves (eigensolver).
  * Values 1..8; the library lowers a request that would not keep every work-group of the
- * pipelined launch resident on the device. */
+ * pipelined launch resident on the device.  The batched PCG (gx_pcg_solve_batch) plans the
+ * work-groups of its joint subdomain solve itself and ignores param 0. */
 gx_status gx_tune(gx_ctx* ctx, int32_t param, int64_t value);
 
 /* Counters of the last setup / solve (host [5]): eigensolver iterations, PCG iterations,
