@@ -155,7 +155,7 @@ def main():
                          "COPY_BYTES and one subdomain band solve (for hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
     import paper_1707_04228_amd as gx
