@@ -449,58 +449,59 @@ __global__ void k_fixed(int64_t n, const int32_t* nodes, uint8_t* fixed) {
 }
 
 // ---------------------------------------------------------------------------------------
-// y = K x, one 64-lane wavefront per block row; lane v of the row reads value v (values of
-// a row are contiguous, so every load instruction is a coalesced 512-byte segment), and
-// all loads of a row are in flight before the first product
+// y = K x, one 64-lane wavefront per block row.  The values of a row are contiguous, 9 per
+// 3x3 block.  Pass u takes the row's blocks 7 u .. 7 u + 6: lane l < 63 reads value
+// 63 u + l, i.e. entry l % 9 of block 7 u + l / 9, so every lane multiplies the same
+// entry position on every pass and keeps a single sum (the block-row component
+// (l % 9) / 3, the x component l % 3), and each pass is one coalesced 504-byte load of
+// values.  All value and column loads of a round are issued, then all gathers of x,
+// before the products.  The three components are then summed through LDS (lanes 0-2, the
+// 21 sums of their component in a fixed order).
+constexpr int SPMV_PASSES = 12;                   // 84 blocks per round (rows of the
+                                                  // 20-node meshes have at most 81)
 __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, const int32_t* __restrict__ rp,
                                               const int32_t* __restrict__ col,
                                               const double* __restrict__ val,
                                               const double* __restrict__ x,
                                               double* __restrict__ y) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= n_rows) return;
-  const int b0 = rp[row], b1 = rp[row + 1];
-  const int64_t v0 = (int64_t)b0 * 9;
-  const int nv = (b1 - b0) * 9;
-  double a0 = 0, a1 = 0, a2 = 0;
-  // VU passes of 64 values at a time: every value and column load of the passes is issued,
-  // then every gather of x, before the products (a row has at most 128 blocks, so one or
-  // two rounds); each lane still sums its values in order
-  constexpr int VU = 12;
-  for (int vb = 0; vb < nv; vb += 64 * VU) {
-    double pv[VU], xv[VU];
-    int cc[VU];
-    int64_t xi[VU];
+  __shared__ double red[4][64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + w;
+  if (row >= n_rows) return;                       // whole wavefronts
+  const int q = lane / 9, e = lane - 9 * q, c = e % 3;
+  const int b0 = rp[row], nb = rp[row + 1] - b0;
+  const double* vrow = val + (int64_t)b0 * 9 + e;
+  const int32_t* crow = col + b0;
+  double acc = 0.0;
+  for (int k0 = q; k0 < nb + q; k0 += 7 * SPMV_PASSES) {
+    double pv[SPMV_PASSES], xv[SPMV_PASSES];
+    int xi[SPMV_PASSES];
 #pragma unroll
-    for (int u = 0; u < VU; ++u) {
-      const int v = min(vb + 64 * u + lane, nv - 1);
-      const int blk = v / 9, c9 = v - 9 * blk;
-      cc[u] = c9;
-      pv[u] = val[v0 + v];
-      xi[u] = 3 * (int64_t)col[b0 + blk] + (c9 - 3 * (c9 / 3));
+    for (int u = 0; u < SPMV_PASSES; ++u) {
+      const int blk = min(k0 + 7 * u, nb - 1);    // clamped: masked below
+      pv[u] = vrow[9 * blk];
+      xi[u] = crow[blk];
     }
 #pragma unroll
-    for (int u = 0; u < VU; ++u) xv[u] = x[xi[u]];
+    for (int u = 0; u < SPMV_PASSES; ++u) xv[u] = x[3 * (int64_t)xi[u] + c];
 #pragma unroll
-    for (int u = 0; u < VU; ++u) {
-      const bool ok = vb + 64 * u + lane < nv;     // masked, not branched: loads stay hoisted
-      const double p = pv[u] * xv[u];
-      const int r = ok ? cc[u] / 3 : 3;
-      a0 += r == 0 ? p : 0.0;
-      a1 += r == 1 ? p : 0.0;
-      a2 += r == 2 ? p : 0.0;
+    for (int u = 0; u < SPMV_PASSES; ++u) {
+      const bool ok = lane < 63 && k0 + 7 * u < nb;  // masked, not branched
+      acc += ok ? pv[u] * xv[u] : 0.0;
     }
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    a0 += __shfl_xor(a0, off);
-    a1 += __shfl_xor(a1, off);
-    a2 += __shfl_xor(a2, off);
-  }
-  if (lane == 0) {
-    y[3 * row + 0] = a0;
-    y[3 * row + 1] = a1;
-    y[3 * row + 2] = a2;
+  // lanes of one wavefront exchange through LDS without a barrier: its LDS accesses are
+  // performed in order
+  red[w][lane] = acc;
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_wave_barrier();
+  if (lane < 3) {
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < 7; ++t)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) s += red[w][9 * t + 3 * lane + j];
+    y[3 * row + lane] = s;
   }
 }
 
