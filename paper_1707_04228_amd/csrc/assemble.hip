@@ -454,7 +454,8 @@ __global__ void k_fixed(int64_t n, const int32_t* nodes, uint8_t* fixed) {
 // 63 u + l, i.e. entry l % 9 of block 7 u + l / 9, so every lane multiplies the same
 // entry position on every pass and keeps a single sum (the block-row component
 // (l % 9) / 3, the x component l % 3), and each pass is one coalesced 504-byte load of
-// values.  All value and column loads of a round are issued, then all gathers of x,
+// values.  A row takes as many passes as it has blocks / 7 (rounds of 12 past 84 blocks).
+// All value and column loads of a round are issued, then all gathers of x,
 // before the products.  The three components are then summed through LDS (lanes 0-2, the
 // 21 sums of their component in a fixed order).
 constexpr int SPMV_PASSES = 12;                   // 84 blocks per round (rows of the
@@ -465,30 +466,52 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, const int32_t* __r
                                               const double* __restrict__ x,
                                               double* __restrict__ y) {
   __shared__ double red[4][64];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + w;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + w;  // uniform: the row bounds are scalar
   if (row >= n_rows) return;                       // whole wavefronts
   const int q = lane / 9, e = lane - 9 * q, c = e % 3;
   const int b0 = rp[row], nb = rp[row + 1] - b0;
   const double* vrow = val + (int64_t)b0 * 9 + e;
   const int32_t* crow = col + b0;
   double acc = 0.0;
-  for (int k0 = q; k0 < nb + q; k0 += 7 * SPMV_PASSES) {
-    double pv[SPMV_PASSES], xv[SPMV_PASSES];
-    int xi[SPMV_PASSES];
+  // one round of P passes over blocks k0 ..; lanes past the row's last block repeat it
+  // and are masked
+  auto round = [&](int k0, auto np) {
+    constexpr int P = decltype(np)::value;
+    double pv[P], xv[P];
+    int xi[P];
 #pragma unroll
-    for (int u = 0; u < SPMV_PASSES; ++u) {
-      const int blk = min(k0 + 7 * u, nb - 1);    // clamped: masked below
+    for (int u = 0; u < P; ++u) {
+      const int blk = min(k0 + 7 * u + q, nb - 1);
       pv[u] = vrow[9 * blk];
       xi[u] = crow[blk];
     }
 #pragma unroll
-    for (int u = 0; u < SPMV_PASSES; ++u) xv[u] = x[3 * (int64_t)xi[u] + c];
+    for (int u = 0; u < P; ++u) xv[u] = x[3 * (int64_t)xi[u] + c];
 #pragma unroll
-    for (int u = 0; u < SPMV_PASSES; ++u) {
-      const bool ok = lane < 63 && k0 + 7 * u < nb;  // masked, not branched
+    for (int u = 0; u < P; ++u) {
+      const bool ok = lane < 63 && k0 + 7 * u + q < nb;  // masked, not branched
       acc += ok ? pv[u] * xv[u] : 0.0;
     }
+  };
+  // exactly the passes the row needs (rounds of SPMV_PASSES past 7 SPMV_PASSES blocks)
+  using std::integral_constant;
+  switch ((nb + 6) / 7) {
+    case 0: break;
+    case 1: round(0, integral_constant<int, 1>{}); break;
+    case 2: round(0, integral_constant<int, 2>{}); break;
+    case 3: round(0, integral_constant<int, 3>{}); break;
+    case 4: round(0, integral_constant<int, 4>{}); break;
+    case 5: round(0, integral_constant<int, 5>{}); break;
+    case 6: round(0, integral_constant<int, 6>{}); break;
+    case 7: round(0, integral_constant<int, 7>{}); break;
+    case 8: round(0, integral_constant<int, 8>{}); break;
+    case 9: round(0, integral_constant<int, 9>{}); break;
+    case 10: round(0, integral_constant<int, 10>{}); break;
+    case 11: round(0, integral_constant<int, 11>{}); break;
+    default:
+      for (int k0 = 0; k0 < nb; k0 += 7 * SPMV_PASSES)
+        round(k0, integral_constant<int, SPMV_PASSES>{});
   }
   // lanes of one wavefront exchange through LDS without a barrier: its LDS accesses are
   // performed in order
