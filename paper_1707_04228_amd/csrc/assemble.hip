@@ -454,10 +454,11 @@ __global__ void k_fixed(int64_t n, const int32_t* nodes, uint8_t* fixed) {
 // 63 u + l, i.e. entry l % 9 of block 7 u + l / 9, so every lane multiplies the same
 // entry position on every pass and keeps a single sum (the block-row component
 // (l % 9) / 3, the x component l % 3), and each pass is one coalesced 504-byte load of
-// values.  A row takes as many passes as it has blocks / 7 (rounds of 12 past 84 blocks).
-// All value and column loads of a round are issued, then all gathers of x,
-// before the products.  The three components are then summed through LDS (lanes 0-2, the
-// 21 sums of their component in a fixed order).
+// values.  A row takes ceil(blocks / 7) passes (rounds of 12 past 84 blocks).  All value
+// loads of a round are issued; its column indices are loaded once, one block per lane, and
+// passed between lanes; then all gathers of x are issued, before the products.  The three
+// components are then summed through LDS (lanes 0-2, the 21 sums of their component in a
+// fixed order).
 constexpr int SPMV_PASSES = 12;                   // 84 blocks per round (rows of the
                                                   // 20-node meshes have at most 81)
 __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, const int32_t* __restrict__ rp,
@@ -479,15 +480,29 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, const int32_t* __r
   auto round = [&](int k0, auto np) {
     constexpr int P = decltype(np)::value;
     double pv[P], xv[P];
-    int xi[P];
+    // the round's column indices, one block per lane (blocks k0 + 64 .. in a second
+    // register past 64 blocks); pass u takes block 7 u + q's from its lane
+    const int cl0 = crow[min(k0 + lane, nb - 1)];
+    const int cl1 = 7 * P > 64 ? crow[min(k0 + 64 + lane, nb - 1)] : 0;
+#pragma unroll
+    for (int u = 0; u < P; ++u) pv[u] = vrow[9 * min(k0 + 7 * u + q, nb - 1)];
 #pragma unroll
     for (int u = 0; u < P; ++u) {
-      const int blk = min(k0 + 7 * u + q, nb - 1);
-      pv[u] = vrow[9 * blk];
-      xi[u] = crow[blk];
+      const int b = 7 * u + q;                     // block within the round (< 84)
+      // (a permute reads 0 from an inactive lane, so both run with the whole wavefront
+      // active and the block's register is selected afterwards)
+      int xi;
+      if (7 * u + 6 < 64) {
+        xi = __builtin_amdgcn_ds_bpermute(4 * b, cl0);
+      } else if (7 * u >= 64) {
+        xi = __builtin_amdgcn_ds_bpermute(4 * (b - 64), cl1);
+      } else {
+        const int i0 = __builtin_amdgcn_ds_bpermute(4 * (b & 63), cl0);
+        const int i1 = __builtin_amdgcn_ds_bpermute(4 * (b & 63), cl1);
+        xi = b < 64 ? i0 : i1;
+      }
+      xv[u] = x[3 * (int64_t)xi + c];
     }
-#pragma unroll
-    for (int u = 0; u < P; ++u) xv[u] = x[3 * (int64_t)xi[u] + c];
 #pragma unroll
     for (int u = 0; u < P; ++u) {
       const bool ok = lane < 63 && k0 + 7 * u + q < nb;  // masked, not branched
