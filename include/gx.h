@@ -259,6 +259,19 @@ gx_status gx_pcg_solve(gx_ctx* ctx, const double* b, double* x, double rtol, int
 /* J for the displacement u (device, 3 n_nodes). */
 gx_status gx_objective(gx_ctx* ctx, const gx_laminate* lam, int32_t region, const double* u,
                        double* J_out);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving or optimisation loops, harnesses that forbid hipMalloc): gx_objective with no
+ * allocation.  Its scratch (the element mask, J per element and their sum) lives in one
+ * static device array of GX_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from
+ * the first gx_create on that GPU until the process ends.  The mesh must satisfy
+ * 9 n_elems + 256 <= GX_NOALLOC_SCRATCH_BYTES (about 1.86 million elements), else
+ * GX_EINVAL and nothing is launched.  Every call on a GPU shares that GPU's array and
+ * overwrites what the last call left there (nothing in it needs to start at zero), so
+ * calls that overlap in time on one GPU, from any contexts or threads, race.  J equals
+ * gx_objective's bit for bit (same kernels, same summation order). */
+#define GX_NOALLOC_SCRATCH_BYTES (16u << 20)
+gx_status gx_objective_noalloc(gx_ctx* ctx, const gx_laminate* lam, int32_t region,
+                               const double* u, double* J_out);
 /* J and dJ/dp by the adjoint method: K lambda = dJ/du is solved by PCG with the current
  * preconditioner to rtol (iters_out: its iterations), then
  * dJ/dp = dJ/dp|_u - lambda^T (dK/dp u - df/dp).  dJdp (host) receives 2 + n_layers

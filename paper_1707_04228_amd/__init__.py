@@ -101,6 +101,7 @@ for _name, _args in [("gx_geneo_setup", [vp, C.POINTER(GeneoOpts), i32p, i64p]),
                      ("gx_band_factor_solve", [vp, C.c_int32, i64p, i64p, vp, C.c_int32,
                                                C.c_int32, C.c_int32, vp]),
                      ("gx_objective", [vp, C.POINTER(Laminate), C.c_int32, vp, f64p]),
+                     ("gx_objective_noalloc", [vp, C.POINTER(Laminate), C.c_int32, vp, f64p]),
                      ("gx_pcg_solve_batch", [C.c_int32, C.POINTER(vp), C.POINTER(vp),
                                              C.POINTER(vp), C.c_double, C.c_int32, i32p, f64p,
                                              i32p]),
@@ -117,7 +118,8 @@ EXPORTS = ["gx_create", "gx_destroy", "gx_last_error", "gx_version", "gx_laminat
            "gx_assemble", "gx_matrix_info", "gx_matrix_copy", "gx_spmv", "gx_geneo_setup",
            "gx_subdomain_info", "gx_geneo_eigenvalues", "gx_precond_apply", "gx_pcg_solve",
            "gx_phase_times", "gx_kernel_time", "gx_stats", "gx_tune", "gx_band_factor_solve",
-           "gx_objective", "gx_adjoint", "gx_pcg_solve_batch", "gx_geneo_setup_batch"]
+           "gx_objective", "gx_objective_noalloc", "gx_adjoint", "gx_pcg_solve_batch",
+           "gx_geneo_setup_batch"]
 
 
 class GxError(RuntimeError):
@@ -366,6 +368,15 @@ class Solver:
         lam, keep = laminate_struct(cfg or self.mesh["cfg"])
         J = C.c_double()
         self._check(lib.gx_objective(self.h, C.byref(lam), region, _ptr(u), C.byref(J)))
+        return J.value
+
+    @_on_stream
+    def objective_noalloc(self, u, cfg=None, region=1):
+        """gx_objective_noalloc: J with the library's static scratch, no device allocation."""
+        lam, keep = laminate_struct(cfg or self.mesh["cfg"])
+        J = C.c_double()
+        self._check(lib.gx_objective_noalloc(self.h, C.byref(lam), region, _ptr(u),
+                                             C.byref(J)))
         return J.value
 
     @_on_stream

@@ -368,14 +368,24 @@ __global__ void k_keyed_sum(int64_t n, const double* v, const int32_t* key, int 
   if (threadIdx.x == 0 && k < n_keys) out[k] = red[0];
 }
 
-static double dev_sum(const double* v, int64_t n, hipStream_t st) {
-  DevBuf<double> o(1);
+// sum of v[0..n) in a fixed order, through the one-value device buffer o
+static double dev_sum_into(const double* v, int64_t n, double* o, hipStream_t st) {
   hipLaunchKernelGGL(k_keyed_sum, dim3(1), dim3(256), 0, st, n, v, (const int32_t*)nullptr, 1,
-                     o.p);
+                     o);
   GX_HIP(hipGetLastError());
   double h = 0.0;
-  to_host(&h, o.p, 1, st);
+  to_host(&h, o, 1, st);
   return h;
+}
+
+static double dev_sum(const double* v, int64_t n, hipStream_t st) {
+  DevBuf<double> o(1);
+  return dev_sum_into(v, n, o.p, st);
+}
+
+__global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 static SensArgs sens_args(gx_ctx* c, const double* u, const double* lam, const double* xd,
@@ -386,26 +396,68 @@ static SensArgs sens_args(gx_ctx* c, const double* u, const double* lam, const d
 
 static unsigned sens_grid(int64_t E) { return (unsigned)std::min<int64_t>(E, 256 * 64); }
 
-// J and (grad != null) dJ/du
-static double objective(gx_ctx* c, const gx_laminate* lam, int32_t region_kind, const double* u,
-                        DevBuf<uint8_t>& region, double* grad) {
-  hipStream_t st = c->stream;
-  const int64_t E = c->n_elems;
+static void check_objective_laminate(gx_ctx* c, const gx_laminate* lam) {
   int64_t nn = 0, ne = 0;
   laminate_sizes(lam, &nn, &ne);
-  GX_REQUIRE(nn == c->n_nodes && ne == E, "laminate does not match the assembled mesh");
-  region.alloc(E);
+  GX_REQUIRE(nn == c->n_nodes && ne == c->n_elems, "laminate does not match the assembled mesh");
+}
+
+// J and (grad != null) dJ/du, with the caller's buffers: region [n_elems] (the element mask),
+// jv [n_elems] (J per element) and sum [1]
+static double objective_into(gx_ctx* c, const gx_laminate* lam, int32_t region_kind,
+                             const double* u, uint8_t* region, double* jv, double* sum,
+                             double* grad) {
+  hipStream_t st = c->stream;
+  const int64_t E = c->n_elems;
   if (region_kind == 0) {
-    GX_HIP(hipMemsetAsync(region.p, 1, E, st));
+    hipLaunchKernelGGL(k_fill_u8, dim3(nblocks(E, 256)), dim3(256), 0, st, region, E,
+                       (uint8_t)1);
+    GX_HIP(hipGetLastError());
   } else {
-    laminate_region(lam, region.p, st);
+    laminate_region(lam, region, st);
   }
-  DevBuf<double> jv(E);
   hipLaunchKernelGGL(k_sens<double>, dim3(sens_grid(E)), dim3(64), sizeof(SensSmem), st,
-                     sens_args(c, u, nullptr, nullptr, nullptr, region.p), E, (double*)nullptr,
-                     jv.p, (double*)nullptr, grad);
+                     sens_args(c, u, nullptr, nullptr, nullptr, region), E, (double*)nullptr,
+                     jv, (double*)nullptr, grad);
   GX_HIP(hipGetLastError());
-  return dev_sum(jv.p, E, st);
+  return dev_sum_into(jv, E, sum, st);
+}
+
+static double objective(gx_ctx* c, const gx_laminate* lam, int32_t region_kind, const double* u,
+                        DevBuf<uint8_t>& region, double* grad) {
+  check_objective_laminate(c, lam);
+  const int64_t E = c->n_elems;
+  region.alloc(E);
+  DevBuf<double> jv(E), sum(1);
+  return objective_into(c, lam, region_kind, u, region.p, jv.p, sum.p, grad);
+}
+
+// ---- scratch of the allocation-free objective (gx_objective_noalloc)
+// One array per device, held until the process ends.  In host code the name `scratch` only
+// stands for the symbol: its device address comes from hipGetSymbolAddress (per device, in
+// noalloc_scratch_init) and only that address is ever passed to kernels or copies.
+constexpr size_t NOALLOC_BYTES = GX_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_ptr;           // device address per device (null: unset)
+
+// Resolve the scratch array's address on `device`, which must be current (gx_create).
+void noalloc_scratch_init(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  GX_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw Error(GX_EHIP, "hipGetSymbolAddress returned a null scratch address");
+  g_scratch_ptr[device] = p;
+}
+
+static unsigned char* noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device >= (int)g_scratch_ptr.size() || !g_scratch_ptr[device])
+    throw Error(GX_ESTATE, "the scratch array of this device was not set up");
+  return static_cast<unsigned char*>(g_scratch_ptr[device]);
 }
 
 }  // namespace gx
@@ -421,6 +473,27 @@ gx_status gx_objective(gx_ctx* c, const gx_laminate* lam, int32_t region, const 
   GX_REQUIRE(lam && u && J_out && (region == 0 || region == 1), "bad objective arguments");
   DevBuf<uint8_t> mask;
   *J_out = objective(c, lam, region, u, mask, nullptr);
+  GX_API_END(c)
+}
+
+gx_status gx_objective_noalloc(gx_ctx* c, const gx_laminate* lam, int32_t region,
+                               const double* u, double* J_out) {
+  GX_API_BEGIN(c)
+  if (!c->assembled) throw Error(GX_ESTATE, "matrix not assembled");
+  GX_REQUIRE(lam && u && J_out && (region == 0 || region == 1), "bad objective arguments");
+  check_objective_laminate(c, lam);
+  // layout: the sum at 0, J per element at 256, the region mask after it
+  const int64_t E = c->n_elems;
+  const size_t need = 256 + 8 * (size_t)E + (size_t)E;
+  if (need > NOALLOC_BYTES)
+    throw Error(GX_EINVAL, "mesh too large for the allocation-free objective: " +
+                               std::to_string(need) + " bytes of scratch needed, " +
+                               std::to_string(NOALLOC_BYTES) + " available");
+  unsigned char* base = noalloc_scratch(c->device);
+  double* sum = reinterpret_cast<double*>(base);
+  double* jv = reinterpret_cast<double*>(base + 256);
+  uint8_t* mask = base + 256 + 8 * (size_t)E;
+  *J_out = objective_into(c, lam, region, u, mask, jv, sum, nullptr);
   GX_API_END(c)
 }
 

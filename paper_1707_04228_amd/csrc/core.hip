@@ -291,6 +291,7 @@ gx_status gx_create(gx_ctx** out, int32_t device, void* hip_stream) {
     c = new gx_ctx();
     c->device = device;
     GX_HIP(hipSetDevice(device));
+    gx::noalloc_scratch_init(device);
     if (hip_stream) {
       c->stream = (hipStream_t)hip_stream;
     } else {

@@ -395,6 +395,9 @@ void precond_finish(gx_ctx* c, const double* r, double* z);
 void laminate_velocity(const gx_laminate* lam, int param, double* xd, hipStream_t st);
 void laminate_region(const gx_laminate* lam, uint8_t* mask, hipStream_t st);
 void laminate_sizes(const gx_laminate* lam, int64_t* n_nodes, int64_t* n_elems);
+// device address of the allocation-free entry points' scratch array (adjoint.hip), resolved
+// once per device with that device current
+void noalloc_scratch_init(int device);
 // HIP event pair on a stream (timing of single launches)
 struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
