@@ -16,6 +16,8 @@ It is a plain, slow, obviously correct restatement of what the paper computes:
 * ``dd``        overlapping decomposition, interior DOF sets and partition of unity
                 (section 2.3, Fig. fig-domaindecomp);
 * ``geneo``     local generalised eigenproblems and the GenEO coarse space (section 2.3);
+* ``direct``    exact sparse direct solves of the local and coarse problems (section 2.4):
+                SuperLU, or LAPACK banded Cholesky for large banded subdomain matrices;
 * ``pcg``       the two-level additive Schwarz preconditioner of Eq. (eq-pre) and CG.
 
 Every function cites the passage it follows.  Where the paper is silent the reading used

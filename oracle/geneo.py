@@ -31,6 +31,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+from .direct import factorized
 from .fem import assemble
 
 
@@ -50,10 +51,13 @@ def local_matrices(dec, j):
     return AN, B, xt, pos
 
 
-def solve_local_eigen(AN, B, nev=0, tau=0.1, nev_max=32, tol=1e-13, dense=None):
+def solve_local_eigen(AN, B, nev=0, tau=0.1, nev_max=32, tol=1e-13, dense=None,
+                      factor="superlu"):
     """Smallest eigenpairs of A^N p = lambda B p by shift-invert (or dense for tiny sizes).
 
     dense=None picks the dense solver below 600 DOFs, True/False force one or the other.
+    factor: the direct method of the shifted matrix A^N + sigma B (see direct.py); ARPACK
+    and the purification step share that one factorisation.
     """
     n = AN.shape[0]
     shift = 1e-4 * (tau if tau else 1.0) if nev > 0 else 1e-3 * tau
@@ -70,12 +74,13 @@ def solve_local_eigen(AN, B, nev=0, tau=0.1, nev_max=32, tol=1e-13, dense=None):
     k = nev if nev > 0 else min(8, nev_max)
     v0 = np.random.default_rng(n).standard_normal(n)
     Msh = (AN + shift * B).tocsc()
-    lu = spla.splu(Msh)
+    solve = factorized(Msh, factor)
+    opinv = spla.LinearOperator((n, n), matvec=solve, dtype=np.float64)
     while True:
         kk = min(k, n - 2)
         _, V = spla.eigsh(AN, k=kk, M=B, sigma=-shift, which="LM", tol=tol, v0=v0,
-                          ncv=min(n - 1, max(2 * kk + 1, kk + 40)))
-        V = lu.solve(B @ V)
+                          ncv=min(n - 1, max(2 * kk + 1, kk + 40)), OPinv=opinv)
+        V = solve(B @ V)
         mu, C = sla.eigh(V.T @ (B @ V), V.T @ (Msh @ V))
         V = V @ C
         lam = 1.0 / mu - shift
@@ -95,13 +100,17 @@ def solve_local_eigen(AN, B, nev=0, tau=0.1, nev_max=32, tol=1e-13, dense=None):
 
 
 class Coarse:
-    def __init__(self, dec, nev=0, tau=0.1, nev_max=32, dense=None):
+    def __init__(self, dec, nev=0, tau=0.1, nev_max=32, dense=None, factor="superlu",
+                 progress=None):
         self.dec = dec
         n = dec.prob.n
         cols, self.lams, self.nev = [], [], []
         for j in range(dec.n_sub):
             AN, B, xt, pos = local_matrices(dec, j)
-            lam, V = solve_local_eigen(AN, B, nev=nev, tau=tau, nev_max=nev_max, dense=dense)
+            lam, V = solve_local_eigen(AN, B, nev=nev, tau=tau, nev_max=nev_max, dense=dense,
+                                       factor=factor)
+            if progress:
+                progress(f"eigensolve {j + 1}/{dec.n_sub}: {len(lam)} modes")
             self.lams.append(lam)
             self.nev.append(len(lam))
             for c in range(V.shape[1]):

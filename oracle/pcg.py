@@ -17,20 +17,21 @@ estimate of the extreme eigenvalues of P K.
 from __future__ import annotations
 
 import numpy as np
-import scipy.sparse.linalg as spla
+
+from .direct import factorized
 
 
 class Schwarz:
-    def __init__(self, dec, coarse=None):
+    def __init__(self, dec, coarse=None, factor="superlu"):
         self.dec = dec
         self.coarse = coarse
         K = dec.prob.K
-        self.lu = [spla.splu(K[Ij][:, Ij].tocsc()) for Ij in dec.I]
+        self.solves = [factorized(K[Ij][:, Ij], factor) for Ij in dec.I]
 
     def apply(self, r):
         z = np.zeros_like(r)
-        for Ij, lu in zip(self.dec.I, self.lu):
-            z[Ij] += lu.solve(r[Ij])
+        for Ij, solve in zip(self.dec.I, self.solves):
+            z[Ij] += solve(r[Ij])
         if self.coarse is not None:
             z += self.coarse.apply(r)
         return z
@@ -85,8 +86,10 @@ def lanczos_extremes(alphas, betas):
     return ev[0], ev[-1]
 
 
-def solve(cfg, prob=None, one_level=False, rtol=None, dense_eigen=None, maxit=2000):
-    """Full oracle pipeline for a laminate descriptor; returns a dict of results."""
+def solve(cfg, prob=None, one_level=False, rtol=None, dense_eigen=None, maxit=2000,
+          factor="superlu", progress=None):
+    """Full oracle pipeline for a laminate descriptor; returns a dict of results.
+    factor: direct method of the subdomain and eigensolver factorisations (direct.py)."""
     from .dd import Decomposition, box_partition
     from .fem import Problem
     from .geneo import Coarse
@@ -95,8 +98,9 @@ def solve(cfg, prob=None, one_level=False, rtol=None, dense_eigen=None, maxit=20
     part = box_partition(prob.mesh, s["px"], s["py"])
     dec = Decomposition(prob, part, s["overlap"])
     coarse = None if one_level else Coarse(dec, nev=s["nev"] or 0, tau=s["tau"] or 0.1,
-                                           nev_max=s["nev_max"], dense=dense_eigen)
-    P = Schwarz(dec, coarse)
+                                           nev_max=s["nev_max"], dense=dense_eigen,
+                                           factor=factor, progress=progress)
+    P = Schwarz(dec, coarse, factor=factor)
     x, it, hist, ab = pcg(prob.K, prob.f, P.apply, rtol=rtol or s["rtol"], maxit=maxit)
     return dict(prob=prob, dec=dec, coarse=coarse, P=P, x=x, iters=it, hist=hist,
                 alphas=ab[0], betas=ab[1])

@@ -476,9 +476,9 @@ def _laminate_objective_fn():
             part = s.partition(c, sv["px"], sv["py"])
             s.geneo_setup(part, sv["px"] * sv["py"], overlap=sv["overlap"],
                           tau=sv["tau"] or 0.1, nev=sv["nev"] or 0, nev_max=sv["nev_max"])
-            u = s.pcg(f, rtol=rtol, maxit=5000, allow_noconv=True)["x"]
-            J, g, _ = s.adjoint(u, c, region=region, rtol=rtol, maxit=5000,
-                                allow_noconv=True)
+            # an unconverged primal or adjoint solve raises GxError (GX_ENOCONV)
+            u = s.pcg(f, rtol=rtol, maxit=5000)["x"]
+            J, g, _ = s.adjoint(u, c, region=region, rtol=rtol, maxit=5000)
             s.close()
             ctx.save_for_backward(torch.tensor(g, dtype=torch.float64))
             return torch.tensor(J, dtype=torch.float64)

@@ -77,7 +77,8 @@ struct SensSmem {
 
 // One 64-lane work-group per element, lane q < 27 at Gauss point q.  Outputs per element:
 // s[e] = derivative part of lambda_e^T K_e u_e, jv[e] = J_e (value), jd[e] = derivative
-// part of J_e; with grad != null (value mode) dJ/du is added into grad.
+// part of J_e; with grad != null (value mode) grad[60 e + 3 a + i] receives dJ_e/du of
+// element node a, component i (k_grad_gather sums them per node).
 template <class R>
 __global__ void __launch_bounds__(64) k_sens(SensArgs A, int64_t n_elems, double* s,
                                              double* jv, double* jd, double* grad) {
@@ -254,13 +255,34 @@ __global__ void __launch_bounds__(64) k_sens(SensArgs A, int64_t n_elems, double
       if (jv) jv[e] = a1;
       if (jd) jd[e] = a2;
     }
-    if (grad && obj && t < 60) {
+    if (grad && t < 60) {
       double acc = 0.0;
-      for (int q = 0; q < 27; ++q) acc += sm.red[q][t];
-      const int64_t dof = 3 * (int64_t)A.conn[20 * e + t / 3] + t % 3;
-      if (!A.fixed[dof]) atomicAdd(&grad[dof], acc);
+      if (obj)
+        for (int q = 0; q < 27; ++q) acc += sm.red[q][t];
+      grad[60 * e + t] = acc;
     }
   }
+}
+
+// dJ/du at every node from the per-element parts ge [60 n_elems] of k_sens: the node's
+// elements in ascending order (fixed summation order, no atomics); zero on clamped DOFs
+__global__ void k_grad_gather(int64_t n_nodes, const int32_t* ne_ptr, const int32_t* ne_idx,
+                              const int32_t* conn, const double* ge, const uint8_t* fixed,
+                              double* grad) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= n_nodes) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int32_t k = ne_ptr[n]; k < ne_ptr[n + 1]; ++k) {
+    const int64_t e = ne_idx[k];
+    int a = 0;
+    while (a < 19 && conn[20 * e + a] != (int32_t)n) ++a;
+    a0 += ge[60 * e + 3 * a];
+    a1 += ge[60 * e + 3 * a + 1];
+    a2 += ge[60 * e + 3 * a + 2];
+  }
+  grad[3 * n] = fixed[3 * n] ? 0.0 : a0;
+  grad[3 * n + 1] = fixed[3 * n + 1] ? 0.0 : a1;
+  grad[3 * n + 2] = fixed[3 * n + 2] ? 0.0 : a2;
 }
 
 // lambda^T df/dp of the face loads: the consistent load of a face (3x3 Gauss rule, traction
@@ -402,11 +424,11 @@ static void check_objective_laminate(gx_ctx* c, const gx_laminate* lam) {
   GX_REQUIRE(nn == c->n_nodes && ne == c->n_elems, "laminate does not match the assembled mesh");
 }
 
-// J and (grad != null) dJ/du, with the caller's buffers: region [n_elems] (the element mask),
-// jv [n_elems] (J per element) and sum [1]
+// J and (grad != null) dJ/du [3 n_nodes], with the caller's buffers: region [n_elems] (the
+// element mask), jv [n_elems] (J per element), sum [1] and, with grad, ge [60 n_elems]
 static double objective_into(gx_ctx* c, const gx_laminate* lam, int32_t region_kind,
                              const double* u, uint8_t* region, double* jv, double* sum,
-                             double* grad) {
+                             double* ge, double* grad) {
   hipStream_t st = c->stream;
   const int64_t E = c->n_elems;
   if (region_kind == 0) {
@@ -418,8 +440,13 @@ static double objective_into(gx_ctx* c, const gx_laminate* lam, int32_t region_k
   }
   hipLaunchKernelGGL(k_sens<double>, dim3(sens_grid(E)), dim3(64), sizeof(SensSmem), st,
                      sens_args(c, u, nullptr, nullptr, nullptr, region), E, (double*)nullptr,
-                     jv, (double*)nullptr, grad);
+                     jv, (double*)nullptr, ge);
   GX_HIP(hipGetLastError());
+  if (grad) {
+    hipLaunchKernelGGL(k_grad_gather, dim3(nblocks(c->n_nodes, 256)), dim3(256), 0, st,
+                       c->n_nodes, c->ne_ptr.p, c->ne_idx.p, c->conn.p, ge, c->fixed.p, grad);
+    GX_HIP(hipGetLastError());
+  }
   return dev_sum_into(jv, E, sum, st);
 }
 
@@ -428,8 +455,8 @@ static double objective(gx_ctx* c, const gx_laminate* lam, int32_t region_kind, 
   check_objective_laminate(c, lam);
   const int64_t E = c->n_elems;
   region.alloc(E);
-  DevBuf<double> jv(E), sum(1);
-  return objective_into(c, lam, region_kind, u, region.p, jv.p, sum.p, grad);
+  DevBuf<double> jv(E), sum(1), ge(grad ? 60 * E : 0);
+  return objective_into(c, lam, region_kind, u, region.p, jv.p, sum.p, ge.p, grad);
 }
 
 // ---- scratch of the allocation-free objective (gx_objective_noalloc)
@@ -493,7 +520,7 @@ gx_status gx_objective_noalloc(gx_ctx* c, const gx_laminate* lam, int32_t region
   double* sum = reinterpret_cast<double*>(base);
   double* jv = reinterpret_cast<double*>(base + 256);
   uint8_t* mask = base + 256 + 8 * (size_t)E;
-  *J_out = objective_into(c, lam, region, u, mask, jv, sum, nullptr);
+  *J_out = objective_into(c, lam, region, u, mask, jv, sum, nullptr, nullptr);
   GX_API_END(c)
 }
 

@@ -11,6 +11,7 @@
 //   5. deterministic gather: every block row sums its elements' blocks in element order
 //      (no floating-point atomics), then clamped DOFs become identity rows / columns;
 //   6. consistent face loads from a 3x3 Gauss rule on each loaded face.
+#include <algorithm>
 #include <cmath>
 
 #include "element.h"
@@ -390,10 +391,12 @@ __global__ void __launch_bounds__(64) k_gather(const int32_t* conn, const int32_
 
 // ---------------------------------------------------------------------------------------
 // 6. consistent face loads; t = t0 + k ((x - c) . d) n_out, 3x3 Gauss rule on the face;
-//    one thread per (face, element node), summed into f with FP64 atomics
+//    one thread per (face, element node) writes its three components to fl; k_face_gather
+//    then sums each node's entries in a fixed order (face, then local node), so f is the
+//    same bit for bit on every run
 __global__ void k_face_loads(int64_t n_faces, const int32_t* fe, const int32_t* fid,
                              const double* xyz, const int32_t* conn, gx_traction tr,
-                             const uint8_t* fixed, double* f) {
+                             double* fl) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n_faces * 20) return;
   const int64_t e = fe[idx / 20];
@@ -435,10 +438,29 @@ __global__ void k_face_loads(int64_t n_faces, const int32_t* fe, const int32_t* 
       fl1 += (tr.t0[1] + lin * sgn * nv1 / dA) * w;
       fl2 += (tr.t0[2] + lin * sgn * nv2 / dA) * w;
     }
-  const int64_t d = 3 * (int64_t)conn[20 * e + na];
-  if (!fixed[d] && fl0 != 0.0) atomicAdd(&f[d], fl0);
-  if (!fixed[d + 1] && fl1 != 0.0) atomicAdd(&f[d + 1], fl1);
-  if (!fixed[d + 2] && fl2 != 0.0) atomicAdd(&f[d + 2], fl2);
+  fl[3 * idx] = fl0;
+  fl[3 * idx + 1] = fl1;
+  fl[3 * idx + 2] = fl2;
+}
+
+// f at the loaded nodes: node unode[i] sums the entries uidx[uptr[i] .. uptr[i + 1]) of fl
+// (ascending (face, local node) order); clamped components stay zero
+__global__ void k_face_gather(int64_t n_unique, const int32_t* uptr, const int32_t* uidx,
+                              const int32_t* unode, const double* fl, const uint8_t* fixed,
+                              double* f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_unique) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int32_t k = uptr[i]; k < uptr[i + 1]; ++k) {
+    const int64_t j = uidx[k];
+    a0 += fl[3 * j];
+    a1 += fl[3 * j + 1];
+    a2 += fl[3 * j + 2];
+  }
+  const int64_t d = 3 * (int64_t)unode[i];
+  f[d] = fixed[d] ? 0.0 : a0;
+  f[d + 1] = fixed[d + 1] ? 0.0 : a1;
+  f[d + 2] = fixed[d + 2] ? 0.0 : a2;
 }
 
 __global__ void k_fixed(int64_t n, const int32_t* nodes, uint8_t* fixed) {
@@ -576,8 +598,9 @@ gx_status gx_assemble(gx_ctx* c, const gx_mesh* m, const gx_plystack* ps, const 
   GX_HIP(hipMemcpyAsync(c->xyz.p, m->xyz, 3 * N * sizeof(double), hipMemcpyDefault, s));
   GX_HIP(hipMemcpyAsync(c->conn.p, m->conn, 20 * E * sizeof(int32_t), hipMemcpyDefault, s));
   GX_HIP(hipMemcpyAsync(c->elayer.p, m->elem_layer, E * sizeof(int32_t), hipMemcpyDefault, s));
+  std::vector<int32_t> hc(20 * E);                 // host copy of conn (checks, face loads)
   {  // validate indices on the host side of a copy (cheap relative to assembly)
-    std::vector<int32_t> hc(20 * E), hl(E);
+    std::vector<int32_t> hl(E);
     to_host(hc.data(), c->conn.p, 20 * E, s);
     to_host(hl.data(), c->elayer.p, E, s);
     for (int32_t v : hc) GX_REQUIRE(v >= 0 && v < N, "connectivity index out of range");
@@ -666,9 +689,31 @@ gx_status gx_assemble(gx_ctx* c, const gx_mesh* m, const gx_plystack* ps, const 
     c->traction = ld->traction;
     to_dev(de.p, he.data(), he.size(), s);
     to_dev(df.p, hf.data(), hf.size(), s);
-    hipLaunchKernelGGL(k_face_loads, dim3(nblocks(ld->n_faces * 20, 64)), dim3(64), 0, s,
+    const int64_t nent = ld->n_faces * 20;
+    DevBuf<double> fl(3 * nent);
+    hipLaunchKernelGGL(k_face_loads, dim3(nblocks(nent, 64)), dim3(64), 0, s,
                        (int64_t)ld->n_faces, de.p, df.p, c->xyz.p, c->conn.p, ld->traction,
-                       c->fixed.p, f_out);
+                       fl.p);
+    GX_HIP(hipGetLastError());
+    // per node, its (face, local node) entries in ascending order
+    std::vector<int32_t> order(nent);
+    for (int64_t k = 0; k < nent; ++k) order[k] = (int32_t)k;
+    auto node_of = [&](int32_t k) { return hc[20 * (int64_t)he[k / 20] + k % 20]; };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return node_of(a) < node_of(b); });
+    std::vector<int32_t> uptr{0}, unode;
+    for (int64_t k = 0; k < nent; ++k) {
+      if (k > 0 && node_of(order[k]) != node_of(order[k - 1])) uptr.push_back((int32_t)k);
+      if (k == 0 || node_of(order[k]) != node_of(order[k - 1])) unode.push_back(node_of(order[k]));
+    }
+    uptr.push_back((int32_t)nent);
+    DevBuf<int32_t> d_uptr(uptr.size()), d_uidx(nent), d_unode(unode.size());
+    to_dev(d_uptr.p, uptr.data(), uptr.size(), s);
+    to_dev(d_uidx.p, order.data(), order.size(), s);
+    to_dev(d_unode.p, unode.data(), unode.size(), s);
+    hipLaunchKernelGGL(k_face_gather, dim3(nblocks((int64_t)unode.size(), 256)), dim3(256), 0, s,
+                       (int64_t)unode.size(), d_uptr.p, d_uidx.p, d_unode.p, fl.p, c->fixed.p,
+                       f_out);
     GX_HIP(hipGetLastError());
     GX_HIP(hipStreamSynchronize(s));
   }

@@ -1,0 +1,206 @@
+"""Host-side bounds check of the band kernels' unconditional loads.
+
+The band solves and the trailing update issue their loads unconditionally from clamped
+addresses and apply the band mask afterwards (so a wave issues every load of a step before
+it waits for any).  Such a load may read outside the band, and past the last row of the
+last matrix: the band allocation carries BAND_PAD trailing entries for that.  This test
+restates every clamped address expression of those kernels (paper_1707_04228_amd/csrc/
+band.hip: the forward and backward sweeps of the one-right-hand-side solve, the chunk
+fetches of the many-right-hand-side solve, the staging loads of the trailing update) and
+evaluates it for every thread of the first and last blocks, for every work-group count,
+over shapes from one row to the subdomain sizes of the 3M-DOF flat laminate (about 90k
+rows, half-bandwidth about 1900).  Every address must lie inside the matrix's storage
+[0, n (B + 1)) plus BAND_PAD, every scratch index inside its segment.
+
+(A load index one past these bounds faulted the GPU once, in the block-0 prefetch of the
+many-right-hand-side solve; its indices are clamped since and this test pins them.)
+"""
+
+import numpy as np
+import pytest
+
+SB = 64            # solve block
+SW = 8             # waves per solve work-group
+RPW = 8            # forward rows per wave
+U = 8              # 64-column steps in flight per wave (forward)
+UB = 32            # band rows in flight per wave (backward)
+GMAX = 4           # work-groups per matrix, one right-hand side
+DL = 8             # inverse-block entries per thread
+MT = 512           # threads of the many-right-hand-side solve
+AL = 8             # band-chunk entries per thread
+TS, NB, ST = 64, 64, 512
+BAND_PAD = 1024
+
+SHAPES = [(1, 0), (2, 1), (63, 5), (64, 63), (65, 64), (127, 64), (128, 65), (129, 100),
+          (300, 150), (1000, 63), (1000, 999), (4097, 700), (90783, 1899), (116493, 2433)]
+
+
+def _blocks(nblk):
+    """Blocks whose loads reach the extremes: the first and last few (the address
+    expressions are monotone in the block index in between)."""
+    return sorted(set(range(min(nblk, 6))) | set(range(max(0, nblk - 6), nblk)))
+
+
+class Bounds:
+    def __init__(self, n, B):
+        self.n, self.B, self.ld = n, B, B + 1
+        self.lo, self.hi = 0, n * (B + 1) + BAND_PAD     # factor storage incl. padding
+        self.worst = 0
+
+    def check(self, idx, what):
+        idx = np.asarray(idx)
+        if idx.size == 0:
+            return
+        assert idx.min() >= self.lo, (what, self.n, self.B, int(idx.min()))
+        assert idx.max() < self.hi, (what, self.n, self.B, int(idx.max()), self.hi)
+        self.worst = max(self.worst, int(idx.max()) - self.n * self.ld + 1)
+
+
+def _single_rhs(n, B, G, bd):
+    """k_band_solve_1 / band_solve_1_mat: forward and backward sweeps."""
+    ld = B + 1
+    nblk = (n + SB - 1) // SB
+    w = np.arange(SW)[:, None, None]
+    lane = np.arange(64)[None, :, None]
+    r = np.arange(RPW)[None, None, :]
+    for k in _blocks(nblk):
+        i0 = k * SB
+        kdone = max(k - G + 1, 0)
+        done_end = kdone * SB
+        ifirst = i0 + RPW * w
+        rc = np.minimum(ifirst + r, n - 1)
+        rowbase = rc * ld - rc + B                         # rp[r] = base + rc ld - rc + B
+        start = np.maximum(ifirst - B, 0) + lane
+        run = start < done_end + lane                      # the c0 loop runs at all
+        last = start + 64 * U * ((done_end + lane - 1 - start) // (64 * U))
+        shape = np.broadcast_shapes(rowbase.shape, run.shape)
+        runf = np.broadcast_to(run, shape)
+        for c0 in (start, last):
+            for u in range(U):
+                bd.check(np.broadcast_to(rowbase + c0 + 64 * u, shape)[runf], "forward band")
+                yi = np.broadcast_to(np.minimum(c0 + 64 * u, done_end - 1), run.shape)[run]
+                assert yi.size == 0 or (yi.min() >= 0 and yi.max() < nblk * SB)
+        for o in range(GMAX - 1):                          # factor entries of blocks in flight
+            cc = min(kdone + o, max(k - 1, 0)) * SB + lane
+            bd.check(rowbase + cc, "forward in-flight")
+            yi = min(kdone + o, max(k - 1, 0)) * SB + np.arange(64)
+            assert yi.min() >= 0 and yi.max() < nblk * SB
+        t = np.arange(512)
+        d = k * SB * SB + t[:, None] + 512 * np.arange(DL)[None, :]
+        assert d.min() >= 0 and d.max() < nblk * SB * SB
+    rs = ld - 1
+    for t in _blocks(nblk):
+        kb = nblk - 1 - t
+        i0 = kb * SB
+        nb = min(SB, n - i0)
+        rend = min(n, i0 + nb + B)
+        kdone = kb + G
+        done_beg = min(rend, kdone * SB)
+        cidx = i0 + np.arange(64)[None, :]
+        for wv in range(SW):
+            r0s = list(range(done_beg + wv, rend, SW * UB))
+            for r0 in (r0s[:1] + r0s[-1:]):
+                for u in range(UB):
+                    rr = min(r0 + SW * u, rend - 1)
+                    bd.check(rr * rs + B + cidx, "backward band")
+                zi = min(r0 + SW * (np.arange(64) % UB).max(), rend - 1)
+                assert 0 <= zi < nblk * SB
+            for o in range(GMAX - 1):
+                for rr_ in range(RPW):
+                    row = min((kb + 1 + o) * SB + wv + SW * rr_, n - 1)
+                    bd.check(row * rs + B + cidx, "backward in-flight")
+        zr = np.minimum((kb + 1 + np.arange(GMAX - 1))[:, None] * SB + np.arange(64)[None, :],
+                        rend - 1)
+        assert zr.min() >= 0 and zr.max() < nblk * SB
+
+
+def _many_rhs(n, B, M, bd):
+    """k_band_solve_m: the chunk fetches (band rows and solution rows) of both sweeps."""
+    ld = B + 1
+    rs = ld - 1
+    nblk = (n + SB - 1) // SB
+    wave = np.arange(MT) // 64
+    lane = np.arange(MT) % 64
+    YL = SB * M // MT
+
+    def fetch(bwd, i0, kk):
+        r0 = (kk * SB if bwd else i0) + wave
+        c = (i0 if bwd else kk * SB) + lane
+        for u in range(AL):
+            bd.check(np.minimum(r0 + 8 * u, n - 1) * rs + B + c, "chunk band")
+        yend = min(SB * M, (n - kk * SB) * M)
+        assert yend > 0
+        for u in range(YL):
+            yi = kk * SB * M + np.minimum(np.arange(MT) + MT * u, yend - 1)
+            assert yi.min() >= 0 and yi.max() < nblk * SB * M
+
+    for k in _blocks(nblk):
+        i0 = k * SB
+        kfirst = max(i0 - B, 0) // SB
+        count = k - kfirst
+        if count > 0:
+            for q in range(count + 2):                     # prefetches run two chunks ahead
+                fetch(False, i0, kfirst + min(q, count - 1))
+        nb = min(SB, n - i0)
+        rows = np.minimum(i0 + np.arange(SB), n - 1)
+        assert rows.max() < n
+    for t in _blocks(nblk):
+        kb = nblk - 1 - t
+        i0 = kb * SB
+        nb = min(SB, n - i0)
+        klast = (min(n, i0 + nb + B) - 1) // SB
+        count = klast - kb
+        if count > 0:
+            for q in range(count + 2):
+                fetch(True, i0, klast - min(q, count - 1))
+
+
+def _trailing_update(n, B, bd):
+    """k_syrk: the staging loads of both 64x64 blocks for every tile of a panel group."""
+    ld = B + 1
+    rs = ld - 1
+    rlast = n - 1
+    cl = np.arange(ST) % NB
+    i0 = np.arange(ST) // NB
+    RS = ST // NB
+    L = TS * NB // ST
+    GP = 4
+    starts = list(range(0, n, GP * NB))
+    for k0 in starts[:3] + starts[-3:]:
+        for p in range(1, GP + 1):                         # column-only updates and full
+            kk = p * NB
+            kj = min(kk, n - k0)
+            t0 = k0 + kj
+            W = min(B, n - t0)
+            if W <= 0:
+                continue
+            nt = (W + TS - 1) // TS
+            tiles = [(tr, ts) for ts in range(nt) for tr in range(ts, nt)]
+            for tr, ts in tiles[:8] + tiles[-8:]:
+                r0, s0 = t0 + tr * TS, t0 + ts * TS
+                for kc in range(0, kj, NB):
+                    col = k0 + kc + cl
+                    for u in range(L):
+                        r = r0 + i0 + RS * u
+                        ss = s0 + i0 + RS * u
+                        bd.check(np.minimum(r, rlast) * rs + B + col, "trailing r")
+                        bd.check(np.minimum(ss, rlast) * rs + B + col, "trailing s")
+
+
+@pytest.mark.parametrize("n,B", SHAPES)
+def test_band_kernel_loads_stay_in_the_padded_allocation(n, B):
+    bd = Bounds(n, B)
+    for G in range(1, GMAX + 1):
+        _single_rhs(n, B, G, bd)
+    for M in (8, 32):
+        _many_rhs(n, B, M, bd)
+    _trailing_update(n, B, bd)
+    assert bd.worst <= 511                                  # far inside BAND_PAD
+
+
+def test_padding_covers_the_worst_forward_overread():
+    """The forward sweep of the one-right-hand-side solve reads furthest past the end: in
+    the last block, rows clamped to n - 1 take columns up to done_end + 510."""
+    bd = Bounds(1000, 63)
+    _single_rhs(1000, 63, 1, bd)
+    assert 400 < bd.worst <= 511

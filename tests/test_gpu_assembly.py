@@ -73,3 +73,21 @@ def test_spmv_matches_scipy(gx, cfg):
         x = rng.standard_normal(K.shape[0])
         y = s.spmv(torch.tensor(x, device="cuda")).cpu().numpy()
         assert rel_err(y, K @ x) <= 1e-14
+
+
+def test_assembly_is_bitwise_repeatable(gx):
+    """K and f are sums in a fixed order (element order for K, (face, node) order for the
+    loads), so two assemblies on two contexts agree bit for bit."""
+    import torch
+    cfg = workloads.small_lsection(nx=12, ny=3)
+    out = []
+    for _ in range(2):
+        s = gx.Solver()
+        s.laminate(cfg)
+        f = s.assemble()
+        rp, col, val = s.matrix()
+        out.append((f.cpu().numpy(), val.cpu().numpy()))
+        s.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.abs(out[0][0]).max() > 0

@@ -159,3 +159,16 @@ def small_lsection(nx=12, ny=2, amp=0.3, wlen=4.0, limb=3.0, layers=None):
                 layers=layers, wrinkle=(float(amp), float(wlen)),
                 load={"kind": "moment", "M": PAPER_MOMENT},
                 solver=dict(px=3, py=1, overlap=1, nev=6, tau=None, nev_max=32, rtol=1e-8))
+
+
+def seeded_vector(n, seed):
+    """A seeded standard-normal vector of length n (test input shared by the oracle runs
+    that write stored results and the GPU tests that read them)."""
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+def sample_indices(n, k, seed=170704228):
+    """k distinct seeded positions in [0, n), ascending (the entries of large vectors that
+    stored results keep)."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, size=min(k, n), replace=False))
