@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Solve time per 1M DOFs at rtol 1e-8 (FP64 vs mixed); CG iters; SpMV GB/s"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 # HBM bytes of one PCG subdomain band solve on this workload (FP64 or FP32 factors), from
 # the FETCH_SIZE / WRITE_SIZE counters of `bench.py --traffic-probe [--precision mixed]`
 # scaled by a 4 GiB copy.  Valid for the solve kernel as it stands: retake the counters
@@ -136,14 +137,64 @@ def traffic_probe(gx, torch, workloads, args):
           flush=True)
 
 
+def solution_diff(x, x_ref):
+    import torch
+    return float(torch.linalg.vector_norm(x - x_ref) / torch.linalg.vector_norm(x_ref))
+
+
+def timed_steps(gx, torch, cfg, prec, steps, warmup, label):
+    """warmup untimed steps, then `steps` timed ones (bracketed by device synchronisations);
+    returns (ms per step, last solver, last PCG output, n0)."""
+    for _ in range(warmup):
+        s, out, nev, n0 = run_step(gx, torch, cfg, prec)
+        print(f"# {label} warmup: {out['iters']} iterations, relres {out['relres']:.2e}",
+              flush=True)
+        del s
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        s, out, nev, n0 = run_step(gx, torch, cfg, prec)
+        if k + 1 < steps:
+            del s
+        print(f"# {label} step {k}: {out['iters']} iterations", flush=True)
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / steps, s, out, n0
+
+
+def n_free(s):
+    return int(3 * s.mesh["n_nodes"] - 3 * s.mesh["clamped"].numel())
+
+
+def precision_block(gx, torch, cfg, steps, warmup, x_fp64, ms_fp64, label):
+    """The same workload with FP32 subdomain factors and solves (FP64 outer CG)."""
+    ms, s, out, n0 = timed_steps(gx, torch, cfg, gx.GX_MIXED, steps, warmup, label)
+    nf = n_free(s)
+    solve_ms, solve_bytes = s.kernel_time(1, reps=5)
+    blk = {"ms_per_step": ms, "value": (ms / 1e3) / (nf / 1e6), "unit": "s/MDOF",
+           "steps": steps, "warmup": warmup, "cg_iters": out["iters"], "relres": out["relres"],
+           "n0": int(n0), "speedup_vs_fp64": ms_fp64 / ms,
+           "rel_diff_vs_fp64_solution": solution_diff(out["x"], x_fp64),
+           "phases_ms": s.phase_times(), "stats": s.stats(),
+           "subdomain_solve_ms": solve_ms,
+           "subdomain_solve_GBps": solve_bytes / (solve_ms * 1e-3) / 1e9}
+    s.close()
+    return blk
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="precision of --batch and --traffic-probe runs")
     ap.add_argument("--small", action="store_true", help="reduced 24x24 workload (testing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision block")
+    ap.add_argument("--no-target", action="store_true",
+                    help="skip the curved wrinkled L-section block (FP64 vs mixed)")
+    ap.add_argument("--mixed-steps", type=int, default=5,
+                    help="timed steps of each extra block, at most --steps")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead: the seeded sweep of wrinkled L-sections, this many samples")
     ap.add_argument("--concurrent", type=int, default=6,
@@ -155,7 +206,9 @@ def main():
                          "COPY_BYTES and one subdomain band solve (for hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (the "
+                                   "build targets a single MI355X; see the design notes for "
+                                   "how the path would shard)"}))
         sys.exit(2)
     import torch
     import paper_1707_04228_amd as gx
@@ -166,36 +219,27 @@ def main():
         return traffic_probe(gx, torch, workloads, args)
 
     cfg = workloads.cfg1(nx=24, ny=24, px=3, py=3) if args.small else workloads.cfg1()
-    prec = gx.GX_MIXED if args.precision == "mixed" else gx.GX_FP64
-    for _ in range(args.warmup):
-        s, out, nev, n0 = run_step(gx, torch, cfg, prec)
-        print(f"# warmup: {out['iters']} iterations, relres {out['relres']:.2e}", flush=True)
-        del s
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = []
-    for k in range(args.steps):
-        s, out, nev, n0 = run_step(gx, torch, cfg, prec)
-        results.append((out["iters"], out["relres"], s.phase_times(), s.stats()))
-        if k + 1 < args.steps:
-            del s
-        print(f"# step {k}: {out['iters']} iterations", flush=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_step = 1e3 * dt / args.steps
-    n_free = int(3 * s.mesh["n_nodes"] - 3 * s.mesh["clamped"].numel())
+    ms_step, s, out, n0 = timed_steps(gx, torch, cfg, gx.GX_FP64, args.steps, args.warmup,
+                                      "fp64")
+    nf = n_free(s)
     # live kernel measurements on the library's stream (HIP events)
     spmv_ms, spmv_bytes = s.kernel_time(0, reps=20)
     solve_ms, solve_bytes = s.kernel_time(1, reps=5)
     pre_ms, _ = s.kernel_time(2, reps=5)
     eig_ms, eig_bytes = s.kernel_time(4)          # recorded during the timed setup
-    phases = results[-1][2]
+    fac_ms, fac_flops = s.kernel_time(5, reps=1)  # the subdomain factorisation, alone
+    bst = s.band_stats()
+    phases = s.phase_times()
+    stats = s.stats()
+    x_fp64 = out["x"].clone()
     spmv_gbs = spmv_bytes / (spmv_ms * 1e-3) / 1e9
     solve_gbs = solve_bytes / (solve_ms * 1e-3) / 1e9
+    stored_gbs = bst["solve_stored_bytes"] / (solve_ms * 1e-3) / 1e9
     eig_gbs = eig_bytes / (eig_ms * 1e-3) / 1e9
+    fac_tflops = fac_flops / (fac_ms * 1e-3) / 1e12
     line = {
         "metric": METRIC,
-        "value": (ms_step / 1e3) / (n_free / 1e6),
+        "value": (ms_step / 1e3) / (nf / 1e6),
         "unit": "s/MDOF",
         "n_gpus": 1,
         "steps": args.steps,
@@ -204,15 +248,15 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == gx.GX_FP64 else "f64+f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": cfg["name"] + " flat 50x50 mm [0/45/90/-45/0/45]s laminate, "
                                "20-node serendipity hexes, 8x8 subdomains, overlap 2, "
                                "GenEO tau 0.1, rtol 1e-8",
-                   "n_dofs": int(3 * s.mesh["n_nodes"]), "n_free_dofs": n_free,
-                   "precision": args.precision},
-        "cg_iters": results[-1][0],
-        "relres": results[-1][1],
+                   "n_dofs": int(3 * s.mesh["n_nodes"]), "n_free_dofs": nf,
+                   "precision": "fp64"},
+        "cg_iters": out["iters"],
+        "relres": out["relres"],
         "n0": int(n0),
         "spmv_GBps": spmv_gbs,
         "spmv_ms": spmv_ms,
@@ -220,20 +264,52 @@ def main():
         "subdomain_solve_ms": solve_ms,
         "precond_apply_ms": pre_ms,
         "phases_ms": phases,
-        "stats": results[-1][3],
+        "stats": stats,
+        "band_stats": bst,
         "roofline": {"bound": "hbm", "kernel": "k_band_solve_1 (PCG subdomain solves, "
                                                "forward+backward)",
                      "achieved": solve_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": solve_gbs / HBM_PEAK_GBS,
-                     "traffic": SOLVE_TRAFFIC_BYTES[args.precision],
-                     "bytes_per_launch": solve_bytes, "ms_per_launch": solve_ms},
+                     "traffic": SOLVE_TRAFFIC_BYTES["fp64"],
+                     "bytes_per_launch": solve_bytes, "ms_per_launch": solve_ms,
+                     "bytes": "envelope of the factors read once per sweep + 4 FP64 vector "
+                              "passes",
+                     "stored_bytes_per_launch": bst["solve_stored_bytes"],
+                     "stored_GBps": stored_gbs},
         "eigensolve_roofline": {"bound": "hbm", "kernel": "k_band_solve_m (GenEO block solves)",
                                 "achieved": eig_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": eig_gbs / HBM_PEAK_GBS, "bytes_per_launch": eig_bytes,
                                 "ms_per_launch": eig_ms},
         "spmv_roofline": {"bound": "hbm", "kernel": "k_spmv", "achieved": spmv_gbs,
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": spmv_gbs / HBM_PEAK_GBS},
+        "factor_roofline": {"bound": "mfma", "kernel": "k_potrf + k_trsm + k_syrk (subdomain "
+                                                       "band Cholesky, FP64)",
+                            "achieved": fac_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                            "frac": fac_tflops / FP64_PEAK_TFLOPS, "flops": fac_flops,
+                            "ms": fac_ms},
     }
+    s.close()
+    del s
+    extra = min(args.mixed_steps, args.steps)
+    if not args.no_mixed:
+        line["mixed"] = precision_block(gx, torch, cfg, extra, 1, x_fp64, ms_step, "mixed")
+    if not args.no_target:
+        tcfg = workloads.cfg2()
+        t64, s2, o2, n02 = timed_steps(gx, torch, tcfg, gx.GX_FP64, extra, 1, "target fp64")
+        xt = o2["x"].clone()
+        tblk = {"workload": tcfg["name"] + " curved L-section, R 5 mm, 40 mm limbs, "
+                                           "wrinkle A 0.3 mm L 4 mm, end moment, 32x2 "
+                                           "subdomains, overlap 2, tau 0.1, rtol 1e-8",
+                "n_free_dofs": n_free(s2), "fp64_ms_per_step": t64,
+                "fp64_cg_iters": o2["iters"], "fp64_phases_ms": s2.phase_times()}
+        s2.close()
+        del s2
+        m = precision_block(gx, torch, tcfg, extra, 1, xt, t64, "target mixed")
+        tblk.update({"mixed_ms_per_step": m["ms_per_step"], "mixed_cg_iters": m["cg_iters"],
+                     "speedup_mixed_vs_fp64": m["speedup_vs_fp64"],
+                     "mixed_rel_diff_vs_fp64_solution": m["rel_diff_vs_fp64_solution"],
+                     "mixed_phases_ms": m["phases_ms"], "steps": extra})
+        line["target"] = tblk
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

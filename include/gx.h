@@ -96,6 +96,16 @@ typedef struct {
   double width;              /* extent along l (mm) */
   double radius, limb;       /* L-section only: inner radius and limb length (mm) */
   double wrinkle_amp, wrinkle_len;  /* A and L of w(s) (mm) */
+  /* The paper's localised wrinkle defect (section 3, Eq. eq-f), L-section only, added to
+   * the shift w(s): f = d sech^2(s_p / b1) sech^2(pi (zeta - zeta_def) / (R b2))
+   * sech^2(pi (l - l_def) / (W b3)), s_p = 2 (s - s_def) / (R + T/2) (the paper's arc
+   * parameter, 0..pi over the 90 degree arc), b2 = b2_in below zeta_def and b2_out above,
+   * R the inner radius.  defect_amp = 0 disables it. */
+  double defect_amp;                         /* d (mm) */
+  double defect_s, defect_l, defect_zeta;    /* centre: arc length from mid-arc, position
+                                                across the width, height above the inner
+                                                surface (mm) */
+  double defect_b1, defect_b2_in, defect_b2_out, defect_b3;
 } gx_laminate;
 
 /* Node, element, clamped-node and loaded-face counts of a laminate (host only). */
@@ -284,6 +294,31 @@ gx_status gx_adjoint(gx_ctx* ctx, const gx_laminate* lam, int32_t region, const 
                      double rtol, int32_t maxit, double* J_out, double* dJdp,
                      int32_t* iters_out);
 
+/* ------------------------------------------------------------------------------------
+ * Delamination onset (section 3.3, Eq. eq-Camanho): at the 27 Gauss points of every
+ * element of the selected layers the stresses of u are recovered in the local frame
+ * (s, l, r) = (e1, e2, e3) of the assembly (the strain rotated into the material axes, times
+ * the layer stiffness, turned back by the ply angle), and
+ *   F = sqrt((max(sigma_r, 0) / s33)^2 + (tau_rs / s13)^2 + (tau_rl / s13)^2).
+ * The paper applies it in the resin interface layers with s33 = 61 MPa, s13 = 97 MPa;
+ * failure initiates at F = 1, i.e. at the load scaled by 1 / F_max (linear problem).
+ * layer_mask: host [n_layers of the ply stack], nonzero = evaluate the layer; NULL selects
+ * the isotropic entries.  F_gauss (device [27 n_elems], point q = 9 k + 3 j + i with i along
+ * xi) and F_elem (device [n_elems], the element's maximum) may be NULL; both are 0 outside
+ * the selected layers.  out (host) receives the maximum, where it occurs (ties: the lowest
+ * element, then the lowest point) and the local stresses there, in MPa, ordered
+ * sigma_s, sigma_l, sigma_r, tau_lr, tau_sr, tau_sl.  Deterministic.
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+  double F_max;
+  int64_t elem;
+  int32_t gauss;
+  int32_t layer;            /* ply-stack entry of that element */
+  double stress[6];
+} gx_failure_result;
+gx_status gx_failure(gx_ctx* ctx, const double* u, const int32_t* layer_mask, double s33,
+                     double s13, double* F_gauss, double* F_elem, gx_failure_result* out);
+
 /* The subdomain solver on its own: batched banded Cholesky factorisation and triangular
  * solves (section 2.4: the local problems are solved exactly by a direct method).
  * n_mat matrices; matrix j has order n[j] and half bandwidth bw[j] (host arrays) and is
@@ -321,7 +356,14 @@ gx_status gx_pcg_solve_batch(int32_t n, gx_ctx* const* ctxs, const double* const
  * subdomain band solves of one preconditioner application (forward and backward);
  * 2 = one whole preconditioner application; 3 = the coarse solve; 4 = the GenEO
  * eigensolver's multi-right-hand-side band solves, as timed during the last
- * gx_geneo_setup (average per solve; reps is ignored). */
+ * gx_geneo_setup (average per solve; reps is ignored); 5 = the Cholesky factorisation of
+ * the subdomain matrices (section 2.4), refilled from K and factored again alone on the
+ * stream (the factors come out unchanged) - `bytes` then receives its flops instead (the
+ * band Cholesky count, sum over columns of w^2 + 2 w + 1 with w the band entries below
+ * the diagonal).  The algorithmic bytes of a band solve are the factor's envelope
+ * (profile: every row from its first nonzero column to the diagonal, where Cholesky
+ * creates all its fill) read once per sweep, 2 w sum_j env_j with w = 8 (FP64) or 4
+ * (FP32 factors), plus four FP64 passes over the right-hand sides (32 n_j per column). */
 gx_status gx_kernel_time(gx_ctx* ctx, int32_t which, int32_t reps, double* avg_ms,
                          double* bytes);
 
@@ -339,6 +381,15 @@ gx_status gx_tune(gx_ctx* ctx, int32_t param, int64_t value);
  * factor broke down and the interior factors were rebuilt in FP64; bit 1: the same for the
  * eigensolver's factors). */
 gx_status gx_stats(gx_ctx* ctx, int64_t* out);
+
+/* Sizes of the subdomain factorisations of the last gx_geneo_setup (host [8]): [0] stored
+ * band entries of the subdomain factors, [1] their envelope entries, [2] their band
+ * Cholesky flops; [3] stored band entries of the eigensolver's Neumann factors, [4] their
+ * envelope entries, [5] their flops; [6] algorithmic bytes of one PCG subdomain solve
+ * (envelope, as gx_kernel_time 1 reports), [7] the bytes that solve's kernels read as
+ * stored (band plus inverse diagonal blocks, plus the vector passes).  GX_ESTATE before
+ * gx_geneo_setup. */
+gx_status gx_band_stats(gx_ctx* ctx, double* out);
 
 /* Time spent in the last call of each phase, milliseconds (host [8], may be NULL):
  * assemble, decomposition, local factors, eigensolves, coarse, pcg, precond total in pcg,

@@ -105,9 +105,43 @@ def wrinkle(cfg, s):
     return A * np.exp(-(u / Lw) ** 2) * np.cos(2.0 * math.pi * u / Lw)
 
 
+def sech2(x):
+    """sech^2 x = 1 / cosh^2 x (written to stay analytic for complex steps)."""
+    return 1.0 / np.cosh(x) ** 2
+
+
+def defect(cfg, s, l, zeta):
+    """The paper's localised wrinkle defect, Eq. eq-f (section 3), as a shift of zeta.
+
+    f = d sech^2(pi (s_p - s_p,def) / (pi b1)) sech^2(pi (r - r_def) / (R b2))
+          sech^2(pi (l - l_def) / (W b3)),
+    b2 = b2_in for r < r_def (towards the inner radius) and b2_out otherwise.  Readings:
+    the paper's s runs over [0, pi] along the 90 degree arc (angle = s / 2), so
+    s_p - s_p,def = 2 (s - s_def) / R_ref in this mesh's arc length s (R_ref = R + T/2, s = 0
+    at mid-arc); r = R + zeta is the unperturbed radius; R in the second factor is the
+    inner radius as printed.  Zero when the descriptor has no "defect".
+    """
+    D = cfg.get("defect")
+    if not D:
+        return np.zeros(np.broadcast(s, l, zeta).shape)
+    T = total_thickness(cfg)
+    R = cfg["radius"]
+    rref = R + 0.5 * T
+    sp = 2.0 * (s - D["s_def"]) / rref
+    r = R + zeta
+    rdef = R + D["zeta_def"]
+    b2 = np.where(np.real(r - rdef) < 0, D["b2_in"], D["b2_out"])
+    return (D["d"] * sech2(sp / D["b1"]) * sech2(np.pi * (r - rdef) / (R * b2)) *
+            sech2(np.pi * (l - D["l_def"]) / (cfg["width"] * D["b3"])))
+
+
 def geometry_map(cfg, s, l, zeta):
     """Physical coordinates of parameter points (s, l, zeta) (section 3 mapping)."""
     zh = zeta + wrinkle(cfg, s)
+    if cfg.get("defect"):
+        if cfg["geometry"] != "lsection":
+            raise ValueError("the sech^2 defect is defined on the curved L-section")
+        zh = zh + defect(cfg, s, l, zeta)
     if cfg["geometry"] == "flat":
         return np.stack([s, l, zh], axis=-1)
     R, T, limb = cfg["radius"], total_thickness(cfg), cfg["limb"]

@@ -41,7 +41,11 @@ class Laminate(C.Structure):
                 ("layer_t", f64p), ("layer_nel", i32p),
                 ("length", C.c_double), ("width", C.c_double), ("radius", C.c_double),
                 ("limb", C.c_double), ("wrinkle_amp", C.c_double),
-                ("wrinkle_len", C.c_double)]
+                ("wrinkle_len", C.c_double), ("defect_amp", C.c_double),
+                ("defect_s", C.c_double), ("defect_l", C.c_double),
+                ("defect_zeta", C.c_double), ("defect_b1", C.c_double),
+                ("defect_b2_in", C.c_double), ("defect_b2_out", C.c_double),
+                ("defect_b3", C.c_double)]
 
 
 class PlyStack(C.Structure):
@@ -61,6 +65,11 @@ class Traction(C.Structure):
 class Loads(C.Structure):
     _fields_ = [("n_clamped", C.c_int64), ("clamped", vp), ("n_faces", C.c_int64),
                 ("face_elem", vp), ("face_id", vp), ("traction", Traction)]
+
+
+class FailureResult(C.Structure):
+    _fields_ = [("F_max", C.c_double), ("elem", C.c_int64), ("gauss", C.c_int32),
+                ("layer", C.c_int32), ("stress", C.c_double * 6)]
 
 
 class GeneoOpts(C.Structure):
@@ -97,6 +106,9 @@ for _name, _args in [("gx_geneo_setup", [vp, C.POINTER(GeneoOpts), i32p, i64p]),
                      ("gx_pcg_solve", [vp, vp, vp, C.c_double, C.c_int32, i32p, f64p, f64p]),
                      ("gx_kernel_time", [vp, C.c_int32, C.c_int32, f64p, f64p]),
                      ("gx_stats", [vp, i64p]),
+                     ("gx_band_stats", [vp, f64p]),
+                     ("gx_failure", [vp, vp, i32p, C.c_double, C.c_double, vp, vp,
+                                     C.POINTER(FailureResult)]),
                      ("gx_tune", [vp, C.c_int32, C.c_int64]),
                      ("gx_band_factor_solve", [vp, C.c_int32, i64p, i64p, vp, C.c_int32,
                                                C.c_int32, C.c_int32, vp]),
@@ -117,7 +129,8 @@ EXPORTS = ["gx_create", "gx_destroy", "gx_last_error", "gx_version", "gx_laminat
            "gx_laminate_mesh", "gx_laminate_partition", "gx_laminate_traction",
            "gx_assemble", "gx_matrix_info", "gx_matrix_copy", "gx_spmv", "gx_geneo_setup",
            "gx_subdomain_info", "gx_geneo_eigenvalues", "gx_precond_apply", "gx_pcg_solve",
-           "gx_phase_times", "gx_kernel_time", "gx_stats", "gx_tune", "gx_band_factor_solve",
+           "gx_phase_times", "gx_kernel_time", "gx_stats", "gx_band_stats", "gx_tune",
+           "gx_band_factor_solve", "gx_failure",
            "gx_objective", "gx_objective_noalloc", "gx_adjoint", "gx_pcg_solve_batch",
            "gx_geneo_setup_batch"]
 
@@ -149,6 +162,12 @@ def laminate_struct(cfg):
     s.limb = cfg.get("limb", 0.0)
     A, Lw = cfg.get("wrinkle", (0.0, 0.0))
     s.wrinkle_amp, s.wrinkle_len = A, Lw
+    D = cfg.get("defect")
+    if D:
+        s.defect_amp, s.defect_s, s.defect_l, s.defect_zeta = (D["d"], D["s_def"], D["l_def"],
+                                                                D["zeta_def"])
+        s.defect_b1, s.defect_b2_in, s.defect_b2_out, s.defect_b3 = (D["b1"], D["b2_in"],
+                                                                     D["b2_out"], D["b3"])
     return s, (t, nel)
 
 
@@ -371,6 +390,29 @@ class Solver:
         return J.value
 
     @_on_stream
+    def failure(self, u, layers=None, s33=61.0, s13=97.0, per_gauss=False):
+        """Delamination onset (gx_failure): max F of Eq. eq-Camanho over the selected layers
+        (default: the isotropic ones), where it occurs, the local stresses there, the
+        per-element maxima (device tensor) and, with per_gauss, F at every Gauss point."""
+        torch = self.torch
+        n_e = self.mesh["n_elems"]
+        Fe = torch.empty(n_e, dtype=torch.float64, device=self.device)
+        Fq = torch.empty(27 * n_e, dtype=torch.float64, device=self.device) if per_gauss else None
+        mask = None
+        if layers is not None:
+            keep = np.zeros(len(self.mesh["cfg"]["layers"]), dtype=np.int32)
+            keep[np.asarray(layers, dtype=np.int64)] = 1
+            mask = keep.ctypes.data_as(i32p)
+        r = FailureResult()
+        self._check(lib.gx_failure(self.h, _ptr(u), mask, s33, s13, _ptr(Fq), _ptr(Fe),
+                                   C.byref(r)))
+        out = dict(F_max=r.F_max, elem=int(r.elem), gauss=int(r.gauss), layer=int(r.layer),
+                   stresses=np.array(list(r.stress)), F_elem=Fe)
+        if per_gauss:
+            out["F_gauss"] = Fq
+        return out
+
+    @_on_stream
     def objective_noalloc(self, u, cfg=None, region=1):
         """gx_objective_noalloc: J with the library's static scratch, no device allocation."""
         lam, keep = laminate_struct(cfg or self.mesh["cfg"])
@@ -426,6 +468,16 @@ class Solver:
         return dict(eig_iters=int(out[0]), pcg_iters=int(out[1]),
                     interior_band_entries=int(out[2]), neumann_band_entries=int(out[3]),
                     fp64_fallbacks=int(out[4]))
+
+    def band_stats(self):
+        """Subdomain and eigensolver factor sizes: band and envelope entries, flops, and the
+        envelope (algorithmic) and stored bytes of one PCG subdomain solve."""
+        out = np.zeros(8)
+        self._check(lib.gx_band_stats(self.h, out.ctypes.data_as(f64p)))
+        keys = ["interior_band_entries", "interior_envelope_entries", "interior_factor_flops",
+                "neumann_band_entries", "neumann_envelope_entries", "neumann_factor_flops",
+                "solve_envelope_bytes", "solve_stored_bytes"]
+        return dict(zip(keys, out.tolist()))
 
     def phase_times(self):
         t = np.zeros(8)

@@ -1215,16 +1215,30 @@ void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, i
 
 // Algorithmic bytes of one solve: the factor and the inverse diagonal blocks read once per
 // sweep, the FP64 right-hand sides read and written once per sweep.
-double band_solve_bytes(const BandSet& bs, int ncol, const int32_t* active_host) {
+double band_solve_bytes(const BandSet& bs, int ncol, const int32_t* active_host, bool band) {
   const double w = bs.fp32 ? 4.0 : 8.0;
   double b = 0.0;
   for (int j = 0; j < bs.n_mat; ++j) {
     if (active_host && !active_host[j]) continue;
     const double nblk = (double)((bs.n[j] + SB - 1) / SB);
-    b += 2.0 * w * ((double)bs.n[j] * (double)(bs.B[j] + 1) + nblk * SB * SB) +
-         4.0 * 8.0 * (double)bs.n[j] * ncol;
+    const double factor = band ? (double)bs.n[j] * (double)(bs.B[j] + 1) + nblk * SB * SB
+                               : (double)bs.env[j];
+    b += 2.0 * w * factor + 4.0 * 8.0 * (double)bs.n[j] * ncol;
   }
   return b;
+}
+
+double band_factor_flops(const BandSet& bs) {
+  double f = 0.0;
+  for (int j = 0; j < bs.n_mat; ++j) {
+    const double n = (double)bs.n[j], B = (double)bs.B[j];
+    // columns 0 .. n - 1 - B have w = B; the last B columns have w = B - 1 .. 0
+    const double full = std::max(0.0, n - B);
+    const double tail = std::min(n, B);                  // w = tail - 1 .. 0
+    f += full * (B * B + 2.0 * B + 1.0);
+    f += (tail - 1.0) * tail * (2.0 * tail - 1.0) / 6.0 + (tail - 1.0) * tail + tail;
+  }
+  return f;
 }
 
 // The table of a multi-set solve: matrix j of set k solves in place on x[k] + xoff[k][j]
@@ -1401,6 +1415,11 @@ void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<i
     bs.max_B = std::max<int64_t>(bs.max_B, B[j]);
   }
   bs.total = o;
+  bs.env.assign(n.size(), 0);
+  for (size_t j = 0; j < n.size(); ++j) {      // the band itself: row r holds min(r, B) + 1
+    const int64_t m = std::min(n[j], B[j] + 1);
+    bs.env[j] = m * (m + 1) / 2 + (n[j] - m) * (B[j] + 1);
+  }
   bs.d_n.alloc(n.size());
   bs.d_B.alloc(n.size());
   bs.d_ld.alloc(n.size());

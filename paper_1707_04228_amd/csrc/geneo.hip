@@ -945,10 +945,14 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   to_dev(d_doff.p, doff.data(), n_sub + 1, s);
   DevBuf<double> dM;
   {
-    std::vector<int64_t> n3(n_sub), B =
-        list_bandwidth(c, sw.D_nodes.p, sw.d_offD.p, sw.d_nD.p, sw.D_loc.p, sw.nD);
+    std::vector<int64_t> n3(n_sub), env, B =
+        list_bandwidth(c, sw.D_nodes.p, sw.d_offD.p, sw.d_nD.p, sw.D_loc.p, sw.nD, &env);
     for (int j = 0; j < n_sub; ++j) n3[j] = 3 * sw.nD[j];
     band_layout(Mb, n3, B, fp32, s);
+    Mb.env = env;
+    c->neumann_envelope = 0;
+    for (int64_t e : env) c->neumann_envelope += e;
+    c->neumann_flops = band_factor_flops(Mb);
     Mb.force_groups[0] = c->tune[0];
     Mb.force_groups[1] = c->tune[1];
     c->neumann_entries = Mb.total;

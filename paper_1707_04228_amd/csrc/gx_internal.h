@@ -210,6 +210,11 @@ struct BandSet {
   // entry (r, c), r - B <= c <= r, of matrix j lives at off[j] + r * ld[j] + (c - r + B).
   int n_mat = 0;
   std::vector<int64_t> n, B, ld, off;          // host copies
+  // envelope (profile) entries of each matrix's lower triangle, diagonal included: the
+  // entries from each row's first nonzero column to the diagonal (Cholesky creates no fill
+  // outside it).  band_layout sets it to the band itself; callers that know the matrices'
+  // profile replace it.
+  std::vector<int64_t> env;
   DevBuf<int64_t> d_n, d_B, d_ld, d_off;       // device copies
   int64_t total = 0;                           // stored entries
   int max_n = 0, max_B = 0;
@@ -321,6 +326,8 @@ struct gx_ctx {
   int32_t pcg_iters = 0;
   int32_t eig_iters = 0;
   int64_t neumann_entries = 0;
+  int64_t neumann_envelope = 0;                // envelope entries of the eigensolver's factors
+  double neumann_flops = 0.0;                  // their band Cholesky flops
   int32_t fp64_fallbacks = 0;                  // bit 0: interior, bit 1: eigensolver factors
   double phase_ms[8] = {0};
   // the eigensolver's multi-right-hand-side band solves of the last setup (HIP events)
@@ -348,9 +355,16 @@ void precond_apply(gx_ctx* c, const double* r, double* z);
 void dd_build(gx_ctx* c, const int32_t* part, int n_sub, int overlap);
 void interior_factors(gx_ctx* c, int precision);
 void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o);
+// half bandwidths (DOFs) of K restricted to each list; env_out (optional): the envelope
+// entries of each restricted matrix's lower triangle, diagonal included
 std::vector<int64_t> list_bandwidth(gx_ctx* c, const int32_t* list, const int64_t* d_off,
                                     const int64_t* d_cnt, const int32_t* loc,
-                                    const std::vector<int64_t>& cnt);
+                                    const std::vector<int64_t>& cnt,
+                                    std::vector<int64_t>* env_out = nullptr);
+double interior_refactor_ms(gx_ctx* c);
+// Cholesky flops of the band matrices of a set: sum over columns of w^2 + 2 w + 1, w the
+// entries below the diagonal inside the band (min(B, n - 1 - c))
+double band_factor_flops(const BandSet& bs);
 void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<int64_t>& B,
                  bool fp32, hipStream_t st);
 void band_factor(BandSet& bs, hipStream_t st, const char* what);
@@ -374,7 +388,7 @@ void band_factor_start(BandSet& bs, hipStream_t st, FactorJob& job, const char* 
 void band_factor_finish(FactorJob& job);
 // The interior factorisation as a job that can run on a side stream (see schwarz.hip).
 struct InteriorJob {
-  std::vector<int64_t> n, B;
+  std::vector<int64_t> n, B, env;
   int64_t maxI = 0;
   bool fp32 = false;
   FactorJob factor;
@@ -384,7 +398,12 @@ void interior_factors_finish(gx_ctx* c, InteriorJob& job);
 void band_solve_check(BandSet& bs, hipStream_t st);
 void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, int ncol = 1,
                 const int32_t* active = nullptr);
-double band_solve_bytes(const BandSet& bs, int ncol, const int32_t* active_host = nullptr);
+// Algorithmic bytes of one forward-and-backward solve with ncol right-hand sides: the
+// factor's envelope read once per sweep (2 w sum env_j) plus the FP64 right-hand side and
+// solution passes (32 n_j ncol); band = true counts the stored band and the inverse diagonal
+// blocks that the kernels read instead of the envelope.
+double band_solve_bytes(const BandSet& bs, int ncol, const int32_t* active_host = nullptr,
+                        bool band = false);
 void multi_solve_plan(MultiSolve& m, const std::vector<BandSet*>& sets,
                       const std::vector<double*>& x, const std::vector<const int64_t*>& xoff,
                       hipStream_t st);

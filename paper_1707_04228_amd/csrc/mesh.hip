@@ -16,6 +16,7 @@ struct LamDev {
   int geometry, nx, ny, nz, nx_limb, n_layers;
   double length, width, radius, limb, amp, wlen, T;
   double s_a, s_b, r_ref;                        // L-section arc ends and mid radius
+  double dd, ds, dl, dz, b1, b2i, b2o, b3;       // sech^2 defect (Eq. eq-f), dd = 0: none
   double t[MAX_LAYERS], z0[MAX_LAYERS];          // thickness, start of each layer
   int nel[MAX_LAYERS], cum[MAX_LAYERS + 1];      // element layers, cumulative count
 };
@@ -35,6 +36,11 @@ static void check_lam(const gx_laminate* L) {
     GX_REQUIRE(L->nx_limb >= 1 && L->nx - 2 * L->nx_limb >= 1, "nx_limb out of range");
   }
   if (L->wrinkle_amp != 0.0) GX_REQUIRE(L->wrinkle_len > 0, "wrinkle length must be > 0");
+  if (L->defect_amp != 0.0) {
+    GX_REQUIRE(L->geometry == GX_GEOM_LSECTION, "the sech^2 defect needs an L-section");
+    GX_REQUIRE(L->defect_b1 > 0 && L->defect_b2_in > 0 && L->defect_b2_out > 0 &&
+                   L->defect_b3 > 0, "defect extents must be > 0");
+  }
 }
 
 static LamDev make_lam(const gx_laminate* L) {
@@ -52,6 +58,14 @@ static LamDev make_lam(const gx_laminate* L) {
   d.limb = L->limb;
   d.amp = L->wrinkle_amp;
   d.wlen = L->wrinkle_len > 0 ? L->wrinkle_len : 1.0;
+  d.dd = L->defect_amp;
+  d.ds = L->defect_s;
+  d.dl = L->defect_l;
+  d.dz = L->defect_zeta;
+  d.b1 = L->defect_b1 > 0 ? L->defect_b1 : 1.0;
+  d.b2i = L->defect_b2_in > 0 ? L->defect_b2_in : 1.0;
+  d.b2o = L->defect_b2_out > 0 ? L->defect_b2_out : 1.0;
+  d.b3 = L->defect_b3 > 0 ? L->defect_b3 : 1.0;
   double z = 0;
   int c = 0;
   d.cum[0] = 0;
@@ -126,8 +140,23 @@ __device__ inline double wrinkle(const LamDev& L, double s) {
   return L.amp * exp(-q * q) * cos(2.0 * M_PI * u / L.wlen);
 }
 
+__device__ inline double sech2(double x) {
+  const double c = cosh(x);
+  return 1.0 / (c * c);
+}
+
+// the localised defect of Eq. eq-f as a shift of zeta (0 without one)
+__device__ inline double defect(const LamDev& L, double s, double l, double zeta) {
+  if (L.dd == 0.0) return 0.0;
+  const double sp = 2.0 * (s - L.ds) / L.r_ref;
+  const double dz = zeta - L.dz;
+  const double b2 = dz < 0 ? L.b2i : L.b2o;
+  return L.dd * sech2(sp / L.b1) * sech2(M_PI * dz / (L.radius * b2)) *
+         sech2(M_PI * (l - L.dl) / (L.width * L.b3));
+}
+
 __device__ inline void map_point(const LamDev& L, double s, double l, double zeta, double* x) {
-  const double zh = zeta + wrinkle(L, s);
+  const double zh = zeta + wrinkle(L, s) + defect(L, s, l, zeta);
   if (L.geometry == GX_GEOM_FLAT) {
     x[0] = s; x[1] = l; x[2] = zh;
     return;

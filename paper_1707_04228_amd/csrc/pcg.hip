@@ -534,7 +534,15 @@ gx_status gx_pcg_solve_batch(int32_t n, gx_ctx* const* ctxs, const double* const
 gx_status gx_kernel_time(gx_ctx* c, int32_t which, int32_t reps, double* avg_ms,
                          double* bytes) {
   GX_API_BEGIN(c)
-  GX_REQUIRE(reps >= 1 && which >= 0 && which <= 4, "bad kernel id or repetition count");
+  GX_REQUIRE(reps >= 1 && which >= 0 && which <= 5, "bad kernel id or repetition count");
+  if (which == 5) {                                // the interior factorisation, alone
+    if (!c->setup_done) throw Error(GX_ESTATE, "preconditioner not set up");
+    double tot = 0.0;
+    for (int k = 0; k < reps; ++k) tot += interior_refactor_ms(c);
+    if (avg_ms) *avg_ms = tot / reps;
+    if (bytes) *bytes = band_factor_flops(c->sw.A);
+    return GX_OK;
+  }
   if (which == 4) {                                // recorded during the last setup
     if (!c->setup_done || c->mrhs_calls == 0) throw Error(GX_ESTATE, "no eigensolver solves recorded");
     if (avg_ms) *avg_ms = c->mrhs_ms / (double)c->mrhs_calls;
@@ -576,6 +584,24 @@ gx_status gx_kernel_time(gx_ctx* c, int32_t which, int32_t reps, double* avg_ms,
   if (which == 1 || which == 3) b = band_solve_bytes(which == 1 ? sw.A : sw.C, 1);
   if (avg_ms) *avg_ms = tot / reps;
   if (bytes) *bytes = b;
+  GX_API_END(c)
+}
+
+gx_status gx_band_stats(gx_ctx* c, double* out) {
+  GX_API_BEGIN(c)
+  if (!c->setup_done) throw Error(GX_ESTATE, "preconditioner not set up");
+  GX_REQUIRE(out, "null output");
+  const BandSet& A = c->sw.A;
+  double env = 0.0;
+  for (int64_t e : A.env) env += (double)e;
+  out[0] = (double)A.total;
+  out[1] = env;
+  out[2] = band_factor_flops(A);
+  out[3] = (double)c->neumann_entries;
+  out[4] = (double)c->neumann_envelope;
+  out[5] = c->neumann_flops;
+  out[6] = band_solve_bytes(A, 1, nullptr, false);
+  out[7] = band_solve_bytes(A, 1, nullptr, true);
   GX_API_END(c)
 }
 

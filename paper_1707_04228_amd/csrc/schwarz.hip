@@ -204,9 +204,13 @@ void dd_build(gx_ctx* c, const int32_t* part, int n_sub, int overlap) {
 
 // ---------------------------------------------------------------------------------------
 // interior band matrices A_j = K[I_j, I_j]
+// Per subdomain: the half bandwidth in nodes (max over the list of ln - first coupled local
+// node) and the envelope of the DOF-level lower triangle: the three rows of node ln start at
+// DOF 3 mn (mn its first coupled local node), so they hold 9 (ln - mn) + 6 entries up to
+// and including their diagonals.  Integer sums: the result does not depend on the order.
 __global__ void k_band_width(const int32_t* rp, const int32_t* col, const int32_t* list,
                              const int64_t* loff, const int64_t* lcnt, const int32_t* loc,
-                             int64_t N, int32_t* bw) {
+                             int64_t N, int32_t* bw, unsigned long long* env) {
   const int j = blockIdx.y;
   const int64_t ln = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ln >= lcnt[j]) return;
@@ -218,6 +222,7 @@ __global__ void k_band_width(const int32_t* rp, const int32_t* col, const int32_
     if (lm >= 0 && lm < mn) mn = lm;
   }
   atomicMax(&bw[j], (int)ln - mn);
+  atomicAdd(&env[j], (unsigned long long)(9 * ((int64_t)ln - mn) + 6));
 }
 
 template <class T>
@@ -262,20 +267,26 @@ __global__ void k_diag(const int32_t* rp, const int32_t* col, const double* val,
 // Half bandwidth (in DOFs) of K restricted to each subdomain's node list, in list order.
 std::vector<int64_t> list_bandwidth(gx_ctx* c, const int32_t* list, const int64_t* d_off,
                                     const int64_t* d_cnt, const int32_t* loc,
-                                    const std::vector<int64_t>& cnt) {
+                                    const std::vector<int64_t>& cnt,
+                                    std::vector<int64_t>* env_out) {
   hipStream_t s = c->stream;
   const int n_sub = (int)cnt.size();
   int64_t mx = 0;
   for (int64_t v : cnt) mx = std::max(mx, v);
   DevBuf<int32_t> bw(n_sub);
+  DevBuf<unsigned long long> env(n_sub);
   zero(bw, s);
+  zero(env, s);
   hipLaunchKernelGGL(k_band_width, dim3(nblocks(mx, 256), n_sub), dim3(256), 0, s,
-                     c->row_ptr.p, c->col.p, list, d_off, d_cnt, loc, c->n_nodes, bw.p);
+                     c->row_ptr.p, c->col.p, list, d_off, d_cnt, loc, c->n_nodes, bw.p, env.p);
   GX_HIP(hipGetLastError());
   std::vector<int32_t> hb(n_sub);
+  std::vector<unsigned long long> he(n_sub);
   to_host(hb.data(), bw.p, n_sub, s);
+  to_host(he.data(), env.p, n_sub, s);
   std::vector<int64_t> B(n_sub);
   for (int j = 0; j < n_sub; ++j) B[j] = 3 * (int64_t)hb[j] + 2;
+  if (env_out) env_out->assign(he.begin(), he.end());
   return B;
 }
 
@@ -287,12 +298,13 @@ void interior_factors_start(gx_ctx* c, int precision, hipStream_t s, InteriorJob
   const int n_sub = sw.n_sub;
   job.maxI = 0;
   for (int j = 0; j < n_sub; ++j) job.maxI = std::max(job.maxI, sw.nI[j]);
-  job.B = list_bandwidth(c, sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, sw.nI);
+  job.B = list_bandwidth(c, sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, sw.nI, &job.env);
   job.n.assign(n_sub, 0);
   for (int j = 0; j < n_sub; ++j) job.n[j] = 3 * sw.nI[j];
   sw.precision = precision;
   job.fp32 = precision == GX_MIXED;
   band_layout(sw.A, job.n, job.B, job.fp32, s);
+  sw.A.env = job.env;
   sw.A.force_groups[0] = c->tune[0];
   sw.A.force_groups[1] = c->tune[1];
   if (job.fp32) {
@@ -326,6 +338,7 @@ void interior_factors_finish(gx_ctx* c, InteriorJob& job) {
     if (!job.fp32 || e.code != GX_ENOTSPD) throw;
     c->fp64_fallbacks |= 1;
     band_layout(sw.A, job.n, job.B, false, s);
+    sw.A.env = job.env;
     BandView bv64{sw.A.d_B.p, sw.A.d_ld.p, sw.A.d_off.p};
     hipLaunchKernelGGL(k_band_fill<double>, dim3((unsigned)job.maxI, n_sub), dim3(64), 0, s,
                        c->row_ptr.p, c->col.p, c->val.p, (const double*)nullptr, sw.I_nodes.p,
@@ -347,6 +360,39 @@ void interior_factors(gx_ctx* c, int precision) {
   InteriorJob job;
   interior_factors_start(c, precision, c->stream, job);
   interior_factors_finish(c, job);
+}
+
+// The interior band matrices filled again from K and factored once more, in the precision
+// of the set-up, alone on the context's stream; returns the factorisation's duration (ms,
+// HIP events around the factorisation kernels, the fill excluded).  The factors come out
+// bit for bit as before (same kernels, same order).
+double interior_refactor_ms(gx_ctx* c) {
+  Schwarz& sw = c->sw;
+  hipStream_t s = c->stream;
+  const int64_t N = c->n_nodes;
+  const int n_sub = sw.n_sub;
+  int64_t maxI = 0;
+  for (int j = 0; j < n_sub; ++j) maxI = std::max(maxI, sw.nI[j]);
+  BandView bv{sw.A.d_B.p, sw.A.d_ld.p, sw.A.d_off.p};
+  if (sw.A.fp32)
+    hipLaunchKernelGGL(k_band_fill<float>, dim3((unsigned)maxI, n_sub), dim3(64), 0, s,
+                       c->row_ptr.p, c->col.p, c->val.p, sw.dg.p, sw.I_nodes.p, sw.d_offI.p,
+                       sw.d_nI.p, sw.I_loc.p, N, bv, sw.A.v32.p);
+  else
+    hipLaunchKernelGGL(k_band_fill<double>, dim3((unsigned)maxI, n_sub), dim3(64), 0, s,
+                       c->row_ptr.p, c->col.p, c->val.p, (const double*)nullptr, sw.I_nodes.p,
+                       sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, N, bv, sw.A.v64.p);
+  GX_HIP(hipGetLastError());
+  EventPair ev;
+  GX_HIP(hipEventRecord(ev.a, s));
+  {
+    FactorJob job;
+    band_factor_start(sw.A, s, job, "the subdomain matrices");
+    GX_HIP(hipEventRecord(ev.b, s));
+    band_factor_finish(job);
+  }
+  GX_HIP(hipEventSynchronize(ev.b));
+  return ev.ms();
 }
 
 // ---------------------------------------------------------------------------------------

@@ -14,7 +14,8 @@ from gpu_helpers import bcsr_to_scipy, oracle_K_with_identity, rel_err
 pytestmark = pytest.mark.gpu
 
 CASES = [workloads.cfg0(), workloads.small_flat(nx=5, ny=3),
-         workloads.small_lsection(nx=12, ny=2), workloads.small_lsection(nx=9, ny=3, amp=0.0)]
+         workloads.small_lsection(nx=12, ny=2), workloads.small_lsection(nx=9, ny=3, amp=0.0),
+         workloads.defect_lsection(nx=20, ny=4, d=0.35)]
 
 
 @pytest.fixture(scope="module")
@@ -58,7 +59,19 @@ def test_assembly_matches_oracle(gx, cfg):
     # block pattern = sorted union of element neighbours (no explicit zeros beyond it)
     assert K.shape == Ko.shape
     fo = prob.f_all * prob.free
-    assert np.abs(f - fo).max() <= 1e-13 * np.abs(fo).max()
+    tol = 1e-13 * np.abs(fo).max()
+    if cfg.get("defect"):
+        # the library writes the moment traction about the end face's shifted mid-thickness
+        # and the oracle in zeta; the sech^2 defect shifts the end face non-uniformly by its
+        # far-field value delta, which moves the load by at most 2 |k| delta W T
+        from oracle.mesh import Mesh, defect, total_thickness
+        m = Mesh(cfg)
+        end = m.lat[:, 0] == 2 * m.nx
+        delta = np.abs(defect(cfg, *m.param[end].T)).max()
+        T = total_thickness(cfg)
+        tol += 2 * 12 * cfg["load"]["M"] / T ** 3 * delta * cfg["width"] * T
+        assert delta < 1e-10
+    assert np.abs(f - fo).max() <= tol
 
 
 @pytest.mark.parametrize("cfg", CASES[:2], ids=lambda c: c["name"])

@@ -172,3 +172,23 @@ def sample_indices(n, k, seed=170704228):
     stored results keep)."""
     rng = np.random.default_rng(seed)
     return np.sort(rng.choice(n, size=min(k, n), replace=False))
+
+
+# Extents of the sech^2 defect of section 3 (b2: towards the inner radius, outwards).
+DEFECT_B = dict(b1=0.2, b2_in=0.5, b2_out=0.25, b3=0.5)
+
+
+def defect_lsection(nx=24, ny=4, d=0.3, angles=(0, 45, 90, -45), ply_nel=1, limb=3.0,
+                    width=4.0, zeta_def=None, px=4, py=1, nev=6):
+    """A small curved L-section with the paper's sech^2 wrinkle defect (section 3, Eq. eq-f)
+    at mid-arc and mid-width, centred through the thickness unless zeta_def is given, under
+    the end moment; resin interfaces between the plies."""
+    layers = ply_layers(list(angles), 0.25, ply_nel, 0.05, 1)
+    T = sum(l["t"] for l in layers)
+    D = dict(DEFECT_B, d=float(d), s_def=0.0, l_def=0.5 * width,
+             zeta_def=0.5 * T if zeta_def is None else float(zeta_def))
+    return dict(name=f"defect_lsec_{nx}x{ny}", geometry="lsection", radius=5.0, limb=limb,
+                width=width, nx=nx, ny=ny, nx_limb=_limb_elems(nx, limb, 5.0, layers),
+                layers=layers, defect=D, load={"kind": "moment", "M": PAPER_MOMENT},
+                solver=dict(px=px, py=py, overlap=1, nev=nev, tau=None, nev_max=32,
+                            rtol=1e-8))
