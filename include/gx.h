@@ -106,6 +106,27 @@ typedef struct {
                                                 across the width, height above the inner
                                                 surface (mm) */
   double defect_b1, defect_b2_in, defect_b2_out, defect_b3;
+  /* Graded meshes (section 2.2: bias ratios 400 across the width and 10 through each layer;
+   * section 3.1: 2 towards the defect): the ratio of the largest to the smallest element,
+   * sizes growing geometrically and symmetric about the segment's middle; <= 1: uniform.
+   * bias_s: a flat part towards mid-length, the arc of an L-section towards mid-arc (limbs
+   * uniform); bias_l: across the width towards the laminate's edges; bias_z: every layer
+   * towards its two faces. */
+  double bias_s, bias_l, bias_z;
+  /* Resin edge strips (sections 2.2 and 3): strips of strip_width (mm, 0: none) at l = 0
+   * and l = width with strip_ny uniform elements each (the laminate between them takes the
+   * other ny - 2 strip_ny elements); their elements take ply-stack entry strip_mat. */
+  double strip_width;
+  int32_t strip_ny, strip_mat;
+  /* The stiff end layer carrying the moment (section 2.2): end_column = 1 gives the last
+   * element column along s ply-stack entry end_mat. */
+  int32_t end_column, end_mat;
+  /* Periodic boundary conditions across the width (section 3: a very wide part; section
+   * 2.1): periodic_l = 1 identifies the nodes at l = width with those at l = 0 (they are
+   * not separate nodes).  The elements of the last column then reach across the seam: their
+   * nodes there take the coordinates of the l = 0 nodes plus the width along l, which
+   * gx_laminate_wrap describes for gx_assemble.  Not with edge strips. */
+  int32_t periodic_l;
 } gx_laminate;
 
 /* Node, element, clamped-node and loaded-face counts of a laminate (host only). */
@@ -121,6 +142,11 @@ gx_status gx_laminate_counts(const gx_laminate* lam, int64_t* n_nodes, int64_t* 
 gx_status gx_laminate_mesh(gx_ctx* ctx, const gx_laminate* lam, double* xyz, int32_t* conn,
                            int32_t* elem_layer, int32_t* clamped, int32_t* face_elem,
                            int32_t* face_id);
+
+/* Which element nodes of a periodic laminate stand for its seam (device [n_elems]): bit a of
+ * elem_wrap[e] is set when node a of element e is a node at l = 0 that the element uses at
+ * l = width (its coordinates plus the period); zero for a laminate that is not periodic. */
+gx_status gx_laminate_wrap(gx_ctx* ctx, const gx_laminate* lam, uint32_t* elem_wrap);
 
 /* Box partition of a laminate into px * py in-plane subdomains of element index ranges
  * (full thickness), box p along an axis of n elements covering [p n / P, (p + 1) n / P)
@@ -161,6 +187,10 @@ typedef struct {
   const double* xyz;        /* device [3 n_nodes] */
   const int32_t* conn;      /* device [20 n_elems], element-local order above */
   const int32_t* elem_layer;/* device [n_elems], index into the ply stack */
+  /* periodic meshes (or NULL): device [n_elems]; element e sees node a at its coordinates
+   * plus period[] when bit a of elem_wrap[e] is set (e.g. from gx_laminate_wrap) */
+  const uint32_t* elem_wrap;
+  double period[3];
 } gx_mesh;
 
 typedef struct {
@@ -284,9 +314,10 @@ gx_status gx_objective_noalloc(gx_ctx* ctx, const gx_laminate* lam, int32_t regi
                                const double* u, double* J_out);
 /* J and dJ/dp by the adjoint method: K lambda = dJ/du is solved by PCG with the current
  * preconditioner to rtol (iters_out: its iterations), then
- * dJ/dp = dJ/dp|_u - lambda^T (dK/dp u - df/dp).  dJdp (host) receives 2 + n_layers
- * values: [0] wrinkle amplitude, [1] wrinkle wavelength, [2 + k] the modulus E11 of layer
- * k (E for an isotropic layer), in the units of J per mm and per MPa.  u must solve the
+ * dJ/dp = dJ/dp|_u - lambda^T (dK/dp u - df/dp).  dJdp (host) receives 2 + n values, n the
+ * entries of the assembled ply stack (the laminate's layers, then any extra materials such
+ * as edge strips): [0] wrinkle amplitude, [1] wrinkle wavelength, [2 + k] the modulus E11
+ * of entry k (E for an isotropic one), in the units of J per mm and per MPa.  u must solve the
  * assembled system (e.g. gx_pcg_solve to a tight tolerance).  GX_ENOCONV if the adjoint
  * solve does not reach rtol in maxit iterations (the outputs are still filled, from its
  * last iterate); GX_ESTATE before gx_geneo_setup. */

@@ -23,7 +23,7 @@ from .mesh import Mesh, total_thickness
 
 def element_data(mesh):
     Cs, angs = layer_material(mesh.cfg)
-    X = mesh.xyz[mesh.conn]
+    X = mesh.elem_coords()
     return X, Cs[mesh.elayer], angs[mesh.elayer]
 
 
@@ -52,7 +52,7 @@ def load_vector(mesh):
     """Consistent nodal loads on all DOFs (Eq. eq-1 right-hand side)."""
     f = np.zeros(mesh.n_dofs, dtype=mesh.xyz.dtype)
     le = mesh.load_elements()
-    X = mesh.xyz[mesh.conn[le]]
+    X = mesh.elem_coords(le)
     load = mesh.cfg["load"]
     if load["kind"] == "traction":
         t0 = np.array(load["t0"], dtype=float)

@@ -104,6 +104,13 @@ def layer_material(cfg, engineering=False):
         eng.append(k)
         Cs.append(orthotropic_stiffness(**k))
         angs.append(L["angle"])
+    # extra materials after the layers: resin edge strips, then the stiff end column
+    for key in ("edge_strip", "stiff_end"):
+        if cfg.get(key):
+            k = isotropic_as_engineering(cfg[key]["E"], cfg[key]["nu"])
+            eng.append(k)
+            Cs.append(orthotropic_stiffness(**k))
+            angs.append(0.0)
     if engineering:
         return np.array(Cs), np.array(angs), eng
     return np.array(Cs), np.array(angs)

@@ -52,35 +52,80 @@ def total_thickness(cfg):
     return float(sum(L["t"] for L in cfg["layers"]))
 
 
+def graded(n, bias, fine):
+    """Boundaries (fractions of the segment, n + 1 values) of n elements graded with the
+    paper's bias ratio (largest over smallest element, section 2.2): element sizes grow
+    geometrically, q^e, symmetric about the segment's middle, with e = min(k, n - 1 - k) for
+    elements refined towards both ends (fine="ends") and m - e for elements refined towards
+    the middle (fine="middle"), m = (n - 1) // 2 and q = bias^(1/m).  bias <= 1: uniform."""
+    m = (n - 1) // 2
+    k = np.arange(n)
+    e = np.minimum(k, n - 1 - k)
+    if bias <= 1.0 or m == 0:
+        h = np.ones(n)
+    else:
+        q = bias ** (1.0 / m)
+        h = q ** (e if fine == "ends" else m - e)
+    b = np.concatenate([[0.0], np.cumsum(h)])
+    return b / b[-1]
+
+
+def _bias(cfg, axis):
+    return float(cfg.get("bias", {}).get(axis, 1.0))
+
+
 def zeta_boundaries(cfg):
-    """Element-layer boundaries through the thickness and the material layer of each."""
+    """Element-layer boundaries through the thickness and the material layer of each; each
+    layer's elements are graded towards its two faces (bias "z", section 2.2)."""
     zb, lay = [0.0], []
     z0 = 0.0
     for li, L in enumerate(cfg["layers"]):
+        g = graded(L["nel"], _bias(cfg, "z"), "ends")
         for k in range(L["nel"]):
-            zb.append(z0 + L["t"] * (k + 1) / L["nel"])
+            zb.append(z0 + L["t"] * g[k + 1])
             lay.append(li)
         z0 += L["t"]
     return np.array(zb), np.array(lay, dtype=np.int64)
 
 
+def l_boundaries(cfg):
+    """Element boundaries across the width: with resin edge strips (section 2.2, 3) each
+    strip carries ny_strip uniform elements and the laminate between them is graded towards
+    its two edges (bias "l"); without strips the whole width is graded towards the free
+    edges."""
+    ny, W = cfg["ny"], cfg["width"]
+    st = cfg.get("edge_strip")
+    if not st:
+        return W * graded(ny, _bias(cfg, "l"), "ends")
+    e, ns = st["width"], st["ny"]
+    mid = e + (W - 2 * e) * graded(ny - 2 * ns, _bias(cfg, "l"), "ends")
+    left = e * np.arange(ns) / ns
+    right = W - e + e * np.arange(1, ns + 1) / ns
+    return np.concatenate([left, mid, right])
+
+
 def s_boundaries(cfg):
-    """Element boundaries along s (the arc-length / length coordinate)."""
+    """Element boundaries along s (the arc-length / length coordinate).  A flat part is
+    graded towards its middle and the arc of an L-section towards mid-arc (where the
+    defects sit), with bias "s" (section 3.1: refinement towards the defect); limbs are
+    uniform."""
     nx = cfg["nx"]
+    bs = _bias(cfg, "s")
     if cfg["geometry"] == "flat":
-        return np.array([cfg["length"] * i / nx for i in range(nx + 1)])
+        return cfg["length"] * graded(nx, bs, "middle")
     R, T, limb = cfg["radius"], total_thickness(cfg), cfg["limb"]
     rref = R + 0.5 * T
     sb = 0.25 * math.pi * rref
     sa = -sb
     nl = cfg["nx_limb"]
     na = nx - 2 * nl
+    ga = graded(na, bs, "middle")
     out = []
     for i in range(nx + 1):
         if i <= nl:
             out.append(sa - limb + limb * i / nl)
         elif i <= nl + na:
-            out.append(sa + (sb - sa) * (i - nl) / na)
+            out.append(sa + (sb - sa) * ga[i - nl])
         else:
             out.append(sb + limb * (i - nl - na) / nl)
     return np.array(out)
@@ -174,15 +219,23 @@ class Mesh:
         nz = len(zb) - 1
         self.nx, self.ny, self.nz = nx, ny, nz
         sp = lattice_params(s_boundaries(cfg))
-        lp = lattice_params(np.array([cfg["width"] * j / ny for j in range(ny + 1)]))
+        lp = lattice_params(l_boundaries(cfg))
         zp = lattice_params(zb)
-        # enumerate the lattice in (k2, j2, i2) lexicographic order and keep the nodes
-        K2, J2, I2 = np.meshgrid(np.arange(2 * nz + 1), np.arange(2 * ny + 1),
+        # enumerate the lattice in (k2, j2, i2) lexicographic order and keep the nodes; a
+        # laminate periodic across the width (section 3: periodic boundary conditions at the
+        # free edge) identifies the lattice plane j2 = 2 ny with j2 = 0
+        self.periodic = bool(cfg.get("periodic"))
+        if self.periodic and cfg.get("edge_strip"):
+            raise ValueError("a periodic laminate has no free edges for resin strips")
+        nj = 2 * ny if self.periodic else 2 * ny + 1
+        K2, J2, I2 = np.meshgrid(np.arange(2 * nz + 1), np.arange(nj),
                                  np.arange(2 * nx + 1), indexing="ij")
         odd = (K2 % 2) + (J2 % 2) + (I2 % 2)
         isnode = odd <= 1
-        self.node_of = -np.ones(K2.shape, dtype=np.int64)
-        self.node_of[isnode] = np.arange(int(isnode.sum()))
+        self.node_of = -np.ones((2 * nz + 1, 2 * ny + 1, 2 * nx + 1), dtype=np.int64)
+        self.node_of[:, :nj][isnode] = np.arange(int(isnode.sum()))
+        if self.periodic:
+            self.node_of[:, 2 * ny] = self.node_of[:, 0]
         self.n_nodes = int(isnode.sum())
         self.lat = np.stack([I2[isnode], J2[isnode], K2[isnode]], axis=1)   # (i2, j2, k2)
         self.param = np.stack([sp[self.lat[:, 0]], lp[self.lat[:, 1]], zp[self.lat[:, 2]]],
@@ -201,9 +254,34 @@ class Mesh:
             conn[:, a] = self.node_of[k2, j2, i2]
         assert (conn >= 0).all()
         self.conn = conn
+        # element nodes that stand for the wrapped plane j2 = 2 ny take the period W along l
+        self.wrap = np.zeros((self.n_elems, 20), dtype=bool)
+        if self.periodic:
+            self.wrap = (ey[:, None] == ny - 1) & (ref[None, :, 1] == 1)
+        self.period = np.array([0.0, cfg["width"], 0.0])
         self.eidx = np.stack([ex, ey, ez], axis=1)
         self.elayer = elay[ez]
+        # material overrides: resin edge strips (elements across the strip width), then the
+        # stiff end column of the loaded limb (section 2.2); their materials follow the
+        # layers' in the material table (material.layer_material)
+        nlay = len(cfg["layers"])
+        if cfg.get("edge_strip"):
+            ns = cfg["edge_strip"]["ny"]
+            self.elayer = np.where((ey < ns) | (ey >= ny - ns), nlay, self.elayer)
+        if cfg.get("stiff_end"):
+            self.elayer = np.where(ex == nx - 1, nlay + (1 if cfg.get("edge_strip") else 0),
+                                   self.elayer)
         self.n_dofs = 3 * self.n_nodes
+
+    def elem_coords(self, elems=None):
+        """Node coordinates (E, 20, 3) of elements, the wrapped nodes of a periodic laminate
+        shifted by the period."""
+        c = self.conn if elems is None else self.conn[elems]
+        w = self.wrap if elems is None else self.wrap[elems]
+        X = self.xyz[c]
+        if self.periodic:
+            X = X + w[..., None] * self.period
+        return X
 
     # --- boundary description (clamp at s = s_min, load on the s = s_max face) ---
     def clamped_nodes(self):

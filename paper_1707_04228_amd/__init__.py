@@ -45,7 +45,11 @@ class Laminate(C.Structure):
                 ("defect_s", C.c_double), ("defect_l", C.c_double),
                 ("defect_zeta", C.c_double), ("defect_b1", C.c_double),
                 ("defect_b2_in", C.c_double), ("defect_b2_out", C.c_double),
-                ("defect_b3", C.c_double)]
+                ("defect_b3", C.c_double), ("bias_s", C.c_double), ("bias_l", C.c_double),
+                ("bias_z", C.c_double), ("strip_width", C.c_double),
+                ("strip_ny", C.c_int32), ("strip_mat", C.c_int32),
+                ("end_column", C.c_int32), ("end_mat", C.c_int32),
+                ("periodic_l", C.c_int32)]
 
 
 class PlyStack(C.Structure):
@@ -54,7 +58,7 @@ class PlyStack(C.Structure):
 
 class Mesh(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_elems", C.c_int64), ("xyz", vp), ("conn", vp),
-                ("elem_layer", vp)]
+                ("elem_layer", vp), ("elem_wrap", vp), ("period", C.c_double * 3)]
 
 
 class Traction(C.Structure):
@@ -93,6 +97,7 @@ _sig("gx_version", [], C.c_char_p)
 _sig("gx_laminate_counts", [C.POINTER(Laminate), i64p, i64p, i64p, i64p])
 _sig("gx_laminate_mesh", [vp, C.POINTER(Laminate), vp, vp, vp, vp, vp, vp])
 _sig("gx_laminate_partition", [vp, C.POINTER(Laminate), C.c_int32, C.c_int32, vp])
+_sig("gx_laminate_wrap", [vp, C.POINTER(Laminate), vp])
 _sig("gx_laminate_traction", [C.POINTER(Laminate), C.c_int32, f64p, C.POINTER(Traction)])
 _sig("gx_assemble", [vp, C.POINTER(Mesh), C.POINTER(PlyStack), C.POINTER(Loads), vp])
 _sig("gx_matrix_info", [vp, i64p, i64p])
@@ -127,6 +132,7 @@ for _name, _args in [("gx_geneo_setup", [vp, C.POINTER(GeneoOpts), i32p, i64p]),
 
 EXPORTS = ["gx_create", "gx_destroy", "gx_last_error", "gx_version", "gx_laminate_counts",
            "gx_laminate_mesh", "gx_laminate_partition", "gx_laminate_traction",
+           "gx_laminate_wrap",
            "gx_assemble", "gx_matrix_info", "gx_matrix_copy", "gx_spmv", "gx_geneo_setup",
            "gx_subdomain_info", "gx_geneo_eigenvalues", "gx_precond_apply", "gx_pcg_solve",
            "gx_phase_times", "gx_kernel_time", "gx_stats", "gx_band_stats", "gx_tune",
@@ -168,6 +174,16 @@ def laminate_struct(cfg):
                                                                 D["zeta_def"])
         s.defect_b1, s.defect_b2_in, s.defect_b2_out, s.defect_b3 = (D["b1"], D["b2_in"],
                                                                      D["b2_out"], D["b3"])
+    bias = cfg.get("bias", {})
+    s.bias_s, s.bias_l, s.bias_z = (float(bias.get(k, 1.0)) for k in ("s", "l", "z"))
+    n_lay = len(cfg["layers"])
+    if cfg.get("edge_strip"):
+        s.strip_width, s.strip_ny = cfg["edge_strip"]["width"], cfg["edge_strip"]["ny"]
+        s.strip_mat = n_lay                       # extra materials follow the layers
+    if cfg.get("stiff_end"):
+        s.end_column = 1
+        s.end_mat = n_lay + (1 if cfg.get("edge_strip") else 0)
+    s.periodic_l = 1 if cfg.get("periodic") else 0
     return s, (t, nel)
 
 
@@ -185,6 +201,10 @@ def plystack_arrays(cfg):
         else:
             eng.append([L.get("E", RESIN["E"]), 0, 0, 0, 0, 0, RESIN["nu"], 0, 0])
         ang.append(L["angle"])
+    for key in ("edge_strip", "stiff_end"):       # extra materials, after the layers
+        if cfg.get(key):
+            eng.append([cfg[key]["E"], 0, 0, 0, 0, 0, cfg[key]["nu"], 0, 0])
+            ang.append(0.0)
     return np.array(eng, dtype=np.float64), np.array(ang, dtype=np.float64)
 
 
@@ -273,6 +293,11 @@ class Solver:
                           "gx_laminate_traction")
         m["traction"] = tr
         m["cfg"] = cfg
+        m["wrap"] = None
+        if cfg.get("periodic"):
+            m["wrap"] = torch.empty(ne.value, dtype=torch.int32, device=d)
+            self._check(lib.gx_laminate_wrap(self.h, C.byref(lam), _ptr(m["wrap"])))
+            m["period"] = (0.0, float(cfg["width"]), 0.0)
         self.mesh = m
         return m
 
@@ -292,7 +317,8 @@ class Solver:
         eng, ang = plystack_arrays(cfg)
         ps = PlyStack(len(ang), eng.ctypes.data_as(f64p), ang.ctypes.data_as(f64p))
         ms = Mesh(m["n_nodes"], m["n_elems"], _ptr(m["xyz"]), _ptr(m["conn"]),
-                  _ptr(m["elem_layer"]))
+                  _ptr(m["elem_layer"]), _ptr(m.get("wrap")),
+                  (C.c_double * 3)(*m.get("period", (0.0, 0.0, 0.0))))
         ld = Loads(m["clamped"].numel(), _ptr(m["clamped"]), m["face_elem"].numel(),
                    _ptr(m["face_elem"]), _ptr(m["face_id"]), m["traction"])
         f = self.torch.empty(3 * m["n_nodes"], dtype=self.torch.float64, device=self.device)
@@ -392,17 +418,19 @@ class Solver:
     @_on_stream
     def failure(self, u, layers=None, s33=61.0, s13=97.0, per_gauss=False):
         """Delamination onset (gx_failure): max F of Eq. eq-Camanho over the selected layers
-        (default: the isotropic ones), where it occurs, the local stresses there, the
-        per-element maxima (device tensor) and, with per_gauss, F at every Gauss point."""
+        (default: the resin interface layers, not edge strips or the stiff end), where it
+        occurs, the local stresses there, the per-element maxima (device tensor) and, with
+        per_gauss, F at every Gauss point."""
         torch = self.torch
         n_e = self.mesh["n_elems"]
         Fe = torch.empty(n_e, dtype=torch.float64, device=self.device)
         Fq = torch.empty(27 * n_e, dtype=torch.float64, device=self.device) if per_gauss else None
-        mask = None
-        if layers is not None:
-            keep = np.zeros(len(self.mesh["cfg"]["layers"]), dtype=np.int32)
-            keep[np.asarray(layers, dtype=np.int64)] = 1
-            mask = keep.ctypes.data_as(i32p)
+        cfg = self.mesh["cfg"]
+        if layers is None:
+            layers = [k for k, L in enumerate(cfg["layers"]) if L["mat"] == "resin"]
+        keep = np.zeros(len(plystack_arrays(cfg)[1]), dtype=np.int32)
+        keep[np.asarray(layers, dtype=np.int64)] = 1
+        mask = keep.ctypes.data_as(i32p)
         r = FailureResult()
         self._check(lib.gx_failure(self.h, _ptr(u), mask, s33, s13, _ptr(Fq), _ptr(Fe),
                                    C.byref(r)))
@@ -426,7 +454,7 @@ class Solver:
         """(J, dJ/dp, adjoint iterations); dJ/dp = [dA, dL_w, dE11 of every layer]."""
         cfg = cfg or self.mesh["cfg"]
         lam, keep = laminate_struct(cfg)
-        out = np.zeros(2 + len(cfg["layers"]))
+        out = np.zeros(2 + len(plystack_arrays(cfg)[1]))
         J, it = C.c_double(), C.c_int32()
         code = lib.gx_adjoint(self.h, C.byref(lam), region, _ptr(u), rtol, maxit, C.byref(J),
                               out.ctypes.data_as(f64p), C.byref(it))

@@ -55,6 +55,7 @@ template <> __device__ inline double mk<double>(double v, double) { return v; }
 template <> __device__ inline Dual mk<Dual>(double v, double d) { return {v, d}; }
 
 struct SensArgs {
+  Periodic P;
   const double* xyz;
   const double* xd;          // dX/dp per node (dual part of the coordinates), or null
   const int32_t* conn;
@@ -102,7 +103,7 @@ __global__ void __launch_bounds__(64) k_sens(SensArgs A, int64_t n_elems, double
     if (t < 60) {
       const int a = t / 3, i = t % 3;
       const int64_t nd = A.conn[20 * e + a];
-      sm.X[a][i] = A.xyz[3 * nd + i];
+      sm.X[a][i] = node_coord(A.xyz, nd, i, A.P, e, a);
       sm.Xd[a][i] = A.xd ? A.xd[3 * nd + i] : 0.0;
       sm.U[a][i] = A.u[3 * nd + i];
       sm.L[a][i] = A.lam ? A.lam[3 * nd + i] : 0.0;
@@ -289,7 +290,7 @@ __global__ void k_grad_gather(int64_t n_nodes, const int32_t* ne_ptr, const int3
 // t = t0 + k zeta_c n_out with zeta_c = (x - c) . d the through-thickness coordinate)
 // evaluated in dual numbers along dX/dp: the face's normal and area element move with the
 // nodes, zeta_c belongs to the laminate and does not; one thread per (face, element node)
-__global__ void __launch_bounds__(64) k_face_dload(int64_t n_faces, const int32_t* fe,
+__global__ void __launch_bounds__(64) k_face_dload(Periodic P, int64_t n_faces, const int32_t* fe,
                                                   const int32_t* fid,
                              const double* xyz, const double* xd, const int32_t* conn,
                              gx_traction tr, const uint8_t* fixed, const double* lam,
@@ -320,7 +321,7 @@ __global__ void __launch_bounds__(64) k_face_dload(int64_t n_faces, const int32_
         const double dc = ax == 0 ? d[2] : (ax == 1 ? d[0] : d[1]);
         const int64_t nd = conn[20 * e + a];
         for (int i = 0; i < 3; ++i) {
-          const Dual X = {xyz[3 * nd + i], xd[3 * nd + i]};
+          const Dual X = {node_coord(xyz, nd, i, P, e, a), xd[3 * nd + i]};
           x[i] += N * X;
           tb[i] += db * X;
           tc[i] += dc * X;
@@ -412,8 +413,8 @@ __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
 
 static SensArgs sens_args(gx_ctx* c, const double* u, const double* lam, const double* xd,
                           const double* Cd, const uint8_t* region) {
-  return SensArgs{c->xyz.p, xd, c->conn.p, c->elayer.p, c->Cl.p, Cd, c->ang.p, u, lam, region,
-                  c->fixed.p};
+  return SensArgs{periodic_of(c), c->xyz.p, xd, c->conn.p, c->elayer.p, c->Cl.p, Cd, c->ang.p, u,
+                  lam, region, c->fixed.p};
 }
 
 static unsigned sens_grid(int64_t E) { return (unsigned)std::min<int64_t>(E, 256 * 64); }
@@ -531,7 +532,7 @@ gx_status gx_adjoint(gx_ctx* c, const gx_laminate* lam, int32_t region, const do
   if (!c->setup_done) throw Error(GX_ESTATE, "gx_geneo_setup has not been called");
   GX_REQUIRE(lam && u && dJdp && (region == 0 || region == 1) && rtol > 0 && maxit > 0,
              "bad adjoint arguments");
-  GX_REQUIRE(lam->n_layers == c->n_layers, "laminate layers differ from the ply stack");
+  GX_REQUIRE(lam->n_layers <= c->n_layers, "the laminate has more layers than the ply stack");
   hipStream_t st = c->stream;
   const int64_t n = 3 * c->n_nodes, E = c->n_elems;
   const int nl = c->n_layers;
@@ -560,7 +561,7 @@ gx_status gx_adjoint(gx_ctx* c, const gx_laminate* lam, int32_t region, const do
     double df = 0.0;
     if (c->n_faces > 0) {
       hipLaunchKernelGGL(k_face_dload, dim3(nblocks(c->n_faces * 20, 64)), dim3(64), 0, st,
-                         c->n_faces, c->face_e.p, c->face_id.p, c->xyz.p, xd.p, c->conn.p,
+                         periodic_of(c), c->n_faces, c->face_e.p, c->face_id.p, c->xyz.p, xd.p, c->conn.p,
                          c->traction, c->fixed.p, lamv.p, fd.p);
       GX_HIP(hipGetLastError());
       df = dev_sum(fd.p, c->n_faces * 20, st);

@@ -274,7 +274,7 @@ __device__ inline void gauss_point_setup(int q, const ElemSmem& sm, const double
   *dvout = det * wq * wy * wz;
 }
 
-__global__ void __launch_bounds__(256) k_element(int64_t n_elems, const double* xyz,
+__global__ void __launch_bounds__(256) k_element(Periodic P, int64_t n_elems, const double* xyz,
                                                  const int32_t* conn, const int32_t* elayer,
                                                  const double* Clayer, const double* angle,
                                                  double* Ke, int* err) {
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(256) k_element(int64_t n_elems, const double* 
   }
   __syncthreads();
   for (int64_t e = blockIdx.x; e < n_elems; e += gridDim.x) {
-    if (t < 60) sm.X[t / 3][t % 3] = xyz[3 * (int64_t)conn[20 * e + t / 3] + t % 3];
+    if (t < 60) sm.X[t / 3][t % 3] = node_coord(xyz, conn[20 * e + t / 3], t % 3, P, e, t / 3);
     __syncthreads();
     const int L = elayer[e];
     if (t < 27) {
@@ -394,7 +394,7 @@ __global__ void __launch_bounds__(64) k_gather(const int32_t* conn, const int32_
 //    one thread per (face, element node) writes its three components to fl; k_face_gather
 //    then sums each node's entries in a fixed order (face, then local node), so f is the
 //    same bit for bit on every run
-__global__ void k_face_loads(int64_t n_faces, const int32_t* fe, const int32_t* fid,
+__global__ void k_face_loads(Periodic P, int64_t n_faces, const int32_t* fe, const int32_t* fid,
                              const double* xyz, const int32_t* conn, gx_traction tr,
                              double* fl) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -422,7 +422,8 @@ __global__ void k_face_loads(int64_t n_faces, const int32_t* fe, const int32_t* 
         const double db = ax == 0 ? d[1] : (ax == 1 ? d[2] : d[0]);
         const double dc = ax == 0 ? d[2] : (ax == 1 ? d[0] : d[1]);
         const int64_t nd = conn[20 * e + a];
-        const double X0 = xyz[3 * nd], X1 = xyz[3 * nd + 1], X2 = xyz[3 * nd + 2];
+        const double X0 = node_coord(xyz, nd, 0, P, e, a), X1 = node_coord(xyz, nd, 1, P, e, a),
+                     X2 = node_coord(xyz, nd, 2, P, e, a);
         x0 += N * X0; x1 += N * X1; x2 += N * X2;
         tb0 += db * X0; tb1 += db * X1; tb2 += db * X2;
         tc0 += dc * X0; tc1 += dc * X1; tc2 += dc * X2;
@@ -598,6 +599,12 @@ gx_status gx_assemble(gx_ctx* c, const gx_mesh* m, const gx_plystack* ps, const 
   GX_HIP(hipMemcpyAsync(c->xyz.p, m->xyz, 3 * N * sizeof(double), hipMemcpyDefault, s));
   GX_HIP(hipMemcpyAsync(c->conn.p, m->conn, 20 * E * sizeof(int32_t), hipMemcpyDefault, s));
   GX_HIP(hipMemcpyAsync(c->elayer.p, m->elem_layer, E * sizeof(int32_t), hipMemcpyDefault, s));
+  c->wrap.release();
+  for (int i = 0; i < 3; ++i) c->period[i] = m->elem_wrap ? m->period[i] : 0.0;
+  if (m->elem_wrap) {
+    c->wrap.alloc(E);
+    GX_HIP(hipMemcpyAsync(c->wrap.p, m->elem_wrap, E * sizeof(uint32_t), hipMemcpyDefault, s));
+  }
   std::vector<int32_t> hc(20 * E);                 // host copy of conn (checks, face loads)
   {  // validate indices on the host side of a copy (cheap relative to assembly)
     std::vector<int32_t> hl(E);
@@ -660,7 +667,7 @@ gx_status gx_assemble(gx_ctx* c, const gx_mesh* m, const gx_plystack* ps, const 
   // element matrices
   c->Ke.alloc((size_t)E * 3600);
   const unsigned eg = (unsigned)std::min<int64_t>(E, 256 * 32);
-  hipLaunchKernelGGL(k_element, dim3(eg), dim3(256), sizeof(ElemSmem), s, E, c->xyz.p,
+  hipLaunchKernelGGL(k_element, dim3(eg), dim3(256), sizeof(ElemSmem), s, periodic_of(c), E, c->xyz.p,
                      c->conn.p, c->elayer.p, Cl.p, ang.p, c->Ke.p, err.p);
   GX_HIP(hipGetLastError());
   to_host(&herr, err.p, 1, s);
@@ -691,7 +698,7 @@ gx_status gx_assemble(gx_ctx* c, const gx_mesh* m, const gx_plystack* ps, const 
     to_dev(df.p, hf.data(), hf.size(), s);
     const int64_t nent = ld->n_faces * 20;
     DevBuf<double> fl(3 * nent);
-    hipLaunchKernelGGL(k_face_loads, dim3(nblocks(nent, 64)), dim3(64), 0, s,
+    hipLaunchKernelGGL(k_face_loads, dim3(nblocks(nent, 64)), dim3(64), 0, s, periodic_of(c),
                        (int64_t)ld->n_faces, de.p, df.p, c->xyz.p, c->conn.p, ld->traction,
                        fl.p);
     GX_HIP(hipGetLastError());

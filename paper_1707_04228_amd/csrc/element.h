@@ -47,6 +47,29 @@ static __device__ inline void shape_one(int a, double p0, double p1, double p2, 
   }
 }
 
+// Coordinates of element nodes of a periodic mesh: node a of element e is seen at its
+// stored coordinates plus the period when bit a of wrap[e] is set (wrap null: never).
+struct Periodic {
+  const uint32_t* wrap;
+  double p[3];
+};
+
+static __device__ inline double node_coord(const double* xyz, int64_t nd, int i,
+                                           const Periodic& P, int64_t e, int a) {
+  double x = xyz[3 * nd + i];
+  if (P.wrap && ((P.wrap[e] >> a) & 1u)) x += P.p[i];
+  return x;
+}
+
+// the context's description (defined where gx_ctx is complete)
+template <class Ctx>
+inline Periodic periodic_of(const Ctx* c) {
+  Periodic P;
+  P.wrap = c->wrap.p;
+  for (int i = 0; i < 3; ++i) P.p[i] = c->period[i];
+  return P;
+}
+
 static __device__ inline void gauss3(int i, double* x, double* w) {
   const double s = 0.7745966692414833770358531;  // sqrt(3/5)
   *x = (i == 0) ? -s : ((i == 1) ? 0.0 : s);

@@ -30,7 +30,7 @@ struct FailSmem {
   double S[64][6];
 };
 
-__global__ void __launch_bounds__(64) k_failure(int64_t n_elems, const double* xyz,
+__global__ void __launch_bounds__(64) k_failure(Periodic P, int64_t n_elems, const double* xyz,
                                                 const int32_t* conn, const int32_t* elayer,
                                                 const double* Cl, const double* ang,
                                                 const uint8_t* sel, const double* u,
@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(64) k_failure(int64_t n_elems, const double* x
     if (t < 60) {
       const int a = t / 3, i = t % 3;
       const int64_t nd = conn[20 * e + a];
-      sm.X[a][i] = xyz[3 * nd + i];
+      sm.X[a][i] = node_coord(xyz, nd, i, P, e, a);
       sm.U[a][i] = u[3 * nd + i];
     }
     __syncthreads();
@@ -132,16 +132,16 @@ __global__ void __launch_bounds__(64) k_failure(int64_t n_elems, const double* x
         for (int K = 0; K < 6; ++K) acc += C[6 * I + K] * ev[K];
         sv[I] = acc;
       }
-      // back to the frame (s, l, r): sigma_geo = P sigma' P^T, P the rotation by the ply
-      // angle about e3 (P[a][m] = e_a . q_m)
+      // back to the frame (s, l, r): sigma_geo = Rp sigma' Rp^T, Rp the rotation by the ply
+      // angle about e3 (Rp[a][m] = e_a . q_m)
       const double Sm[3][3] = {{sv[0], sv[5], sv[4]}, {sv[5], sv[1], sv[3]}, {sv[4], sv[3], sv[2]}};
-      const double P[3][3] = {{ca, -sa, 0.0}, {sa, ca, 0.0}, {0.0, 0.0, 1.0}};
+      const double Rp[3][3] = {{ca, -sa, 0.0}, {sa, ca, 0.0}, {0.0, 0.0, 1.0}};
       double Sg[3][3];
       for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {
           double acc = 0.0;
           for (int m = 0; m < 3; ++m)
-            for (int k = 0; k < 3; ++k) acc += P[a][m] * Sm[m][k] * P[b][k];
+            for (int k = 0; k < 3; ++k) acc += Rp[a][m] * Sm[m][k] * Rp[b][k];
           Sg[a][b] = acc;
         }
       loc[0] = Sg[0][0];
@@ -233,7 +233,7 @@ extern "C" gx_status gx_failure(gx_ctx* c, const double* u, const int32_t* layer
   }
   se.alloc(6 * E);
   hipLaunchKernelGGL(k_failure, dim3((unsigned)std::min<int64_t>(E, 256 * 64)), dim3(64), 0, st,
-                     E, c->xyz.p, c->conn.p, c->elayer.p, c->Cl.p, c->ang.p, sel.p, u, s33, s13,
+                     periodic_of(c), E, c->xyz.p, c->conn.p, c->elayer.p, c->Cl.p, c->ang.p, sel.p, u, s33, s13,
                      F_gauss, Fe, qe.p, se.p);
   hipLaunchKernelGGL(k_failure_max, dim3(1), dim3(256), 0, st, E, Fe, be.p);
   GX_HIP(hipGetLastError());

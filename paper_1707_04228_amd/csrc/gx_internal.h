@@ -308,6 +308,8 @@ struct gx_ctx {
   int64_t n_nodes = 0, n_elems = 0;
   gx::DevBuf<double> xyz;
   gx::DevBuf<int32_t> conn, elayer;
+  gx::DevBuf<uint32_t> wrap;                   // periodic meshes: element nodes at the seam
+  double period[3] = {0.0, 0.0, 0.0};
   gx::DevBuf<int32_t> ne_ptr, ne_idx;          // node -> element incidence (sorted)
   gx::DevBuf<uint8_t> fixed;                   // per DOF: 1 if clamped
   // element matrices, block-major: Ke[((e * 20 + a) * 20 + b) * 9 + 3 i + k]

@@ -17,6 +17,10 @@ struct LamDev {
   double length, width, radius, limb, amp, wlen, T;
   double s_a, s_b, r_ref;                        // L-section arc ends and mid radius
   double dd, ds, dl, dz, b1, b2i, b2o, b3;       // sech^2 defect (Eq. eq-f), dd = 0: none
+  double bs, bl, bz;                             // bias ratios (<= 1: uniform)
+  double strip_w;                                // resin edge strips (0: none)
+  int strip_ny, strip_mat, end_column, end_mat;
+  int periodic;                                  // lattice plane j2 = 2 ny is j2 = 0
   double t[MAX_LAYERS], z0[MAX_LAYERS];          // thickness, start of each layer
   int nel[MAX_LAYERS], cum[MAX_LAYERS + 1];      // element layers, cumulative count
 };
@@ -36,6 +40,16 @@ static void check_lam(const gx_laminate* L) {
     GX_REQUIRE(L->nx_limb >= 1 && L->nx - 2 * L->nx_limb >= 1, "nx_limb out of range");
   }
   if (L->wrinkle_amp != 0.0) GX_REQUIRE(L->wrinkle_len > 0, "wrinkle length must be > 0");
+  GX_REQUIRE(std::isfinite(L->bias_s) && std::isfinite(L->bias_l) && std::isfinite(L->bias_z),
+             "bias ratios must be finite");
+  if (L->strip_width > 0) {
+    GX_REQUIRE(L->strip_ny >= 1 && 2 * L->strip_ny < L->ny, "strip_ny out of range");
+    GX_REQUIRE(2 * L->strip_width < L->width, "edge strips wider than the part");
+    GX_REQUIRE(L->strip_mat >= 0, "strip material index");
+  }
+  if (L->end_column) GX_REQUIRE(L->end_mat >= 0, "end-column material index");
+  if (L->periodic_l)
+    GX_REQUIRE(!(L->strip_width > 0), "a periodic laminate has no free edges for strips");
   if (L->defect_amp != 0.0) {
     GX_REQUIRE(L->geometry == GX_GEOM_LSECTION, "the sech^2 defect needs an L-section");
     GX_REQUIRE(L->defect_b1 > 0 && L->defect_b2_in > 0 && L->defect_b2_out > 0 &&
@@ -66,6 +80,15 @@ static LamDev make_lam(const gx_laminate* L) {
   d.b2i = L->defect_b2_in > 0 ? L->defect_b2_in : 1.0;
   d.b2o = L->defect_b2_out > 0 ? L->defect_b2_out : 1.0;
   d.b3 = L->defect_b3 > 0 ? L->defect_b3 : 1.0;
+  d.bs = L->bias_s;
+  d.bl = L->bias_l;
+  d.bz = L->bias_z;
+  d.strip_w = L->strip_width > 0 ? L->strip_width : 0.0;
+  d.strip_ny = d.strip_w > 0 ? L->strip_ny : 0;
+  d.strip_mat = L->strip_mat;
+  d.end_column = L->end_column ? 1 : 0;
+  d.end_mat = L->end_mat;
+  d.periodic = L->periodic_l ? 1 : 0;
   double z = 0;
   int c = 0;
   d.cum[0] = 0;
@@ -85,27 +108,36 @@ static LamDev make_lam(const gx_laminate* L) {
   return d;
 }
 
+// Nodes per lattice row and plane: re nodes on a row with even j2 and k2, ro on the other
+// rows; pe nodes on a plane of even k2, po on one of odd k2.  A periodic laminate has the
+// rows j2 = 0 .. 2 ny - 1 only (j2 = 2 ny is j2 = 0).
+__host__ __device__ inline int64_t rows_even(const LamDev& L) { return L.periodic ? L.ny : L.ny + 1; }
+__host__ __device__ inline int64_t plane_even(const LamDev& L) {
+  return rows_even(L) * (2 * (int64_t)L.nx + 1) + (int64_t)L.ny * ((int64_t)L.nx + 1);
+}
+__host__ __device__ inline int64_t plane_odd(const LamDev& L) {
+  return ((int64_t)L.nx + 1) * rows_even(L);
+}
+
 struct Counts {
-  int64_t re, ro, pe, po, nodes, elems, clamped, faces;
+  int64_t nodes, elems, clamped, faces;
 };
-static Counts counts(int nx, int ny, int nz) {
+static Counts counts(const LamDev& L) {
   Counts k;
-  k.re = 2 * (int64_t)nx + 1;
-  k.ro = (int64_t)nx + 1;
-  k.pe = ((int64_t)ny + 1) * k.re + (int64_t)ny * k.ro;
-  k.po = ((int64_t)nx + 1) * ((int64_t)ny + 1);
-  k.nodes = ((int64_t)nz + 1) * k.pe + (int64_t)nz * k.po;
-  k.elems = (int64_t)nx * ny * nz;
-  k.clamped = ((int64_t)nz + 1) * (2 * (int64_t)ny + 1) + (int64_t)nz * ((int64_t)ny + 1);
-  k.faces = (int64_t)ny * nz;
+  const int64_t nz = L.nz;
+  k.nodes = (nz + 1) * plane_even(L) + nz * plane_odd(L);
+  k.elems = (int64_t)L.nx * L.ny * nz;
+  // nodes on the s = s_min face: 2 ny (+1) on a plane of even k2, ny (+1) on an odd one
+  k.clamped = (nz + 1) * (2 * (int64_t)L.ny + (L.periodic ? 0 : 1)) + nz * rows_even(L);
+  k.faces = (int64_t)L.ny * nz;
   return k;
 }
 
 // node number of lattice point (i2, j2, k2); at most one index is odd
 __device__ inline int64_t node_id(const LamDev& L, int i2, int j2, int k2) {
   const int64_t re = 2 * (int64_t)L.nx + 1, ro = (int64_t)L.nx + 1;
-  const int64_t pe = ((int64_t)L.ny + 1) * re + (int64_t)L.ny * ro;
-  const int64_t po = ((int64_t)L.nx + 1) * ((int64_t)L.ny + 1);
+  const int64_t pe = plane_even(L), po = plane_odd(L);
+  if (L.periodic && j2 == 2 * L.ny) j2 = 0;
   int64_t id = (int64_t)(k2 >> 1) * (pe + po);
   if (k2 & 1) return id + pe + (int64_t)(j2 >> 1) * ro + (i2 >> 1);
   id += (int64_t)(j2 >> 1) * (re + ro);
@@ -113,12 +145,40 @@ __device__ inline int64_t node_id(const LamDev& L, int i2, int j2, int k2) {
   return id + i2;
 }
 
+// Boundary i (0..n) of n elements graded with ratio `bias` (largest over smallest element,
+// sizes q^e growing geometrically, symmetric about the middle): as a fraction of the
+// segment.  e = min(k, n - 1 - k) refines towards both ends, m - e towards the middle
+// (m = (n - 1) / 2, q = bias^(1/m)); bias <= 1 gives i / n.
+__device__ inline double graded_frac(int i, int n, double bias, bool middle) {
+  const int m = (n - 1) / 2;
+  if (!(bias > 1.0) || m == 0) return (double)i / n;
+  const double q = pow(bias, 1.0 / m);
+  double s = 0.0, tot = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const int e = min(k, n - 1 - k);
+    const double h = pow(q, (double)(middle ? m - e : e));
+    if (k < i) s += h;
+    tot += h;
+  }
+  return s / tot;
+}
+
 __device__ inline double s_bound(const LamDev& L, int i) {
-  if (L.geometry == GX_GEOM_FLAT) return L.length * i / L.nx;
+  if (L.geometry == GX_GEOM_FLAT) return L.length * graded_frac(i, L.nx, L.bs, true);
   const int nl = L.nx_limb, na = L.nx - 2 * L.nx_limb;
   if (i <= nl) return L.s_a - L.limb + L.limb * i / nl;
-  if (i <= nl + na) return L.s_a + (L.s_b - L.s_a) * (i - nl) / na;
+  if (i <= nl + na) return L.s_a + (L.s_b - L.s_a) * graded_frac(i - nl, na, L.bs, true);
   return L.s_b + L.limb * (i - nl - na) / nl;
+}
+
+// across the width: uniform strips at both edges, the laminate between graded towards them
+__device__ inline double l_bound(const LamDev& L, int j) {
+  if (L.strip_ny == 0) return L.width * graded_frac(j, L.ny, L.bl, false);
+  const int ns = L.strip_ny;
+  const double e = L.strip_w;
+  if (j < ns) return e * j / ns;
+  if (j > L.ny - ns) return L.width - e + e * (j - (L.ny - ns)) / ns;
+  return e + (L.width - 2.0 * e) * graded_frac(j - ns, L.ny - 2 * ns, L.bl, false);
 }
 
 __device__ inline double z_bound(const LamDev& L, int k) {
@@ -126,7 +186,7 @@ __device__ inline double z_bound(const LamDev& L, int k) {
   const int e = k - 1;                           // element layer whose top this is
   int li = 0;
   while (li + 1 < L.n_layers && L.cum[li + 1] <= e) ++li;
-  return L.z0[li] + L.t[li] * (e - L.cum[li] + 1) / L.nel[li];
+  return L.z0[li] + L.t[li] * graded_frac(e - L.cum[li] + 1, L.nel[li], L.bz, false);
 }
 
 __device__ inline double lattice(double a, double b, bool odd) {
@@ -180,8 +240,7 @@ __device__ inline void map_point(const LamDev& L, double s, double l, double zet
 __device__ inline void node_param(const LamDev& L, int64_t n, double* s, double* l,
                                   double* z) {
   const int64_t re = 2 * (int64_t)L.nx + 1, ro = (int64_t)L.nx + 1;
-  const int64_t pe = ((int64_t)L.ny + 1) * re + (int64_t)L.ny * ro;
-  const int64_t po = ((int64_t)L.nx + 1) * ((int64_t)L.ny + 1);
+  const int64_t pe = plane_even(L), po = plane_odd(L);
   const int64_t kp = n / (pe + po);
   int64_t rem = n - kp * (pe + po);
   int i2, j2, k2;
@@ -198,7 +257,7 @@ __device__ inline void node_param(const LamDev& L, int64_t n, double* s, double*
     i2 = (int)(2 * (rem % ro));
   }
   *s = lattice(s_bound(L, i2 >> 1), s_bound(L, (i2 >> 1) + (i2 & 1)), i2 & 1);
-  *l = lattice(L.width * (j2 >> 1) / L.ny, L.width * ((j2 >> 1) + (j2 & 1)) / L.ny, j2 & 1);
+  *l = lattice(l_bound(L, j2 >> 1), l_bound(L, (j2 >> 1) + (j2 & 1)), j2 & 1);
   *z = lattice(z_bound(L, k2 >> 1), z_bound(L, (k2 >> 1) + (k2 & 1)), k2 & 1);
 }
 
@@ -268,18 +327,35 @@ __global__ void k_elems(LamDev L, int64_t n_elems, int32_t* conn, int32_t* elaye
         (int32_t)node_id(L, 2 * ex + c_loc[a][0], 2 * ey + c_loc[a][1], 2 * ez + c_loc[a][2]);
   int li = 0;
   while (li + 1 < L.n_layers && L.cum[li + 1] <= ez) ++li;
+  // material overrides: the edge strips, then the stiff end column of the loaded limb
+  if (L.strip_ny > 0 && (ey < L.strip_ny || ey >= L.ny - L.strip_ny)) li = L.strip_mat;
+  if (L.end_column && ex == L.nx - 1) li = L.end_mat;
   elayer[e] = li;
 }
 
 __global__ void k_clamped(LamDev L, int64_t n, int32_t* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int64_t per = 3 * (int64_t)L.ny + 2;     // (2 ny + 1) + (ny + 1) per plane pair
+  const int64_t ne = 2 * (int64_t)L.ny + (L.periodic ? 0 : 1);   // even plane's face nodes
+  const int64_t per = ne + rows_even(L);                           // per plane pair
   const int64_t kp = i / per, r = i - kp * per;
   int k2, j2;
-  if (r < 2 * L.ny + 1) { k2 = (int)(2 * kp); j2 = (int)r; }
-  else { k2 = (int)(2 * kp + 1); j2 = (int)(2 * (r - (2 * L.ny + 1))); }
+  if (r < ne) { k2 = (int)(2 * kp); j2 = (int)r; }
+  else { k2 = (int)(2 * kp + 1); j2 = (int)(2 * (r - ne)); }
   out[i] = (int32_t)node_id(L, 0, j2, k2);
+}
+
+// bit a of wrap[e]: element node a stands for the lattice plane j2 = 2 ny of a periodic
+// laminate (its coordinates are those of the node at j2 = 0 plus the width along l)
+__global__ void k_wrap(LamDev L, int64_t n_elems, uint32_t* wrap) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_elems) return;
+  const int ey = (int)((e / L.nx) % L.ny);
+  uint32_t m = 0;
+  if (L.periodic && ey == L.ny - 1)
+    for (int a = 0; a < 20; ++a)
+      if (c_loc[a][1] == 2) m |= 1u << a;
+  wrap[e] = m;
 }
 
 __global__ void k_faces(LamDev L, int64_t n, int32_t* fe, int32_t* fid) {
@@ -303,7 +379,7 @@ __global__ void k_partition(LamDev L, int64_t n_elems, int px, int py, int32_t* 
 void laminate_velocity(const gx_laminate* lam, int param, double* xd, hipStream_t st) {
   LamDev L = make_lam(lam);
   GX_REQUIRE(lam->wrinkle_len > 0, "shape derivatives need a wrinkle wavelength > 0");
-  Counts k = counts(L.nx, L.ny, L.nz);
+  Counts k = counts(L);
   hipLaunchKernelGGL(k_node_velocity, dim3(nblocks(k.nodes, 256)), dim3(256), 0, st, L, param,
                      k.nodes, xd);
   GX_HIP(hipGetLastError());
@@ -311,7 +387,7 @@ void laminate_velocity(const gx_laminate* lam, int param, double* xd, hipStream_
 
 void laminate_region(const gx_laminate* lam, uint8_t* mask, hipStream_t st) {
   LamDev L = make_lam(lam);
-  Counts k = counts(L.nx, L.ny, L.nz);
+  Counts k = counts(L);
   hipLaunchKernelGGL(k_arc_mask, dim3(nblocks(k.elems, 256)), dim3(256), 0, st, L, k.elems,
                      mask);
   GX_HIP(hipGetLastError());
@@ -319,7 +395,7 @@ void laminate_region(const gx_laminate* lam, uint8_t* mask, hipStream_t st) {
 
 void laminate_sizes(const gx_laminate* lam, int64_t* n_nodes, int64_t* n_elems) {
   LamDev L = make_lam(lam);
-  Counts k = counts(L.nx, L.ny, L.nz);
+  Counts k = counts(L);
   *n_nodes = k.nodes;
   *n_elems = k.elems;
 }
@@ -334,7 +410,7 @@ gx_status gx_laminate_counts(const gx_laminate* lam, int64_t* n_nodes, int64_t* 
                              int64_t* n_clamped, int64_t* n_faces) {
   try {
     LamDev L = make_lam(lam);
-    Counts k = counts(L.nx, L.ny, L.nz);
+    Counts k = counts(L);
     GX_REQUIRE(k.nodes < ((int64_t)1 << 31) / 3, "mesh too large for 32-bit DOF indices");
     if (n_nodes) *n_nodes = k.nodes;
     if (n_elems) *n_elems = k.elems;
@@ -351,7 +427,7 @@ gx_status gx_laminate_mesh(gx_ctx* c, const gx_laminate* lam, double* xyz, int32
                            int32_t* face_id) {
   GX_API_BEGIN(c)
   LamDev L = make_lam(lam);
-  Counts k = counts(L.nx, L.ny, L.nz);
+  Counts k = counts(L);
   GX_REQUIRE(xyz && conn && elem_layer, "null mesh output");
   hipLaunchKernelGGL(k_nodes, dim3(nblocks(k.nodes, 256)), dim3(256), 0, c->stream, L,
                      k.nodes, xyz);
@@ -368,13 +444,25 @@ gx_status gx_laminate_mesh(gx_ctx* c, const gx_laminate* lam, double* xyz, int32
   GX_API_END(c)
 }
 
+gx_status gx_laminate_wrap(gx_ctx* c, const gx_laminate* lam, uint32_t* elem_wrap) {
+  GX_API_BEGIN(c)
+  LamDev L = make_lam(lam);
+  GX_REQUIRE(elem_wrap, "null wrap output");
+  Counts k = counts(L);
+  hipLaunchKernelGGL(k_wrap, dim3(nblocks(k.elems, 256)), dim3(256), 0, c->stream, L, k.elems,
+                     elem_wrap);
+  GX_HIP(hipGetLastError());
+  GX_HIP(hipStreamSynchronize(c->stream));
+  GX_API_END(c)
+}
+
 gx_status gx_laminate_partition(gx_ctx* c, const gx_laminate* lam, int32_t px, int32_t py,
                                 int32_t* part) {
   GX_API_BEGIN(c)
   LamDev L = make_lam(lam);
   GX_REQUIRE(px >= 1 && py >= 1 && px <= L.nx && py <= L.ny, "px, py out of range");
   GX_REQUIRE(part, "null partition output");
-  Counts k = counts(L.nx, L.ny, L.nz);
+  Counts k = counts(L);
   hipLaunchKernelGGL(k_partition, dim3(nblocks(k.elems, 256)), dim3(256), 0, c->stream, L,
                      k.elems, px, py, part);
   GX_HIP(hipGetLastError());

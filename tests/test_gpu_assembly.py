@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 CASES = [workloads.cfg0(), workloads.small_flat(nx=5, ny=3),
          workloads.small_lsection(nx=12, ny=2), workloads.small_lsection(nx=9, ny=3, amp=0.0),
-         workloads.defect_lsection(nx=20, ny=4, d=0.35)]
+         workloads.defect_lsection(nx=20, ny=4, d=0.35),
+         workloads.graded_lsection(nx=20, ny=8)]
 
 
 @pytest.fixture(scope="module")

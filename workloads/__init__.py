@@ -192,3 +192,44 @@ def defect_lsection(nx=24, ny=4, d=0.3, angles=(0, 45, 90, -45), ply_nel=1, limb
                 layers=layers, defect=D, load={"kind": "moment", "M": PAPER_MOMENT},
                 solver=dict(px=px, py=py, overlap=1, nev=nev, tau=None, nev_max=32,
                             rtol=1e-8))
+
+
+# The "very stiff" end layer that carries the moment (section 2.2); the paper gives no
+# value: ten times the ply's fibre modulus, isotropic.
+STIFF_END = dict(E=10 * PLY["E1"], nu=0.3)
+
+
+def graded_lsection(nx=20, ny=8, ny_strip=2, strip=0.5, bias=None, stiff=True, d=0.25,
+                    angles=(0, 90, 0), ply_nel=2, limb=3.0, width=4.0, px=4, py=2, nev=6):
+    """A small edge-treated, graded L-section (section 2.2 / 3.1 features): resin edge strips
+    of `strip` mm with ny_strip elements each, the laminate graded towards its edges, every
+    layer towards its faces and the arc towards mid-arc, a stiff end column on the loaded
+    limb, and the sech^2 defect at mid-arc."""
+    cfg = defect_lsection(nx=nx, ny=ny, d=d, angles=angles, ply_nel=ply_nel, limb=limb,
+                          width=width, px=px, py=py, nev=nev)
+    cfg["name"] = f"graded_lsec_{nx}x{ny}"
+    cfg["bias"] = dict(s=2.0, l=20.0, z=4.0) if bias is None else dict(bias)
+    if strip:
+        cfg["edge_strip"] = dict(width=float(strip), ny=int(ny_strip), **RESIN_EDGE)
+    if stiff:
+        cfg["stiff_end"] = dict(STIFF_END)
+    return cfg
+
+
+def verification_model(px=8, py=8, overlap=1):
+    """The corner-unfolding verification model of section 2.2: R = 6.6 mm, 3 mm limbs,
+    W = 15 mm, the 12-ply layup [+-45/90/0/-+45/-+45/0/90/+-45] of 0.23 mm plies and 0.02 mm
+    resin interfaces (T = 2.98 mm), 6 elements in every layer, 56 elements along s and l
+    (432,768 elements, 5,362,047 DOFs); 2 mm resin edge strips, the mesh graded with bias
+    400 across the width (towards the laminate's edges) and 10 through every layer, a stiff
+    end layer carrying the 96.8 N mm/mm moment.  The strips carry 4 of the 56 elements
+    each (the paper does not say how many)."""
+    angles = [45, -45, 90, 0, -45, 45, -45, 45, 0, 90, 45, -45]
+    layers = ply_layers(angles, 0.23, 6, 0.02, 6)
+    return dict(name="verification_56x56x138", geometry="lsection", radius=6.6, limb=3.0,
+                width=15.0, nx=56, ny=56, nx_limb=_limb_elems(56, 3.0, 6.6, layers),
+                layers=layers, bias=dict(s=1.0, l=400.0, z=10.0),
+                edge_strip=dict(width=2.0, ny=4, **RESIN_EDGE), stiff_end=dict(STIFF_END),
+                load={"kind": "moment", "M": PAPER_MOMENT},
+                solver=dict(px=px, py=py, overlap=overlap, nev=0, tau=0.1, nev_max=32,
+                            rtol=1e-8))
