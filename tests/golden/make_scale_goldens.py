@@ -13,7 +13,9 @@ norm.  Cases:
   rtol 1e-8 (trajectory parity, section 2.3 / Eq. eq-pre);
 * lsec60: the curved wrinkled L-section of the 3M-DOF target reduced to 60 x 6 x 59
   elements and 8 x 2 subdomains: GenEO modes and eigenvalues, and the solution of K u = f
-  by the oracle's PCG to rtol 1e-12 (the discrete solution, for the FP64 and mixed paths).
+  by the oracle's PCG to rtol 1e-12 (the discrete solution, for the FP64 and mixed paths),
+  with the oracle's own sensitivity to assembly rounding: K summed in reverse element order
+  and solved again (any two FP64 assemblies of K differ by that much, times kappa(K)).
 
 Local and eigensolver factorisations use LAPACK banded Cholesky (oracle/direct.py).
 """
@@ -64,6 +66,19 @@ def run(name, cfg, rtol, extra_rtol=None):
         log(f"{name}: {it2} PCG iterations to rtol {extra_rtol}")
         out.update(x_tight=xt[pos[idx]], x_tight_norm=np.linalg.norm(xt),
                    tight_rtol=extra_rtol, tight_iters=it2)
+        # sensitivity of the discrete solution to the rounding of assembly: K summed over the
+        # elements in reverse order (the same matrix up to rounding) and solved again
+        from oracle.fem import assemble
+        Kr = assemble(prob.mesh, prob.Ke, elems=np.arange(prob.mesh.n_elems)[::-1])
+        Kr = Kr[prob.free][:, prob.free].tocsr()
+        nd = int((Kr != prob.K).nnz)
+        xr, it3, _, _ = pcg.pcg(Kr, prob.f, R["P"].apply, rtol=extra_rtol, maxit=4000)
+        d = float(np.linalg.norm(xr - xt) / np.linalg.norm(xt))
+        log(f"{name}: reverse-order assembly differs in {nd} entries; its solution differs by "
+            f"{d:.3e} ({it3} iterations)")
+        out.update(reorder_entries=nd, reorder_diff=d,
+                   reorder_sample_diff=float(np.linalg.norm(xr[pos[idx]] - xt[pos[idx]]) /
+                                             np.linalg.norm(xt[pos[idx]])))
     path = os.path.join(HERE, f"scale_{name}.npz")
     np.savez_compressed(path, **out)
     log(f"{name}: wrote {path}")

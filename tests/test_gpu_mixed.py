@@ -51,5 +51,10 @@ def test_mixed_precision_matches_oracle(gx, cfg):
     Kg = bcsr_to_scipy(*s.matrix(), s.mesh["n_nodes"])[prob.free][:, prob.free].tocsr()
     xg, _ = refined_solve(Kg, f.cpu().numpy()[prob.free])
     tight = s.pcg(f, rtol=1e-13, maxit=1000, allow_noconv=True)
-    tol = max(1e-10, 0.1 * kappa(prob.K) * 1.11e-16)
-    assert rel_err(tight["x"].cpu().numpy()[prob.free], xg) <= tol
+    kap = kappa(prob.K)
+    tol = max(1e-10, 0.01 * kap * 1.11e-16)
+    err = rel_err(tight["x"].cpu().numpy()[prob.free], xg)
+    print(f"mixed: rtol-1e-8 solution vs the oracle's exact solution {rel_err(x, xo):.2e}; "
+          f"rtol 1e-13 vs the exact solution of the assembled system {err:.2e} (kappa(K) "
+          f"{kap:.2e}, bound {tol:.2e})", flush=True)
+    assert err <= tol

@@ -121,10 +121,14 @@ def check_solution(s, f, prob, out, histo):
     assert rel_err(xf, xg) <= 1e-6
     tight = s.pcg(f, rtol=1e-13, maxit=1000, allow_noconv=True)
     xt = tight["x"].cpu().numpy()[prob.free]
-    # a backward-stable FP64 solve guarantees only kappa(K) u; require 1e-10, or a tenth of
-    # that bound on the most ill-conditioned (thin strip, kappa ~ 1e9) cases
-    tol = max(1e-10, 0.1 * kappa(prob.K) * 1.11e-16)
-    assert rel_err(xt, xg) <= tol
+    # a backward-stable FP64 solve guarantees only kappa(K) u; require 1e-10, or a hundredth
+    # of that bound on the ill-conditioned cases
+    kap = kappa(prob.K)
+    tol = max(1e-10, 0.01 * kap * 1.11e-16)
+    err = rel_err(xt, xg)
+    print(f"solution vs the exact solution of the assembled system: {err:.2e} "
+          f"(kappa(K) {kap:.2e}, bound {tol:.2e})", flush=True)
+    assert err <= tol
     # end to end: the assembly difference explains the rest (first-order perturbation)
     pred = lu.solve((fg - prob.f) - (Kg - prob.K) @ xo)
     assert np.linalg.norm((xt - xo) - pred) <= 0.1 * np.linalg.norm(pred) + tol * np.linalg.norm(xo)
