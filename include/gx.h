@@ -215,6 +215,14 @@ gx_status gx_matrix_info(gx_ctx* ctx, int64_t* n_block_rows, int64_t* n_blocks);
 /* Copy K out: row_ptr device [n_block_rows + 1], col device [n_blocks], val device
  * [9 n_blocks] (each block row-major).  Columns are sorted within each row. */
 gx_status gx_matrix_copy(gx_ctx* ctx, int32_t* row_ptr, int32_t* col, double* val);
+/* Install a 3x3-block matrix given by the caller as K (in place of gx_assemble), for
+ * gx_spmv, gx_matrix_info and gx_matrix_copy: n_block_rows block rows, n_blocks blocks,
+ * row_ptr [n_block_rows + 1], col [n_blocks], val [9 n_blocks] (each block row-major),
+ * host or device pointers, copied.  Rows may be empty, columns need not be sorted.  The
+ * mesh-dependent calls (set-up, objective, adjoint, failure criterion) then return
+ * GX_ESTATE.  GX_EINVAL for inconsistent row pointers or out-of-range columns. */
+gx_status gx_matrix_load(gx_ctx* ctx, int64_t n_block_rows, int64_t n_blocks,
+                         const int32_t* row_ptr, const int32_t* col, const double* val);
 /* y = K x (device vectors of 3 n_nodes). */
 gx_status gx_spmv(gx_ctx* ctx, const double* x, double* y);
 

@@ -103,6 +103,7 @@ _sig("gx_assemble", [vp, C.POINTER(Mesh), C.POINTER(PlyStack), C.POINTER(Loads),
 _sig("gx_matrix_info", [vp, i64p, i64p])
 _sig("gx_matrix_copy", [vp, vp, vp, vp])
 _sig("gx_spmv", [vp, vp, vp])
+_sig("gx_matrix_load", [vp, C.c_int64, C.c_int64, vp, vp, vp])
 _sig("gx_phase_times", [vp, f64p])
 for _name, _args in [("gx_geneo_setup", [vp, C.POINTER(GeneoOpts), i32p, i64p]),
                      ("gx_subdomain_info", [vp, i64p, i64p, i64p]),
@@ -133,7 +134,8 @@ for _name, _args in [("gx_geneo_setup", [vp, C.POINTER(GeneoOpts), i32p, i64p]),
 EXPORTS = ["gx_create", "gx_destroy", "gx_last_error", "gx_version", "gx_laminate_counts",
            "gx_laminate_mesh", "gx_laminate_partition", "gx_laminate_traction",
            "gx_laminate_wrap",
-           "gx_assemble", "gx_matrix_info", "gx_matrix_copy", "gx_spmv", "gx_geneo_setup",
+           "gx_assemble", "gx_matrix_info", "gx_matrix_copy", "gx_matrix_load", "gx_spmv",
+           "gx_geneo_setup",
            "gx_subdomain_info", "gx_geneo_eigenvalues", "gx_precond_apply", "gx_pcg_solve",
            "gx_phase_times", "gx_kernel_time", "gx_stats", "gx_band_stats", "gx_tune",
            "gx_band_factor_solve", "gx_failure",
@@ -338,6 +340,15 @@ class Solver:
         val = torch.empty(9 * nb.value, dtype=torch.float64, device=self.device)
         self._check(lib.gx_matrix_copy(self.h, _ptr(rp), _ptr(col), _ptr(val)))
         return rp, col, val
+
+    @_on_stream
+    def load_matrix(self, row_ptr, col, val):
+        """Install a 3x3-block CSR matrix (torch tensors: int32 row_ptr, int32 col, float64
+        val with 9 entries per block, row-major) as K for spmv."""
+        n_rows = row_ptr.numel() - 1
+        self._check(lib.gx_matrix_load(self.h, n_rows, col.numel(), _ptr(row_ptr), _ptr(col),
+                                       _ptr(val)))
+        self.n_dofs = 3 * n_rows
 
     @_on_stream
     def spmv(self, x, y=None):

@@ -498,6 +498,7 @@ gx_status gx_objective(gx_ctx* c, const gx_laminate* lam, int32_t region, const 
                        double* J_out) {
   GX_API_BEGIN(c)
   if (!c->assembled) throw Error(GX_ESTATE, "matrix not assembled");
+  if (c->matrix_only) throw Error(GX_ESTATE, "needs an assembled mesh, not a loaded matrix");
   GX_REQUIRE(lam && u && J_out && (region == 0 || region == 1), "bad objective arguments");
   DevBuf<uint8_t> mask;
   *J_out = objective(c, lam, region, u, mask, nullptr);
@@ -508,6 +509,7 @@ gx_status gx_objective_noalloc(gx_ctx* c, const gx_laminate* lam, int32_t region
                                const double* u, double* J_out) {
   GX_API_BEGIN(c)
   if (!c->assembled) throw Error(GX_ESTATE, "matrix not assembled");
+  if (c->matrix_only) throw Error(GX_ESTATE, "needs an assembled mesh, not a loaded matrix");
   GX_REQUIRE(lam && u && J_out && (region == 0 || region == 1), "bad objective arguments");
   check_objective_laminate(c, lam);
   // layout: the sum at 0, J per element at 256, the region mask after it

@@ -588,6 +588,7 @@ gx_status gx_assemble(gx_ctx* c, const gx_mesh* m, const gx_plystack* ps, const 
   Timer tm(c->stream);
   hipStream_t s = c->stream;
   c->assembled = false;
+  c->matrix_only = false;
   c->setup_done = false;
   c->sw = Schwarz();
   c->n_nodes = m->n_nodes;
@@ -747,6 +748,41 @@ gx_status gx_matrix_copy(gx_ctx* c, int32_t* rp, int32_t* col, double* val) {
   if (col) GX_HIP(hipMemcpyAsync(col, c->col.p, c->nnzb * 4, hipMemcpyDefault, s));
   if (val) GX_HIP(hipMemcpyAsync(val, c->val.p, c->nnzb * 72, hipMemcpyDefault, s));
   GX_HIP(hipStreamSynchronize(s));
+  GX_API_END(c)
+}
+
+gx_status gx_matrix_load(gx_ctx* c, int64_t n_block_rows, int64_t n_blocks,
+                         const int32_t* row_ptr, const int32_t* col, const double* val) {
+  GX_API_BEGIN(c)
+  GX_REQUIRE(n_block_rows >= 1 && n_blocks >= 0 && row_ptr && (col && val || n_blocks == 0),
+             "bad block matrix");
+  GX_REQUIRE(n_block_rows < ((int64_t)1 << 31) / 3 && n_blocks < ((int64_t)1 << 31),
+             "block matrix too large for 32-bit indices");
+  hipStream_t s = c->stream;
+  std::vector<int32_t> hp(n_block_rows + 1), hc(n_blocks);
+  GX_HIP(hipMemcpyAsync(hp.data(), row_ptr, hp.size() * 4, hipMemcpyDefault, s));
+  if (n_blocks) GX_HIP(hipMemcpyAsync(hc.data(), col, hc.size() * 4, hipMemcpyDefault, s));
+  GX_HIP(hipStreamSynchronize(s));
+  GX_REQUIRE(hp[0] == 0 && hp[n_block_rows] == n_blocks, "row pointers do not span the blocks");
+  for (int64_t r = 0; r < n_block_rows; ++r) GX_REQUIRE(hp[r] <= hp[r + 1], "row pointers decrease");
+  for (int32_t v : hc) GX_REQUIRE(v >= 0 && v < n_block_rows, "column index out of range");
+  c->assembled = false;
+  c->setup_done = false;
+  c->sw = Schwarz();
+  c->n_nodes = n_block_rows;
+  c->n_elems = 0;
+  c->nnzb = n_blocks;
+  c->row_ptr.alloc(n_block_rows + 1);
+  c->col.alloc(std::max<int64_t>(n_blocks, 1));
+  c->val.alloc(std::max<int64_t>(9 * n_blocks, 1));
+  to_dev(c->row_ptr.p, hp.data(), hp.size(), s);
+  if (n_blocks) {
+    to_dev(c->col.p, hc.data(), hc.size(), s);
+    GX_HIP(hipMemcpyAsync(c->val.p, val, 9 * n_blocks * sizeof(double), hipMemcpyDefault, s));
+  }
+  GX_HIP(hipStreamSynchronize(s));
+  c->assembled = true;
+  c->matrix_only = true;
   GX_API_END(c)
 }
 

@@ -209,6 +209,7 @@ extern "C" gx_status gx_failure(gx_ctx* c, const double* u, const int32_t* layer
                                 gx_failure_result* out) {
   GX_API_BEGIN(c)
   if (!c->assembled) throw Error(GX_ESTATE, "matrix not assembled");
+  if (c->matrix_only) throw Error(GX_ESTATE, "needs an assembled mesh, not a loaded matrix");
   GX_REQUIRE(u && out && s33 > 0 && s13 > 0, "bad failure-criterion arguments");
   hipStream_t st = c->stream;
   const int64_t E = c->n_elems;

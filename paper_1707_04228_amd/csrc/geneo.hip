@@ -1301,6 +1301,7 @@ gx_status gx_geneo_setup(gx_ctx* c, const gx_geneo_opts* o, int32_t* nev_out,
                          int64_t* n0_out) {
   GX_API_BEGIN(c)
   if (!c->assembled) throw Error(GX_ESTATE, "gx_assemble has not been called");
+  if (c->matrix_only) throw Error(GX_ESTATE, "needs an assembled mesh, not a loaded matrix");
   GX_REQUIRE(o && o->elem_part, "null options");
   GX_REQUIRE(o->n_sub >= 1 && o->n_sub <= 4096, "n_sub out of range");
   GX_REQUIRE(o->overlap >= 1 && o->overlap <= 16, "overlap must be in [1, 16]");

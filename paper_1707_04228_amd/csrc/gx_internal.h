@@ -319,6 +319,7 @@ struct gx_ctx {
   gx::DevBuf<double> val;
   int64_t nnzb = 0;
   bool assembled = false;
+  bool matrix_only = false;                    // K given by gx_matrix_load (no mesh)
   // preconditioner
   gx::Schwarz sw;
   bool setup_done = false;

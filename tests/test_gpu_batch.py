@@ -156,3 +156,35 @@ def test_autotune_keeps_the_fastest_and_the_solution():
     assert abs(o2["iters"] - o1["iters"]) <= 1
     assert np.abs(x - ref).max() <= 1e-9 * np.abs(ref).max()
     batch.close()
+
+
+def test_batch_of_seeded_samples_matches_the_oracle():
+    """Two laminates drawn from the seeded wrinkle-sample sweep (different ply counts,
+    amplitudes and wavelengths; meshes reduced to 16 x 2 elements in plane) solved together
+    by the batched PCG with FP32 factors, each against the oracle's exact solution of its own
+    system (refined sparse LU): within 1e-8 at rtol 1e-10."""
+    import paper_1707_04228_amd as gx
+    from oracle import fem
+    from test_gpu_schwarz import refined_solve
+    smp = workloads.cfg4_samples()
+    picks = [0, next(i for i in range(1, 32) if len(smp[i]["angles"]) != len(smp[0]["angles"]))]
+    cfgs = []
+    for i in picks:
+        layers = workloads.ply_layers(smp[i]["angles"], 0.25, 1, 0.05, 1)
+        c = workloads.small_lsection(nx=16, ny=2, amp=smp[i]["amp"], wlen=smp[i]["wlen"],
+                                     layers=layers)
+        c["name"] = f"sample{i}_16x2"
+        cfgs.append(c)
+    batch = gx.Batch(cfgs, precision=gx.GX_MIXED)
+    batch.setup()
+    xs, it, rr, st = batch.solve(rtol=1e-10, maxit=1000)
+    assert np.all(st == gx.GX_OK)
+    for k, cfg in enumerate(cfgs):
+        prob = fem.Problem(cfg)
+        xo, _ = refined_solve(prob.K, prob.f)
+        x = xs[k].cpu().numpy()[prob.free]
+        err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+        print(f"{cfg['name']} ({len(cfg['layers'])} layers): {it[k]} iterations, error vs the "
+              f"oracle {err:.2e}", flush=True)
+        assert err <= 1e-8
+    batch.close()
