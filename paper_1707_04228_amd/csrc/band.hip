@@ -26,6 +26,32 @@ constexpr int SB = 64;          // solve block (one wavefront)
 constexpr int SOLVE_THREADS = 512;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// The 16x16x4 matrix instruction in the precision of a factor: FP64 factors multiply in FP64,
+// FP32 factors (the mixed path) in FP32.  Both take A[l % 16][l / 16] and B[l / 16][l % 16]
+// from lane l; the output row of accumulator register q differs: 4 q + l / 16 in FP64,
+// 4 (l / 16) + q in FP32.  S is the type staged in LDS and multiplied.
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double S;
+  typedef v4d V;
+  static __device__ inline V mma(S a, S b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int q, int lk) { return 4 * q + lk; }
+};
+template <>
+struct Mfma<float> {
+  typedef float S;
+  typedef v4f V;
+  static __device__ inline V mma(S a, S b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int q, int lk) { return 4 * lk + q; }
+};
 
 struct BandArgs {
   const int64_t* n;
@@ -261,7 +287,9 @@ constexpr int ST = 512;                           // threads of the trailing upd
 template <class T>
 __global__ void __launch_bounds__(ST) k_syrk(BandArgs a, T* v, int64_t k0, int64_t kk,
                                              int col_only, int64_t ts_lo, int64_t ts_hi) {
-  __shared__ double Pr[TS][NB + 1], Ps[TS][NB + 1];
+  typedef Mfma<T> MT;
+  typedef typename MT::S S;
+  __shared__ S Pr[TS][NB + 1], Ps[TS][NB + 1];
   const int j = blockIdx.y;
   const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
   if (k0 >= n) return;
@@ -297,46 +325,46 @@ __global__ void __launch_bounds__(ST) k_syrk(BandArgs a, T* v, int64_t k0, int64
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int rb = 16 * (w & 3), sb = 32 * (w >> 2);
-  v4d acc[2];
+  typename MT::V acc[2];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < 2; ++q) acc[q] = typename MT::V{0, 0, 0, 0};
   for (int64_t kc = 0; kc < kj; kc += NB) {
     const int64_t col = k0 + kc + cl;
     const bool okc = kc + cl < kj;
-    double vr[L], vs[L];
+    S vr[L], vs[L];
 #pragma unroll
     for (int u = 0; u < L; ++u) {
       const int64_t r = r0 + i0 + RS * u, ss = s0 + i0 + RS * u;
-      vr[u] = (double)base[min(r, rlast) * rs + B + col];
-      vs[u] = (double)base[min(ss, rlast) * rs + B + col];
+      vr[u] = (S)base[min(r, rlast) * rs + B + col];
+      vs[u] = (S)base[min(ss, rlast) * rs + B + col];
     }
 #pragma unroll
     for (int u = 0; u < L; ++u) {
       const int64_t r = r0 + i0 + RS * u, ss = s0 + i0 + RS * u;
       const bool okr = okc && r < wend && col >= r - B;
       const bool oks = okc && ss < wend && col >= ss - B;
-      Pr[i0 + RS * u][cl] = okr ? vr[u] : 0.0;
-      Ps[i0 + RS * u][cl] = oks ? vs[u] : 0.0;
+      Pr[i0 + RS * u][cl] = okr ? vr[u] : (S)0;
+      Ps[i0 + RS * u][cl] = oks ? vs[u] : (S)0;
     }
     __syncthreads();
 #pragma unroll 4
     for (int k = 0; k < NB; k += 4) {
-      const double a0 = Pr[rb + li][k + lk];
-      const double b0 = Ps[sb + li][k + lk], b1 = Ps[sb + 16 + li][k + lk];
-      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[1], 0, 0, 0);
+      const S a0 = Pr[rb + li][k + lk];
+      const S b0 = Ps[sb + li][k + lk], b1 = Ps[sb + 16 + li][k + lk];
+      acc[0] = MT::mma(a0, b0, acc[0]);
+      acc[1] = MT::mma(a0, b1, acc[1]);
     }
     __syncthreads();
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int64_t r = r0 + rb + 4 * q + lk;
+    const int64_t r = r0 + rb + MT::row(q, lk);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int64_t s = s0 + sb + 16 * t + li;
       if (r < wend && s <= r && (!col_only || s < t0 + TS)) {
         T* e = base + r * ld + (s - r + B);
-        *e = (T)((double)*e - acc[t][q]);
+        *e = (T)((S)*e - acc[t][q]);
       }
     }
   }
@@ -822,11 +850,13 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
     BandArgs a, const T* v, const T* dinv, const int64_t* boff, const int64_t* xoff,
     const double* xall, double* yall, double* zall, const int64_t* yoff, int G, int n_pad,
     int n_mat, const int32_t* active, int* err) {
+  typedef Mfma<T> MF;
+  typedef typename MF::S S;
   constexpr int NCT = (M + 15) / 16;              // column tiles (1 or 2)
   constexpr int MP = 16 * NCT;                    // LDS row stride (zero columns past M)
   constexpr int YL = SB * M / MT;                 // solution-chunk entries per thread
-  __shared__ double Ab[2][SB][SB + 1];            // band chunks (double buffer); buffer 0
-  __shared__ double Yc[2][SB * MP];               // holds the inverse block in finish
+  __shared__ S Ab[2][SB][SB + 1];                 // band chunks (double buffer); buffer 0
+  __shared__ S Yc[2][SB * MP];                    // holds the inverse block in finish
   const int g = blockIdx.x / n_pad, j = blockIdx.x % n_pad;
   if (j >= n_mat || g >= G) return;
   if (active && !active[j]) return;
@@ -846,7 +876,7 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
   if constexpr (MP > M)
     for (int idx = threadIdx.x; idx < 2 * SB * (MP - M); idx += MT) {
       const int e = idx % (SB * (MP - M));
-      Yc[idx / (SB * (MP - M))][(e / (MP - M)) * MP + M + e % (MP - M)] = 0.0;
+      Yc[idx / (SB * (MP - M))][(e / (MP - M)) * MP + M + e % (MP - M)] = (S)0;
     }
   // forward chunk kk of block i0: band rows i0.., columns 64 kk..; backward chunk kk:
   // band rows 64 kk.., columns i0..; both with solution rows 64 kk..  Thread t stages band
@@ -893,30 +923,30 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
     for (int u = 0; u < AL; ++u) {
       const int64_t r = r0 + 8 * u;
       const bool in = r < n && c <= r && c >= r - B && (!bwd || lane < nb);
-      Ab[buf][wave + 8 * u][lane] = in ? (double)fa[u] : 0.0;
+      Ab[buf][wave + 8 * u][lane] = in ? (S)fa[u] : (S)0;
     }
     const int64_t yend = min<int64_t>((int64_t)SB * M, (n - kk * SB) * M);   // rows < n
 #pragma unroll
     for (int u = 0; u < YL; ++u) {
       const int idx = threadIdx.x + MT * u;
-      Yc[buf][(idx / M) * MP + idx % M] = idx < yend ? fy[u] : 0.0;
+      Yc[buf][(idx / M) * MP + idx % M] = idx < yend ? (S)fy[u] : (S)0;
     }
   };
   // acc += A Yc over the 64-deep chunk for this wave's tile; A = Ab or Ab^T.  Even and odd
   // 4-deep steps go to two accumulators, so consecutive matrix instructions do not wait
   // for each other's result.
-  auto mma = [&](int buf, bool trans, v4d& acc) {
+  auto mma = [&](int buf, bool trans, typename MF::V& acc) {
     if (!tile) return;
-    v4d acc1 = {0.0, 0.0, 0.0, 0.0};
+    typename MF::V acc1 = {0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < SB / 4; ks += 2) {
       const int kq0 = 4 * ks + lk, kq1 = kq0 + 4;
-      const double a0 = trans ? Ab[buf][kq0][16 * rt + li] : Ab[buf][16 * rt + li][kq0];
-      const double a1 = trans ? Ab[buf][kq1][16 * rt + li] : Ab[buf][16 * rt + li][kq1];
-      const double b0 = Yc[buf][kq0 * MP + 16 * ct + li];
-      const double b1 = Yc[buf][kq1 * MP + 16 * ct + li];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
+      const S a0 = trans ? Ab[buf][kq0][16 * rt + li] : Ab[buf][16 * rt + li][kq0];
+      const S a1 = trans ? Ab[buf][kq1][16 * rt + li] : Ab[buf][16 * rt + li][kq1];
+      const S b0 = Yc[buf][kq0 * MP + 16 * ct + li];
+      const S b1 = Yc[buf][kq1 * MP + 16 * ct + li];
+      acc = MF::mma(a0, b0, acc);
+      acc1 = MF::mma(a1, b1, acc1);
     }
     acc += acc1;
   };
@@ -926,7 +956,7 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
   // per chunk separates the staging of a buffer from its readers (the product two chunks
   // back, and the next product)
   auto sweep = [&](bool bwd, int64_t i0, int nb, int64_t first, int64_t count, int step,
-                   v4d& acc) {
+                   typename MF::V& acc) {
     if (count <= 0) return;
     T fa0[AL], fa1[AL];
     double fy0[YL], fy1[YL];
@@ -956,13 +986,14 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
   // block's forward solution (polled) backward.
   // (dd: the block's inverse diagonal block, loaded before the sweep so that its latency
   // stays off the chain of hand-overs)
-  auto finish = [&](bool bwd, int64_t i0, int nb, const T (&dd)[AL], const v4d& acc) {
+  auto finish = [&](bool bwd, int64_t i0, int nb, const T (&dd)[AL],
+                    const typename MF::V& acc) {
     double bb[4];
     const int cc = min(16 * ct + li, M - 1);
     if (!bwd) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = min<int64_t>(i0 + 16 * rt + 4 * r + lk, n - 1);
+        const int64_t row = min<int64_t>(i0 + 16 * rt + MF::row(r, lk), n - 1);
         bb[r] = x[row * M + cc];
       }
     } else {
@@ -971,7 +1002,7 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
         bool ok = true;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int ii = 16 * rt + 4 * r + lk;
+          const int ii = 16 * rt + MF::row(r, lk);
           bb[r] = poll_load(y + (i0 + min(ii, nb - 1)) * M + cc);
           ok = ok && (!tile || ii >= nb || !is_mark(bb[r]));
         }
@@ -982,23 +1013,23 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
 #pragma unroll
     for (int u = 0; u < AL; ++u) {
       const int idx = threadIdx.x + MT * u;
-      Ab[0][idx >> 6][idx & 63] = (double)dd[u];
+      Ab[0][idx >> 6][idx & 63] = (S)dd[u];
     }
     if (tile)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int ii = 16 * rt + 4 * r + lk, col = 16 * ct + li;
-        if (col < M) Yc[0][ii * MP + col] = ii < nb ? bb[r] - acc[r] : 0.0;
+        const int ii = 16 * rt + MF::row(r, lk), col = 16 * ct + li;
+        if (col < M) Yc[0][ii * MP + col] = ii < nb ? (S)(bb[r] - (double)acc[r]) : (S)0;
       }
     __syncthreads();
-    v4d yv = {0.0, 0.0, 0.0, 0.0};
+    typename MF::V yv = {0, 0, 0, 0};
     mma(0, bwd, yv);
     double* dst = bwd ? z : y;
     if (tile)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int ii = 16 * rt + 4 * r + lk, col = 16 * ct + li;
-        if (ii < nb && col < M) hand_over(dst + (i0 + ii) * M + col, yv[r]);
+        const int ii = 16 * rt + MF::row(r, lk), col = 16 * ct + li;
+        if (ii < nb && col < M) hand_over(dst + (i0 + ii) * M + col, (double)yv[r]);
       }
     __syncthreads();
   };
@@ -1010,7 +1041,7 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
     T dd[AL];
 #pragma unroll
     for (int u = 0; u < AL; ++u) dd[u] = dv[k * SB * SB + threadIdx.x + MT * u];
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    typename MF::V acc = {0, 0, 0, 0};
     sweep(false, i0, nb, kfirst, k - kfirst, 1, acc);
     finish(false, i0, nb, dd, acc);
   }
@@ -1023,7 +1054,7 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
     T dd[AL];
 #pragma unroll
     for (int u = 0; u < AL; ++u) dd[u] = dv[kb * SB * SB + threadIdx.x + MT * u];
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    typename MF::V acc = {0, 0, 0, 0};
     sweep(true, i0, nb, klast, klast - kb, -1, acc);
     finish(true, i0, nb, dd, acc);
   }
