@@ -60,382 +60,565 @@ struct BandArgs {
   const int64_t* off;
 };
 
-// Diagonal block of step c0: Cholesky in LDS, written back; its inverse goes to inv[j].
+// ---- Factorisation: right-looking blocked Cholesky in groups of GP panels of NB columns.
+// The columns of a group [k0, k0 + GP NB) are factored by one launch (k_chain below).  The
+// update of the trailing window by the group's panels is split in two k_syrk_wide
+// launches: the next group's columns (then that group's k_chain, on the same stream), and
+// all further columns on a second stream, at the same time.
+constexpr int GP = 4;                             // panels per group
+constexpr int CT = 256;                           // threads of a panel work-group
+constexpr int64_t SPIN_LIMIT = (int64_t)1 << 22;  // polls before a wait gives up
+
+// Loads and stores of data handed between the work-groups of one launch: agent-scope
+// relaxed atomics, which bypass the per-XCD caches, so a reader sees the writer's values
+// without a cache flush or invalidate on either side.
 template <class T>
-__global__ void __launch_bounds__(256) k_potrf(BandArgs a, T* v, int64_t c0, double* inv,
-                                               T* dinv, const int64_t* boff, int* err) {
-  __shared__ double D[NB][NB + 1];
-  __shared__ double Li[NB][NB + 1];
-  const int j = blockIdx.x;
-  const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
-  if (c0 >= n) return;
-  T* base = v + a.off[j];
-  const int nb = (int)min<int64_t>(NB, n - c0);
-  {
-    constexpr int L = NB * NB / 256;
-    double vd[L];
-#pragma unroll
-    for (int u = 0; u < L; ++u) {
-      const int idx = threadIdx.x + 256 * u;
-      const int i = idx / NB, l = idx % NB;
-      double x = (i == l && i >= nb) ? 1.0 : 0.0;
-      if (i < nb && l <= i && i - l <= B) x = (double)base[(c0 + i) * ld + (l - i + B)];
-      vd[u] = x;
-    }
-#pragma unroll
-    for (int u = 0; u < L; ++u) {
-      const int idx = threadIdx.x + 256 * u;
-      D[idx / NB][idx % NB] = vd[u];
-    }
-  }
-  __syncthreads();
-  // right-looking elimination on the unscaled columns: step i subtracts
-  // D[r][i] D[s][i] / D[i][i] from the trailing lower triangle (s <= r); the columns are
-  // scaled by 1/sqrt(pivot) at the end.  A non-positive pivot is reported and replaced by 1.
-  // The steps go in blocks of BK columns, with the same operations in the same order per
-  // entry: (1) wave 0 eliminates the BK x BK diagonal block in registers (lane r: row r,
-  // pivots and column entries from wave-uniform lane reads), (2) one thread per row below
-  // it applies the block's steps to its BK panel entries in registers and keeps the
-  // multipliers f = D[r][i] / D[i][i], (3) all threads apply the block's steps to the
-  // trailing lower triangle.  Three barriers per block instead of one per column.
-  constexpr int BK = 16;
-  __shared__ double piv[NB];
-  __shared__ double F[NB][BK + 1];                 // multipliers of the current block
-  {
-    for (int k0 = 0; k0 < nb; k0 += BK) {
-      const int kn = min(BK, nb - k0);             // steps of this block
-      if (threadIdx.x < 64) {                      // (1) diagonal block
-        const int lane = threadIdx.x;
-        const int rr = min(lane, BK - 1);
-        double a[BK];
-#pragma unroll
-        for (int c = 0; c < BK; ++c) a[c] = D[k0 + rr][k0 + c];
-#pragma unroll
-        for (int i = 0; i < BK; ++i) {
-          if (i < kn) {
-            const double dii = lane_value(a[i], i);
-            const double d = dii > 0.0 ? dii : 1.0;
-            const double f = a[i] / d;
-#pragma unroll
-            for (int s2 = i + 1; s2 < BK; ++s2) {
-              const double dsi = lane_value(a[i], s2);      // D[k0 + s2][k0 + i]
-              if (lane > i && lane < BK && s2 <= lane) a[s2] -= f * dsi;
-            }
-            if (lane == 0) {
-              if (!(dii > 0.0)) atomicOr(err, 1);
-              piv[k0 + i] = d;
-            }
-          }
-        }
-        if (lane < BK)
-#pragma unroll
-          for (int c = 0; c < BK; ++c)
-            if (c <= lane) D[k0 + lane][k0 + c] = a[c];
-      }
-      __syncthreads();
-      const int r0 = k0 + BK;                      // first row below the block
-      if (r0 + (int)threadIdx.x < NB) {            // (2) panel rows
-        const int r = r0 + threadIdx.x;
-        double p[BK];
-#pragma unroll
-        for (int c = 0; c < BK; ++c) p[c] = D[r][k0 + c];
-#pragma unroll
-        for (int i = 0; i < BK; ++i) {
-          if (i < kn) {
-            const double f = p[i] / piv[k0 + i];
-            F[r][i] = f;
-#pragma unroll
-            for (int s2 = i + 1; s2 < BK; ++s2) p[s2] -= f * D[k0 + s2][k0 + i];
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < BK; ++c) D[r][k0 + c] = p[c];
-      }
-      __syncthreads();
-      // (3) trailing lower triangle rows and columns r0 .. NB - 1, entry e -> (r, s)
-      const int nt = NB - r0;
-      for (int e = threadIdx.x; e < nt * (nt + 1) / 2; e += blockDim.x) {
-        int r = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while ((r + 1) * (r + 2) / 2 <= e) ++r;
-        while (r * (r + 1) / 2 > e) --r;
-        const int s2 = e - r * (r + 1) / 2;
-        double x = D[r0 + r][r0 + s2];
-        for (int i = 0; i < kn; ++i) x -= F[r0 + r][i] * D[r0 + s2][k0 + i];
-        D[r0 + r][r0 + s2] = x;
-      }
-      __syncthreads();
-    }
-    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-      const int rr = idx / NB, c = idx % NB;
-      if (c < nb && rr < nb && c <= rr) D[rr][c] = (rr == c) ? sqrt(piv[c]) : D[rr][c] / sqrt(piv[c]);
-    }
-    __syncthreads();
-  }
-  // inverse of the lower triangle (padding rows are identity): column c by forward
-  // substitution, four threads per column (thread t: column t / 4, rows q = t mod 4 of
-  // every four, kept in registers); each row's sum is combined across the four by two lane
-  // exchanges
-  if (threadIdx.x < NB) piv[threadIdx.x] = 1.0 / D[threadIdx.x][threadIdx.x];
-  __syncthreads();
-  {
-    const int c = threadIdx.x >> 2, q = threadIdx.x & 3;
-    double xr[NB / 4];
-#pragma unroll
-    for (int m = 0; m < NB / 4; ++m) xr[m] = 0.0;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      double part = 0.0;
-#pragma unroll
-      for (int m = 0; m < (i + 3) / 4; ++m)
-        if (4 * m + q < i) part += D[i][4 * m + q] * xr[m];
-      part += __shfl_xor(part, 1);
-      part += __shfl_xor(part, 2);
-      const double xi = ((i == c ? 1.0 : 0.0) - part) * piv[i];
-      if (q == (i & 3)) xr[i >> 2] = xi;
-    }
-#pragma unroll
-    for (int m = 0; m < NB / 4; ++m) Li[4 * m + q][c] = xr[m];
-  }
-  __syncthreads();
-  double* ij = inv + (int64_t)j * NB * NB;
-  T* dj = dinv + boff[j] + (c0 / NB) * NB * NB;   // kept for the triangular solves
-  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-    const int i = idx / NB, l = idx % NB;
-    ij[idx] = Li[i][l];
-    dj[idx] = (T)Li[i][l];
-    if (i < nb && l <= i && i - l <= B) base[(c0 + i) * ld + (l - i + B)] = (T)D[i][l];
-  }
+__device__ inline T co_load(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ inline void co_store(T* p, T x) {
+  __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// panel rows r in [c0 + nb, c0 + nb + min(B, n - c0 - nb)): L[r, blk] = A[r, blk] L_kk^-T,
-// 64 rows per work-group as a GEMM against the inverted diagonal block
-template <class T>
-__global__ void __launch_bounds__(256) k_trsm(BandArgs a, T* v, int64_t c0, const double* inv) {
-  __shared__ double A[TS][NB + 1];
-  __shared__ double Li[NB][NB + 1];
-  const int j = blockIdx.y;
-  const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
-  if (c0 >= n) return;
-  const int nb = (int)min<int64_t>(NB, n - c0);
-  const int64_t nrow = min<int64_t>(B, n - c0 - nb);
-  const int64_t r0 = c0 + nb + (int64_t)blockIdx.x * TS;
-  if ((int64_t)blockIdx.x * TS >= nrow) return;
-  T* base = v + a.off[j];
-  const double* ij = inv + (int64_t)j * NB * NB;
-  {
-    constexpr int L = TS * NB / 256;             // 16 loads per thread, issued together
-    double va[L], vl[L];
-#pragma unroll
-    for (int u = 0; u < L; ++u) {
-      const int idx = threadIdx.x + 256 * u;
-      const int i = idx / NB, k = idx % NB;
-      const int64_t r = r0 + i, col = c0 + k;
-      va[u] = (k < nb && r - c0 - nb < nrow && col >= r - B) ? (double)base[r * ld + (col - r + B)]
-                                                             : 0.0;
-      vl[u] = ij[idx];
-    }
-#pragma unroll
-    for (int u = 0; u < L; ++u) {
-      const int idx = threadIdx.x + 256 * u;
-      A[idx / NB][idx % NB] = va[u];
-      Li[idx / NB][idx % NB] = vl[u];
-    }
-  }
+// Raises a block's flag to this launch's epoch once every thread's hand-over stores have
+// completed (waited for per thread, then a barrier).
+__device__ inline void chain_signal(int* f, int epoch) {
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double acc[4][4];
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-  for (int k = 0; k < NB; ++k) {
-    double ar[4], lc[4];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) ar[p] = A[4 * ty + p][k];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) lc[q] = Li[4 * tx + q][k];      // X = A Li^T
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[p][q] += ar[p] * lc[q];
-  }
-#pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const int64_t r = r0 + 4 * ty + p;
-    if (r - c0 - nb >= nrow) continue;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = 4 * tx + q;
-      const int64_t col = c0 + k;
-      if (k < nb && col >= r - B) base[r * ld + (col - r + B)] = (T)acc[p][q];
-    }
-  }
+  if (threadIdx.x == 0) __hip_atomic_store(f, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Update by the panels of columns [k0, k0 + kk): A[r][s] -= sum_c L[r][c] L[s][c] for
-// t0 <= s <= r < t0 + W, t0 = k0 + kk, W = min(B, n - t0) (rows further down get nothing
-// from these columns inside the band).  64x64 tiles of that lower triangle, or with
-// col_only the first tile column only (the look-ahead update of the next panel inside a
-// group).  The reduction runs over 64-column chunks of the panels: each chunk's two 64x64
-// blocks are staged in LDS and each of the
-// eight waves forms a 16x32 eighth of the tile with the FP64 matrix instruction (1x2 tiles
-// of 16x16, 16 steps of k = 4); two work-groups fit a compute unit.  Lane l supplies row l % 16 and reduction index l / 16 of both
-// operands; accumulator register q of a tile holds output row 4 q + l / 16, column l % 16.
-// Grouping panels makes one read-modify-write pass over the trailing band serve kk columns.
-constexpr int ST = 512;                           // threads of the trailing update
+// Bounded poll of a flag (thread 0); a poll that gives up raises bit 2 of the error word,
+// so every wave still reaches the end of the kernel.
+__device__ inline void chain_wait(const int* f, int epoch, int* err) {
+  for (int64_t k = 0; k < SPIN_LIMIT; ++k) {
+    if (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch) return;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  atomicOr(err, 2);
+}
 
+template <class S>
+struct Chunk;                                     // reduction chunk: KC columns, LDS stride KS
+template <>
+struct Chunk<double> {
+  static constexpr int KC = 32, KS = 34;
+};
+template <>
+struct Chunk<float> {
+  static constexpr int KC = 64, KS = 68;
+};
+
+// One launch per group.  Work-group (p, j, t) owns the 64 rows [c0 + 64 t, c0 + 64 t + 64)
+// of panel p (columns [c0, c0 + 64), c0 = k0 + 64 p) of matrix j; t = 0 is the diagonal
+// block.  Work-groups are numbered: panel 0's diagonal blocks (all matrices), then panel by
+// panel and matrix by matrix the blocks t >= 1, with the next panel's diagonal block right
+// after block t = 1 (the last one it needs), so that the next factorisation runs while
+// the rest of the panel is dispatched.  Every wait is for a lower number, so the in-order
+// dispatch of work-groups rules out deadlock.
+//   1. The block is brought up to date by this group's earlier panels (the earlier groups'
+//      updates are done before the launch): A -= L[rows][K] L[panel rows][K]^T, after
+//      waiting for the work-groups that produced them, with the matrix instruction in the
+//      factor's precision.
+//   2. t = 0: Cholesky of the 64x64 block by one wave (lane r holds row r in registers;
+//      step i broadcasts column i through LDS), then the inverse of the factor; the inverse
+//      is handed to the panel's other work-groups and kept for the triangular solves.
+//      t > 0: waits for the inverse and forms L[rows][panel] = A Li^T (FP64 instruction).
+//   3. The flag of (p, j, t) is raised.
+// A non-positive pivot raises bit 1 of the error word and is replaced by 1.
 template <class T>
-__global__ void __launch_bounds__(ST) k_syrk(BandArgs a, T* v, int64_t k0, int64_t kk,
-                                             int col_only, int64_t ts_lo, int64_t ts_hi) {
+__global__ void __launch_bounds__(CT) k_chain(BandArgs a, T* v, int64_t k0, int NR, int n_mat,
+                                              int* flags, int epoch, double* inv, T* dinv,
+                                              const int64_t* boff, int* err) {
   typedef Mfma<T> MT;
   typedef typename MT::S S;
-  __shared__ S Pr[TS][NB + 1], Ps[TS][NB + 1];
-  const int j = blockIdx.y;
+  constexpr int KC = Chunk<S>::KC, KS = Chunk<S>::KS;
+  constexpr int RP = CT / KC;                    // rows staged per pass
+  constexpr int PER = NB / RP;                   // staged entries per thread and operand
+  __shared__ double D[NB][NB + 1];               // the block; the factor (t = 0)
+  __shared__ double Li[NB][NB + 1];              // the inverse of the diagonal block
+  __shared__ double Wd[GP][16][17];              // inverses of the 16x16 diagonal blocks
+  __shared__ double Tt[16][17];                  // one tile of the inverse's assembly
+  static_assert(NB * KS * sizeof(S) <= sizeof(D), "staging fits in the block buffers");
+  S* Pr = reinterpret_cast<S*>(&D[0][0]);        // staging of step 1 (aliases D and Li)
+  S* Ps = reinterpret_cast<S*>(&Li[0][0]);
+  int p, j, t;
+  {
+    int b = blockIdx.x;
+    if (b < n_mat || NR == 1) {                  // panel 0's diagonal blocks
+      p = b / n_mat;
+      j = b - p * n_mat;
+      t = 0;
+    } else {
+      b -= n_mat;
+      for (p = 0; p < GP; ++p) {                 // section of panel p
+        const int m = NR - 1 + (p + 1 < GP);
+        if (b < n_mat * m) break;
+        b -= n_mat * m;
+      }
+      j = b / (NR - 1 + (p + 1 < GP));
+      const int o = b - j * (NR - 1 + (p + 1 < GP));
+      if (o == 0) {
+        t = 1;
+      } else if (p + 1 < GP && o == 1) {         // the next panel's diagonal block
+        p += 1;
+        t = 0;
+      } else {
+        t = p + 1 < GP ? o : o + 1;
+      }
+    }
+  }
+  const int tr = p + t;                          // row block, counted from k0
+  const int NRT = NR + GP - 1;
+  int* fj = flags + (int64_t)j * GP * NRT;       // flag of (q, j, row block b): fj[q NRT + b]
+  const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
+  const int64_t c0 = k0 + (int64_t)NB * p, r0 = c0 + (int64_t)NB * t;
+  if (c0 >= n || r0 >= n || r0 > c0 + NB - 1 + B) {   // no entries: only the flag
+    if (threadIdx.x == 0) __hip_atomic_store(fj + p * NRT + tr, epoch, __ATOMIC_RELEASE,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  T* base = v + a.off[j];
+  const int64_t rs = ld - 1;                     // entry (r, c) at r * rs + B + c
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = 32 * (w & 1), wc = 32 * (w >> 1);
+  const int kc_t = threadIdx.x % KC, i0 = threadIdx.x / KC;
+  // the block's entries, loaded now and used after step 1 (entries outside the matrix or
+  // the band read as 0; the diagonal block keeps its lower triangle)
+  const int nb = (int)min<int64_t>(NB, n - c0);  // columns of the panel inside the matrix
+  double av[2][4][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const int rl = wr + 16 * i + MT::row(q, lk), cl = wc + 16 * jj + li;
+        const int64_t r = r0 + rl, c = c0 + cl;
+        av[i][q][jj] = (r < n && cl < nb && c >= r - B && (t > 0 || cl <= rl))
+                           ? (double)base[r * rs + B + c] : 0.0;
+      }
+  // 1. A -= L[rows][K] L[panel rows][K]^T over this group's earlier panels K = [k0, c0),
+  // once the work-groups that produced them are done; the next chunk is fetched while
+  // the current one is multiplied
+  typename MT::V acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) acc[i][jj] = typename MT::V{0, 0, 0, 0};
+  if (p > 0) {
+    if (threadIdx.x == 0)
+      for (int q = 0; q < p; ++q) {               // blocks past a panel's reach have none
+        if (tr - q < NR) chain_wait(fj + q * NRT + tr, epoch, err);
+        if (p - q < NR) chain_wait(fj + q * NRT + p, epoch, err);
+      }
+    __syncthreads();
+    // the first chunk with an entry inside the band of the block's top row
+    const int64_t lo = r0 - B;
+    const int64_t kstart = lo > k0 ? k0 + (lo - k0) / KC * KC : k0;
+    S xr[PER], xs[PER];
+    // 32-bit terms relative to the block: row i of a block is inside the matrix if
+    // i < lim, and panel column q (counted from k0) is inside the band of that row if
+    // q - i >= lo; rows' band origins are 32-bit offsets from the matrix start
+    const int lim_r = (int)min<int64_t>(n - r0, NB), lim_s = (int)min<int64_t>(n - c0, NB);
+    const int lo_r = (int)(r0 - B - k0), lo_s = (int)(c0 - B - k0), qend = (int)(c0 - k0);
+    const uint32_t or0 = (uint32_t)(min(r0 + i0, n - 1) * rs + B + k0 + kc_t);
+    const uint32_t os0 = (uint32_t)(min(c0 + i0, n - 1) * rs + B + k0 + kc_t);
+    const uint32_t ostep = (uint32_t)(RP * rs);
+    auto fetch = [&](int64_t kc) {
+      const int qq = (int)(kc - k0) + kc_t;
+      const uint32_t kd = (uint32_t)(kc - k0);
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int i = i0 + RP * u;
+        const bool okr = qq < qend && i < lim_r && qq - i >= lo_r;
+        const bool oks = qq < qend && i < lim_s && qq - i >= lo_s;
+        xr[u] = okr ? (S)co_load(base + (or0 + u * ostep + kd)) : (S)0;
+        xs[u] = oks ? (S)co_load(base + (os0 + u * ostep + kd)) : (S)0;
+      }
+    };
+    if (kstart < c0) fetch(kstart);
+    for (int64_t kc = kstart; kc < c0; kc += KC) {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        Pr[(i0 + RP * u) * KS + kc_t] = xr[u];
+        Ps[(i0 + RP * u) * KS + kc_t] = xs[u];
+      }
+      __syncthreads();
+      if (kc + KC < c0) fetch(kc + KC);
+#pragma unroll
+      for (int k = 0; k < KC; k += 4) {
+        S fa[2], fb[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) fa[i] = Pr[(wr + 16 * i + li) * KS + k + lk];
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) fb[jj] = Ps[(wc + 16 * jj + li) * KS + k + lk];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) acc[i][jj] = MT::mma(fa[i], fb[jj], acc[i][jj]);
+      }
+      __syncthreads();
+    }
+  }
+  // the updated block into D
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const int rl = wr + 16 * i + MT::row(q, lk), cl = wc + 16 * jj + li;
+        double x = av[i][q][jj] - (double)acc[i][jj][q];
+        if (t == 0 && rl == cl && rl >= nb) x = 1.0;       // padding of a short last panel
+        D[rl][cl] = x;
+      }
+  __syncthreads();
+  double* invj = inv + ((int64_t)j * GP + p) * NB * NB;
+  if (t == 0) {
+    // 2a. Cholesky of the diagonal block and its inverse, by wave 0 alone (no barriers), in
+    // 16-column blocks: the 16x16 diagonal block is factored in registers (lane r holds
+    // row r; pivots and column entries come from other lanes by reads of their registers)
+    // and inverted by forward substitution (lane c: column c); the panel below it is
+    // L = A W^T with W that inverse, and the trailing triangle takes -= L L^T, both as
+    // 16x16 tiles on the FP64 matrix instruction.  The inverse of the 64x64 factor is then
+    // built tile by tile: Li(i, i) = W_i, Li(i, j) = -W_i sum_{j <= k < i} L(i, k) Li(k, j).
+    if (w == 0) {
+      typedef Mfma<double> M64;
+      const int r16 = lane & 15;
+      for (int kb = 0; kb < 4; ++kb) {
+        const int b0 = 16 * kb;
+        double f[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) f[c] = c <= r16 ? D[b0 + r16][b0 + c] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const double dii = lane_value(f[i], i);
+          const bool ok = dii > 0.0;
+          if (!ok && lane == 0) atomicOr(err, 1);
+          const double d = ok ? sqrt(dii) : 1.0;
+          f[i] = r16 == i ? d : f[i] / d;
+#pragma unroll
+          for (int s2 = i + 1; s2 < 16; ++s2) f[s2] -= f[i] * lane_value(f[i], s2);
+        }
+        if (lane < 16)
+#pragma unroll
+          for (int c = 0; c < 16; ++c) D[b0 + r16][b0 + c] = c <= r16 ? f[c] : 0.0;
+        double xi[16];                             // column r16 of the block's inverse
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          double sum = i == r16 ? 1.0 : 0.0;
+#pragma unroll
+          for (int k = 0; k < i; ++k) sum -= lane_value(f[k], i) * xi[k];
+          xi[i] = sum / lane_value(f[i], i);
+        }
+        if (lane < 16)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) Wd[kb][i][r16] = xi[i];
+        for (int ti = kb + 1; ti < 4; ++ti) {      // panel tiles: L = A W^T
+          v4d acc = v4d{0, 0, 0, 0};
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks)
+            acc = M64::mma(D[16 * ti + li][b0 + 4 * ks + lk], Wd[kb][li][4 * ks + lk], acc);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) D[16 * ti + M64::row(q, lk)][b0 + li] = acc[q];
+        }
+        for (int tj = kb + 1; tj < 4; ++tj)        // trailing tiles: -= L L^T
+          for (int ti = tj; ti < 4; ++ti) {
+            v4d acc = v4d{0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+              acc = M64::mma(D[16 * ti + li][b0 + 4 * ks + lk], D[16 * tj + li][b0 + 4 * ks + lk],
+                             acc);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) D[16 * ti + M64::row(q, lk)][16 * tj + li] -= acc[q];
+          }
+      }
+      for (int idx = lane; idx < NB * NB; idx += 64) {
+        const int i = idx / NB, l = idx % NB;
+        Li[i][l] = (i >> 4) == (l >> 4) ? Wd[i >> 4][i & 15][l & 15] : 0.0;
+      }
+      for (int dd = 1; dd < 4; ++dd)
+        for (int ti = dd; ti < 4; ++ti) {
+          const int tj = ti - dd;
+          v4d acc = v4d{0, 0, 0, 0};
+          for (int kt = tj; kt < ti; ++kt)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+              acc = M64::mma(D[16 * ti + li][16 * kt + 4 * ks + lk],
+                             Li[16 * kt + 4 * ks + lk][16 * tj + li], acc);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Tt[M64::row(q, lk)][li] = acc[q];
+          v4d o = v4d{0, 0, 0, 0};
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks)
+            o = M64::mma(Wd[ti][li][4 * ks + lk], Tt[4 * ks + lk][li], o);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Li[16 * ti + M64::row(q, lk)][16 * tj + li] = -o[q];
+        }
+    }
+    __syncthreads();
+    T* dj = dinv + boff[j] + (c0 / NB) * NB * NB;
+    for (int idx = threadIdx.x; idx < NB * NB; idx += CT) {
+      const int i = idx / NB, l = idx % NB;
+      co_store(invj + idx, Li[i][l]);
+      dj[idx] = (T)Li[i][l];
+      if (i < nb && l <= i && i - l <= B) base[(c0 + i) * rs + B + c0 + l] = (T)D[i][l];
+    }
+  } else {
+    // 2b. L[rows][panel] = A Li^T with the inverse of the diagonal block
+    if (threadIdx.x == 0) chain_wait(fj + p * NRT + p, epoch, err);
+    __syncthreads();
+    {
+      double lv[NB * NB / CT];                   // all loads issued before any is used
+#pragma unroll
+      for (int u = 0; u < NB * NB / CT; ++u) lv[u] = co_load(invj + threadIdx.x + CT * u);
+#pragma unroll
+      for (int u = 0; u < NB * NB / CT; ++u) {
+        const int idx = threadIdx.x + CT * u;
+        Li[idx / NB][idx % NB] = lv[u];
+      }
+    }
+    __syncthreads();
+    v4d x[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) x[i][jj] = v4d{0, 0, 0, 0};
+#pragma unroll 4
+    for (int k = 0; k < NB; k += 4) {
+      double fa[2], fb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) fa[i] = D[wr + 16 * i + li][k + lk];
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) fb[jj] = Li[wc + 16 * jj + li][k + lk];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) x[i][jj] = Mfma<double>::mma(fa[i], fb[jj], x[i][jj]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const int rl = wr + 16 * i + Mfma<double>::row(q, lk), cl = wc + 16 * jj + li;
+          const int64_t r = r0 + rl, c = c0 + cl;
+          if (r < n && cl < nb && c >= r - B) co_store(base + r * rs + B + c, (T)x[i][jj][q]);
+        }
+  }
+  // 3.
+  chain_signal(fj + p * NRT + tr, epoch);
+}
+
+// The update of the trailing window by a group's panels, past the next group's columns,
+// in 128 x 128 tiles of its lower triangle.  Eight waves each
+// form a 64 x 32 eighth as 4 x 2 matrix-instruction tiles of 16 x 16, so six fragment reads
+// from LDS feed eight instructions; two work-groups fit a compute unit.  The panels stream through LDS in chunks
+// of KW columns (256 bytes of a row); the next chunk is loaded into registers while the
+// current one is multiplied.  Chunks that lie left of the band for every row of the tile
+// are skipped.  The LDS row stride (KW plus 2 doubles or 4 floats) spreads the 16 rows x 4
+// reduction indices of one fragment read over distinct banks.
+// The grid is one-dimensional over (matrix, tile) and consecutive tiles of a matrix go to
+// the same XCD (work-groups are dealt round-robin to the eight XCDs), so a matrix's panels
+// stay in that XCD's L2 while its tiles run.
+constexpr int T2 = 128;                           // tile edge
+constexpr int U2 = 512;                           // threads
+template <class S>
+struct Wide;
+template <>
+struct Wide<double> {
+  static constexpr int KW = 16, KS = 18;
+};
+template <>
+struct Wide<float> {
+  static constexpr int KW = 64, KS = 68;
+};
+
+template <class T>
+__device__ inline void wide_tile(BandArgs a, T* v, int64_t k0, int64_t kk, int64_t ts_lo,
+                                 int64_t ts_hi, int64_t per_mat, int64_t lin) {
+  typedef Mfma<T> MT;
+  typedef typename MT::S S;
+  constexpr int KW = Wide<S>::KW, KS = Wide<S>::KS;
+  constexpr int RP = U2 / KW;                    // rows staged per pass
+  constexpr int PER = T2 / RP;                   // entries per thread and operand
+  __shared__ S Pr[T2][KS], Ps[T2][KS];
+  const int j = (int)(lin / per_mat);
+  const int64_t tile = lin - (int64_t)j * per_mat;
   const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
   if (k0 >= n) return;
-  const int64_t kj = min<int64_t>(kk, n - k0);   // panel columns of this matrix
+  const int64_t kj = min<int64_t>(kk, n - k0);
   const int64_t t0 = k0 + kj;
   const int64_t W = min<int64_t>(B, n - t0);
   if (W <= 0) return;
-  const int64_t nt = (W + TS - 1) / TS;
-  const int64_t tile = blockIdx.x;
-  int64_t tr, ts;
-  if (col_only) {
-    if (tile >= nt) return;
-    tr = tile;
-    ts = 0;
-  } else {
-    // tile columns ts_lo <= ts < ts_hi, each with its rows ts <= tr < nt, column by column
-    const int64_t te = min(ts_hi, nt);
-    int64_t rem = tile;
-    for (ts = ts_lo; ts < te && rem >= nt - ts; ++ts) rem -= nt - ts;
-    if (ts >= te) return;
-    tr = ts + rem;
-  }
+  const int64_t nt = (W + T2 - 1) / T2;
+  const int64_t te = min(ts_hi, nt);
+  int64_t ts, rem = tile;
+  for (ts = ts_lo; ts < te && rem >= nt - ts; ++ts) rem -= nt - ts;
+  if (ts >= te) return;
+  const int64_t tr = ts + rem;
   T* base = v + a.off[j];
-  const int64_t r0 = t0 + tr * TS, s0 = t0 + ts * TS, wend = t0 + W;
-  // thread t loads column t % 64 of rows t / 64 + 4 u (u < 16) of both blocks; loads are
-  // unconditional (a masked entry reads a neighbouring band entry: the row index is clamped
-  // below n and the allocation is padded past its end) and the mask applies afterwards
-  constexpr int L = TS * NB / ST;
-  constexpr int RS = ST / NB;                    // rows staged per pass
-  const int cl = threadIdx.x % NB, i0 = threadIdx.x / NB;
+  const int64_t r0 = t0 + tr * T2, s0 = t0 + ts * T2, wend = t0 + W;
   const int64_t rs = ld - 1;                     // entry (r, c) at r * rs + B + c
-  const int64_t rlast = n - 1;
+  const int kc_t = threadIdx.x % KW, i0 = threadIdx.x / KW;
+  // first chunk with an entry inside the band for the tile's top row (lower rows start later)
+  const int64_t lo = r0 - B - k0;
+  const int64_t kc_first = lo > 0 ? lo / KW * KW : 0;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int rb = 16 * (w & 3), sb = 32 * (w >> 2);
-  typename MT::V acc[2];
+  const int wr = 64 * (w & 1), wc = 32 * (w >> 1);
+  const bool idle = ts == tr && wc >= wr + 64;   // above the diagonal of a diagonal tile
+  typename MT::V acc[4][2];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) acc[q] = typename MT::V{0, 0, 0, 0};
-  for (int64_t kc = 0; kc < kj; kc += NB) {
-    const int64_t col = k0 + kc + cl;
-    const bool okc = kc + cl < kj;
-    S vr[L], vs[L];
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int u = 0; u < L; ++u) {
-      const int64_t r = r0 + i0 + RS * u, ss = s0 + i0 + RS * u;
-      vr[u] = (S)base[min(r, rlast) * rs + B + col];
-      vs[u] = (S)base[min(ss, rlast) * rs + B + col];
+    for (int jj = 0; jj < 2; ++jj) acc[i][jj] = typename MT::V{0, 0, 0, 0};
+  S vr[PER], vs[PER];
+  // 32-bit offsets from the matrix start (the host checks that they fit).  Rows past the
+  // end of the matrix are not clamped: they read at most T2 rows further, which the band
+  // allocation's padding covers, and are masked.
+  const uint32_t ostep = (uint32_t)(RP * rs);
+  const uint32_t or0 = (uint32_t)((r0 + i0) * rs + B + k0 + kc_t);
+  const uint32_t os0 = (uint32_t)((s0 + i0) * rs + B + k0 + kc_t);
+  auto load = [&](int64_t kc) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      vr[u] = (S)base[or0 + u * ostep + (uint32_t)kc];
+      vs[u] = (S)base[os0 + u * ostep + (uint32_t)kc];
     }
+  };
+  // masks in 32-bit tile-relative terms: row i of a block is inside the window if
+  // i < lim, and panel column q (0-based in the group) is inside the band of that row if
+  // q - i >= lo (the block's first row starts the band at panel column lo)
+  const int lim_r = (int)min<int64_t>(wend - r0, T2), lim_s = (int)min<int64_t>(wend - s0, T2);
+  const int lo_r = (int)(r0 - B - k0), lo_s = (int)(s0 - B - k0);
+  const int kjn = (int)kj;
+  auto stage = [&](int64_t kc) {
+    const int q = (int)kc + kc_t;
+    const bool okc = q < kjn;
 #pragma unroll
-    for (int u = 0; u < L; ++u) {
-      const int64_t r = r0 + i0 + RS * u, ss = s0 + i0 + RS * u;
-      const bool okr = okc && r < wend && col >= r - B;
-      const bool oks = okc && ss < wend && col >= ss - B;
-      Pr[i0 + RS * u][cl] = okr ? vr[u] : (S)0;
-      Ps[i0 + RS * u][cl] = oks ? vs[u] : (S)0;
+    for (int u = 0; u < PER; ++u) {
+      const int i = i0 + RP * u;
+      Pr[i][kc_t] = (okc && i < lim_r && q - i >= lo_r) ? vr[u] : (S)0;
+      Ps[i][kc_t] = (okc && i < lim_s && q - i >= lo_s) ? vs[u] : (S)0;
     }
+  };
+  if (kc_first < kj) load(kc_first);
+  for (int64_t kc = kc_first; kc < kj; kc += KW) {
+    stage(kc);
     __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < NB; k += 4) {
-      const S a0 = Pr[rb + li][k + lk];
-      const S b0 = Ps[sb + li][k + lk], b1 = Ps[sb + 16 + li][k + lk];
-      acc[0] = MT::mma(a0, b0, acc[0]);
-      acc[1] = MT::mma(a0, b1, acc[1]);
-    }
-    __syncthreads();
-  }
+    if (kc + KW < kj) load(kc + KW);              // in flight during the products below
+    if (!idle) {
+#pragma unroll 1
+      for (int k = 0; k < KW; k += 4) {
+        S fa[4], fb[2];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t r = r0 + rb + MT::row(q, lk);
+        for (int i = 0; i < 4; ++i) fa[i] = Pr[wr + 16 * i + li][k + lk];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int64_t s = s0 + sb + 16 * t + li;
-      if (r < wend && s <= r && (!col_only || s < t0 + TS)) {
-        T* e = base + r * ld + (s - r + B);
-        *e = (T)((S)*e - acc[t][q]);
+        for (int jj = 0; jj < 2; ++jj) fb[jj] = Ps[wc + 16 * jj + li][k + lk];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) acc[i][jj] = MT::mma(fa[i], fb[jj], acc[i][jj]);
       }
     }
+    __syncthreads();
   }
+  if (idle) return;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t r = r0 + wr + 16 * i + MT::row(q, lk);
+      if (r >= wend) continue;
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const int64_t s = s0 + wc + 16 * jj + li;
+        if (s <= r) {
+          T* e = base + r * ld + (s - r + B);
+          *e = (T)((S)*e - acc[i][jj][q]);
+        }
+      }
+    }
 }
 
-// Number of tiles k_syrk enumerates for tile columns [lo, hi) of an nt x nt lower triangle.
-static unsigned syrk_tiles(int64_t nt, int64_t lo, int64_t hi) {
+// One tile per work-group: work-group b runs on XCD x = b mod 8 and takes the (b / 8)-th
+// tile of that XCD's consecutive share.
+template <class T>
+__global__ void __launch_bounds__(U2, 4) k_syrk_wide(BandArgs a, T* v, int64_t k0, int64_t kk,
+                                                  int64_t ts_lo, int64_t ts_hi,
+                                                  int64_t per_mat, int64_t total) {
+  const int64_t x = blockIdx.x & 7, q = total >> 3, rem = total & 7;
+  wide_tile<T>(a, v, k0, kk, ts_lo, ts_hi, per_mat, x * q + min(x, rem) + (blockIdx.x >> 3));
+}
+
+// Number of tiles k_syrk_wide enumerates per matrix for 128-column tile columns [lo, hi).
+static int64_t wide_tiles(int64_t max_B, int64_t lo, int64_t hi) {
+  const int64_t nt = (max_B + T2 - 1) / T2;
   int64_t c = 0;
   for (int64_t ts = lo; ts < std::min(hi, nt); ++ts) c += nt - ts;
-  return (unsigned)c;
+  return c;
 }
+
 
 template <class T>
 void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job) {
   BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p};
-  job.inv.alloc((size_t)bs.n_mat * NB * NB);
-  double* inv = job.inv.p;
-  int* err = job.err.p;
-  // right-looking blocked Cholesky in groups of GP panels of NB columns: inside a group
-  // each panel is first brought up to date by the group's earlier panels (its own tile
-  // column only), then factored (diagonal block, panel below it); the rest of the band is
-  // updated once per group, by all GP panels together.  That update is split with
-  // look-ahead: the next group's GP tile columns on st, which then goes on to factor that
-  // group's panels, and all further tile columns on a second stream at the same time.
-  // The next group's own update of the columns after it waits for that second part (the
-  // two touch the same tiles); everything else they do touches disjoint tiles.
-  constexpr int GP = 4;
-  const int64_t nt = (bs.max_B + TS - 1) / TS;
-  const unsigned tiles_next = syrk_tiles(nt, 0, GP), tiles_rest = syrk_tiles(nt, GP, nt);
-  const unsigned trsm_blocks = (unsigned)((bs.max_B + TS - 1) / TS);
+  static_assert(GP * NB == 2 * T2, "the rest update starts two wide tile columns on");
+  for (int j = 0; j < bs.n_mat; ++j)
+    GX_REQUIRE((bs.n[j] + T2) * bs.ld[j] + 64 < ((int64_t)1 << 31),
+               "a band matrix of 2^31 entries or more exceeds the update's 32-bit offsets");
+  const int NR = (int)((bs.max_B + NB - 1) / NB) + 1;   // row blocks of a panel
+  const int NRT = NR + GP - 1;                           // row blocks of a group
+  job.inv.alloc((size_t)bs.n_mat * GP * NB * NB);
+  job.flags.alloc((size_t)bs.n_mat * GP * NRT);
+  zero(job.flags, st);
+  const int64_t nt2 = (bs.max_B + T2 - 1) / T2;
+  const int64_t per_rest = wide_tiles(bs.max_B, 2, nt2), tot_rest = per_rest * bs.n_mat;
+  const int64_t per_next = wide_tiles(bs.max_B, 0, 2), tot_next = per_next * bs.n_mat;
+  const unsigned chain_blocks = (unsigned)((int64_t)GP * bs.n_mat * NR);
+  // group g on st: the update of its columns by group g - 1 (after the update of the same
+  // columns by group g - 2, which ran on the second stream), then its k_chain; then the
+  // update of the columns from group g + 2 on by its panels on the second stream, at the
+  // same time as group g + 1's work on st.
   GX_HIP(hipStreamCreateWithFlags(&job.la, hipStreamNonBlocking));
-  GX_HIP(hipEventCreateWithFlags(&job.panels, hipEventDisableTiming));
-  GX_HIP(hipEventCreateWithFlags(&job.rest, hipEventDisableTiming));
-  bool rest_pending = false;
-  for (int64_t k0 = 0; k0 < bs.max_n; k0 += GP * NB) {
-    for (int p = 0; p < GP && k0 + p * NB < bs.max_n; ++p) {
-      const int64_t c0 = k0 + p * NB;
-      if (p > 0 && bs.max_B > 0)
-        hipLaunchKernelGGL(k_syrk<T>, dim3((unsigned)nt, bs.n_mat), dim3(ST), 0, st, a, v, k0,
-                           (int64_t)p * NB, 1, (int64_t)0, (int64_t)0);
-      hipLaunchKernelGGL(k_potrf<T>, dim3(bs.n_mat), dim3(256), 0, st, a, v, c0, inv, dinv,
-                         bs.d_boff.p, err);
-      if (bs.max_B > 0)
-        hipLaunchKernelGGL(k_trsm<T>, dim3(trsm_blocks, bs.n_mat), dim3(256), 0, st, a, v, c0,
-                           inv);
-    }
-    if (bs.max_B > 0) {
-      GX_HIP(hipEventRecord(job.panels, st));
-      if (tiles_rest) {
-        GX_HIP(hipStreamWaitEvent(job.la, job.panels, 0));
-        hipLaunchKernelGGL(k_syrk<T>, dim3(tiles_rest, bs.n_mat), dim3(ST), 0, job.la, a, v, k0,
-                           (int64_t)GP * NB, 0, (int64_t)GP, nt);
-      }
-      if (rest_pending) GX_HIP(hipStreamWaitEvent(st, job.rest, 0));
-      hipLaunchKernelGGL(k_syrk<T>, dim3(tiles_next, bs.n_mat), dim3(ST), 0, st, a, v, k0,
-                         (int64_t)GP * NB, 0, (int64_t)0, (int64_t)GP);
-      if (tiles_rest) {
-        GX_HIP(hipEventRecord(job.rest, job.la));
-        rest_pending = true;
-      }
+  GX_HIP(hipEventCreateWithFlags(&job.chain, hipEventDisableTiming));
+  GX_HIP(hipEventCreateWithFlags(&job.rest[0], hipEventDisableTiming));
+  GX_HIP(hipEventCreateWithFlags(&job.rest[1], hipEventDisableTiming));
+  bool recorded[2] = {false, false};
+  int g = 0;
+  for (int64_t k0 = 0; k0 < bs.max_n; k0 += GP * NB, ++g) {
+    if (recorded[g % 2]) GX_HIP(hipStreamWaitEvent(st, job.rest[g % 2], 0));
+    if (g > 0 && bs.max_B > 0)
+      hipLaunchKernelGGL(k_syrk_wide<T>, dim3((unsigned)tot_next), dim3(U2), 0, st, a, v,
+                         k0 - GP * NB, (int64_t)GP * NB, (int64_t)0, (int64_t)2, per_next,
+                         tot_next);
+    hipLaunchKernelGGL(k_chain<T>, dim3(chain_blocks), dim3(CT), 0, st, a, v, k0, NR,
+                       bs.n_mat, job.flags.p, g + 1, job.inv.p, dinv, bs.d_boff.p, job.err.p);
+    if (tot_rest && k0 + GP * NB < bs.max_n) {
+      GX_HIP(hipEventRecord(job.chain, st));
+      GX_HIP(hipStreamWaitEvent(job.la, job.chain, 0));
+      hipLaunchKernelGGL(k_syrk_wide<T>, dim3((unsigned)tot_rest), dim3(U2), 0, job.la, a, v,
+                         k0, (int64_t)GP * NB, (int64_t)2, nt2, per_rest, tot_rest);
+      GX_HIP(hipEventRecord(job.rest[g % 2], job.la));
+      recorded[g % 2] = true;
     }
   }
-  if (rest_pending) GX_HIP(hipStreamWaitEvent(st, job.rest, 0));
+  for (int q = 0; q < 2; ++q)
+    if (recorded[q]) GX_HIP(hipStreamWaitEvent(st, job.rest[q], 0));
   GX_HIP(hipGetLastError());
 }
 
 FactorJob::~FactorJob() {
   if (st) (void)hipStreamSynchronize(st);         // nothing of the job may still run when
   if (la) (void)hipStreamSynchronize(la);         // its buffers are released
-  if (panels) (void)hipEventDestroy(panels);
-  if (rest) (void)hipEventDestroy(rest);
+  if (chain) (void)hipEventDestroy(chain);
+  for (hipEvent_t e : rest)
+    if (e) (void)hipEventDestroy(e);
   if (la) (void)hipStreamDestroy(la);
 }
 
@@ -455,6 +638,9 @@ void band_factor_finish(FactorJob& job) {
   GX_REQUIRE(job.st, "factorisation job not started");
   int h = 0;
   to_host(&h, job.err.p, 1, job.st);               // waits for all of the job
+  if (h & 2)
+    throw Error(GX_EHIP, "banded Cholesky factorisation of " + job.what +
+                             ": a work-group timed out waiting for a panel block");
   if (h)
     throw Error(GX_ENOTSPD,
                 "non-positive pivot in the banded Cholesky factorisation of " + job.what);
@@ -484,8 +670,11 @@ constexpr int RPW = SB / SW;                      // forward rows per wave (8)
 constexpr int GMAX = 4;                           // work-groups per matrix, 1-RHS solve
 constexpr int DL = SB * SB / SOLVE_THREADS;       // inverse-block entries per thread (8)
 static_assert(DL == RPW, "the inverse-block products reuse the 8-row lane reduction");
-constexpr int64_t SPIN_LIMIT = (int64_t)1 << 22;
 constexpr int64_t BAND_PAD = 1024;               // trailing entries of a band allocation
+
+// zero entries after the last matrix: the solves read up to BAND_PAD past its end, the
+// trailing update up to T2 rows
+static int64_t band_pad(int64_t max_B) { return BAND_PAD + T2 * (max_B + 1); }
 
 // Band entry (r, c) loaded from a clamped, always valid address; the caller masks entries
 // outside the band.  The loads are unconditional so that a wave issues all of them before
@@ -1467,14 +1656,14 @@ void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<i
   if (fp32) {
     bs.v64.release();
     bs.dinv64.release();
-    bs.v32.alloc(o + BAND_PAD);
-    GX_HIP(hipMemsetAsync(bs.v32.p + o, 0, BAND_PAD * sizeof(float), st));
+    bs.v32.alloc(o + band_pad(bs.max_B));
+    GX_HIP(hipMemsetAsync(bs.v32.p + o, 0, band_pad(bs.max_B) * sizeof(float), st));
     bs.dinv32.alloc(bs.boff[n.size()]);
   } else {
     bs.v32.release();
     bs.dinv32.release();
-    bs.v64.alloc(o + BAND_PAD);
-    GX_HIP(hipMemsetAsync(bs.v64.p + o, 0, BAND_PAD * sizeof(double), st));
+    bs.v64.alloc(o + band_pad(bs.max_B));
+    GX_HIP(hipMemsetAsync(bs.v64.p + o, 0, band_pad(bs.max_B) * sizeof(double), st));
     bs.dinv64.alloc(bs.boff[n.size()]);
   }
   bs.solve_groups[0] = bs.solve_groups[1] = 0;

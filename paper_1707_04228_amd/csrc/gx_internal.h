@@ -379,9 +379,10 @@ struct FactorJob {
   hipStream_t st = nullptr;
   std::string what;
   DevBuf<int> err;
-  DevBuf<double> inv;
-  hipStream_t la = nullptr;                    // look-ahead stream (default priority)
-  hipEvent_t panels = nullptr, rest = nullptr;
+  DevBuf<double> inv;                          // inverse diagonal blocks handed over
+  DevBuf<int> flags;                           // per panel block: epoch of its completion
+  hipStream_t la = nullptr;                    // trailing-update stream (default priority)
+  hipEvent_t chain = nullptr, rest[2] = {nullptr, nullptr};
   FactorJob() = default;
   ~FactorJob();
   FactorJob(const FactorJob&) = delete;

@@ -28,7 +28,7 @@ GMAX = 4           # work-groups per matrix, one right-hand side
 DL = 8             # inverse-block entries per thread
 MT = 512           # threads of the many-right-hand-side solve
 AL = 8             # band-chunk entries per thread
-TS, NB, ST = 64, 64, 512
+NB = 64
 BAND_PAD = 1024
 
 SHAPES = [(1, 0), (2, 1), (63, 5), (64, 63), (65, 64), (127, 64), (128, 65), (129, 100),
@@ -156,35 +156,40 @@ def _many_rhs(n, B, M, bd):
 
 
 def _trailing_update(n, B, bd):
-    """k_syrk: the staging loads of both 64x64 blocks for every tile of a panel group."""
+    """k_syrk_wide: the staging loads of both 128-row panel blocks for every tile of the
+    update of a group's trailing window (tile columns two and on), in 32-bit offsets from
+    the matrix start.  The panel work-groups (k_chain) load only inside the band."""
     ld = B + 1
     rs = ld - 1
     rlast = n - 1
-    cl = np.arange(ST) % NB
-    i0 = np.arange(ST) // NB
-    RS = ST // NB
-    L = TS * NB // ST
-    GP = 4
+    T2, U2, GP = 128, 512, 4
     starts = list(range(0, n, GP * NB))
-    for k0 in starts[:3] + starts[-3:]:
-        for p in range(1, GP + 1):                         # column-only updates and full
-            kk = p * NB
-            kj = min(kk, n - k0)
+    for KW in (16, 32):                                     # FP64 and FP32 chunks
+        kt = np.arange(U2) % KW
+        i0 = np.arange(U2) // KW
+        RP = U2 // KW
+        PER = T2 // RP
+        for k0 in starts[:3] + starts[-3:]:
+            kj = min(GP * NB, n - k0)
             t0 = k0 + kj
             W = min(B, n - t0)
             if W <= 0:
                 continue
-            nt = (W + TS - 1) // TS
-            tiles = [(tr, ts) for ts in range(nt) for tr in range(ts, nt)]
+            nt = (W + T2 - 1) // T2
+            tiles = [(tr, ts) for ts in range(2, nt) for tr in range(ts, nt)]
             for tr, ts in tiles[:8] + tiles[-8:]:
-                r0, s0 = t0 + tr * TS, t0 + ts * TS
-                for kc in range(0, kj, NB):
-                    col = k0 + kc + cl
-                    for u in range(L):
-                        r = r0 + i0 + RS * u
-                        ss = s0 + i0 + RS * u
-                        bd.check(np.minimum(r, rlast) * rs + B + col, "trailing r")
-                        bd.check(np.minimum(ss, rlast) * rs + B + col, "trailing s")
+                r0, s0 = t0 + tr * T2, t0 + ts * T2
+                lo = r0 - B - k0
+                kc_first = lo // KW * KW if lo > 0 else 0
+                for kc in range(kc_first, kj, KW):
+                    for u in range(PER):
+                        r = np.minimum(r0 + i0 + RP * u, rlast)
+                        ss = np.minimum(s0 + i0 + RP * u, rlast)
+                        idx_r = r * rs + B + k0 + kt + kc
+                        idx_s = ss * rs + B + k0 + kt + kc
+                        assert idx_r.max() < 2 ** 31 and idx_s.max() < 2 ** 31
+                        bd.check(idx_r, "trailing r")
+                        bd.check(idx_s, "trailing s")
 
 
 @pytest.mark.parametrize("n,B", SHAPES)
