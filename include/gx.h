@@ -398,8 +398,8 @@ gx_status gx_pcg_solve_batch(int32_t n, gx_ctx* const* ctxs, const double* const
  * gx_geneo_setup (average per solve; reps is ignored); 5 = the Cholesky factorisation of
  * the subdomain matrices (section 2.4), refilled from K and factored again alone on the
  * stream (the factors come out unchanged) - `bytes` then receives its flops instead (the
- * band Cholesky count, sum over columns of w^2 + 2 w + 1 with w the band entries below
- * the diagonal).  The algorithmic bytes of a band solve are the factor's envelope
+ * Cholesky count over the envelope, sum over columns of h^2 + 2 h + 1 with h the rows
+ * below the diagonal inside the envelope).  The algorithmic bytes of a band solve are the factor's envelope
  * (profile: every row from its first nonzero column to the diagonal, where Cholesky
  * creates all its fill) read once per sweep, 2 w sum_j env_j with w = 8 (FP64) or 4
  * (FP32 factors), plus four FP64 passes over the right-hand sides (32 n_j per column). */
@@ -422,12 +422,12 @@ gx_status gx_tune(gx_ctx* ctx, int32_t param, int64_t value);
 gx_status gx_stats(gx_ctx* ctx, int64_t* out);
 
 /* Sizes of the subdomain factorisations of the last gx_geneo_setup (host [8]): [0] stored
- * band entries of the subdomain factors, [1] their envelope entries, [2] their band
- * Cholesky flops; [3] stored band entries of the eigensolver's Neumann factors, [4] their
+ * band entries of the subdomain factors, [1] their envelope (profile) entries, [2] their
+ * Cholesky flops over the envelope (column c: h^2 + 2 h + 1, h the rows below c inside the
+ * envelope); [3] stored band entries of the eigensolver's Neumann factors, [4] their
  * envelope entries, [5] their flops; [6] algorithmic bytes of one PCG subdomain solve
- * (envelope, as gx_kernel_time 1 reports), [7] the bytes that solve's kernels read as
- * stored (band plus inverse diagonal blocks, plus the vector passes).  GX_ESTATE before
- * gx_geneo_setup. */
+ * (envelope, as gx_kernel_time 1 reports), [7] the bytes of the stored band, the inverse
+ * diagonal blocks and the vector passes.  GX_ESTATE before gx_geneo_setup. */
 gx_status gx_band_stats(gx_ctx* ctx, double* out);
 
 /* Time spent in the last call of each phase, milliseconds (host [8], may be NULL):

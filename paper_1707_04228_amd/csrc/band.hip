@@ -58,6 +58,9 @@ struct BandArgs {
   const int64_t* B;
   const int64_t* ld;
   const int64_t* off;
+  const int64_t* eoff;                            // envelope tables by 64-row blocks
+  const int64_t* fcb;
+  const int64_t* lrb;
 };
 
 // ---- Factorisation: right-looking blocked Cholesky in groups of GP panels of NB columns.
@@ -215,8 +218,8 @@ __global__ void __launch_bounds__(CT) k_chain(BandArgs a, T* v, int64_t k0, int 
         if (p - q < NR) chain_wait(fj + q * NRT + p, epoch, err);
       }
     __syncthreads();
-    // the first chunk with an entry inside the band of the block's top row
-    const int64_t lo = r0 - B;
+    // the first chunk with an entry inside the envelope of the block's rows
+    const int64_t lo = max(r0 - B, a.fcb[a.eoff[j] + r0 / NB]);
     const int64_t kstart = lo > k0 ? k0 + (lo - k0) / KC * KC : k0;
     S xr[PER], xs[PER];
     // 32-bit terms relative to the block: row i of a block is inside the matrix if
@@ -465,8 +468,11 @@ __device__ inline void wide_tile(BandArgs a, T* v, int64_t k0, int64_t kk, int64
   const int64_t r0 = t0 + tr * T2, s0 = t0 + ts * T2, wend = t0 + W;
   const int64_t rs = ld - 1;                     // entry (r, c) at r * rs + B + c
   const int kc_t = threadIdx.x % KW, i0 = threadIdx.x / KW;
-  // first chunk with an entry inside the band for the tile's top row (lower rows start later)
-  const int64_t lo = r0 - B - k0;
+  // first chunk with an entry inside the envelope of the tile's rows (its two 64-row blocks)
+  const int64_t* fcj = a.fcb + a.eoff[j];
+  const int64_t b0 = r0 / NB;
+  const int64_t fmin = b0 + 1 < (n + NB - 1) / NB ? min(fcj[b0], fcj[b0 + 1]) : fcj[b0];
+  const int64_t lo = max(r0 - B, fmin) - k0;
   const int64_t kc_first = lo > 0 ? lo / KW * KW : 0;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -567,7 +573,7 @@ static int64_t wide_tiles(int64_t max_B, int64_t lo, int64_t hi) {
 
 template <class T>
 void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job) {
-  BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p};
+  BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p, bs.d_eoff.p, bs.d_fcb.p, bs.d_lrb.p};
   static_assert(GP * NB == 2 * T2, "the rest update starts two wide tile columns on");
   for (int j = 0; j < bs.n_mat; ++j)
     GX_REQUIRE((bs.n[j] + T2) * bs.ld[j] + 64 < ((int64_t)1 << 31),
@@ -750,11 +756,14 @@ __device__ inline bool poll_give_up(int64_t& spins, int* err) {
 }
 
 // Work-group g of the G that solve one matrix of n rows, half-bandwidth B and row stride
-// ld: factor from base, inverse diagonal blocks from dv, right-hand side x, scratch y, z.
+// ld: factor from base, inverse diagonal blocks from dv, envelope tables fcb / lrb (by
+// 64-row blocks), right-hand side x, scratch y, z.
 template <class T>
 __device__ __forceinline__ void band_solve_1_mat(int64_t n, int64_t B, int64_t ld,
-                                                 const T* base, const T* dv, const double* x,
-                                                 double* y, double* z, int g, int G, int* err) {
+                                                 const T* base, const T* dv,
+                                                 const int64_t* fcb, const int64_t* lrb,
+                                                 const double* x, double* y, double* z, int g,
+                                                 int G, int* err) {
   __shared__ double acc[SB];
   __shared__ double part[SW][SB];
   __shared__ double xs[GMAX - 1][SB];               // polled solutions of blocks in flight
@@ -782,7 +791,8 @@ __device__ __forceinline__ void band_solve_1_mat(int64_t n, int64_t B, int64_t l
     double s[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) s[r] = 0.0;
-    for (int64_t c0 = max<int64_t>(ifirst - B, 0) + lane; c0 < done_end + lane; c0 += 64 * U) {
+    const int64_t cstart = max(max<int64_t>(ifirst - B, 0), fcb[k]);   // envelope start
+    for (int64_t c0 = cstart + lane; c0 < done_end + lane; c0 += 64 * U) {
       T l[U][RPW];
       double xv[U];
 #pragma unroll
@@ -866,7 +876,7 @@ __device__ __forceinline__ void band_solve_1_mat(int64_t n, int64_t B, int64_t l
     const int64_t kb = nblk - 1 - t;
     const int64_t i0 = kb * SB;
     const int nb = (int)min<int64_t>(SB, n - i0);
-    const int64_t rend = min<int64_t>(n, i0 + nb + B);
+    const int64_t rend = min(min<int64_t>(n, i0 + nb + B), lrb[kb]);   // envelope end
     const int64_t kdone = kb + G;                  // row blocks >= kdone complete
     const int64_t done_beg = min<int64_t>(rend, kdone * SB);
     const int64_t cidx = i0 + lane;
@@ -978,8 +988,9 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1(
   if (j >= n_mat || g >= G) return;
   const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
   if (n == 0) return;
-  band_solve_1_mat<T>(n, B, ld, v + a.off[j], dinv + boff[j], xall + xoff[j], yall + yoff[j],
-                      zall + yoff[j], g, G, err);
+  band_solve_1_mat<T>(n, B, ld, v + a.off[j], dinv + boff[j], a.fcb + a.eoff[j],
+                      a.lrb + a.eoff[j], xall + xoff[j], yall + yoff[j], zall + yoff[j], g, G,
+                      err);
 }
 
 // The matrices of several band sets in one launch (all of one precision): work-group i
@@ -995,7 +1006,8 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_band_solve_1_multi(const Band
   const BandPtrs t = tab[j];
   if (t.n == 0) return;
   band_solve_1_mat<T>(t.n, t.B, t.B + 1, static_cast<const T*>(t.v),
-                      static_cast<const T*>(t.dinv), t.x, t.y, t.z, g, (int)t.G, err);
+                      static_cast<const T*>(t.dinv), t.fcb, t.lrb, t.x, t.y, t.z, g, (int)t.G,
+                      err);
 }
 
 // y and z scratch of every matrix of a multi-set solve back to the marker
@@ -1054,6 +1066,8 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
   const T* cb = v + a.off[j] + B;                 // entry (r, c) = cb[r * rs + c]
   const int64_t rs = ld - 1;
   const T* dv = dinv + boff[j];
+  const int64_t* fcb = a.fcb + a.eoff[j];
+  const int64_t* lrb = a.lrb + a.eoff[j];
   const double* x = xall + xoff[j];
   double* y = yall + yoff[j] * M;
   double* z = zall + yoff[j] * M;
@@ -1226,7 +1240,7 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
   for (int64_t k = g; k < nblk; k += G) {
     const int64_t i0 = k * SB;
     const int nb = (int)min<int64_t>(SB, n - i0);
-    const int64_t kfirst = max<int64_t>(i0 - B, 0) / SB;
+    const int64_t kfirst = max(max<int64_t>(i0 - B, 0), fcb[k]) / SB;   // envelope start
     T dd[AL];
 #pragma unroll
     for (int u = 0; u < AL; ++u) dd[u] = dv[k * SB * SB + threadIdx.x + MT * u];
@@ -1239,7 +1253,7 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
     const int64_t kb = nblk - 1 - t;
     const int64_t i0 = kb * SB;
     const int nb = (int)min<int64_t>(SB, n - i0);
-    const int64_t klast = (min<int64_t>(n, i0 + nb + B) - 1) / SB;   // last row block
+    const int64_t klast = (min(min<int64_t>(n, i0 + nb + B), lrb[kb]) - 1) / SB;   // last row block
     T dd[AL];
 #pragma unroll
     for (int u = 0; u < AL; ++u) dd[u] = dv[kb * SB * SB + threadIdx.x + MT * u];
@@ -1398,7 +1412,7 @@ void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, i
     GX_HIP(hipGetLastError());
     return;
   }
-  BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p};
+  BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p, bs.d_eoff.p, bs.d_fcb.p, bs.d_lrb.p};
   int n_pad = 0;
   if (ncol == 1 && !active) {
     const void* kf = bs.fp32 ? reinterpret_cast<const void*>(&k_band_solve_1<float, false>)
@@ -1448,19 +1462,6 @@ double band_solve_bytes(const BandSet& bs, int ncol, const int32_t* active_host,
   return b;
 }
 
-double band_factor_flops(const BandSet& bs) {
-  double f = 0.0;
-  for (int j = 0; j < bs.n_mat; ++j) {
-    const double n = (double)bs.n[j], B = (double)bs.B[j];
-    // columns 0 .. n - 1 - B have w = B; the last B columns have w = B - 1 .. 0
-    const double full = std::max(0.0, n - B);
-    const double tail = std::min(n, B);                  // w = tail - 1 .. 0
-    f += full * (B * B + 2.0 * B + 1.0);
-    f += (tail - 1.0) * tail * (2.0 * tail - 1.0) / 6.0 + (tail - 1.0) * tail + tail;
-  }
-  return f;
-}
-
 // The table of a multi-set solve: matrix j of set k solves in place on x[k] + xoff[k][j]
 // (xoff[k]: host offsets of set k's right-hand-side segments).  Synchronises st.
 void multi_solve_plan(MultiSolve& m, const std::vector<BandSet*>& sets,
@@ -1491,6 +1492,8 @@ void multi_solve_plan(MultiSolve& m, const std::vector<BandSet*>& sets,
       t.z = bs.ybuf.p + half + yo;
       t.n = bs.n[j];
       t.B = bs.B[j];
+      t.fcb = bs.d_fcb.p + bs.eoff[j];
+      t.lrb = bs.d_lrb.p + bs.eoff[j];
       yo += (bs.n[j] + SB - 1) / SB * SB;
       m.max_n = std::max(m.max_n, bs.n[j]);
       m.host.push_back(t);
@@ -1612,7 +1615,7 @@ void band_solve_check(BandSet& bs, hipStream_t st) {
 }
 
 void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<int64_t>& B,
-                 bool fp32, hipStream_t st) {
+                 bool fp32, hipStream_t st, const std::vector<int32_t>* first_node) {
   bs.n_mat = (int)n.size();
   bs.n = n;
   bs.B = B;
@@ -1635,11 +1638,49 @@ void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<i
     bs.max_B = std::max<int64_t>(bs.max_B, B[j]);
   }
   bs.total = o;
+  // the envelope: row r from its first column f(r) (3 x its node's first coupled node, or
+  // r - B) to the diagonal; env counts its entries, env_flops the Cholesky flops over it
+  // (column c: h^2 + 2 h + 1 with h the rows below c that reach it), fcb / lrb its tables
+  bs.eoff.assign(n.size() + 1, 0);
+  for (size_t j = 0; j < n.size(); ++j) bs.eoff[j + 1] = bs.eoff[j] + (n[j] + SB - 1) / SB;
+  std::vector<int64_t> fcb(std::max<int64_t>(bs.eoff[n.size()], 1)), lrb(fcb.size());
   bs.env.assign(n.size(), 0);
-  for (size_t j = 0; j < n.size(); ++j) {      // the band itself: row r holds min(r, B) + 1
-    const int64_t m = std::min(n[j], B[j] + 1);
-    bs.env[j] = m * (m + 1) / 2 + (n[j] - m) * (B[j] + 1);
+  bs.env_flops = 0.0;
+  size_t node0 = 0;
+  for (size_t j = 0; j < n.size(); ++j) {
+    const int64_t nj = n[j], Bj = B[j], nbk = (nj + SB - 1) / SB;
+    GX_REQUIRE(!first_node || (nj % 3 == 0 && node0 + nj / 3 <= first_node->size()),
+               "band layout: a first node for every node of every matrix");
+    int64_t* fj = fcb.data() + bs.eoff[j];
+    int64_t* lj = lrb.data() + bs.eoff[j];
+    std::vector<int64_t> reach(nbk, 0), diff(nj + 1, 0);
+    for (int64_t b = 0; b < nbk; ++b) fj[b] = nj;
+    for (int64_t r = 0; r < nj; ++r) {
+      int64_t f = first_node ? 3 * (int64_t)(*first_node)[node0 + r / 3] : r - Bj;
+      f = std::min(std::max(f, std::max<int64_t>(r - Bj, 0)), r);
+      fj[r / SB] = std::min(fj[r / SB], f);
+      reach[f / SB] = std::max(reach[f / SB], r + 1);
+      bs.env[j] += r - f + 1;
+      ++diff[f];
+      --diff[r];
+    }
+    int64_t run = 0, h = 0;
+    for (int64_t b = 0; b < nbk; ++b) {
+      run = std::max(run, reach[b]);
+      lj[b] = std::max(run, std::min(nj, (b + 1) * SB));
+    }
+    for (int64_t c = 0; c < nj; ++c) {
+      h += diff[c];
+      bs.env_flops += (double)h * h + 2.0 * h + 1.0;
+    }
+    if (first_node) node0 += nj / 3;
   }
+  bs.d_eoff.alloc(n.size() + 1);
+  bs.d_fcb.alloc(fcb.size());
+  bs.d_lrb.alloc(lrb.size());
+  to_dev(bs.d_eoff.p, bs.eoff.data(), n.size() + 1, st);
+  to_dev(bs.d_fcb.p, fcb.data(), fcb.size(), st);
+  to_dev(bs.d_lrb.p, lrb.data(), lrb.size(), st);
   bs.d_n.alloc(n.size());
   bs.d_B.alloc(n.size());
   bs.d_ld.alloc(n.size());

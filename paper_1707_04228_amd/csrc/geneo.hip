@@ -945,14 +945,15 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   to_dev(d_doff.p, doff.data(), n_sub + 1, s);
   DevBuf<double> dM;
   {
-    std::vector<int64_t> n3(n_sub), env, B =
-        list_bandwidth(c, sw.D_nodes.p, sw.d_offD.p, sw.d_nD.p, sw.D_loc.p, sw.nD, &env);
+    std::vector<int64_t> n3(n_sub), env;
+    std::vector<int32_t> first;
+    std::vector<int64_t> B =
+        list_bandwidth(c, sw.D_nodes.p, sw.d_offD.p, sw.d_nD.p, sw.D_loc.p, sw.nD, &env, &first);
     for (int j = 0; j < n_sub; ++j) n3[j] = 3 * sw.nD[j];
-    band_layout(Mb, n3, B, fp32, s);
-    Mb.env = env;
+    band_layout(Mb, n3, B, fp32, s, &first);
     c->neumann_envelope = 0;
-    for (int64_t e : env) c->neumann_envelope += e;
-    c->neumann_flops = band_factor_flops(Mb);
+    for (int64_t e : Mb.env) c->neumann_envelope += e;
+    c->neumann_flops = Mb.env_flops;
     Mb.force_groups[0] = c->tune[0];
     Mb.force_groups[1] = c->tune[1];
     c->neumann_entries = Mb.total;
@@ -983,7 +984,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
       if (!fp32 || e.code != GX_ENOTSPD) throw;
       // an FP32 factor broke down: this matrix set is refactored in FP64 (reported)
       c->fp64_fallbacks |= 2;
-      band_layout(Mb, n3, B, false, s);
+      band_layout(Mb, n3, B, false, s, &first);
       bv = BandView{Mb.d_B.p, Mb.d_ld.p, Mb.d_off.p};
       GX_HIP(hipMemsetAsync(Mb.v64.p, 0, Mb.total * sizeof(double), s));
       hipLaunchKernelGGL(k_neumann_fill<double>, dim3((unsigned)maxD, n_sub), dim3(64), 0, s, g,

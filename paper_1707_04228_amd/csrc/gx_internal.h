@@ -215,6 +215,14 @@ struct BandSet {
   // outside it).  band_layout sets it to the band itself; callers that know the matrices'
   // profile replace it.
   std::vector<int64_t> env;
+  double env_flops = 0.0;                      // Cholesky flops over the envelope
+  // the envelope by 64-row blocks (block b of matrix j at eoff[j] + b): fcb, the first
+  // column any row of the block reaches; lrb, one past the last row that reaches a column
+  // of the block.  From each row's first column when band_layout is given it, otherwise
+  // from the band.  The kernels skip the 64-column steps outside it (exact zeros: Cholesky
+  // creates no fill outside the envelope).
+  std::vector<int64_t> eoff;
+  DevBuf<int64_t> d_eoff, d_fcb, d_lrb;
   DevBuf<int64_t> d_n, d_B, d_ld, d_off;       // device copies
   int64_t total = 0;                           // stored entries
   int max_n = 0, max_B = 0;
@@ -249,6 +257,8 @@ struct BandPtrs {
   double* y;                                   // forward-solution scratch (64-aligned length)
   double* z;                                   // backward-solution scratch
   int64_t n, B;                                // rows, half-bandwidth
+  const int64_t* fcb;                          // envelope by 64-row blocks (see BandSet)
+  const int64_t* lrb;
   int64_t G;                                   // work-groups sharing the matrix
 };
 
@@ -363,13 +373,14 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o);
 std::vector<int64_t> list_bandwidth(gx_ctx* c, const int32_t* list, const int64_t* d_off,
                                     const int64_t* d_cnt, const int32_t* loc,
                                     const std::vector<int64_t>& cnt,
-                                    std::vector<int64_t>* env_out = nullptr);
+                                    std::vector<int64_t>* env_out = nullptr,
+                                    std::vector<int32_t>* first_out = nullptr);
 double interior_refactor_ms(gx_ctx* c);
-// Cholesky flops of the band matrices of a set: sum over columns of w^2 + 2 w + 1, w the
-// entries below the diagonal inside the band (min(B, n - 1 - c))
-double band_factor_flops(const BandSet& bs);
+// first_node (optional): for each matrix's nodes in order (n_j / 3 each, concatenated),
+// the first node its rows couple to; it gives the envelope (env, env_flops, the block
+// tables), otherwise the band itself is taken
 void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<int64_t>& B,
-                 bool fp32, hipStream_t st);
+                 bool fp32, hipStream_t st, const std::vector<int32_t>* first_node = nullptr);
 void band_factor(BandSet& bs, hipStream_t st, const char* what);
 // A banded factorisation in flight (band_factor_start enqueues it on st, band_factor_finish
 // waits for it and raises GX_ENOTSPD on a non-positive pivot).  It owns the look-ahead
@@ -393,6 +404,7 @@ void band_factor_finish(FactorJob& job);
 // The interior factorisation as a job that can run on a side stream (see schwarz.hip).
 struct InteriorJob {
   std::vector<int64_t> n, B, env;
+  std::vector<int32_t> first;                  // first coupled node of every node
   int64_t maxI = 0;
   bool fp32 = false;
   FactorJob factor;

@@ -540,7 +540,7 @@ gx_status gx_kernel_time(gx_ctx* c, int32_t which, int32_t reps, double* avg_ms,
     double tot = 0.0;
     for (int k = 0; k < reps; ++k) tot += interior_refactor_ms(c);
     if (avg_ms) *avg_ms = tot / reps;
-    if (bytes) *bytes = band_factor_flops(c->sw.A);
+    if (bytes) *bytes = c->sw.A.env_flops;
     return GX_OK;
   }
   if (which == 4) {                                // recorded during the last setup
@@ -596,7 +596,7 @@ gx_status gx_band_stats(gx_ctx* c, double* out) {
   for (int64_t e : A.env) env += (double)e;
   out[0] = (double)A.total;
   out[1] = env;
-  out[2] = band_factor_flops(A);
+  out[2] = A.env_flops;
   out[3] = (double)c->neumann_entries;
   out[4] = (double)c->neumann_envelope;
   out[5] = c->neumann_flops;

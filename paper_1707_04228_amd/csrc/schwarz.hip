@@ -210,7 +210,7 @@ void dd_build(gx_ctx* c, const int32_t* part, int n_sub, int overlap) {
 // and including their diagonals.  Integer sums: the result does not depend on the order.
 __global__ void k_band_width(const int32_t* rp, const int32_t* col, const int32_t* list,
                              const int64_t* loff, const int64_t* lcnt, const int32_t* loc,
-                             int64_t N, int32_t* bw, unsigned long long* env) {
+                             int64_t N, int32_t* bw, unsigned long long* env, int32_t* first) {
   const int j = blockIdx.y;
   const int64_t ln = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ln >= lcnt[j]) return;
@@ -223,6 +223,7 @@ __global__ void k_band_width(const int32_t* rp, const int32_t* col, const int32_
   }
   atomicMax(&bw[j], (int)ln - mn);
   atomicAdd(&env[j], (unsigned long long)(9 * ((int64_t)ln - mn) + 6));
+  first[loff[j] + ln] = mn;
 }
 
 template <class T>
@@ -268,18 +269,29 @@ __global__ void k_diag(const int32_t* rp, const int32_t* col, const double* val,
 std::vector<int64_t> list_bandwidth(gx_ctx* c, const int32_t* list, const int64_t* d_off,
                                     const int64_t* d_cnt, const int32_t* loc,
                                     const std::vector<int64_t>& cnt,
-                                    std::vector<int64_t>* env_out) {
+                                    std::vector<int64_t>* env_out,
+                                    std::vector<int32_t>* first_out) {
   hipStream_t s = c->stream;
   const int n_sub = (int)cnt.size();
   int64_t mx = 0;
   for (int64_t v : cnt) mx = std::max(mx, v);
-  DevBuf<int32_t> bw(n_sub);
+  std::vector<int64_t> hoff(n_sub + 1);
+  to_host(hoff.data(), d_off, n_sub + 1, s);
+  DevBuf<int32_t> bw(n_sub), first(std::max<int64_t>(hoff[n_sub], 1));
   DevBuf<unsigned long long> env(n_sub);
   zero(bw, s);
   zero(env, s);
   hipLaunchKernelGGL(k_band_width, dim3(nblocks(mx, 256), n_sub), dim3(256), 0, s,
-                     c->row_ptr.p, c->col.p, list, d_off, d_cnt, loc, c->n_nodes, bw.p, env.p);
+                     c->row_ptr.p, c->col.p, list, d_off, d_cnt, loc, c->n_nodes, bw.p, env.p,
+                     first.p);
   GX_HIP(hipGetLastError());
+  if (first_out) {                                  // the matrices' nodes in order
+    std::vector<int32_t> all(hoff[n_sub]);
+    to_host(all.data(), first.p, all.size(), s);
+    first_out->clear();
+    for (int j = 0; j < n_sub; ++j)
+      first_out->insert(first_out->end(), all.begin() + hoff[j], all.begin() + hoff[j] + cnt[j]);
+  }
   std::vector<int32_t> hb(n_sub);
   std::vector<unsigned long long> he(n_sub);
   to_host(hb.data(), bw.p, n_sub, s);
@@ -298,13 +310,13 @@ void interior_factors_start(gx_ctx* c, int precision, hipStream_t s, InteriorJob
   const int n_sub = sw.n_sub;
   job.maxI = 0;
   for (int j = 0; j < n_sub; ++j) job.maxI = std::max(job.maxI, sw.nI[j]);
-  job.B = list_bandwidth(c, sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, sw.nI, &job.env);
+  job.B = list_bandwidth(c, sw.I_nodes.p, sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, sw.nI, &job.env,
+                         &job.first);
   job.n.assign(n_sub, 0);
   for (int j = 0; j < n_sub; ++j) job.n[j] = 3 * sw.nI[j];
   sw.precision = precision;
   job.fp32 = precision == GX_MIXED;
-  band_layout(sw.A, job.n, job.B, job.fp32, s);
-  sw.A.env = job.env;
+  band_layout(sw.A, job.n, job.B, job.fp32, s, &job.first);
   sw.A.force_groups[0] = c->tune[0];
   sw.A.force_groups[1] = c->tune[1];
   if (job.fp32) {
@@ -337,8 +349,7 @@ void interior_factors_finish(gx_ctx* c, InteriorJob& job) {
   } catch (const Error& e) {
     if (!job.fp32 || e.code != GX_ENOTSPD) throw;
     c->fp64_fallbacks |= 1;
-    band_layout(sw.A, job.n, job.B, false, s);
-    sw.A.env = job.env;
+    band_layout(sw.A, job.n, job.B, false, s, &job.first);
     BandView bv64{sw.A.d_B.p, sw.A.d_ld.p, sw.A.d_off.p};
     hipLaunchKernelGGL(k_band_fill<double>, dim3((unsigned)job.maxI, n_sub), dim3(64), 0, s,
                        c->row_ptr.p, c->col.p, c->val.p, (const double*)nullptr, sw.I_nodes.p,
