@@ -743,6 +743,17 @@ __device__ inline void hand_over(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// the same in FP32 (the hand-over scratch of the FP32 many-right-hand-side solve): the
+// marker is a signalling-NaN payload, which arithmetic never produces either
+constexpr uint32_t YMARK32 = 0x7FA5C0DEu;
+__device__ inline bool is_mark(float v) { return __float_as_uint(v) == YMARK32; }
+__device__ inline float poll_load(const float* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void hand_over(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Spin-limit bookkeeping of a polling loop: true when the wait must give up (time-out, or
 // another wait of the launch already timed out).
 __device__ inline bool poll_give_up(int64_t& spins, int* err) {
@@ -1039,9 +1050,11 @@ __global__ void k_copy_out_multi(const BandPtrs* tab) {
 // (the chunk loop is unrolled by two so that each set and buffer has a name of its own).
 // Hand-over between work-groups
 // goes through marker-filled scratch solutions as in the single-right-hand-side solve
-// (forward into y, backward into z, z copied into x afterwards): solution entries are
-// loaded with agent-scope relaxed atomics, and a chunk is staged only once none of the
-// entries it needs is a marker (a chunk still in flight is polled again until then).
+// (forward into y, backward into z, z copied into x afterwards), kept in the factor's
+// precision (FP32 factors: FP32 scratch, half the bytes of the solution rows that every
+// chunk reads): solution entries are loaded with agent-scope relaxed atomics, and a chunk
+// is staged only once none of the entries it needs is a marker (a chunk still in flight
+// is polled again until then).
 constexpr int MC = 32;                            // right-hand sides per launch, at most
 constexpr int MT = 512;                           // threads per work-group
 constexpr int AL = SB * SB / MT;                  // band-chunk entries per thread (8)
@@ -1049,10 +1062,11 @@ constexpr int AL = SB * SB / MT;                  // band-chunk entries per thre
 template <class T, int M>
 __global__ void __launch_bounds__(MT) k_band_solve_m(
     BandArgs a, const T* v, const T* dinv, const int64_t* boff, const int64_t* xoff,
-    const double* xall, double* yall, double* zall, const int64_t* yoff, int G, int n_pad,
+    const double* xall, T* yall, T* zall, const int64_t* yoff, int G, int n_pad,
     int n_mat, const int32_t* active, int* err) {
   typedef Mfma<T> MF;
   typedef typename MF::S S;
+  typedef T Y;                                    // hand-over scratch: the factor's precision
   constexpr int NCT = (M + 15) / 16;              // column tiles (1 or 2)
   constexpr int MP = 16 * NCT;                    // LDS row stride (zero columns past M)
   constexpr int YL = SB * M / MT;                 // solution-chunk entries per thread
@@ -1069,8 +1083,8 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
   const int64_t* fcb = a.fcb + a.eoff[j];
   const int64_t* lrb = a.lrb + a.eoff[j];
   const double* x = xall + xoff[j];
-  double* y = yall + yoff[j] * M;
-  double* z = zall + yoff[j] * M;
+  Y* y = yall + yoff[j] * M;
+  Y* z = zall + yoff[j] * M;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rt = wave & 3, ct = wave >> 2;        // this wave's row and column tile
   const bool tile = ct < NCT;                      // waves past the column tiles only stage
@@ -1084,21 +1098,21 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
   // forward chunk kk of block i0: band rows i0.., columns 64 kk..; backward chunk kk:
   // band rows 64 kk.., columns i0..; both with solution rows 64 kk..  Thread t stages band
   // rows t / 64 + 8 u at column t % 64.
-  auto fetch = [&](bool bwd, int64_t i0, int64_t kk, T (&fa)[AL], double (&fy)[YL]) {
+  auto fetch = [&](bool bwd, int64_t i0, int64_t kk, T (&fa)[AL], Y (&fy)[YL]) {
     const int64_t r0 = (bwd ? kk * SB : i0) + wave;
     const int64_t c = (bwd ? i0 : kk * SB) + lane;
 #pragma unroll
     for (int u = 0; u < AL; ++u) fa[u] = cb[min<int64_t>(r0 + 8 * u, n - 1) * rs + c];
     const int64_t yend = min<int64_t>((int64_t)SB * M, (n - kk * SB) * M);   // rows < n
-    const double* xs = (bwd ? z : y) + kk * SB * M;
+    const Y* xs = (bwd ? z : y) + kk * SB * M;
 #pragma unroll
     for (int u = 0; u < YL; ++u) fy[u] = poll_load(xs + min<int64_t>(threadIdx.x + MT * u, yend - 1));
   };
   auto stage = [&](int buf, bool bwd, int64_t i0, int nb, int64_t kk, const T (&fa)[AL],
-                   double (&fy)[YL]) {
+                   Y (&fy)[YL]) {
     {                                              // until every needed entry is handed over
       const int64_t yend = min<int64_t>((int64_t)SB * M, (n - kk * SB) * M);
-      const double* xs = (bwd ? z : y) + kk * SB * M;
+      const Y* xs = (bwd ? z : y) + kk * SB * M;
       // the first test on the values already loaded is straight-line code, so the wait
       // before it covers only this chunk's loads, not the prefetch of the next one; the
       // polling loop is the slow path of a chunk still in flight
@@ -1162,7 +1176,7 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
                    typename MF::V& acc) {
     if (count <= 0) return;
     T fa0[AL], fa1[AL];
-    double fy0[YL], fy1[YL];
+    Y fy0[YL], fy1[YL];
     // chunk q, clamped to the last one: every prefetch is issued unconditionally (a chunk
     // past the end repeats the last, never used), which keeps the loads in flight the same
     // on every path and lets each wait count only the chunk it needs
@@ -1206,8 +1220,9 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int ii = 16 * rt + MF::row(r, lk);
-          bb[r] = poll_load(y + (i0 + min(ii, nb - 1)) * M + cc);
-          ok = ok && (!tile || ii >= nb || !is_mark(bb[r]));
+          const Y yb = poll_load(y + (i0 + min(ii, nb - 1)) * M + cc);
+          bb[r] = (double)yb;
+          ok = ok && (!tile || ii >= nb || !is_mark(yb));
         }
         if (__all(ok) || poll_give_up(spins, err)) break;
       }
@@ -1227,12 +1242,12 @@ __global__ void __launch_bounds__(MT) k_band_solve_m(
     __syncthreads();
     typename MF::V yv = {0, 0, 0, 0};
     mma(0, bwd, yv);
-    double* dst = bwd ? z : y;
+    Y* dst = bwd ? z : y;
     if (tile)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int ii = 16 * rt + MF::row(r, lk), col = 16 * ct + li;
-        if (ii < nb && col < M) hand_over(dst + (i0 + ii) * M + col, (double)yv[r]);
+        if (ii < nb && col < M) hand_over(dst + (i0 + ii) * M + col, (Y)yv[r]);
       }
     __syncthreads();
   };
@@ -1333,13 +1348,19 @@ __global__ void k_copy_out(const int64_t* nrows, const int64_t* xoff, const int6
   if (i < nrows[j]) x[xoff[j] + i] = z[yoff[j] + i];
 }
 
+__global__ void k_fill_mark32(float* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = __uint_as_float(YMARK32);
+}
+
 // z_j -> x_j for the active matrices (n_j rows of w columns)
+template <class Y>
 __global__ void k_copy_out_m(const int64_t* nrows, const int64_t* xoff, const int64_t* yoff,
-                             int w, const double* z, double* x, const int32_t* active) {
+                             int w, const Y* z, double* x, const int32_t* active) {
   const int j = blockIdx.y;
   if (active && !active[j]) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nrows[j] * w) x[xoff[j] + i] = z[yoff[j] * w + i];
+  if (i < nrows[j] * w) x[xoff[j] + i] = (double)z[yoff[j] * w + i];
 }
 
 template <int M>
@@ -1353,20 +1374,28 @@ static void launch_m(BandSet& bs, const BandArgs& a, const int64_t* d_xoff, doub
   if (!bs.d_yoff.n) (void)solve1_scratch(bs, st);
   const int64_t rows = (int64_t)bs.ybuf.n / 2;     // padded rows of all matrices
   if (bs.mbuf.n < (size_t)(2 * rows * MC)) bs.mbuf.alloc(2 * rows * MC);
-  hipLaunchKernelGGL(k_fill_mark, dim3(nblocks(2 * rows * M, 256)), dim3(256), 0, st, bs.mbuf.p,
-                     2 * rows * M);
-  double* y = bs.mbuf.p;
-  double* z = bs.mbuf.p + rows * M;
-  if (bs.fp32)
+  const dim3 cgrid(nblocks(bs.max_n * M, 256), bs.n_mat);
+  if (bs.fp32) {                                   // FP32 scratch in the same buffer
+    float* y = reinterpret_cast<float*>(bs.mbuf.p);
+    float* z = y + rows * M;
+    hipLaunchKernelGGL(k_fill_mark32, dim3(nblocks(2 * rows * M, 256)), dim3(256), 0, st, y,
+                       2 * rows * M);
     hipLaunchKernelGGL((k_band_solve_m<float, M>), dim3(G * n_pad), dim3(MT), 0, st, a, bs.v32.p,
                        bs.dinv32.p, bs.d_boff.p, d_xoff, x, y, z, bs.d_yoff.p, G, n_pad,
                        bs.n_mat, active, err);
-  else
+    hipLaunchKernelGGL(k_copy_out_m<float>, cgrid, dim3(256), 0, st, bs.d_n.p, d_xoff,
+                       bs.d_yoff.p, M, z, x, active);
+  } else {
+    double* y = bs.mbuf.p;
+    double* z = bs.mbuf.p + rows * M;
+    hipLaunchKernelGGL(k_fill_mark, dim3(nblocks(2 * rows * M, 256)), dim3(256), 0, st, y,
+                       2 * rows * M);
     hipLaunchKernelGGL((k_band_solve_m<double, M>), dim3(G * n_pad), dim3(MT), 0, st, a,
                        bs.v64.p, bs.dinv64.p, bs.d_boff.p, d_xoff, x, y, z, bs.d_yoff.p, G,
                        n_pad, bs.n_mat, active, err);
-  hipLaunchKernelGGL(k_copy_out_m, dim3(nblocks(bs.max_n * M, 256), bs.n_mat), dim3(256), 0, st,
-                     bs.d_n.p, d_xoff, bs.d_yoff.p, M, z, x, active);
+    hipLaunchKernelGGL(k_copy_out_m<double>, cgrid, dim3(256), 0, st, bs.d_n.p, d_xoff,
+                       bs.d_yoff.p, M, z, x, active);
+  }
 }
 
 // Columns c0 .. c0 + w of a row-major block of ncol columns to or from a contiguous panel
