@@ -44,7 +44,7 @@ FP64_PEAK_TFLOPS = 78.6
 # the FETCH_SIZE / WRITE_SIZE counters of `bench.py --traffic-probe [--precision mixed]`
 # scaled by a 4 GiB copy.  Valid for the solve kernel as it stands: retake the counters
 # when it changes.
-SOLVE_TRAFFIC_BYTES = {"fp64": 158.5e9, "mixed": 83.0e9}
+SOLVE_TRAFFIC_BYTES = {"fp64": 148.5e9, "mixed": 77.2e9}
 
 
 def run_step(gx, torch, cfg, precision):
