@@ -802,7 +802,9 @@ __device__ __forceinline__ void band_solve_1_mat(int64_t n, int64_t B, int64_t l
     double s[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) s[r] = 0.0;
-    const int64_t cstart = max(max<int64_t>(ifirst - B, 0), fcb[k]);   // envelope start
+    // envelope start, rounded down to a 128-byte line (rows start on one: see band_layout)
+    constexpr int64_t LA = 128 / sizeof(T);
+    const int64_t cstart = max(max<int64_t>(ifirst - B, 0), fcb[k]) / LA * LA;
     for (int64_t c0 = cstart + lane; c0 < done_end + lane; c0 += 64 * U) {
       T l[U][RPW];
       double xv[U];
@@ -1643,6 +1645,20 @@ void band_solve_check(BandSet& bs, hipStream_t st) {
   }
 }
 
+// zero the entries between one matrix's storage and the next (the line alignment of the
+// starts leaves up to A - 1 of them); the fills write only the matrices' own rows, and a
+// load left of a row's band, masked by a factor 0, must not meet a NaN there
+template <class T>
+__global__ void k_zero_gaps(int n_mat, int A, const int64_t* off, const int64_t* nn,
+                            const int64_t* ld, int64_t total, T* v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = i / A, k = i % A;
+  if (j >= n_mat) return;
+  const int64_t e = off[j] + nn[j] * ld[j] + k;
+  const int64_t next = j + 1 < n_mat ? off[j + 1] : total;
+  if (e < next) v[e] = (T)0;
+}
+
 void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<int64_t>& B,
                  bool fp32, hipStream_t st, const std::vector<int32_t>* first_node) {
   bs.n_mat = (int)n.size();
@@ -1659,12 +1675,19 @@ void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<i
   bs.d_yoff.release();
   bs.mbuf.release();
   bs.max_B = 0;
+  // the stored half-bandwidth is B rounded up to a multiple of A, the entries of a 128-byte
+  // line, and every matrix starts on a multiple of A: entry (r, c) then sits at an offset
+  // congruent to c modulo A, so a row's entries from any multiple of A on fill whole
+  // lines.  The extra band entries left of the band are zeros (outside the envelope).
+  const int64_t A = fp32 ? 32 : 16;
   for (size_t j = 0; j < n.size(); ++j) {
-    bs.ld[j] = B[j] + 1;
+    bs.B[j] = (B[j] + A - 1) / A * A;
+    bs.ld[j] = bs.B[j] + 1;
+    o = (o + A - 1) / A * A;
     bs.off[j] = o;
     o += n[j] * bs.ld[j];
     bs.max_n = std::max<int64_t>(bs.max_n, n[j]);
-    bs.max_B = std::max<int64_t>(bs.max_B, B[j]);
+    bs.max_B = std::max<int64_t>(bs.max_B, bs.B[j]);
   }
   bs.total = o;
   // the envelope: row r from its first column f(r) (3 x its node's first coupled node, or
@@ -1728,12 +1751,16 @@ void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<i
     bs.dinv64.release();
     bs.v32.alloc(o + band_pad(bs.max_B));
     GX_HIP(hipMemsetAsync(bs.v32.p + o, 0, band_pad(bs.max_B) * sizeof(float), st));
+    hipLaunchKernelGGL(k_zero_gaps<float>, dim3(nblocks((int64_t)n.size() * A, 256)), dim3(256),
+                       0, st, bs.n_mat, (int)A, bs.d_off.p, bs.d_n.p, bs.d_ld.p, o, bs.v32.p);
     bs.dinv32.alloc(bs.boff[n.size()]);
   } else {
     bs.v32.release();
     bs.dinv32.release();
     bs.v64.alloc(o + band_pad(bs.max_B));
     GX_HIP(hipMemsetAsync(bs.v64.p + o, 0, band_pad(bs.max_B) * sizeof(double), st));
+    hipLaunchKernelGGL(k_zero_gaps<double>, dim3(nblocks((int64_t)n.size() * A, 256)), dim3(256),
+                       0, st, bs.n_mat, (int)A, bs.d_off.p, bs.d_n.p, bs.d_ld.p, o, bs.v64.p);
     bs.dinv64.alloc(bs.boff[n.size()]);
   }
   bs.solve_groups[0] = bs.solve_groups[1] = 0;
@@ -1744,18 +1771,23 @@ void band_layout(BandSet& bs, const std::vector<int64_t>& n, const std::vector<i
 // ---------------------------------------------------------------------------------------
 // Stand-alone factor-and-solve of caller-supplied band matrices (exposed for testing the
 // subdomain solver in isolation).
+// caller band entry e (bandwidth bw[j], rows of bw[j] + 1 entries) into the set's storage
+// (bandwidth sB[j], offsets soff[j]), which is zero beforehand
 __global__ void k_band_import(int64_t total, const double* src, const double* dscale,
                               const int64_t* off, const int64_t* nn, const int64_t* bw,
-                              const int64_t* doff, int n_mat, float* d32, double* d64) {
+                              const int64_t* doff, int n_mat, const int64_t* soff,
+                              const int64_t* sB, float* d32, double* d64) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
   int j = 0;
   while (j + 1 < n_mat && off[j + 1] <= e) ++j;
   const int64_t B = bw[j], r = (e - off[j]) / (B + 1), c = r + (e - off[j]) % (B + 1) - B;
+  if (c < 0) return;                               // left of the first column: none
   double v = src[e];
-  if (dscale) v *= (c >= 0) ? dscale[doff[j] + r] * dscale[doff[j] + c] : 0.0;
-  if (d32) d32[e] = (float)v;
-  else d64[e] = v;
+  if (dscale) v *= dscale[doff[j] + r] * dscale[doff[j] + c];
+  const int64_t d = soff[j] + r * (sB[j] + 1) + (c - r + sB[j]);
+  if (d32) d32[d] = (float)v;
+  else d64[d] = v;
 }
 
 __global__ void k_band_diag(int64_t rows, const double* src, const int64_t* off,
@@ -1801,19 +1833,25 @@ extern "C" gx_status gx_band_factor_solve(gx_ctx* c, int32_t n_mat, const int64_
   BandSet bs;
   band_layout(bs, nv, bv, fp32, s);
   bs.force_groups[0] = bs.force_groups[1] = groups;
-  DevBuf<int64_t> d_off(n_mat + 1), d_doff(n_mat + 1), d_xoff(n_mat);
+  if (fp32)
+    zero(bs.v32, s);
+  else
+    zero(bs.v64, s);
+  DevBuf<int64_t> d_off(n_mat + 1), d_doff(n_mat + 1), d_xoff(n_mat), d_bw(n_mat);
   to_dev(d_off.p, off.data(), n_mat + 1, s);
+  to_dev(d_bw.p, bv.data(), n_mat, s);
   to_dev(d_doff.p, doff.data(), n_mat + 1, s);
   to_dev(d_xoff.p, xoff.data(), n_mat, s);
   DevBuf<double> dsc;
   if (fp32) {
     dsc.alloc(doff[n_mat]);
     hipLaunchKernelGGL(k_band_diag, dim3(nblocks(doff[n_mat], 256)), dim3(256), 0, s,
-                       doff[n_mat], band, d_off.p, bs.d_n.p, bs.d_B.p, d_doff.p, n_mat, dsc.p);
+                       doff[n_mat], band, d_off.p, bs.d_n.p, d_bw.p, d_doff.p, n_mat, dsc.p);
   }
   hipLaunchKernelGGL(k_band_import, dim3(nblocks(off[n_mat], 256)), dim3(256), 0, s,
-                     off[n_mat], band, fp32 ? dsc.p : nullptr, d_off.p, bs.d_n.p, bs.d_B.p,
-                     d_doff.p, n_mat, fp32 ? bs.v32.p : nullptr, fp32 ? nullptr : bs.v64.p);
+                     off[n_mat], band, fp32 ? dsc.p : nullptr, d_off.p, bs.d_n.p, d_bw.p,
+                     d_doff.p, n_mat, bs.d_off.p, bs.d_B.p, fp32 ? bs.v32.p : nullptr,
+                     fp32 ? nullptr : bs.v64.p);
   GX_HIP(hipGetLastError());
   band_factor(bs, s, "the given band matrices");
   if (fp32)

@@ -893,12 +893,13 @@ __global__ void __launch_bounds__(256) k_coarse_pair(GeneoDev g, CoarseDev cd, i
 }
 
 // symmetrise K_0 into full band storage (B = n0 - 1, ld = n0)
-__global__ void k_coarse_fill(int64_t n0, const double* K0, double* band) {
+__global__ void k_coarse_fill(int64_t n0, const double* K0, int64_t B, int64_t ld,
+                              double* band) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n0 * n0) return;
   const int64_t r = e / n0, c = e % n0;
   if (c > r) return;
-  band[r * n0 + (c - r + n0 - 1)] = 0.5 * (K0[r * n0 + c] + K0[c * n0 + r]);
+  band[r * ld + (c - r + B)] = 0.5 * (K0[r * n0 + c] + K0[c * n0 + r]);
 }
 
 void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
@@ -1265,7 +1266,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
   sw.C.coarse = true;
   zero(sw.C.v64, s);
   hipLaunchKernelGGL(k_coarse_fill, dim3(nblocks(n0 * n0, 256)), dim3(256), 0, s, n0, K0.p,
-                     sw.C.v64.p);
+                     sw.C.B[0], sw.C.ld[0], sw.C.v64.p);
   GX_HIP(hipGetLastError());
   band_factor(sw.C, s, "the coarse matrix K0 (near-dependent coarse vectors?)");
   const int64_t zero64 = 0;

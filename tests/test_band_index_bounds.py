@@ -70,7 +70,9 @@ def _single_rhs(n, B, G, bd):
         ifirst = i0 + RPW * w
         rc = np.minimum(ifirst + r, n - 1)
         rowbase = rc * ld - rc + B                         # rp[r] = base + rc ld - rc + B
-        start = np.maximum(ifirst - B, 0) + lane
+        # the band (envelope) start, rounded down to a 128-byte line of FP64 (16) or FP32
+        # (32) entries: the first one is the lower bound
+        start = np.maximum(ifirst - B, 0) // 32 * 32 + lane
         run = start < done_end + lane                      # the c0 loop runs at all
         last = start + 64 * U * ((done_end + lane - 1 - start) // (64 * U))
         shape = np.broadcast_shapes(rowbase.shape, run.shape)
