@@ -805,22 +805,50 @@ __device__ __forceinline__ void band_solve_1_mat(int64_t n, int64_t B, int64_t l
     // envelope start, rounded down to a 128-byte line (rows start on one: see band_layout)
     constexpr int64_t LA = 128 / sizeof(T);
     const int64_t cstart = max(max<int64_t>(ifirst - B, 0), fcb[k]) / LA * LA;
-    for (int64_t c0 = cstart + lane; c0 < done_end + lane; c0 += 64 * U) {
-      T l[U][RPW];
-      double xv[U];
+    if constexpr (sizeof(T) == 4) {
+      // FP32 factors: a lane takes two adjacent columns (one 8-byte load per row; columns
+      // from a line start are even, so the pair is aligned), 128 columns per step
+      constexpr int U2 = U / 2;
+      for (int64_t c0 = cstart + 2 * lane; c0 < done_end + 2 * lane; c0 += 128 * U2) {
+        float2 l[U2][RPW];
+        double xa[U2], xb[U2];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        xv[u] = poll_load(y + min<int64_t>(c0 + 64 * u, done_end - 1));
+        for (int u = 0; u < U2; ++u) {
+          const int64_t cc = c0 + 128 * u;
+          xa[u] = poll_load(y + min<int64_t>(cc, done_end - 1));
+          xb[u] = poll_load(y + min<int64_t>(cc + 1, done_end - 1));
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) l[u][r] = rp[r][c0 + 64 * u];
+          for (int r = 0; r < RPW; ++r) l[u][r] = *reinterpret_cast<const float2*>(rp[r] + cc);
+        }
+#pragma unroll
+        for (int u = 0; u < U2; ++u) {
+          const int64_t cc = c0 + 128 * u;
+          const double x0 = cc < done_end ? xa[u] : 0.0, x1 = cc + 1 < done_end ? xb[u] : 0.0;
+#pragma unroll
+          for (int r = 0; r < RPW; ++r) {
+            s[r] += (double)l[u][r].x * (cc >= ifirst + r - B ? x0 : 0.0);
+            s[r] += (double)l[u][r].y * (cc + 1 >= ifirst + r - B ? x1 : 0.0);
+          }
+        }
       }
+    } else {
+      for (int64_t c0 = cstart + lane; c0 < done_end + lane; c0 += 64 * U) {
+        T l[U][RPW];
+        double xv[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t cc = c0 + 64 * u;
-        const double xu = cc < done_end ? xv[u] : 0.0;
+        for (int u = 0; u < U; ++u) {
+          xv[u] = poll_load(y + min<int64_t>(c0 + 64 * u, done_end - 1));
 #pragma unroll
-        for (int r = 0; r < RPW; ++r)
-          s[r] += (double)l[u][r] * (cc >= ifirst + r - B ? xu : 0.0);
+          for (int r = 0; r < RPW; ++r) l[u][r] = rp[r][c0 + 64 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t cc = c0 + 64 * u;
+          const double xu = cc < done_end ? xv[u] : 0.0;
+#pragma unroll
+          for (int r = 0; r < RPW; ++r)
+            s[r] += (double)l[u][r] * (cc >= ifirst + r - B ? xu : 0.0);
+        }
       }
     }
     // blocks in flight, kdone .. k - 1 (at most GMAX - 1): their factor entries and this
@@ -894,20 +922,49 @@ __device__ __forceinline__ void band_solve_1_mat(int64_t n, int64_t B, int64_t l
     const int64_t done_beg = min<int64_t>(rend, kdone * SB);
     const int64_t cidx = i0 + lane;
     double sacc = 0.0;
-    for (int64_t r0 = done_beg + wave; r0 < rend; r0 += SW * UB) {
-      // lane u < UB loads the solution of row r0 + 8 u, handed to all lanes by a lane read
-      T l[UB];
-      const double xz = poll_load(z + min<int64_t>(r0 + SW * (lane % UB), rend - 1));
+    if constexpr (sizeof(T) == 4) {
+      // FP32 factors: lane l takes the column pair 2 (l mod 32), +1 (one aligned 8-byte
+      // load) of the rows r0 + 8 (2 v + l / 32), so one load covers two rows; the halves'
+      // sums are then added and handed to the lanes of their columns
+      const int pr = lane & 31, hf = lane >> 5;
+      const int64_t c2 = i0 + 2 * pr;
+      double s0 = 0.0, s1 = 0.0;
+      for (int64_t r0 = done_beg + wave; r0 < rend; r0 += SW * UB) {
+        float2 l[UB / 2];
+        const double xz = poll_load(z + min<int64_t>(r0 + SW * (lane % UB), rend - 1));
 #pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        const int64_t rr = min<int64_t>(r0 + SW * u, rend - 1);
-        l[u] = cb[rr * rs + cidx];
+        for (int v = 0; v < UB / 2; ++v) {
+          const int64_t rr = min<int64_t>(r0 + SW * (2 * v + hf), rend - 1);
+          l[v] = *reinterpret_cast<const float2*>(cb + rr * rs + c2);
+        }
+#pragma unroll
+        for (int v = 0; v < UB / 2; ++v) {
+          const int64_t rr = r0 + SW * (2 * v + hf);
+          const double xu = __shfl(xz, 2 * v + hf);
+          s0 += (double)l[v].x * ((rr < rend && rr - B <= c2) ? xu : 0.0);
+          s1 += (double)l[v].y * ((rr < rend && rr - B <= c2 + 1) ? xu : 0.0);
+        }
       }
+      s0 += __shfl_xor(s0, 32);
+      s1 += __shfl_xor(s1, 32);
+      const double v0 = __shfl(s0, lane >> 1), v1 = __shfl(s1, lane >> 1);
+      sacc = (lane & 1) ? v1 : v0;
+    } else {
+      for (int64_t r0 = done_beg + wave; r0 < rend; r0 += SW * UB) {
+        // lane u < UB loads the solution of row r0 + 8 u, handed to all lanes by a lane read
+        T l[UB];
+        const double xz = poll_load(z + min<int64_t>(r0 + SW * (lane % UB), rend - 1));
 #pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        const int64_t rr = r0 + SW * u;
-        const double xu = __shfl(xz, u);
-        sacc += (double)l[u] * ((rr < rend && rr - B <= cidx) ? xu : 0.0);
+        for (int u = 0; u < UB; ++u) {
+          const int64_t rr = min<int64_t>(r0 + SW * u, rend - 1);
+          l[u] = cb[rr * rs + cidx];
+        }
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+          const int64_t rr = r0 + SW * u;
+          const double xu = __shfl(xz, u);
+          sacc += (double)l[u] * ((rr < rend && rr - B <= cidx) ? xu : 0.0);
+        }
       }
     }
     // row blocks in flight, kb + 1 .. kin (at most GMAX - 1): factor entries and the

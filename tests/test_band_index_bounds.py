@@ -82,6 +82,17 @@ def _single_rhs(n, B, G, bd):
                 bd.check(np.broadcast_to(rowbase + c0 + 64 * u, shape)[runf], "forward band")
                 yi = np.broadcast_to(np.minimum(c0 + 64 * u, done_end - 1), run.shape)[run]
                 assert yi.size == 0 or (yi.min() >= 0 and yi.max() < nblk * SB)
+        # FP32 factors: lane l takes columns c0 + 2 l and c0 + 2 l + 1, 128 per step
+        start2 = np.maximum(ifirst - B, 0) // 32 * 32 + 2 * lane
+        run2 = start2 < done_end + 2 * lane
+        last2 = start2 + 128 * (U // 2) * ((done_end + 2 * lane - 1 - start2) // (128 * (U // 2)))
+        shape2 = np.broadcast_shapes(rowbase.shape, run2.shape)
+        runf2 = np.broadcast_to(run2, shape2)
+        for c0 in (start2, last2):
+            for u in range(U // 2):
+                for e in (0, 1):
+                    bd.check(np.broadcast_to(rowbase + c0 + 128 * u + e, shape2)[runf2],
+                             "forward band (FP32 pairs)")
         for o in range(GMAX - 1):                          # factor entries of blocks in flight
             cc = min(kdone + o, max(k - 1, 0)) * SB + lane
             bd.check(rowbase + cc, "forward in-flight")
