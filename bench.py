@@ -137,6 +137,30 @@ def traffic_probe(gx, torch, workloads, args):
           flush=True)
 
 
+def verification_timing(gx, torch, workloads, args):
+    """The corner-unfolding verification model of section 2.2 (graded mesh, resin edge
+    strips, stiff end layer, end moment; --e1-sub squared subdomains, overlap 1) timed end to end:
+    `warmup` untimed steps, then `steps` timed ones in the chosen precision."""
+    cfg = workloads.verification_model(px=args.e1_sub, py=args.e1_sub)
+    prec = gx.GX_MIXED if args.precision == "mixed" else gx.GX_FP64
+    ms, s, out, n0 = timed_steps(gx, torch, cfg, prec, args.steps, args.warmup,
+                                 "verification " + args.precision)
+    nf = n_free(s)
+    line = {"metric": "verification model: solve time per 1M DOFs at rtol 1e-8",
+            "value": (ms / 1e3) / (nf / 1e6), "unit": "s/MDOF", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": False, "data": "synthetic", "dtype": args.precision,
+            "config": {"workload": cfg["name"] + " L-section R 6.6 mm, 3 mm limbs, W 15 mm, "
+                                   "12 plies, graded 400 / 10, 2 mm resin strips, stiff end "
+                                   f"layer, {args.e1_sub}x{args.e1_sub} subdomains, "
+                                   "overlap 1, tau 0.1",
+                       "n_dofs": int(3 * s.mesh["n_nodes"]), "n_free_dofs": nf},
+            "cg_iters": out["iters"], "relres": out["relres"], "n0": int(n0),
+            "phases_ms": s.phase_times(), "stats": s.stats()}
+    s.close()
+    print(json.dumps(line), flush=True)
+
+
 def solution_diff(x, x_ref):
     import torch
     return float(torch.linalg.vector_norm(x - x_ref) / torch.linalg.vector_norm(x_ref))
@@ -201,6 +225,11 @@ def main():
                     help="with --batch: set-ups run at a time")
     ap.add_argument("--hw-queues", type=int, default=HW_QUEUES_SWEEP,
                     help="with --batch: HIP hardware queues of the process (1 to 32)")
+    ap.add_argument("--e1", action="store_true",
+                    help="instead: the verification model of section 2.2 (432,768 elements, "
+                         "5.36M DOFs) as a timing workload, in --precision")
+    ap.add_argument("--e1-sub", type=int, default=8,
+                    help="with --e1: subdomains per direction (8: 64 subdomains)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="instead: set up the workload, then launch one plain copy of "
                          "COPY_BYTES and one subdomain band solve (for hardware counters)")
@@ -217,6 +246,8 @@ def main():
         return batch_sweep(gx, torch, workloads, args)
     if args.traffic_probe:
         return traffic_probe(gx, torch, workloads, args)
+    if args.e1:
+        return verification_timing(gx, torch, workloads, args)
 
     cfg = workloads.cfg1(nx=24, ny=24, px=3, py=3) if args.small else workloads.cfg1()
     ms_step, s, out, n0 = timed_steps(gx, torch, cfg, gx.GX_FP64, args.steps, args.warmup,
