@@ -8,10 +8,10 @@
 //
 // Storage of matrix j: entry (r, c), r - B_j <= c <= r, at off_j + r * ld_j + (c - r + B_j).
 //
-// Factorisation: right-looking, block columns of NB; per step one kernel factors the
-// diagonal block in LDS (and keeps its inverse for the solves), one solves the panel rows,
-// one updates the trailing window with 64x64 tiles.  Matrices of different size and
-// bandwidth run in the same launches.
+// Factorisation: right-looking, block columns of NB taken GP at a time; one launch per
+// group factors its panels (diagonal blocks, their inverses, kept for the solves, and the
+// panel rows), and the trailing window is updated with 128x128 tiles.  Matrices of
+// different size and bandwidth run in the same launches.
 //
 // Solves: see the comment above the solve kernels.
 #include <algorithm>
@@ -93,10 +93,13 @@ __device__ inline void chain_signal(int* f, int epoch) {
 }
 
 // Bounded poll of a flag (thread 0); a poll that gives up raises bit 2 of the error word,
-// so every wave still reaches the end of the kernel.
+// and polls stop early once that bit is up, so every wave still reaches the end of the
+// kernel.
 __device__ inline void chain_wait(const int* f, int epoch, int* err) {
   for (int64_t k = 0; k < SPIN_LIMIT; ++k) {
     if (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch) return;
+    if ((k & 255) == 255 && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2))
+      return;
     __builtin_amdgcn_s_sleep(1);
   }
   atomicOr(err, 2);
@@ -118,22 +121,24 @@ struct Chunk<float> {
 // block.  Work-groups are numbered: panel 0's diagonal blocks (all matrices), then panel by
 // panel and matrix by matrix the blocks t >= 1, with the next panel's diagonal block right
 // after block t = 1 (the last one it needs), so that the next factorisation runs while
-// the rest of the panel is dispatched.  Every wait is for a lower number, so the in-order
-// dispatch of work-groups rules out deadlock.
+// the rest of the panel is dispatched.  A work-group takes its number from a counter of the
+// launch when it starts, not from its position in the grid, so every wait is for a
+// work-group that is already running: the launch cannot deadlock, whatever order the
+// hardware dispatches its work-groups in and whatever else occupies the device.
 //   1. The block is brought up to date by this group's earlier panels (the earlier groups'
 //      updates are done before the launch): A -= L[rows][K] L[panel rows][K]^T, after
 //      waiting for the work-groups that produced them, with the matrix instruction in the
 //      factor's precision.
-//   2. t = 0: Cholesky of the 64x64 block by one wave (lane r holds row r in registers;
-//      step i broadcasts column i through LDS), then the inverse of the factor; the inverse
-//      is handed to the panel's other work-groups and kept for the triangular solves.
+//   2. t = 0: Cholesky of the 64x64 block and the inverse of its factor by one wave, in
+//      16-column blocks (step 2a below); the inverse is handed to the panel's other
+//      work-groups and kept for the triangular solves.
 //      t > 0: waits for the inverse and forms L[rows][panel] = A Li^T (FP64 instruction).
 //   3. The flag of (p, j, t) is raised.
 // A non-positive pivot raises bit 1 of the error word and is replaced by 1.
 template <class T>
 __global__ void __launch_bounds__(CT) k_chain(BandArgs a, T* v, int64_t k0, int NR, int n_mat,
-                                              int* flags, int epoch, double* inv, T* dinv,
-                                              const int64_t* boff, int* err) {
+                                              int* flags, int* ticket, int epoch, double* inv,
+                                              T* dinv, const int64_t* boff, int* err) {
   typedef Mfma<T> MT;
   typedef typename MT::S S;
   constexpr int KC = Chunk<S>::KC, KS = Chunk<S>::KS;
@@ -148,7 +153,10 @@ __global__ void __launch_bounds__(CT) k_chain(BandArgs a, T* v, int64_t k0, int 
   S* Ps = reinterpret_cast<S*>(&Li[0][0]);
   int p, j, t;
   {
-    int b = blockIdx.x;
+    __shared__ int tk;
+    if (threadIdx.x == 0) tk = atomicAdd(ticket, 1);
+    __syncthreads();
+    int b = tk;
     if (b < n_mat || NR == 1) {                  // panel 0's diagonal blocks
       p = b / n_mat;
       j = b - p * n_mat;
@@ -581,8 +589,10 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job) {
   const int NR = (int)((bs.max_B + NB - 1) / NB) + 1;   // row blocks of a panel
   const int NRT = NR + GP - 1;                           // row blocks of a group
   job.inv.alloc((size_t)bs.n_mat * GP * NB * NB);
-  job.flags.alloc((size_t)bs.n_mat * GP * NRT);
+  const int64_t n_groups = (bs.max_n + GP * NB - 1) / (GP * NB);
+  job.flags.alloc((size_t)bs.n_mat * GP * NRT + n_groups);   // then one ticket counter per launch
   zero(job.flags, st);
+  int* tickets = job.flags.p + (int64_t)bs.n_mat * GP * NRT;
   const int64_t nt2 = (bs.max_B + T2 - 1) / T2;
   const int64_t per_rest = wide_tiles(bs.max_B, 2, nt2), tot_rest = per_rest * bs.n_mat;
   const int64_t per_next = wide_tiles(bs.max_B, 0, 2), tot_next = per_next * bs.n_mat;
@@ -604,7 +614,8 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job) {
                          k0 - GP * NB, (int64_t)GP * NB, (int64_t)0, (int64_t)2, per_next,
                          tot_next);
     hipLaunchKernelGGL(k_chain<T>, dim3(chain_blocks), dim3(CT), 0, st, a, v, k0, NR,
-                       bs.n_mat, job.flags.p, g + 1, job.inv.p, dinv, bs.d_boff.p, job.err.p);
+                       bs.n_mat, job.flags.p, tickets + g, g + 1, job.inv.p, dinv, bs.d_boff.p,
+                       job.err.p);
     if (tot_rest && k0 + GP * NB < bs.max_n) {
       GX_HIP(hipEventRecord(job.chain, st));
       GX_HIP(hipStreamWaitEvent(job.la, job.chain, 0));

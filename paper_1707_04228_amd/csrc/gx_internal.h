@@ -391,7 +391,8 @@ struct FactorJob {
   std::string what;
   DevBuf<int> err;
   DevBuf<double> inv;                          // inverse diagonal blocks handed over
-  DevBuf<int> flags;                           // per panel block: epoch of its completion
+  DevBuf<int> flags;                           // per panel block: epoch of its completion;
+                                               // then per launch: the work-group counter
   hipStream_t la = nullptr;                    // trailing-update stream (default priority)
   hipEvent_t chain = nullptr, rest[2] = {nullptr, nullptr};
   FactorJob() = default;

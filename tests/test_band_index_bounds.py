@@ -14,6 +14,9 @@ rows, half-bandwidth about 1900).  Every address must lie inside the matrix's st
 
 (A load index one past these bounds faulted the GPU once, in the block-0 prefetch of the
 many-right-hand-side solve; its indices are clamped since and this test pins them.)
+
+The last test restates the factorisation launch's work-group numbering and waits and checks
+that every wait is for a lower number.
 """
 
 import numpy as np
@@ -222,3 +225,60 @@ def test_padding_covers_the_worst_forward_overread():
     bd = Bounds(1000, 63)
     _single_rhs(1000, 63, 1, bd)
     assert 400 < bd.worst <= 511
+
+
+GP = 4             # panels per factorisation launch
+
+
+def _chain_item(b, n_mat, NR):
+    """The (panel p, matrix j, row block t) that k_chain's work-group number b works on."""
+    if b < n_mat or NR == 1:
+        return b // n_mat, b % n_mat, 0
+    b -= n_mat
+    for p in range(GP):
+        m = NR - 1 + (p + 1 < GP)
+        if b < n_mat * m:
+            break
+        b -= n_mat * m
+    m = NR - 1 + (p + 1 < GP)
+    j, o = divmod(b, m)
+    if o == 0:
+        return p, j, 1
+    if p + 1 < GP and o == 1:
+        return p + 1, j, 0
+    return p, j, (o if p + 1 < GP else o + 1)
+
+
+def _chain_waits(p, j, t, NR):
+    """(panel, matrix, row block counted from the group start) of every flag the
+    work-group waits for (restated from k_chain's steps 1 and 2b)."""
+    tr = p + t
+    w = []
+    if p > 0:
+        for q in range(p):
+            if tr - q < NR:
+                w.append((q, j, tr))
+            if p - q < NR:
+                w.append((q, j, p))
+    if t > 0:
+        w.append((p, j, p))
+    return w
+
+
+@pytest.mark.parametrize("n_mat,NR", [(1, 1), (1, 2), (3, 2), (2, 5), (16, 31), (64, 31),
+                                      (64, 39)])
+def test_factorisation_waits_are_for_earlier_numbers(n_mat, NR):
+    """k_chain: the numbering covers every (panel, matrix, row block) once, every flag
+    waited for is raised by exactly one work-group, and that work-group has a lower number.
+    Work-groups take their numbers in the order they start, so the lowest-numbered
+    unfinished one never waits: the launch always drains."""
+    total = GP * n_mat * NR
+    items = [_chain_item(b, n_mat, NR) for b in range(total)]
+    assert sorted(items) == sorted((p, j, t) for p in range(GP) for j in range(n_mat)
+                                   for t in range(NR))
+    raised = {(p, j, p + t): b for b, (p, j, t) in enumerate(items)}
+    assert len(raised) == total
+    for b, (p, j, t) in enumerate(items):
+        for f in _chain_waits(p, j, t, NR):
+            assert f in raised, (b, f)
+            assert raised[f] < b, (b, (p, j, t), f, raised[f])
