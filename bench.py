@@ -44,7 +44,7 @@ FP64_PEAK_TFLOPS = 78.6
 # the FETCH_SIZE / WRITE_SIZE counters of `bench.py --traffic-probe [--precision mixed]`
 # scaled by a 4 GiB copy.  Valid for the solve kernel as it stands: retake the counters
 # when it changes.
-SOLVE_TRAFFIC_BYTES = {"fp64": 148.5e9, "mixed": 77.2e9}
+SOLVE_TRAFFIC_BYTES = {"fp64": 135.4e9, "mixed": 67.3e9}
 
 
 def run_step(gx, torch, cfg, precision):
@@ -324,6 +324,7 @@ def main():
     extra = min(args.mixed_steps, args.steps)
     if not args.no_mixed:
         line["mixed"] = precision_block(gx, torch, cfg, extra, 1, x_fp64, ms_step, "mixed")
+        line["mixed"]["subdomain_solve_traffic"] = SOLVE_TRAFFIC_BYTES["mixed"]
     if not args.no_target:
         tcfg = workloads.cfg2()
         t64, s2, o2, n02 = timed_steps(gx, torch, tcfg, gx.GX_FP64, extra, 1, "target fp64")
