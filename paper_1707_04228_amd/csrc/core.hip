@@ -33,6 +33,7 @@ struct CachedBlock {
   hipStream_t st;                                // the stream its last kernels ran on
   hipEvent_t ev;                                 // recorded on st at release
   bool idle;
+  uint64_t seq;                                  // release order (large blocks: eviction)
 };
 
 // The stream a context's work on this thread goes to (null outside any context).
@@ -41,6 +42,7 @@ hipStream_t cur_stream(const gx_ctx* me) { return tls_stream ? tls_stream : me ?
 std::mutex cache_mu;
 std::vector<CachedBlock> cache_blocks;
 std::vector<size_t> cache_bytes, cache_cap, small_bytes;   // per device
+uint64_t release_seq = 0;
 
 void ensure_dev(int dev) {                         // caller holds cache_mu
   if ((int)cache_bytes.size() <= dev) {
@@ -50,7 +52,7 @@ void ensure_dev(int dev) {                         // caller holds cache_mu
   }
   if (!cache_cap[dev]) {
     size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) == hipSuccess) cache_cap[dev] = tot / 2;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) cache_cap[dev] = tot / 4 * 3;
   }
 }
 
@@ -146,10 +148,28 @@ void dev_free(void* p, size_t bytes, int dev) {
     std::lock_guard<std::mutex> lk(cache_mu);
     ensure_dev(dev);
     const bool large = bytes >= CACHE_MIN;
+    if (large && cache_bytes[dev] + bytes > cache_cap[dev] && bytes <= cache_cap[dev]) {
+      // the latest release is the likeliest to be asked for again (the next solve of the
+      // same problem): make room by freeing the large blocks released longest ago
+      (void)hipDeviceSynchronize();
+      while (cache_bytes[dev] + bytes > cache_cap[dev]) {
+        int old = -1;
+        for (int i = 0; i < (int)cache_blocks.size(); ++i) {
+          const CachedBlock& c = cache_blocks[i];
+          if (c.dev == dev && c.bytes >= CACHE_MIN &&
+              (old < 0 || c.seq < cache_blocks[old].seq))
+            old = i;
+        }
+        if (old < 0) break;
+        if (cache_blocks[old].ev) (void)hipEventDestroy(cache_blocks[old].ev);
+        (void)hipFree(cache_blocks[old].p);
+        drop_block(old);
+      }
+    }
     const bool room = large ? cache_bytes[dev] + bytes <= cache_cap[dev]
                             : (me || tls_idle) && small_bytes[dev] + bytes <= SMALL_CAP;
     if (room) {
-      CachedBlock c{dev, bytes, p, nullptr, nullptr, nullptr, tls_idle};
+      CachedBlock c{dev, bytes, p, nullptr, nullptr, nullptr, tls_idle, ++release_seq};
       if (!tls_idle && me) {
         // tag with the owner's stream position; without an event the block stays untagged
         hipEvent_t ev = nullptr;

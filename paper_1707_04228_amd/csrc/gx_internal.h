@@ -57,9 +57,11 @@ inline bool poison_alloc() {
 // stream's work up to the release, not the whole device).  Blocks released on an
 // idle device (IdleScope, a destroyed context) need no wait; blocks released outside any
 // context are reused after a device synchronisation.  Blocks of 64 MiB and more are cached
-// up to half the device's memory, smaller tagged or idle blocks up to 1 GiB per device.  A
-// failed hipMalloc empties the cache of that device and retries.  dev_forget(ctx) marks a
-// context's blocks idle (its stream must have been synchronised).
+// up to three quarters of the device's memory (a large block released with no room left
+// frees the large blocks released longest ago, after a device synchronisation), smaller
+// tagged or idle blocks up to 1 GiB per device.  A failed hipMalloc empties the cache of
+// that device and retries.  dev_forget(ctx) marks a context's blocks idle (its stream
+// must have been synchronised).
 void* dev_alloc(size_t bytes, int* dev, hipError_t* err);
 void dev_free(void* p, size_t bytes, int dev);
 void dev_forget(const gx_ctx* c);
