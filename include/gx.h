@@ -249,7 +249,7 @@ typedef struct {
   const int32_t* nev_per_sub;/* optional host [n_sub]: modes per subdomain (overrides) */
   double eig_tol;            /* eigenpair backward-error target ||M x - theta B x|| <=
                                 eig_tol S ||x||, S = max over the block of ||M x|| / ||x||
-                                (0: default 1e-6) */
+                                (0: default 1e-4) */
   int32_t eig_maxit;         /* eigensolver iteration cap (0: default 1000) */
 } gx_geneo_opts;
 
