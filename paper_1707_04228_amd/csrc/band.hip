@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(CT) k_chain(BandArgs a, T* v, int64_t k0, int 
   constexpr int PER = NB / RP;                   // staged entries per thread and operand
   __shared__ double D[NB][NB + 1];               // the block; the factor (t = 0)
   __shared__ double Li[NB][NB + 1];              // the inverse of the diagonal block
-  __shared__ double Wd[GP][16][17];              // inverses of the 16x16 diagonal blocks
+  __shared__ double Wd[NB / 16][16][17];         // inverses of the 16x16 diagonal blocks
   __shared__ double Tt[16][17];                  // one tile of the inverse's assembly
   static_assert(NB * KS * sizeof(S) <= sizeof(D), "staging fits in the block buffers");
   S* Pr = reinterpret_cast<S*>(&D[0][0]);        // staging of step 1 (aliases D and Li)
@@ -582,7 +582,8 @@ static int64_t wide_tiles(int64_t max_B, int64_t lo, int64_t hi) {
 template <class T>
 void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job) {
   BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p, bs.d_eoff.p, bs.d_fcb.p, bs.d_lrb.p};
-  static_assert(GP * NB == 2 * T2, "the rest update starts two wide tile columns on");
+  static_assert(GP * NB % T2 == 0, "a group spans whole wide tile columns");
+  constexpr int64_t NEXT_TS = GP * NB / T2;              // tile columns of the next group
   for (int j = 0; j < bs.n_mat; ++j)
     GX_REQUIRE((bs.n[j] + T2) * bs.ld[j] + 64 < ((int64_t)1 << 31),
                "a band matrix of 2^31 entries or more exceeds the update's 32-bit offsets");
@@ -594,8 +595,8 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job) {
   zero(job.flags, st);
   int* tickets = job.flags.p + (int64_t)bs.n_mat * GP * NRT;
   const int64_t nt2 = (bs.max_B + T2 - 1) / T2;
-  const int64_t per_rest = wide_tiles(bs.max_B, 2, nt2), tot_rest = per_rest * bs.n_mat;
-  const int64_t per_next = wide_tiles(bs.max_B, 0, 2), tot_next = per_next * bs.n_mat;
+  const int64_t per_rest = wide_tiles(bs.max_B, NEXT_TS, nt2), tot_rest = per_rest * bs.n_mat;
+  const int64_t per_next = wide_tiles(bs.max_B, 0, NEXT_TS), tot_next = per_next * bs.n_mat;
   const unsigned chain_blocks = (unsigned)((int64_t)GP * bs.n_mat * NR);
   // group g on st: the update of its columns by group g - 1 (after the update of the same
   // columns by group g - 2, which ran on the second stream), then its k_chain; then the
@@ -611,7 +612,7 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job) {
     if (recorded[g % 2]) GX_HIP(hipStreamWaitEvent(st, job.rest[g % 2], 0));
     if (g > 0 && bs.max_B > 0)
       hipLaunchKernelGGL(k_syrk_wide<T>, dim3((unsigned)tot_next), dim3(U2), 0, st, a, v,
-                         k0 - GP * NB, (int64_t)GP * NB, (int64_t)0, (int64_t)2, per_next,
+                         k0 - GP * NB, (int64_t)GP * NB, (int64_t)0, NEXT_TS, per_next,
                          tot_next);
     hipLaunchKernelGGL(k_chain<T>, dim3(chain_blocks), dim3(CT), 0, st, a, v, k0, NR,
                        bs.n_mat, job.flags.p, tickets + g, g + 1, job.inv.p, dinv, bs.d_boff.p,
@@ -620,7 +621,7 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job) {
       GX_HIP(hipEventRecord(job.chain, st));
       GX_HIP(hipStreamWaitEvent(job.la, job.chain, 0));
       hipLaunchKernelGGL(k_syrk_wide<T>, dim3((unsigned)tot_rest), dim3(U2), 0, job.la, a, v,
-                         k0, (int64_t)GP * NB, (int64_t)2, nt2, per_rest, tot_rest);
+                         k0, (int64_t)GP * NB, NEXT_TS, nt2, per_rest, tot_rest);
       GX_HIP(hipEventRecord(job.rest[g % 2], job.la));
       recorded[g % 2] = true;
     }
