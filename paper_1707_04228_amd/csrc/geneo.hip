@@ -902,7 +902,7 @@ __global__ void k_coarse_fill(int64_t n0, const double* K0, int64_t B, int64_t l
   band[r * ld + (c - r + B)] = 0.5 * (K0[r * n0 + c] + K0[c * n0 + r]);
 }
 
-void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
+void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o, const std::function<void()>& after_factor) {
   Schwarz& sw = c->sw;
   hipStream_t s = c->stream;
   const int n_sub = sw.n_sub;
@@ -996,6 +996,7 @@ void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o) {
       band_factor(Mb, s, "the shifted Neumann matrices (GenEO eigensolver)");
     }
   }
+  if (after_factor) after_factor();
   const bool m32 = Mb.fp32;
   // B as stored node block rows (see k_b_fill)
   int64_t sumD = 0;
@@ -1321,18 +1322,20 @@ gx_status gx_geneo_setup(gx_ctx* c, const gx_geneo_opts* o, int32_t* nev_out,
   if (c->sw.two_level) {
     // The interior factorisation shares nothing with the eigensolves: it runs on a side
     // stream while they run on the context's stream (the two sets of factors are then
-    // resident together).  The side stream is declared first, so the job (which waits for
+    // resident together).  It starts once the eigensolver's factorisation is done, so that
+    // it runs beside the eigensolver's iterations (bound by memory traffic), not beside the
+    // other factorisation.  The side stream is declared first, so the job (which waits for
     // its streams when it goes) is destroyed before it.
     SideStream side;
     InteriorJob job;
     EventPair ev;
-    {
+    auto start_interior = [&]() {
       StreamScope scope(side.st);
       GX_HIP(hipEventRecord(ev.a, side.st));
       interior_factors_start(c, o->precision, side.st, job);
       GX_HIP(hipEventRecord(ev.b, side.st));
-    }
-    geneo_coarse(c, o);
+    };
+    geneo_coarse(c, o, start_interior);
     interior_factors_finish(c, job);
     c->phase_ms[2] = ev.ms();
   } else {

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -369,7 +370,9 @@ void geneo_setup(gx_ctx* c, const gx_geneo_opts* o, int32_t* nev_out, int64_t* n
 void precond_apply(gx_ctx* c, const double* r, double* z);
 void dd_build(gx_ctx* c, const int32_t* part, int n_sub, int overlap);
 void interior_factors(gx_ctx* c, int precision);
-void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o);
+// after_factor (if set) runs once the eigensolver's shifted Neumann matrices are factored
+void geneo_coarse(gx_ctx* c, const gx_geneo_opts* o,
+                  const std::function<void()>& after_factor = nullptr);
 // half bandwidths (DOFs) of K restricted to each list; env_out (optional): the envelope
 // entries of each restricted matrix's lower triangle, diagonal included
 std::vector<int64_t> list_bandwidth(gx_ctx* c, const int32_t* list, const int64_t* d_off,
