@@ -64,8 +64,9 @@ struct BandArgs {
 };
 
 // ---- Factorisation: right-looking blocked Cholesky in groups of GP panels of NB columns.
-// The columns of a group [k0, k0 + GP NB) are factored by one launch (k_chain below).  The
-// update of the trailing window by the group's panels is split in two k_syrk_wide
+// The columns of a group [k0, k0 + GP NB) are factored by two launches: k_chain for the
+// group's own rows, k_far for the rows below them.  The update of the trailing window by
+// the group's panels is split in two k_syrk_wide
 // launches: the next group's columns (then that group's k_chain, on the same stream), and
 // all further columns on a second stream, at the same time.
 constexpr int GP = 4;                             // panels per group
@@ -116,9 +117,10 @@ struct Chunk<float> {
   static constexpr int KC = 64, KS = 68;
 };
 
-// One launch per group.  Work-group (p, j, t) owns the 64 rows [c0 + 64 t, c0 + 64 t + 64)
-// of panel p (columns [c0, c0 + 64), c0 = k0 + 64 p) of matrix j; t = 0 is the diagonal
-// block.  Work-groups are numbered: panel 0's diagonal blocks (all matrices), then panel by
+// One launch per group for the group's own rows.  Work-group (p, j, t) owns the 64 rows
+// [c0 + 64 t, c0 + 64 t + 64) of panel p (columns [c0, c0 + 64), c0 = k0 + 64 p) of matrix
+// j; t = 0 is the diagonal block; blocks below the group (p + t >= GP) are k_far's and only
+// raise their flags.  Work-groups are numbered: panel 0's diagonal blocks (all matrices), then panel by
 // panel and matrix by matrix the blocks t >= 1, with the next panel's diagonal block right
 // after block t = 1 (the last one it needs), so that the next factorisation runs while
 // the rest of the panel is dispatched.  A work-group takes its number from a counter of the
@@ -185,7 +187,8 @@ __global__ void __launch_bounds__(CT) k_chain(BandArgs a, T* v, int64_t k0, int 
   int* fj = flags + (int64_t)j * GP * NRT;       // flag of (q, j, row block b): fj[q NRT + b]
   const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
   const int64_t c0 = k0 + (int64_t)NB * p, r0 = c0 + (int64_t)NB * t;
-  if (c0 >= n || r0 >= n || r0 > c0 + NB - 1 + B) {   // no entries: only the flag
+  // no entries, or rows below the group (k_far's): only the flag
+  if (c0 >= n || r0 >= n || r0 > c0 + NB - 1 + B || tr >= GP) {
     if (threadIdx.x == 0) __hip_atomic_store(fj + p * NRT + tr, epoch, __ATOMIC_RELEASE,
                                              __HIP_MEMORY_SCOPE_AGENT);
     return;
@@ -425,6 +428,152 @@ __global__ void __launch_bounds__(CT) k_chain(BandArgs a, T* v, int64_t k0, int 
   chain_signal(fj + p * NRT + tr, epoch);
 }
 
+// The rows below a group (row blocks GP, GP + 1, .. counted from k0) for all of the
+// group's panels, once k_chain has factored the group's own rows: work-group (j, f) owns
+// the 64 rows [k0 + 64 (GP + f), + 64) of matrix j and takes the panels in turn, each as
+// k_chain's steps 1 and 2 for a block t > 0 - the update by the group's earlier panels
+// (from its own results and the group's rows), then the product with the inverse of the
+// panel's diagonal block.  Everything it reads was written by earlier launches or by
+// itself, so nothing is waited for and plain loads suffice; the products are the same,
+// in the same order, as k_chain's.
+template <class T>
+__global__ void __launch_bounds__(CT, 2) k_far(BandArgs a, T* v, int64_t k0, int NF, int n_mat,
+                                               const double* inv) {
+  typedef Mfma<T> MT;
+  typedef typename MT::S S;
+  constexpr int KC = Chunk<S>::KC, KS = Chunk<S>::KS;
+  constexpr int RP = CT / KC;                    // rows staged per pass
+  constexpr int PER = NB / RP;                   // staged entries per thread and operand
+  __shared__ double D[NB][NB + 1];               // the block
+  __shared__ double Li[NB][NB + 1];              // the inverse of the panel's diagonal block
+  static_assert(NB * KS * sizeof(S) <= sizeof(D), "staging fits in the block buffers");
+  S* Pr = reinterpret_cast<S*>(&D[0][0]);        // staging of the update (aliases D and Li)
+  S* Ps = reinterpret_cast<S*>(&Li[0][0]);
+  const int j = blockIdx.x / NF, f = blockIdx.x % NF;
+  if (j >= n_mat) return;
+  const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
+  const int64_t r0 = k0 + (int64_t)NB * (GP + f);
+  if (r0 >= n) return;
+  T* base = v + a.off[j];
+  const int64_t rs = ld - 1;                     // entry (r, c) at r * rs + B + c
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = 32 * (w & 1), wc = 32 * (w >> 1);
+  const int kc_t = threadIdx.x % KC, i0 = threadIdx.x / KC;
+#pragma unroll 1
+  for (int p = 0; p < GP; ++p) {
+    const int64_t c0 = k0 + (int64_t)NB * p;
+    if (c0 >= n || r0 > c0 + NB - 1 + B) continue;   // no entries in this panel
+    const int nb = (int)min<int64_t>(NB, n - c0);
+    typename MT::V acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) acc[i][jj] = typename MT::V{0, 0, 0, 0};
+    if (p > 0) {
+      const int64_t lo = max(r0 - B, a.fcb[a.eoff[j] + r0 / NB]);
+      const int64_t kstart = lo > k0 ? k0 + (lo - k0) / KC * KC : k0;
+      S xr[PER], xs[PER];
+      const int lim_r = (int)min<int64_t>(n - r0, NB), lim_s = (int)min<int64_t>(n - c0, NB);
+      const int lo_r = (int)(r0 - B - k0), lo_s = (int)(c0 - B - k0), qend = (int)(c0 - k0);
+      const uint32_t or0 = (uint32_t)(min(r0 + i0, n - 1) * rs + B + k0 + kc_t);
+      const uint32_t os0 = (uint32_t)(min(c0 + i0, n - 1) * rs + B + k0 + kc_t);
+      const uint32_t ostep = (uint32_t)(RP * rs);
+      auto fetch = [&](int64_t kc) {
+        const int qq = (int)(kc - k0) + kc_t;
+        const uint32_t kd = (uint32_t)(kc - k0);
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int i = i0 + RP * u;
+          const bool okr = qq < qend && i < lim_r && qq - i >= lo_r;
+          const bool oks = qq < qend && i < lim_s && qq - i >= lo_s;
+          xr[u] = okr ? (S)base[or0 + u * ostep + kd] : (S)0;
+          xs[u] = oks ? (S)base[os0 + u * ostep + kd] : (S)0;
+        }
+      };
+      if (kstart < c0) fetch(kstart);
+      for (int64_t kc = kstart; kc < c0; kc += KC) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          Pr[(i0 + RP * u) * KS + kc_t] = xr[u];
+          Ps[(i0 + RP * u) * KS + kc_t] = xs[u];
+        }
+        __syncthreads();
+        if (kc + KC < c0) fetch(kc + KC);
+#pragma unroll 4
+        for (int k = 0; k < KC; k += 4) {
+          S fa[2], fb[2];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) fa[i] = Pr[(wr + 16 * i + li) * KS + k + lk];
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) fb[jj] = Ps[(wc + 16 * jj + li) * KS + k + lk];
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) acc[i][jj] = MT::mma(fa[i], fb[jj], acc[i][jj]);
+        }
+        __syncthreads();
+      }
+    }
+    // the block's entries, loaded after the update (the registers of a prefetch are
+    // needed by the update's staging)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const int rl = wr + 16 * i + MT::row(q, lk), cl = wc + 16 * jj + li;
+          const int64_t r = r0 + rl, c = c0 + cl;
+          const double av = (r < n && cl < nb && c >= r - B) ? (double)base[r * rs + B + c] : 0.0;
+          D[rl][cl] = av - (double)acc[i][jj][q];
+        }
+    {
+      const double* invj = inv + ((int64_t)j * GP + p) * NB * NB;
+      double lv[NB * NB / CT];                   // all loads issued before any is used
+#pragma unroll
+      for (int u = 0; u < NB * NB / CT; ++u) lv[u] = invj[threadIdx.x + CT * u];
+#pragma unroll
+      for (int u = 0; u < NB * NB / CT; ++u) {
+        const int idx = threadIdx.x + CT * u;
+        Li[idx / NB][idx % NB] = lv[u];
+      }
+    }
+    __syncthreads();
+    v4d x[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) x[i][jj] = v4d{0, 0, 0, 0};
+#pragma unroll 4
+    for (int k = 0; k < NB; k += 4) {
+      double fa[2], fb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) fa[i] = D[wr + 16 * i + li][k + lk];
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) fb[jj] = Li[wc + 16 * jj + li][k + lk];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) x[i][jj] = Mfma<double>::mma(fa[i], fb[jj], x[i][jj]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const int rl = wr + 16 * i + Mfma<double>::row(q, lk), cl = wc + 16 * jj + li;
+          const int64_t r = r0 + rl, c = c0 + cl;
+          if (r < n && cl < nb && c >= r - B) base[r * rs + B + c] = (T)x[i][jj][q];
+        }
+    // this panel's rows are read back by the next panel's update (other threads), and the
+    // LDS buffers are restaged
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+}
+
 // The update of the trailing window by a group's panels, past the next group's columns,
 // in 128 x 128 tiles of its lower triangle.  Eight waves each
 // form a 64 x 32 eighth as 4 x 2 matrix-instruction tiles of 16 x 16, so six fragment reads
@@ -588,7 +737,9 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job) {
     GX_REQUIRE((bs.n[j] + T2) * bs.ld[j] + 64 < ((int64_t)1 << 31),
                "a band matrix of 2^31 entries or more exceeds the update's 32-bit offsets");
   const int NR = (int)((bs.max_B + NB - 1) / NB) + 1;   // row blocks of a panel
-  const int NRT = NR + GP - 1;                           // row blocks of a group
+  // k_chain takes the group's own rows (GP row blocks per panel, those below the group
+  // exit at once), k_far the NF row blocks below the group
+  const int NRC = GP, NRT = NRC + GP - 1, NF = NR - 1;
   job.inv.alloc((size_t)bs.n_mat * GP * NB * NB);
   const int64_t n_groups = (bs.max_n + GP * NB - 1) / (GP * NB);
   job.flags.alloc((size_t)bs.n_mat * GP * NRT + n_groups);   // then one ticket counter per launch
@@ -597,11 +748,12 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job) {
   const int64_t nt2 = (bs.max_B + T2 - 1) / T2;
   const int64_t per_rest = wide_tiles(bs.max_B, NEXT_TS, nt2), tot_rest = per_rest * bs.n_mat;
   const int64_t per_next = wide_tiles(bs.max_B, 0, NEXT_TS), tot_next = per_next * bs.n_mat;
-  const unsigned chain_blocks = (unsigned)((int64_t)GP * bs.n_mat * NR);
+  const unsigned chain_blocks = (unsigned)((int64_t)GP * bs.n_mat * NRC);
+  const unsigned far_blocks = (unsigned)((int64_t)bs.n_mat * NF);
   // group g on st: the update of its columns by group g - 1 (after the update of the same
-  // columns by group g - 2, which ran on the second stream), then its k_chain; then the
-  // update of the columns from group g + 2 on by its panels on the second stream, at the
-  // same time as group g + 1's work on st.
+  // columns by group g - 2, which ran on the second stream), then its k_chain and k_far;
+  // then the update of the columns from group g + 2 on by its panels on the second stream,
+  // at the same time as group g + 1's work on st.
   GX_HIP(hipStreamCreateWithFlags(&job.la, hipStreamNonBlocking));
   GX_HIP(hipEventCreateWithFlags(&job.chain, hipEventDisableTiming));
   GX_HIP(hipEventCreateWithFlags(&job.rest[0], hipEventDisableTiming));
@@ -614,9 +766,12 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job) {
       hipLaunchKernelGGL(k_syrk_wide<T>, dim3((unsigned)tot_next), dim3(U2), 0, st, a, v,
                          k0 - GP * NB, (int64_t)GP * NB, (int64_t)0, NEXT_TS, per_next,
                          tot_next);
-    hipLaunchKernelGGL(k_chain<T>, dim3(chain_blocks), dim3(CT), 0, st, a, v, k0, NR,
+    hipLaunchKernelGGL(k_chain<T>, dim3(chain_blocks), dim3(CT), 0, st, a, v, k0, NRC,
                        bs.n_mat, job.flags.p, tickets + g, g + 1, job.inv.p, dinv, bs.d_boff.p,
                        job.err.p);
+    if (far_blocks)
+      hipLaunchKernelGGL(k_far<T>, dim3(far_blocks), dim3(CT), 0, st, a, v, k0, NF, bs.n_mat,
+                         (const double*)job.inv.p);
     if (tot_rest && k0 + GP * NB < bs.max_n) {
       GX_HIP(hipEventRecord(job.chain, st));
       GX_HIP(hipStreamWaitEvent(job.la, job.chain, 0));
