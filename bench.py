@@ -313,7 +313,7 @@ def main():
                                 "ms_per_launch": eig_ms},
         "spmv_roofline": {"bound": "hbm", "kernel": "k_spmv", "achieved": spmv_gbs,
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": spmv_gbs / HBM_PEAK_GBS},
-        "factor_roofline": {"bound": "mfma", "kernel": "k_chain + k_syrk_wide (subdomain "
+        "factor_roofline": {"bound": "mfma", "kernel": "k_chain + k_far + k_syrk_wide (subdomain "
                                                        "band Cholesky, FP64)",
                             "achieved": fac_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                             "frac": fac_tflops / FP64_PEAK_TFLOPS, "flops": fac_flops,
