@@ -604,9 +604,12 @@ __device__ inline void wide_tile(BandArgs a, T* v, int64_t k0, int64_t kk, int64
   typedef Mfma<T> MT;
   typedef typename MT::S S;
   constexpr int KW = Wide<S>::KW, KS = Wide<S>::KS;
-  constexpr int RP = U2 / KW;                    // rows staged per pass
-  constexpr int PER = T2 / RP;                   // entries per thread and operand
-  __shared__ S Pr[T2][KS], Ps[T2][KS];
+  constexpr int VW = 16 / sizeof(S);             // entries per 16-byte load
+  typedef S SV __attribute__((ext_vector_type(VW)));
+  constexpr int RP = U2 / (KW / VW);             // rows staged per pass
+  constexpr int PER = T2 / RP;                   // 16-byte loads per thread and operand
+  __shared__ __attribute__((aligned(16))) S Pr[T2][KS];
+  __shared__ __attribute__((aligned(16))) S Ps[T2][KS];
   const int j = (int)(lin / per_mat);
   const int64_t tile = lin - (int64_t)j * per_mat;
   const int64_t n = a.n[j], B = a.B[j], ld = a.ld[j];
@@ -624,7 +627,7 @@ __device__ inline void wide_tile(BandArgs a, T* v, int64_t k0, int64_t kk, int64
   T* base = v + a.off[j];
   const int64_t r0 = t0 + tr * T2, s0 = t0 + ts * T2, wend = t0 + W;
   const int64_t rs = ld - 1;                     // entry (r, c) at r * rs + B + c
-  const int kc_t = threadIdx.x % KW, i0 = threadIdx.x / KW;
+  const int kc_t = threadIdx.x % (KW / VW) * VW, i0 = threadIdx.x / (KW / VW);
   // first chunk with an entry inside the envelope of the tile's rows (its two 64-row blocks)
   const int64_t* fcj = a.fcb + a.eoff[j];
   const int64_t b0 = r0 / NB;
@@ -640,20 +643,23 @@ __device__ inline void wide_tile(BandArgs a, T* v, int64_t k0, int64_t kk, int64
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int jj = 0; jj < 2; ++jj) acc[i][jj] = typename MT::V{0, 0, 0, 0};
-  S vr[PER], vs[PER];
+  SV vr[PER], vs[PER];
   // 32-bit offsets from the matrix start (the host checks that they fit).  Rows past the
   // end of the matrix are not clamped: they read at most T2 rows further, which the band
-  // allocation's padding covers, and are masked.
+  // allocation's padding covers, and are masked.  Each thread loads VW consecutive entries
+  // of a row at once: rows start on 128-byte lines and k0 + kc + kc_t is a multiple of VW,
+  // so every load is 16-byte aligned.
   const uint32_t ostep = (uint32_t)(RP * rs);
   const uint32_t or0 = (uint32_t)((r0 + i0) * rs + B + k0 + kc_t);
   const uint32_t os0 = (uint32_t)((s0 + i0) * rs + B + k0 + kc_t);
   auto load = [&](int64_t kc) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      vr[u] = (S)base[or0 + u * ostep + (uint32_t)kc];
-      vs[u] = (S)base[os0 + u * ostep + (uint32_t)kc];
+      vr[u] = *reinterpret_cast<const SV*>(base + (or0 + u * ostep + (uint32_t)kc));
+      vs[u] = *reinterpret_cast<const SV*>(base + (os0 + u * ostep + (uint32_t)kc));
     }
   };
+
   // masks in 32-bit tile-relative terms: row i of a block is inside the window if
   // i < lim, and panel column q (0-based in the group) is inside the band of that row if
   // q - i >= lo (the block's first row starts the band at panel column lo)
@@ -661,13 +667,18 @@ __device__ inline void wide_tile(BandArgs a, T* v, int64_t k0, int64_t kk, int64
   const int lo_r = (int)(r0 - B - k0), lo_s = (int)(s0 - B - k0);
   const int kjn = (int)kj;
   auto stage = [&](int64_t kc) {
-    const int q = (int)kc + kc_t;
-    const bool okc = q < kjn;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int i = i0 + RP * u;
-      Pr[i][kc_t] = (okc && i < lim_r && q - i >= lo_r) ? vr[u] : (S)0;
-      Ps[i][kc_t] = (okc && i < lim_s && q - i >= lo_s) ? vs[u] : (S)0;
+      SV wr_, ws_;
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const int q = (int)kc + kc_t + e;
+        wr_[e] = (q < kjn && i < lim_r && q - i >= lo_r) ? vr[u][e] : (S)0;
+        ws_[e] = (q < kjn && i < lim_s && q - i >= lo_s) ? vs[u][e] : (S)0;
+      }
+      *reinterpret_cast<SV*>(&Pr[i][kc_t]) = wr_;
+      *reinterpret_cast<SV*>(&Ps[i][kc_t]) = ws_;
     }
   };
   if (kc_first < kj) load(kc_first);
