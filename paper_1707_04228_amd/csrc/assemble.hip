@@ -491,7 +491,11 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, const int32_t* __r
                                               double* __restrict__ y) {
   __shared__ double red[4][64];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + w;  // uniform: the row bounds are scalar
+  // work-groups are dealt to the eight XCDs in turn; each XCD takes a contiguous eighth of
+  // the rows, so the part of x its rows gather stays in its L2
+  const int64_t xcd = blockIdx.x & 7, nq = gridDim.x >> 3, nrem = gridDim.x & 7;
+  const int64_t lb = xcd * nq + min(xcd, nrem) + (blockIdx.x >> 3);
+  const int64_t row = lb * 4 + w;                 // uniform: the row bounds are scalar
   if (row >= n_rows) return;                       // whole wavefronts
   const int q = lane / 9, e = lane - 9 * q, c = e % 3;
   const int b0 = rp[row], nb = rp[row + 1] - b0;
@@ -508,7 +512,8 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, const int32_t* __r
     const int cl0 = crow[min(k0 + lane, nb - 1)];
     const int cl1 = 7 * P > 64 ? crow[min(k0 + 64 + lane, nb - 1)] : 0;
 #pragma unroll
-    for (int u = 0; u < P; ++u) pv[u] = vrow[9 * min(k0 + 7 * u + q, nb - 1)];
+    for (int u = 0; u < P; ++u)                   // read once: kept out of the caches' way
+      pv[u] = __builtin_nontemporal_load(&vrow[9 * min(k0 + 7 * u + q, nb - 1)]);
 #pragma unroll
     for (int u = 0; u < P; ++u) {
       const int b = 7 * u + q;                     // block within the round (< 84)
