@@ -95,6 +95,42 @@ def test_band_factor_solve_mixed(solver, nrhs):
         assert np.abs(g - ref).max() <= 1e-4 * np.abs(ref).max(), (n, B)
 
 
+# launches whose widest matrix has fewer 64-row blocks below a panel than a factorisation
+# group has panels (the group's own rows are then the whole band, or nearly), and one with
+# no off-diagonal entries at all
+NARROW = [[(300, 50), (129, 10), (64, 63), (700, 63)],
+          [(513, 127), (300, 120), (1, 0), (1000, 100)],
+          [(5, 0), (300, 0), (257, 0)]]
+
+
+@pytest.mark.parametrize("shapes", NARROW)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("nrhs", [1, 16])
+def test_band_factor_solve_narrow_bands(solver, shapes, precision, nrhs):
+    import torch
+    gx, s = solver
+    rng = np.random.default_rng(11 + nrhs + len(shapes))
+    bands, los, xs = [], [], []
+    for n, B in shapes:
+        band, lo = _band_spd(n, B, rng)
+        bands.append(band)
+        los.append(lo)
+        xs.append(rng.standard_normal((n, nrhs)))
+    band_t = torch.tensor(np.concatenate(bands), device="cuda")
+    x_t = torch.tensor(np.concatenate([x.ravel() for x in xs]), device="cuda")
+    prec = gx.GX_FP64 if precision == "fp64" else gx.GX_MIXED
+    s.band_factor_solve([n for n, _ in shapes], [B for _, B in shapes], band_t, x_t,
+                        precision=prec)
+    got = x_t.cpu().numpy()
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    o = 0
+    for (n, B), lo, x in zip(shapes, los, xs):
+        ref = sla.cho_solve_banded((sla.cholesky_banded(lo, lower=True), True), x)
+        g = got[o: o + n * nrhs].reshape(n, nrhs)
+        o += n * nrhs
+        assert np.abs(g - ref).max() <= tol * np.abs(ref).max(), (n, B)
+
+
 def test_band_rejects_bad_input(solver):
     import torch
     gx, s = solver
