@@ -174,7 +174,8 @@ def _many_rhs(n, B, M, bd):
 def _trailing_update(n, B, bd):
     """k_syrk_wide: the staging loads of both 128-row panel blocks for every tile of the
     update of a group's trailing window (tile columns two and on), in 32-bit offsets from
-    the matrix start.  The panel work-groups (k_chain) load only inside the band."""
+    the matrix start (its 16-byte loads read the same entries as one load per entry).  The
+    panel launches (k_chain, k_far) load only entries inside the band."""
     ld = B + 1
     rs = ld - 1
     rlast = n - 1
