@@ -66,9 +66,9 @@ struct BandArgs {
 // ---- Factorisation: right-looking blocked Cholesky in groups of GP panels of NB columns.
 // The columns of a group [k0, k0 + GP NB) are factored by two launches: k_chain for the
 // group's own rows, k_far for the rows below them.  The update of the trailing window by
-// the group's panels is split in two k_syrk_wide
-// launches: the next group's columns (then that group's k_chain, on the same stream), and
-// all further columns on a second stream, at the same time.
+// the group's panels is split in two k_syrk_wide launches: the next group's columns (then
+// that group's k_chain, on the same stream), and all further columns on a second stream,
+// at the same time.
 constexpr int GP = 4;                             // panels per group
 constexpr int CT = 256;                           // threads of a panel work-group
 constexpr int64_t SPIN_LIMIT = (int64_t)1 << 22;  // polls before a wait gives up
@@ -120,10 +120,10 @@ struct Chunk<float> {
 // One launch per group for the group's own rows.  Work-group (p, j, t) owns the 64 rows
 // [c0 + 64 t, c0 + 64 t + 64) of panel p (columns [c0, c0 + 64), c0 = k0 + 64 p) of matrix
 // j; t = 0 is the diagonal block; blocks below the group (p + t >= GP) are k_far's and only
-// raise their flags.  Work-groups are numbered: panel 0's diagonal blocks (all matrices), then panel by
-// panel and matrix by matrix the blocks t >= 1, with the next panel's diagonal block right
-// after block t = 1 (the last one it needs), so that the next factorisation runs while
-// the rest of the panel is dispatched.  A work-group takes its number from a counter of the
+// raise their flags.  Work-groups are numbered: panel 0's diagonal blocks (all matrices),
+// then panel by panel and matrix by matrix the blocks t >= 1, with the next panel's
+// diagonal block right after block t = 1 (the last one it needs), so that the next
+// factorisation runs while the rest of the panel is dispatched.  A work-group takes its number from a counter of the
 // launch when it starts, not from its position in the grid, so every wait is for a
 // work-group that is already running: the launch cannot deadlock, whatever order the
 // hardware dispatches its work-groups in and whatever else occupies the device.
