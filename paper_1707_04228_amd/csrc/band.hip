@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(CT) k_chain(BandArgs a, T* v, int64_t k0, int 
       const int r16 = lane & 15;
       for (int kb = 0; kb < 4; ++kb) {
         const int b0 = 16 * kb;
-        double f[16];
+        double f[16], rdg[16];                     // rdg: reciprocals of the pivots
 #pragma unroll
         for (int c = 0; c < 16; ++c) f[c] = c <= r16 ? D[b0 + r16][b0 + c] : 0.0;
 #pragma unroll
@@ -312,8 +312,16 @@ __global__ void __launch_bounds__(CT) k_chain(BandArgs a, T* v, int64_t k0, int 
           const double dii = lane_value(f[i], i);
           const bool ok = dii > 0.0;
           if (!ok && lane == 0) atomicOr(err, 1);
-          const double d = ok ? sqrt(dii) : 1.0;
-          f[i] = r16 == i ? d : f[i] / d;
+          // 1 / sqrt(dii): the hardware estimate, then two Newton steps
+          // r <- r (3 - dii r^2) / 2, which bring it to full FP64 precision
+          double r = 1.0;
+          if (ok) {
+            r = __builtin_amdgcn_rsq(dii);
+            r = r * (1.5 - 0.5 * dii * r * r);
+            r = r * (1.5 - 0.5 * dii * r * r);
+          }
+          rdg[i] = r;
+          f[i] = r16 == i ? (ok ? dii * r : 1.0) : f[i] * r;
 #pragma unroll
           for (int s2 = i + 1; s2 < 16; ++s2) f[s2] -= f[i] * lane_value(f[i], s2);
         }
@@ -326,7 +334,7 @@ __global__ void __launch_bounds__(CT) k_chain(BandArgs a, T* v, int64_t k0, int 
           double sum = i == r16 ? 1.0 : 0.0;
 #pragma unroll
           for (int k = 0; k < i; ++k) sum -= lane_value(f[k], i) * xi[k];
-          xi[i] = sum / lane_value(f[i], i);
+          xi[i] = sum * rdg[i];
         }
         if (lane < 16)
 #pragma unroll
@@ -350,15 +358,16 @@ __global__ void __launch_bounds__(CT) k_chain(BandArgs a, T* v, int64_t k0, int 
             for (int q = 0; q < 4; ++q) D[16 * ti + M64::row(q, lk)][16 * tj + li] -= acc[q];
           }
       }
-      for (int idx = lane; idx < NB * NB; idx += 64) {
-        const int i = idx / NB, l = idx % NB;
-        Li[i][l] = (i >> 4) == (l >> 4) ? Wd[i >> 4][i & 15][l & 15] : 0.0;
-      }
+      // Li is assembled below the diagonal tiles only: its diagonal tiles are the W_i (read
+      // from Wd) and it is zero above them
       for (int dd = 1; dd < 4; ++dd)
         for (int ti = dd; ti < 4; ++ti) {
           const int tj = ti - dd;
           v4d acc = v4d{0, 0, 0, 0};
-          for (int kt = tj; kt < ti; ++kt)
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks)              // kt = tj: Li(tj, tj) = W_tj
+            acc = M64::mma(D[16 * ti + li][16 * tj + 4 * ks + lk], Wd[tj][4 * ks + lk][li], acc);
+          for (int kt = tj + 1; kt < ti; ++kt)
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks)
               acc = M64::mma(D[16 * ti + li][16 * kt + 4 * ks + lk],
@@ -377,8 +386,11 @@ __global__ void __launch_bounds__(CT) k_chain(BandArgs a, T* v, int64_t k0, int 
     T* dj = dinv + boff[j] + (c0 / NB) * NB * NB;
     for (int idx = threadIdx.x; idx < NB * NB; idx += CT) {
       const int i = idx / NB, l = idx % NB;
-      co_store(invj + idx, Li[i][l]);
-      dj[idx] = (T)Li[i][l];
+      const double lv = (i >> 4) > (l >> 4)    ? Li[i][l]
+                        : (i >> 4) == (l >> 4) ? Wd[i >> 4][i & 15][l & 15]
+                                               : 0.0;
+      co_store(invj + idx, lv);
+      dj[idx] = (T)lv;
       if (i < nb && l <= i && i - l <= B) base[(c0 + i) * rs + B + c0 + l] = (T)D[i][l];
     }
   } else {
