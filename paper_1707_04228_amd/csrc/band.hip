@@ -329,11 +329,14 @@ __global__ void __launch_bounds__(CT) k_chain(BandArgs a, T* v, int64_t k0, int 
 #pragma unroll
           for (int c = 0; c < 16; ++c) D[b0 + r16][b0 + c] = c <= r16 ? f[c] : 0.0;
         double xi[16];                             // column r16 of the block's inverse
+        // (the factor's entries L(i, k) are read back from LDS, the same address in every
+        // lane, rather than from lane i's registers: they do not depend on xi, so the
+        // reads are issued ahead, and they take no scalar registers)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           double sum = i == r16 ? 1.0 : 0.0;
 #pragma unroll
-          for (int k = 0; k < i; ++k) sum -= lane_value(f[k], i) * xi[k];
+          for (int k = 0; k < i; ++k) sum -= D[b0 + i][b0 + k] * xi[k];
           xi[i] = sum * rdg[i];
         }
         if (lane < 16)
