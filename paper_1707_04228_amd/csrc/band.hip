@@ -755,7 +755,7 @@ static int64_t wide_tiles(int64_t max_B, int64_t lo, int64_t hi) {
 
 
 template <class T>
-void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job) {
+void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job, bool threaded) {
   BandArgs a{bs.d_n.p, bs.d_B.p, bs.d_ld.p, bs.d_off.p, bs.d_eoff.p, bs.d_fcb.p, bs.d_lrb.p};
   static_assert(GP * NB % T2 == 0, "a group spans whole wide tile columns");
   constexpr int64_t NEXT_TS = GP * NB / T2;              // tile columns of the next group
@@ -784,35 +784,62 @@ void band_factor_t(BandSet& bs, T* v, T* dinv, hipStream_t st, FactorJob& job) {
   GX_HIP(hipEventCreateWithFlags(&job.chain, hipEventDisableTiming));
   GX_HIP(hipEventCreateWithFlags(&job.rest[0], hipEventDisableTiming));
   GX_HIP(hipEventCreateWithFlags(&job.rest[1], hipEventDisableTiming));
-  bool recorded[2] = {false, false};
-  int g = 0;
-  for (int64_t k0 = 0; k0 < bs.max_n; k0 += GP * NB, ++g) {
-    if (recorded[g % 2]) GX_HIP(hipStreamWaitEvent(st, job.rest[g % 2], 0));
-    if (g > 0 && bs.max_B > 0)
-      hipLaunchKernelGGL(k_syrk_wide<T>, dim3((unsigned)tot_next), dim3(U2), 0, st, a, v,
-                         k0 - GP * NB, (int64_t)GP * NB, (int64_t)0, NEXT_TS, per_next,
-                         tot_next);
-    hipLaunchKernelGGL(k_chain<T>, dim3(chain_blocks), dim3(CT), 0, st, a, v, k0, NRC,
-                       bs.n_mat, job.flags.p, tickets + g, g + 1, job.inv.p, dinv, bs.d_boff.p,
-                       job.err.p);
-    if (far_blocks)
-      hipLaunchKernelGGL(k_far<T>, dim3(far_blocks), dim3(CT), 0, st, a, v, k0, NF, bs.n_mat,
-                         (const double*)job.inv.p);
-    if (tot_rest && k0 + GP * NB < bs.max_n) {
-      GX_HIP(hipEventRecord(job.chain, st));
-      GX_HIP(hipStreamWaitEvent(job.la, job.chain, 0));
-      hipLaunchKernelGGL(k_syrk_wide<T>, dim3((unsigned)tot_rest), dim3(U2), 0, job.la, a, v,
-                         k0, (int64_t)GP * NB, NEXT_TS, nt2, per_rest, tot_rest);
-      GX_HIP(hipEventRecord(job.rest[g % 2], job.la));
-      recorded[g % 2] = true;
+  const int64_t max_n = bs.max_n, max_B = bs.max_B;
+  const int n_mat = bs.n_mat;
+  const int64_t* boff = bs.d_boff.p;
+  int* flags = job.flags.p;
+  double* inv = job.inv.p;
+  int* err = job.err.p;
+  hipStream_t la = job.la;
+  hipEvent_t ev_chain = job.chain, ev_rest[2] = {job.rest[0], job.rest[1]};
+  auto launches = [=]() {
+    bool recorded[2] = {false, false};
+    int g = 0;
+    for (int64_t k0 = 0; k0 < max_n; k0 += GP * NB, ++g) {
+      if (recorded[g % 2]) GX_HIP(hipStreamWaitEvent(st, ev_rest[g % 2], 0));
+      if (g > 0 && max_B > 0)
+        hipLaunchKernelGGL(k_syrk_wide<T>, dim3((unsigned)tot_next), dim3(U2), 0, st, a, v,
+                           k0 - GP * NB, (int64_t)GP * NB, (int64_t)0, NEXT_TS, per_next,
+                           tot_next);
+      hipLaunchKernelGGL(k_chain<T>, dim3(chain_blocks), dim3(CT), 0, st, a, v, k0, NRC,
+                         n_mat, flags, tickets + g, g + 1, inv, dinv, boff, err);
+      if (far_blocks)
+        hipLaunchKernelGGL(k_far<T>, dim3(far_blocks), dim3(CT), 0, st, a, v, k0, NF, n_mat,
+                           (const double*)inv);
+      if (tot_rest && k0 + GP * NB < max_n) {
+        GX_HIP(hipEventRecord(ev_chain, st));
+        GX_HIP(hipStreamWaitEvent(la, ev_chain, 0));
+        hipLaunchKernelGGL(k_syrk_wide<T>, dim3((unsigned)tot_rest), dim3(U2), 0, la, a, v,
+                           k0, (int64_t)GP * NB, NEXT_TS, nt2, per_rest, tot_rest);
+        GX_HIP(hipEventRecord(ev_rest[g % 2], la));
+        recorded[g % 2] = true;
+      }
     }
+    for (int q = 0; q < 2; ++q)
+      if (recorded[q]) GX_HIP(hipStreamWaitEvent(st, ev_rest[q], 0));
+    GX_HIP(hipGetLastError());
+  };
+  if (!threaded) {
+    launches();
+    return;
   }
-  for (int q = 0; q < 2; ++q)
-    if (recorded[q]) GX_HIP(hipStreamWaitEvent(st, job.rest[q], 0));
-  GX_HIP(hipGetLastError());
+  // The launches only enqueue work (no host wait, no allocation), so a thread of the job
+  // may make them while the caller goes on; band_factor_finish and the job's destructor
+  // join it, and an error it met is raised by band_factor_finish.
+  int dev = 0;
+  GX_HIP(hipGetDevice(&dev));
+  job.launcher = std::thread([launches, dev, &job]() {
+    try {
+      GX_HIP(hipSetDevice(dev));
+      launches();
+    } catch (...) {
+      job.launch_error = std::current_exception();
+    }
+  });
 }
 
 FactorJob::~FactorJob() {
+  if (launcher.joinable()) launcher.join();
   if (st) (void)hipStreamSynchronize(st);         // nothing of the job may still run when
   if (la) (void)hipStreamSynchronize(la);         // its buffers are released
   if (chain) (void)hipEventDestroy(chain);
@@ -821,20 +848,23 @@ FactorJob::~FactorJob() {
   if (la) (void)hipStreamDestroy(la);
 }
 
-void band_factor_start(BandSet& bs, hipStream_t st, FactorJob& job, const char* what) {
+void band_factor_start(BandSet& bs, hipStream_t st, FactorJob& job, const char* what,
+                       bool threaded) {
   GX_REQUIRE(!job.st, "factorisation job already started");
   job.st = st;
   job.what = what;
   job.err.alloc(1);
   zero(job.err, st);
   if (bs.fp32)
-    band_factor_t<float>(bs, bs.v32.p, bs.dinv32.p, st, job);
+    band_factor_t<float>(bs, bs.v32.p, bs.dinv32.p, st, job, threaded);
   else
-    band_factor_t<double>(bs, bs.v64.p, bs.dinv64.p, st, job);
+    band_factor_t<double>(bs, bs.v64.p, bs.dinv64.p, st, job, threaded);
 }
 
 void band_factor_finish(FactorJob& job) {
   GX_REQUIRE(job.st, "factorisation job not started");
+  if (job.launcher.joinable()) job.launcher.join();
+  if (job.launch_error) std::rethrow_exception(job.launch_error);
   int h = 0;
   to_host(&h, job.err.p, 1, job.st);               // waits for all of the job
   if (h & 2)

@@ -1322,21 +1322,27 @@ gx_status gx_geneo_setup(gx_ctx* c, const gx_geneo_opts* o, int32_t* nev_out,
   if (c->sw.two_level) {
     // The interior factorisation shares nothing with the eigensolves: it runs on a side
     // stream while they run on the context's stream (the two sets of factors are then
-    // resident together).  It starts once the eigensolver's factorisation is done, so that
-    // it runs beside the eigensolver's iterations (bound by memory traffic), not beside the
-    // other factorisation.  The side stream is declared first, so the job (which waits for
-    // its streams when it goes) is destroyed before it.
+    // resident together).  Its matrices are laid out and filled first; its factorisation
+    // starts once the eigensolver's factorisation is done, so that it runs beside the
+    // eigensolver's iterations (bound by memory traffic), not beside the other
+    // factorisation, and a host thread of the job enqueues its launches, so that this
+    // thread goes on to the iterations at once.  The side stream is declared first, so the
+    // job (which waits for its streams when it goes) is destroyed before it.
     SideStream side;
     InteriorJob job;
     EventPair ev;
-    auto start_interior = [&]() {
+    {
       StreamScope scope(side.st);
       GX_HIP(hipEventRecord(ev.a, side.st));
-      interior_factors_start(c, o->precision, side.st, job);
-      GX_HIP(hipEventRecord(ev.b, side.st));
+      interior_factors_prepare(c, o->precision, side.st, job);
+    }
+    auto start_interior = [&]() {
+      StreamScope scope(side.st);
+      interior_factors_launch(c, side.st, job, true);
     };
     geneo_coarse(c, o, start_interior);
-    interior_factors_finish(c, job);
+    interior_factors_finish(c, job);                 // joins the launching thread
+    GX_HIP(hipEventRecord(ev.b, side.st));
     c->phase_ms[2] = ev.ms();
   } else {
     Timer t2(c->stream);

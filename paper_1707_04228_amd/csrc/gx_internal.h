@@ -7,10 +7,12 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <functional>
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -400,12 +402,18 @@ struct FactorJob {
                                                // then per launch: the work-group counter
   hipStream_t la = nullptr;                    // trailing-update stream (default priority)
   hipEvent_t chain = nullptr, rest[2] = {nullptr, nullptr};
+  std::thread launcher;                        // enqueues the launches of a threaded job
+  std::exception_ptr launch_error;
   FactorJob() = default;
   ~FactorJob();
   FactorJob(const FactorJob&) = delete;
   FactorJob& operator=(const FactorJob&) = delete;
 };
-void band_factor_start(BandSet& bs, hipStream_t st, FactorJob& job, const char* what);
+// threaded: a host thread of the job enqueues the launches, so the caller goes on at once
+// (a long chain of launches blocks the enqueuing thread once the device's queues are
+// full); band_factor_finish joins it.
+void band_factor_start(BandSet& bs, hipStream_t st, FactorJob& job, const char* what,
+                       bool threaded = false);
 void band_factor_finish(FactorJob& job);
 // The interior factorisation as a job that can run on a side stream (see schwarz.hip).
 struct InteriorJob {
@@ -416,6 +424,10 @@ struct InteriorJob {
   FactorJob factor;
 };
 void interior_factors_start(gx_ctx* c, int precision, hipStream_t s, InteriorJob& job);
+// the same in two parts: the bandwidths, layout, allocation and band fill (enqueued on s),
+// then the factorisation's launches
+void interior_factors_prepare(gx_ctx* c, int precision, hipStream_t s, InteriorJob& job);
+void interior_factors_launch(gx_ctx* c, hipStream_t s, InteriorJob& job, bool threaded);
 void interior_factors_finish(gx_ctx* c, InteriorJob& job);
 void band_solve_check(BandSet& bs, hipStream_t st);
 void band_solve(BandSet& bs, const int64_t* d_xoff, double* x, hipStream_t st, int ncol = 1,
@@ -452,6 +464,7 @@ struct EventPair {
   }
   float ms() const {
     float t = 0;
+    GX_HIP(hipEventSynchronize(b));
     GX_HIP(hipEventElapsedTime(&t, a, b));
     return t;
   }

@@ -304,7 +304,7 @@ std::vector<int64_t> list_bandwidth(gx_ctx* c, const int32_t* list, const int64_
 
 // Fills the interior band matrices and enqueues their factorisation on s (which may be a
 // side stream: nothing here waits for it); interior_factors_finish completes the job.
-void interior_factors_start(gx_ctx* c, int precision, hipStream_t s, InteriorJob& job) {
+void interior_factors_prepare(gx_ctx* c, int precision, hipStream_t s, InteriorJob& job) {
   Schwarz& sw = c->sw;
   const int64_t N = c->n_nodes;
   const int n_sub = sw.n_sub;
@@ -334,7 +334,15 @@ void interior_factors_start(gx_ctx* c, int precision, hipStream_t s, InteriorJob
                        c->row_ptr.p, c->col.p, c->val.p, (const double*)nullptr, sw.I_nodes.p,
                        sw.d_offI.p, sw.d_nI.p, sw.I_loc.p, N, bv, sw.A.v64.p);
   GX_HIP(hipGetLastError());
-  band_factor_start(sw.A, s, job.factor, "the subdomain matrices");
+}
+
+void interior_factors_launch(gx_ctx* c, hipStream_t s, InteriorJob& job, bool threaded) {
+  band_factor_start(c->sw.A, s, job.factor, "the subdomain matrices", threaded);
+}
+
+void interior_factors_start(gx_ctx* c, int precision, hipStream_t s, InteriorJob& job) {
+  interior_factors_prepare(c, precision, s, job);
+  interior_factors_launch(c, s, job, false);
 }
 
 // Waits for the factorisation (an FP32 breakdown is redone in FP64 on the context's
