@@ -1003,7 +1003,6 @@ __device__ __forceinline__ void band_solve_1_mat(int64_t n, int64_t B, int64_t l
   __shared__ double xs[GMAX - 1][SB];               // polled solutions of blocks in flight
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t nblk = (n + SB - 1) / SB;
-  constexpr int U = 8;                             // 64-column steps in flight per wave
   constexpr int UB = 32;                           // band rows in flight per wave (backward)
   // ---- forward: wave w owns rows 8w..8w+7 of the block, lanes run along the columns
   for (int64_t k = g; k < nblk; k += G) {
@@ -1028,49 +1027,34 @@ __device__ __forceinline__ void band_solve_1_mat(int64_t n, int64_t B, int64_t l
     // envelope start, rounded down to a 128-byte line (rows start on one: see band_layout)
     constexpr int64_t LA = 128 / sizeof(T);
     const int64_t cstart = max(max<int64_t>(ifirst - B, 0), fcb[k]) / LA * LA;
-    if constexpr (sizeof(T) == 4) {
-      // FP32 factors: a lane takes two adjacent columns (one 8-byte load per row; columns
-      // from a line start are even, so the pair is aligned), 128 columns per step
-      constexpr int U2 = U / 2;
-      for (int64_t c0 = cstart + 2 * lane; c0 < done_end + 2 * lane; c0 += 128 * U2) {
-        float2 l[U2][RPW];
-        double xa[U2], xb[U2];
+    {
+      // a lane loads V adjacent columns of a row at once (16 bytes: two FP64 or four FP32
+      // entries; columns from a line start are multiples of V, so every load is aligned),
+      // 64 V columns per step, 512 columns per pass
+      constexpr int V = 16 / sizeof(T);
+      constexpr int US = 512 / (64 * V);            // steps per pass
+      typedef T TV __attribute__((ext_vector_type(V)));
+      for (int64_t c0 = cstart + V * lane; c0 < done_end + V * lane; c0 += 64 * V * US) {
+        TV l[US][RPW];
+        double xv[US][V];
 #pragma unroll
-        for (int u = 0; u < U2; ++u) {
-          const int64_t cc = c0 + 128 * u;
-          xa[u] = poll_load(y + min<int64_t>(cc, done_end - 1));
-          xb[u] = poll_load(y + min<int64_t>(cc + 1, done_end - 1));
+        for (int u = 0; u < US; ++u) {
+          const int64_t cc = c0 + 64 * V * u;
 #pragma unroll
-          for (int r = 0; r < RPW; ++r) l[u][r] = *reinterpret_cast<const float2*>(rp[r] + cc);
+          for (int e = 0; e < V; ++e) xv[u][e] = poll_load(y + min<int64_t>(cc + e, done_end - 1));
+#pragma unroll
+          for (int r = 0; r < RPW; ++r) l[u][r] = *reinterpret_cast<const TV*>(rp[r] + cc);
         }
 #pragma unroll
-        for (int u = 0; u < U2; ++u) {
-          const int64_t cc = c0 + 128 * u;
-          const double x0 = cc < done_end ? xa[u] : 0.0, x1 = cc + 1 < done_end ? xb[u] : 0.0;
+        for (int u = 0; u < US; ++u) {
+          const int64_t cc = c0 + 64 * V * u;
 #pragma unroll
-          for (int r = 0; r < RPW; ++r) {
-            s[r] += (double)l[u][r].x * (cc >= ifirst + r - B ? x0 : 0.0);
-            s[r] += (double)l[u][r].y * (cc + 1 >= ifirst + r - B ? x1 : 0.0);
+          for (int e = 0; e < V; ++e) {
+            const double xe = cc + e < done_end ? xv[u][e] : 0.0;
+#pragma unroll
+            for (int r = 0; r < RPW; ++r)
+              s[r] += (double)l[u][r][e] * (cc + e >= ifirst + r - B ? xe : 0.0);
           }
-        }
-      }
-    } else {
-      for (int64_t c0 = cstart + lane; c0 < done_end + lane; c0 += 64 * U) {
-        T l[U][RPW];
-        double xv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          xv[u] = poll_load(y + min<int64_t>(c0 + 64 * u, done_end - 1));
-#pragma unroll
-          for (int r = 0; r < RPW; ++r) l[u][r] = rp[r][c0 + 64 * u];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int64_t cc = c0 + 64 * u;
-          const double xu = cc < done_end ? xv[u] : 0.0;
-#pragma unroll
-          for (int r = 0; r < RPW; ++r)
-            s[r] += (double)l[u][r] * (cc >= ifirst + r - B ? xu : 0.0);
         }
       }
     }
@@ -1145,49 +1129,43 @@ __device__ __forceinline__ void band_solve_1_mat(int64_t n, int64_t B, int64_t l
     const int64_t done_beg = min<int64_t>(rend, kdone * SB);
     const int64_t cidx = i0 + lane;
     double sacc = 0.0;
-    if constexpr (sizeof(T) == 4) {
-      // FP32 factors: lane l takes the column pair 2 (l mod 32), +1 (one aligned 8-byte
-      // load) of the rows r0 + 8 (2 v + l / 32), so one load covers two rows; the halves'
-      // sums are then added and handed to the lanes of their columns
-      const int pr = lane & 31, hf = lane >> 5;
-      const int64_t c2 = i0 + 2 * pr;
-      double s0 = 0.0, s1 = 0.0;
+    {
+      // lane l loads the V adjacent columns from V (l mod 64 / V) of the rows
+      // r0 + 8 (V v + l / (64 / V)) (16 bytes, aligned as above), so one load covers V
+      // rows; the row groups' sums are then added and handed to the lanes of their columns
+      constexpr int V = 16 / sizeof(T);
+      constexpr int LPR = 64 / V;                   // lanes per row
+      typedef T TV __attribute__((ext_vector_type(V)));
+      const int pr = lane % LPR, hf = lane / LPR;
+      const int64_t cv = i0 + V * pr;
+      double sv[V];
+#pragma unroll
+      for (int e = 0; e < V; ++e) sv[e] = 0.0;
       for (int64_t r0 = done_beg + wave; r0 < rend; r0 += SW * UB) {
-        float2 l[UB / 2];
+        TV l[UB / V];
         const double xz = poll_load(z + min<int64_t>(r0 + SW * (lane % UB), rend - 1));
 #pragma unroll
-        for (int v = 0; v < UB / 2; ++v) {
-          const int64_t rr = min<int64_t>(r0 + SW * (2 * v + hf), rend - 1);
-          l[v] = *reinterpret_cast<const float2*>(cb + rr * rs + c2);
+        for (int v = 0; v < UB / V; ++v) {
+          const int64_t rr = min<int64_t>(r0 + SW * (V * v + hf), rend - 1);
+          l[v] = *reinterpret_cast<const TV*>(cb + rr * rs + cv);
         }
 #pragma unroll
-        for (int v = 0; v < UB / 2; ++v) {
-          const int64_t rr = r0 + SW * (2 * v + hf);
-          const double xu = __shfl(xz, 2 * v + hf);
-          s0 += (double)l[v].x * ((rr < rend && rr - B <= c2) ? xu : 0.0);
-          s1 += (double)l[v].y * ((rr < rend && rr - B <= c2 + 1) ? xu : 0.0);
+        for (int v = 0; v < UB / V; ++v) {
+          const int64_t rr = r0 + SW * (V * v + hf);
+          const double xu = __shfl(xz, V * v + hf);
+#pragma unroll
+          for (int e = 0; e < V; ++e)
+            sv[e] += (double)l[v][e] * ((rr < rend && rr - B <= cv + e) ? xu : 0.0);
         }
       }
-      s0 += __shfl_xor(s0, 32);
-      s1 += __shfl_xor(s1, 32);
-      const double v0 = __shfl(s0, lane >> 1), v1 = __shfl(s1, lane >> 1);
-      sacc = (lane & 1) ? v1 : v0;
-    } else {
-      for (int64_t r0 = done_beg + wave; r0 < rend; r0 += SW * UB) {
-        // lane u < UB loads the solution of row r0 + 8 u, handed to all lanes by a lane read
-        T l[UB];
-        const double xz = poll_load(z + min<int64_t>(r0 + SW * (lane % UB), rend - 1));
 #pragma unroll
-        for (int u = 0; u < UB; ++u) {
-          const int64_t rr = min<int64_t>(r0 + SW * u, rend - 1);
-          l[u] = cb[rr * rs + cidx];
-        }
+      for (int m = LPR; m < 64; m *= 2)
 #pragma unroll
-        for (int u = 0; u < UB; ++u) {
-          const int64_t rr = r0 + SW * u;
-          const double xu = __shfl(xz, u);
-          sacc += (double)l[u] * ((rr < rend && rr - B <= cidx) ? xu : 0.0);
-        }
+        for (int e = 0; e < V; ++e) sv[e] += __shfl_xor(sv[e], m);
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const double t = __shfl(sv[e], lane / V);
+        if (lane % V == e) sacc = t;
       }
     }
     // row blocks in flight, kb + 1 .. kin (at most GMAX - 1): factor entries and the

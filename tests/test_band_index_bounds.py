@@ -25,7 +25,6 @@ import pytest
 SB = 64            # solve block
 SW = 8             # waves per solve work-group
 RPW = 8            # forward rows per wave
-U = 8              # 64-column steps in flight per wave (forward)
 UB = 32            # band rows in flight per wave (backward)
 GMAX = 4           # work-groups per matrix, one right-hand side
 DL = 8             # inverse-block entries per thread
@@ -73,29 +72,26 @@ def _single_rhs(n, B, G, bd):
         ifirst = i0 + RPW * w
         rc = np.minimum(ifirst + r, n - 1)
         rowbase = rc * ld - rc + B                         # rp[r] = base + rc ld - rc + B
-        # the band (envelope) start, rounded down to a 128-byte line of FP64 (16) or FP32
-        # (32) entries: the first one is the lower bound
-        start = np.maximum(ifirst - B, 0) // 32 * 32 + lane
-        run = start < done_end + lane                      # the c0 loop runs at all
-        last = start + 64 * U * ((done_end + lane - 1 - start) // (64 * U))
-        shape = np.broadcast_shapes(rowbase.shape, run.shape)
-        runf = np.broadcast_to(run, shape)
-        for c0 in (start, last):
-            for u in range(U):
-                bd.check(np.broadcast_to(rowbase + c0 + 64 * u, shape)[runf], "forward band")
-                yi = np.broadcast_to(np.minimum(c0 + 64 * u, done_end - 1), run.shape)[run]
-                assert yi.size == 0 or (yi.min() >= 0 and yi.max() < nblk * SB)
-        # FP32 factors: lane l takes columns c0 + 2 l and c0 + 2 l + 1, 128 per step
-        start2 = np.maximum(ifirst - B, 0) // 32 * 32 + 2 * lane
-        run2 = start2 < done_end + 2 * lane
-        last2 = start2 + 128 * (U // 2) * ((done_end + 2 * lane - 1 - start2) // (128 * (U // 2)))
-        shape2 = np.broadcast_shapes(rowbase.shape, run2.shape)
-        runf2 = np.broadcast_to(run2, shape2)
-        for c0 in (start2, last2):
-            for u in range(U // 2):
-                for e in (0, 1):
-                    bd.check(np.broadcast_to(rowbase + c0 + 128 * u + e, shape2)[runf2],
-                             "forward band (FP32 pairs)")
+        # lane l loads V = 2 (FP64) or 4 (FP32) adjacent columns from c0 + V l (16 bytes),
+        # 64 V columns per step, 512 columns per pass; the band (envelope) start, rounded
+        # down to a 128-byte line of FP64 (16) or FP32 (32) entries: the first one is the
+        # lower bound
+        for V in (2, 4):
+            US = 512 // (64 * V)
+            start = np.maximum(ifirst - B, 0) // 32 * 32 + V * lane
+            run = start < done_end + V * lane              # the c0 loop runs at all
+            last = start + 512 * ((done_end + V * lane - 1 - start) // 512)
+            shape = np.broadcast_shapes(rowbase.shape, run.shape)
+            runf = np.broadcast_to(run, shape)
+            for c0 in (start, last):
+                assert (np.broadcast_to(c0 % V, run.shape)[run] == 0).all()   # aligned
+                for u in range(US):
+                    for e in range(V):
+                        bd.check(np.broadcast_to(rowbase + c0 + 64 * V * u + e, shape)[runf],
+                                 "forward band")
+                        yi = np.broadcast_to(np.minimum(c0 + 64 * V * u + e, done_end - 1),
+                                             run.shape)[run]
+                        assert yi.size == 0 or (yi.min() >= 0 and yi.max() < nblk * SB)
         for o in range(GMAX - 1):                          # factor entries of blocks in flight
             cc = min(kdone + o, max(k - 1, 0)) * SB + lane
             bd.check(rowbase + cc, "forward in-flight")
@@ -116,9 +112,15 @@ def _single_rhs(n, B, G, bd):
         for wv in range(SW):
             r0s = list(range(done_beg + wv, rend, SW * UB))
             for r0 in (r0s[:1] + r0s[-1:]):
-                for u in range(UB):
-                    rr = min(r0 + SW * u, rend - 1)
-                    bd.check(rr * rs + B + cidx, "backward band")
+                # lane l loads the V columns from i0 + V (l mod 64 / V) of the rows
+                # r0 + 8 (V v + l / (64 / V)), v < UB / V
+                for V in (2, 4):
+                    lpr = 64 // V
+                    pr, hf = np.arange(64) % lpr, np.arange(64) // lpr
+                    for v in range(UB // V):
+                        rr = np.minimum(r0 + SW * (V * v + hf), rend - 1)
+                        for e in range(V):
+                            bd.check(rr * rs + B + i0 + V * pr + e, "backward band")
                 zi = min(r0 + SW * (np.arange(64) % UB).max(), rend - 1)
                 assert 0 <= zi < nblk * SB
             for o in range(GMAX - 1):
