@@ -457,11 +457,15 @@ __global__ void __launch_bounds__(CT, 2) k_far(BandArgs a, T* v, int64_t k0, int
   typedef Mfma<T> MT;
   typedef typename MT::S S;
   constexpr int KC = Chunk<S>::KC, KS = Chunk<S>::KS;
-  constexpr int RP = CT / KC;                    // rows staged per pass
-  constexpr int PER = NB / RP;                   // staged entries per thread and operand
-  __shared__ double D[NB][NB + 1];               // the block
-  __shared__ double Li[NB][NB + 1];              // the inverse of the panel's diagonal block
+  constexpr int VW = 16 / sizeof(S);             // entries per 16-byte load
+  typedef S SV __attribute__((ext_vector_type(VW)));
+  constexpr int RP = CT / (KC / VW);             // rows staged per pass
+  constexpr int PER = NB / RP;                   // 16-byte loads per thread and operand
+  __shared__ __attribute__((aligned(16))) double D[NB][NB + 1];    // the block
+  __shared__ __attribute__((aligned(16))) double Li[NB][NB + 1];   // the inverse of the
+                                                                   // panel's diagonal block
   static_assert(NB * KS * sizeof(S) <= sizeof(D), "staging fits in the block buffers");
+  static_assert(KS * sizeof(S) % 16 == 0, "staged rows start on 16 bytes");
   S* Pr = reinterpret_cast<S*>(&D[0][0]);        // staging of the update (aliases D and Li)
   S* Ps = reinterpret_cast<S*>(&Li[0][0]);
   const int j = blockIdx.x / NF, f = blockIdx.x % NF;
@@ -474,7 +478,7 @@ __global__ void __launch_bounds__(CT, 2) k_far(BandArgs a, T* v, int64_t k0, int
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wr = 32 * (w & 1), wc = 32 * (w >> 1);
-  const int kc_t = threadIdx.x % KC, i0 = threadIdx.x / KC;
+  const int kc_t = threadIdx.x % (KC / VW) * VW, i0 = threadIdx.x / (KC / VW);
 #pragma unroll 1
   for (int p = 0; p < GP; ++p) {
     const int64_t c0 = k0 + (int64_t)NB * p;
@@ -488,30 +492,40 @@ __global__ void __launch_bounds__(CT, 2) k_far(BandArgs a, T* v, int64_t k0, int
     if (p > 0) {
       const int64_t lo = max(r0 - B, a.fcb[a.eoff[j] + r0 / NB]);
       const int64_t kstart = lo > k0 ? k0 + (lo - k0) / KC * KC : k0;
-      S xr[PER], xs[PER];
+      // Each thread loads VW consecutive entries of a row at once (16 bytes: rows start on
+      // 128-byte lines and k0 + (kc - k0) + kc_t is a multiple of VW, so the loads are
+      // aligned).  The loads are unconditional: rows past the end of the matrix read at
+      // most NB rows further, which the band allocation's padding covers, and entries
+      // outside the band or the window are masked when they are staged.
+      SV xr[PER], xs[PER];
       const int lim_r = (int)min<int64_t>(n - r0, NB), lim_s = (int)min<int64_t>(n - c0, NB);
       const int lo_r = (int)(r0 - B - k0), lo_s = (int)(c0 - B - k0), qend = (int)(c0 - k0);
-      const uint32_t or0 = (uint32_t)(min(r0 + i0, n - 1) * rs + B + k0 + kc_t);
-      const uint32_t os0 = (uint32_t)(min(c0 + i0, n - 1) * rs + B + k0 + kc_t);
+      const uint32_t or0 = (uint32_t)((r0 + i0) * rs + B + k0 + kc_t);
+      const uint32_t os0 = (uint32_t)((c0 + i0) * rs + B + k0 + kc_t);
       const uint32_t ostep = (uint32_t)(RP * rs);
       auto fetch = [&](int64_t kc) {
-        const int qq = (int)(kc - k0) + kc_t;
         const uint32_t kd = (uint32_t)(kc - k0);
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
-          const int i = i0 + RP * u;
-          const bool okr = qq < qend && i < lim_r && qq - i >= lo_r;
-          const bool oks = qq < qend && i < lim_s && qq - i >= lo_s;
-          xr[u] = okr ? (S)base[or0 + u * ostep + kd] : (S)0;
-          xs[u] = oks ? (S)base[os0 + u * ostep + kd] : (S)0;
+          xr[u] = *reinterpret_cast<const SV*>(base + (or0 + u * ostep + kd));
+          xs[u] = *reinterpret_cast<const SV*>(base + (os0 + u * ostep + kd));
         }
       };
       if (kstart < c0) fetch(kstart);
       for (int64_t kc = kstart; kc < c0; kc += KC) {
+        const int qq = (int)(kc - k0) + kc_t;
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
-          Pr[(i0 + RP * u) * KS + kc_t] = xr[u];
-          Ps[(i0 + RP * u) * KS + kc_t] = xs[u];
+          const int i = i0 + RP * u;
+          SV wr_, ws_;
+#pragma unroll
+          for (int e = 0; e < VW; ++e) {
+            const int q = qq + e;
+            wr_[e] = (q < qend && i < lim_r && q - i >= lo_r) ? xr[u][e] : (S)0;
+            ws_[e] = (q < qend && i < lim_s && q - i >= lo_s) ? xs[u][e] : (S)0;
+          }
+          *reinterpret_cast<SV*>(&Pr[i * KS + kc_t]) = wr_;
+          *reinterpret_cast<SV*>(&Ps[i * KS + kc_t]) = ws_;
         }
         __syncthreads();
         if (kc + KC < c0) fetch(kc + KC);

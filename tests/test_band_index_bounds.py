@@ -177,7 +177,7 @@ def _trailing_update(n, B, bd):
     """k_syrk_wide: the staging loads of both 128-row panel blocks for every tile of the
     update of a group's trailing window (tile columns two and on), in 32-bit offsets from
     the matrix start (its 16-byte loads read the same entries as one load per entry).  The
-    panel launches (k_chain, k_far) load only entries inside the band."""
+    panel launch k_chain loads only entries inside the band."""
     ld = B + 1
     rs = ld - 1
     rlast = n - 1
@@ -211,6 +211,45 @@ def _trailing_update(n, B, bd):
                         bd.check(idx_s, "trailing s")
 
 
+def _far_rows(n, B):
+    """k_far: the 16-byte staging loads of the update of the rows below a group by the
+    group's earlier panels.  Rows are not clamped: a row block that ends past the matrix
+    reads up to 63 rows further, which the band allocation's padding (BAND_PAD + 128 rows)
+    covers; offsets are 32-bit from the matrix start."""
+    ld = B + 1
+    rs = ld - 1
+    CT, GP = 256, 4
+    hi = n * ld + BAND_PAD + 128 * ld                       # the allocation's padding
+    NR = (B + NB - 1) // NB + 1
+    starts = list(range(0, n, GP * NB))
+    for KC, VW in ((32, 2), (64, 4)):                       # FP64 and FP32 chunks
+        tpr = KC // VW                                      # threads per staged row
+        kt = np.arange(CT) % tpr * VW
+        i0 = np.arange(CT) // tpr
+        RP = CT // tpr
+        PER = NB // RP
+        for k0 in starts[:3] + starts[-3:]:
+            for f in sorted(set(range(min(NR - 1, 3))) | set(range(max(0, NR - 4), NR - 1))):
+                r0 = k0 + NB * (GP + f)
+                if r0 >= n:
+                    continue
+                for p in range(1, GP):
+                    c0 = k0 + NB * p
+                    if c0 >= n or r0 > c0 + NB - 1 + B:
+                        continue
+                    lo = r0 - B                             # the envelope starts no earlier
+                    kstart = k0 + (lo - k0) // KC * KC if lo > k0 else k0
+                    kcs = list(range(kstart, c0, KC))
+                    for kc in kcs[:1] + kcs[-1:]:
+                        assert ((kc + kt) % VW == 0).all()  # 16-byte aligned (B % VW == 0)
+                        for u in range(PER):
+                            for row0 in (r0, c0):
+                                idx = (row0 + i0 + RP * u) * rs + B + kc + kt
+                                for e in range(VW):
+                                    assert (idx + e).min() >= 0, ("far", n, B)
+                                    assert (idx + e).max() < min(hi, 2 ** 31), ("far", n, B)
+
+
 @pytest.mark.parametrize("n,B", SHAPES)
 def test_band_kernel_loads_stay_in_the_padded_allocation(n, B):
     bd = Bounds(n, B)
@@ -219,6 +258,7 @@ def test_band_kernel_loads_stay_in_the_padded_allocation(n, B):
     for M in (8, 32):
         _many_rhs(n, B, M, bd)
     _trailing_update(n, B, bd)
+    _far_rows(n, B)
     assert bd.worst <= 511                                  # far inside BAND_PAD
 
 
