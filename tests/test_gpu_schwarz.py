@@ -132,3 +132,23 @@ def check_solution(s, f, prob, out, histo):
     # end to end: the assembly difference explains the rest (first-order perturbation)
     pred = lu.solve((fg - prob.f) - (Kg - prob.K) @ xo)
     assert np.linalg.norm((xt - xo) - pred) <= 0.1 * np.linalg.norm(pred) + tol * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_side_stream_interior_factors_equal_a_sequential_factorisation(gx, precision):
+    """The two-level set-up factors the interior matrices on a side stream, its launches
+    enqueued by a host thread while the eigensolver runs.  Filling and factoring them again
+    alone on the context's stream, from the calling thread (the factorisation whose time
+    the library reports), must give the same factors: the PCG afterwards repeats the
+    first one's iterations and solution bit for bit."""
+    cfg = workloads.cfg0()
+    p = gx.GX_FP64 if precision == "fp64" else gx.GX_MIXED
+    s, f, _ = _setup(gx, cfg, coarse=True, precision=p)
+    first = s.pcg(f, rtol=1e-8, maxit=500)
+    x1 = first["x"].cpu().numpy().copy()
+    ms, flops = s.kernel_time(5, reps=1)           # interior fill and factorisation again
+    assert ms > 0 and flops > 0
+    again = s.pcg(f, rtol=1e-8, maxit=500)
+    assert again["iters"] == first["iters"]
+    assert np.array_equal(again["x"].cpu().numpy(), x1)
+    s.close()
