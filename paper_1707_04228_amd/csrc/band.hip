@@ -607,7 +607,7 @@ __global__ void __launch_bounds__(CT, 2) k_far(BandArgs a, T* v, int64_t k0, int
 // in 128 x 128 tiles of its lower triangle.  Eight waves each
 // form a 64 x 32 eighth as 4 x 2 matrix-instruction tiles of 16 x 16, so six fragment reads
 // from LDS feed eight instructions; two work-groups fit a compute unit.  The panels stream through LDS in chunks
-// of KW columns (256 bytes of a row); the next chunk is loaded into registers while the
+// of KW columns (128 bytes of a row in FP64, 256 in FP32); the next chunk is loaded into registers while the
 // current one is multiplied.  Chunks that lie left of the band for every row of the tile
 // are skipped.  The LDS row stride (KW plus 2 doubles or 4 floats) spreads the 16 rows x 4
 // reduction indices of one fragment read over distinct banks.
