@@ -484,6 +484,23 @@ __global__ void __launch_bounds__(CT, 2) k_far(BandArgs a, T* v, int64_t k0, int
     const int64_t c0 = k0 + (int64_t)NB * p;
     if (c0 >= n || r0 > c0 + NB - 1 + B) continue;   // no entries in this panel
     const int nb = (int)min<int64_t>(NB, n - c0);
+    // the block's entries and the inverse of the panel's diagonal block are loaded first, so
+    // that they arrive during the update
+    T av[2][4][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const int rl = wr + 16 * i + MT::row(q, lk), cl = wc + 16 * jj + li;
+          const int64_t r = r0 + rl, c = c0 + cl;
+          av[i][q][jj] = (r < n && cl < nb && c >= r - B) ? base[r * rs + B + c] : (T)0;
+        }
+    const double* invj = inv + ((int64_t)j * GP + p) * NB * NB;
+    double lv[NB * NB / CT];
+#pragma unroll
+    for (int u = 0; u < NB * NB / CT; ++u) lv[u] = invj[threadIdx.x + CT * u];
     typename MT::V acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -544,8 +561,6 @@ __global__ void __launch_bounds__(CT, 2) k_far(BandArgs a, T* v, int64_t k0, int
         __syncthreads();
       }
     }
-    // the block's entries, loaded after the update (the registers of a prefetch are
-    // needed by the update's staging)
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -553,20 +568,12 @@ __global__ void __launch_bounds__(CT, 2) k_far(BandArgs a, T* v, int64_t k0, int
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) {
           const int rl = wr + 16 * i + MT::row(q, lk), cl = wc + 16 * jj + li;
-          const int64_t r = r0 + rl, c = c0 + cl;
-          const double av = (r < n && cl < nb && c >= r - B) ? (double)base[r * rs + B + c] : 0.0;
-          D[rl][cl] = av - (double)acc[i][jj][q];
+          D[rl][cl] = (double)av[i][q][jj] - (double)acc[i][jj][q];
         }
-    {
-      const double* invj = inv + ((int64_t)j * GP + p) * NB * NB;
-      double lv[NB * NB / CT];                   // all loads issued before any is used
 #pragma unroll
-      for (int u = 0; u < NB * NB / CT; ++u) lv[u] = invj[threadIdx.x + CT * u];
-#pragma unroll
-      for (int u = 0; u < NB * NB / CT; ++u) {
-        const int idx = threadIdx.x + CT * u;
-        Li[idx / NB][idx % NB] = lv[u];
-      }
+    for (int u = 0; u < NB * NB / CT; ++u) {
+      const int idx = threadIdx.x + CT * u;
+      Li[idx / NB][idx % NB] = lv[u];
     }
     __syncthreads();
     v4d x[2][2];
